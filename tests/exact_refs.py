@@ -1,0 +1,137 @@
+"""Exact and asymptotic references taken from the paper (test-only, independent of oracle/).
+
+Every function cites the passage it restates.  Nothing here calls the oracle or the GPU
+path; these are the values the oracle is pinned to.
+"""
+from __future__ import annotations
+
+import math
+
+import mpmath as mp
+import numpy as np
+
+
+def gamma_cfi(species, gamma_b, k):
+    """Temporal CFI rate, Eq. CFI_temporal: (sum_s omega_bs^2 k^2/(k^2+1))^(1/2) with
+    omega_bs^2 = q_s^2 n_bs/(m_s gamma_b) (definition below Eq. full_master_eq)."""
+    w2 = sum(q * q * nb / (m * gamma_b) for (q, m, nb) in species)
+    return math.sqrt(w2 * k * k / (k * k + 1.0))
+
+
+def gamma_otsi(species, gamma_b, k):
+    """Temporal OTSI rate, Eq. OTSI_temporal."""
+    w2 = sum(q * q * nb / (m * gamma_b) for (q, m, nb) in species)
+    return math.sqrt(3.0) / 2 ** (4.0 / 3.0) * w2 ** (1.0 / 3.0) * \
+        ((k * k + gamma_b ** -2) / (k * k + 1.0)) ** (1.0 / 3.0)
+
+
+def gamma_tsi(species, gamma_b):
+    """Temporal TSI rate (Sec. IV.A): sqrt(3)/2^(4/3) (sum_s omega_bs^2/gamma_b^2)^(1/3)."""
+    w2 = sum(q * q * nb / (m * gamma_b) for (q, m, nb) in species)
+    return math.sqrt(3.0) / 2 ** (4.0 / 3.0) * (w2 / gamma_b ** 2) ** (1.0 / 3.0)
+
+
+def rk4_growth_factor(z):
+    """Amplification factor of classic RK4 for y' = lambda y with z = lambda dt."""
+    return 1.0 + z + z * z / 2.0 + z ** 3 / 6.0 + z ** 4 / 24.0
+
+
+def impulse_series(tau, xi, G, dps=40, tol=1e-30):
+    """Exact impulse response of [(d_xi^2+1) d_tau^2 - G^2] n = delta(xi) delta(tau)
+    (Eq. CFI_st_master with a delta source).  Laplace-transforming in tau gives
+    n = sin(kappa xi)/(kappa s^2), kappa^2 = 1 - G^2/s^2 (Eq. n_alpha_xi with alpha = -i s);
+    expanding in G^2/s^2 with spherical Bessel functions and inverting term by term:
+        n = sum_j G^(2j) tau^(2j+1)/(2j+1)! * xi^(j+1) j_j(xi) / (2^j j!).
+    The j = 0 term, tau sin(xi), is the free plasma response."""
+    if xi <= 0 or tau <= 0:
+        return 0.0
+    with mp.workdps(dps):
+        G, tau, xi = mp.mpf(G), mp.mpf(tau), mp.mpf(xi)
+        total = mp.mpf(0)
+        j = 0
+        big = mp.mpf(0)
+        while True:
+            jj = mp.sqrt(mp.pi / (2 * xi)) * mp.besselj(j + mp.mpf(1) / 2, xi)
+            term = G ** (2 * j) * tau ** (2 * j + 1) / mp.factorial(2 * j + 1) * \
+                xi ** (j + 1) * jj / (2 ** j * mp.factorial(j))
+            total += term
+            big = max(big, abs(term))
+            if j > 4 and abs(term) < tol * max(big, mp.mpf(1e-300)) and j > xi:
+                break
+            j += 1
+            if j > 4000:
+                raise RuntimeError("impulse series did not converge")
+        return float(total)
+
+
+def front_limit_exact(tau, xi, G):
+    """Exact impulse response of (d_tau^2 d_xi^2 - G^2) n = delta(xi) delta(tau),
+    Eq. CFI_st_master_front, solved in Appendix A:  [I_0(2 sqrt(G xi tau)) - J_0(...)]/(2G)."""
+    if xi <= 0 or tau <= 0:
+        return 0.0
+    z = 2.0 * math.sqrt(G * xi * tau)
+    return float((mp.besseli(0, z) - mp.besselj(0, z)) / (2.0 * G))
+
+
+def asym_front(tau, xi, G):
+    """Front-region asymptote, Eq. CFI_ST / Eq. np_small_C (xi << xi_tr)."""
+    th = xi / tau
+    return (1 + 3 * th / (8 * G)) / (4 * math.sqrt(math.pi)) * \
+        math.exp(2 * math.sqrt(G * tau * xi) * (1 - th / (4 * G))) / (G * (G * tau * xi) ** 0.25)
+
+
+def asym_critical(tau, G):
+    """Critical-line asymptote, Eq. CFI_T / Eq. np_C_cr, at xi = (2/sqrt(27)) G tau."""
+    return 3 ** (1.0 / 6.0) * math.gamma(1.0 / 3.0) * math.exp(4.0 / 3.0 * math.sqrt(2.0 / 3.0) * G * tau) / \
+        (4 * math.sqrt(2.0) * math.pi * G * (G * tau) ** (1.0 / 3.0))
+
+
+def asym_rear(tau, xi, G):
+    """Rear asymptote (spatiotemporal OTSI), Eq. OTSI_ST / Eq. np_large_C; returns the real
+    value 2 Re{...}."""
+    C = xi / (G * tau)
+    pref = 1.0 / (4 * G) * math.sqrt(2.0 / (3 * math.pi * xi))
+    corr = 1 + 1.0 / (6 * C ** (2.0 / 3.0)) * complex(0.25, math.sqrt(3) / 2)
+    ph = 1j * xi + 0.75 * complex(math.sqrt(3), -1) * (G * tau) ** (2.0 / 3.0) * xi ** (1.0 / 3.0) - 1j * math.pi / 4
+    return pref * 2 * (corr * np.exp(ph)).real
+
+
+def xi_transition(G, tau):
+    """CFI/OTSI transition point xi_tr = (2/sqrt(27)) G tau (Sec. III.B)."""
+    return 2.0 / math.sqrt(27.0) * G * tau
+
+
+def impulse_series_long(tau, xi, G, beta, dps=40, tol=1e-30):
+    """Exact impulse response of the transverse master equation with its longitudinal term,
+    [(d_xi^2+1) d_tau^2 - G^2 + beta^2 d_xi^2] n = delta(xi) delta(tau)  (Eq. full_master_eq in
+    one Fourier mode: G^2 = sum w^2 k^2/(1+k^2), beta^2 = sum w^2/(gamma^2 (1+k^2))).
+
+    Laplace in tau: n = sin(kappa xi)/(kappa (s^2+beta^2)), kappa^2 = (s^2-G^2)/(s^2+beta^2).
+    With 1 - kappa^2 = (G^2+beta^2)/(s^2+beta^2) and the spherical-Bessel expansion of
+    sin(xi sqrt(q))/sqrt(q) about q = 1,
+        n(s) = sum_j xi^(j+1) j_j(xi)/(2^j j!) (G^2+beta^2)^j / (s^2+beta^2)^(j+1),
+    and L^-1[(s^2+b^2)^-m] = sqrt(pi)/Gamma(m) (tau/2b)^(m-1/2) J_(m-1/2)(b tau).
+    For beta -> 0 this is impulse_series."""
+    if xi <= 0 or tau <= 0:
+        return 0.0
+    if beta == 0:
+        return impulse_series(tau, xi, G, dps, tol)
+    with mp.workdps(dps):
+        G, b, tau, xi = mp.mpf(G), mp.mpf(beta), mp.mpf(tau), mp.mpf(xi)
+        a2 = G * G + b * b
+        total = mp.mpf(0)
+        big = mp.mpf(0)
+        j = 0
+        while True:
+            sj = mp.sqrt(mp.pi / (2 * xi)) * mp.besselj(j + mp.mpf(1) / 2, xi)
+            lj = mp.sqrt(mp.pi) / mp.factorial(j) * (tau / (2 * b)) ** (j + mp.mpf(1) / 2) * \
+                mp.besselj(j + mp.mpf(1) / 2, b * tau)
+            term = xi ** (j + 1) * sj / (2 ** j * mp.factorial(j)) * a2 ** j * lj
+            total += term
+            big = max(big, abs(term))
+            if j > 4 and abs(term) < tol * max(big, mp.mpf(1e-300)) and j > xi and j > b * tau:
+                break
+            j += 1
+            if j > 4000:
+                raise RuntimeError("impulse series did not converge")
+        return float(total)
