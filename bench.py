@@ -1,0 +1,178 @@
+"""Benchmark of the spectral hot path on one MI355X.
+
+One "step" is one tau-step of the whole workload: the fused xi-march carrying the four
+Runge-Kutta stages, the tau-push, the field outputs and the renormalization, for every mode.
+Default workload: the 3D spectral run -- 205,859 modes of the 512 x 512 (k_x, k_y) grid
+with |k| <= 6, 4096 xi cells, electron beam n_b = 0.01 n_p, gamma = 1000, length 100,
+d_tau = 10, random-phase seed 1e-6, FP32 state with FP64 oscillator carry; outputs: the
+per-step max over xi of ln A for every mode and full ln|E|, ln|B| snapshots every 500 steps.
+
+Prints one JSON line (see the field list at the bottom).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("mode·ξ·τ cell-updates/s at 1 GPU; surrogate vs solver speed at "
+          "≤1e-2 log-amp err")
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    p = os.path.join(ROOT, "paper_2607_24234_amd", "csrc", "qs_spectral.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(precision_name):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE, if they were
+    taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "spectral3d_step_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        e = d.get(precision_name)
+        if not e or e.get("kernel_sha256_16") != kernel_source_hash():
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(inst, seconds=15.0):
+    """The FP64 oracle timed on the host cores on a bounded sample of the same workload:
+    `n_modes` modes spread over the mode list, all 4096 cells, a few tau-steps."""
+    import numpy as np
+    import oracle as O
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import mode_k, oracle_beam
+    O.build()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    beam = oracle_beam(inst)
+    k_all = mode_k(inst)
+    n_modes = 4 * threads
+    sel = np.linspace(0, len(k_all) - 1, n_modes).astype(int)
+    st = O.seed(beam, k_all[sel], O.SEED_NOISE, inst["seed_amp"], rng_seed=inst["rng_seed"])
+    t = time.perf_counter()
+    O.run(beam, k_all[sel], inst["d_tau"], 1, st, want_fields=False, want_max=True, n_threads=threads)
+    one = time.perf_counter() - t
+    steps = max(1, min(200, int(seconds / max(one, 1e-6))))
+    t = time.perf_counter()
+    O.run(beam, k_all[sel], inst["d_tau"], steps, st, want_fields=False, want_max=True,
+          n_threads=threads)
+    dt = time.perf_counter() - t
+    cells = n_modes * inst["n_xi"] * steps
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d modes evenly spread over the 205,859-mode list x %d cells x %d steps "
+                      "(FP64, per-step max ln A output), %.1f s wall" % (n_modes, inst["n_xi"], steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1995)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--snapshot-every", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the spectral modes are independent, so a "
+              "multi-GPU run is G independent shards of the mode list (see the design notes); "
+              "run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_24234_amd import inputs, qs
+
+    torch.cuda.set_device(0)
+    inst = inputs.spectral3d()
+    prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64
+    solver = qs.Solver([inst], precision=prec)
+    n_modes, n_xi = solver.total_modes, inst["n_xi"]
+    dtype = solver.dtype
+    K, W = args.steps, args.warmup
+
+    # output buffers, allocated before timing
+    n_snap = -(-K // args.snapshot_every) if args.snapshot_every > 0 else 0
+    max_buf = torch.empty((max(K, W, 1), n_modes), dtype=dtype, device="cuda")
+    snap_e = torch.empty((max(n_snap, 1), n_modes * n_xi), dtype=dtype, device="cuda")
+    snap_b = torch.empty_like(snap_e)
+    stream = solver.stream
+    L = qs.lib()
+
+    def one_step(s, row):
+        snap = args.snapshot_every > 0 and s % args.snapshot_every == 0
+        pe = snap_e[s // args.snapshot_every].data_ptr() if snap else None
+        pb = snap_b[s // args.snapshot_every].data_ptr() if snap else None
+        qs._check(L.qs_step_tau(solver.ctx, 1, 1, pe, pb, max_buf[row].data_ptr()))
+
+    for s in range(W):
+        qs._check(L.qs_step_tau(solver.ctx, 1, 1, None, None, max_buf[s].data_ptr()))
+    torch.cuda.synchronize()
+    solver.sync_check()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(K):
+        one_step(s, s)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    solver.sync_check()
+
+    wall = t1 - t0
+    per = [ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(K)]
+    avg_launch = sum(per) / K
+    cells = n_modes * n_xi
+    value = cells * K / wall
+    bpc = 48 if prec == qs.QS_FP32 else 96
+    achieved = bpc * cells / avg_launch / 1e9
+    traffic = read_traffic(args.precision)
+    growth = float((max_buf[K - 1].max() - max_buf[0].max()).item()) if K > 1 else 0.0
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": wall / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == qs.QS_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "spectral3d: 512x512 (k_x,k_y) grid |k|<=6 (205,859 modes), 4096 xi cells, "
+                               "n_b/n_p=0.01, gamma_b=1000, length 100, d_tau=10, noise seed 1e-6",
+                   "modes": n_modes, "n_xi": n_xi, "d_tau": inst["d_tau"],
+                   "state": args.precision, "oscillator_carry": "f64",
+                   "outputs": "per-step max ln A per mode; ln|E|,ln|B| snapshots every %d steps" % args.snapshot_every,
+                   "growth_nepers_over_run": growth},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "step_kernel (one launch = one tau-step of all modes)",
+                     "algorithmic_bytes_per_launch": bpc * cells,
+                     "avg_launch_ms": avg_launch * 1e3},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

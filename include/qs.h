@@ -1,0 +1,232 @@
+/*
+ * qs.h -- C ABI of the MI355X quasistatic beam-plasma instability solver.
+ *
+ * The model (San Miguel Claveria et al., "Quasistatic modeling of ultrarelativistic
+ * beam-plasma instabilities", Sec. II):  a dilute, cold beam of one or more species
+ * (charge q_s, mass m_s, unperturbed density n_bs, common Lorentz factor gamma_b) crosses
+ * a cold plasma of immobile ions.  In the co-moving coordinates xi = t - x (distance
+ * behind the beam front) and tau = t, with every quantity normalized as in Sec. II, the
+ * linear perturbations of one transverse Fourier mode exp(i k.r_perp) obey
+ *
+ *   (d_xi^2 + 1) n_p = rho                         plasma response, Eq. plasma_oscillations_QSA
+ *   (1 + k^2) Psi  = n_p                           pseudo-potential, Eq. poisson_QSA
+ *   d_tau rho      = d_xi j_par - i k j_perp       beam charge continuity, Eq. beam_continuity
+ *   d_tau j_par    = -gamma^-3 Omega d_xi Psi      beam current response, Eq. beam_momentum
+ *   d_tau j_perp   = +gamma^-1 Omega i k Psi
+ *
+ * with rho = sum_s q_s n_s the perturbed beam charge density, j_par, j_perp the perturbed
+ * beam current densities sum_s q_s n0_s v_s, and Omega(xi) = sum_s q_s^2 n0_s(xi)/m_s
+ * (for a xi-dependent profile the continuity equation is in flux form, Sec. III.D).  The
+ * solver marches the plasma response causally in xi from the front (n_p = d_xi n_p = 0
+ * ahead of the beam), with no slowly-varying-envelope approximation, alternating with a
+ * fourth-order Runge-Kutta push of (rho, j_par, j_perp) in tau.  Eliminating the currents
+ * gives the master equation, Eq. full_master_eq (Eq. full_master_eq_v2 for a profile).
+ *
+ * Fields written by the solver (ln of magnitudes, at cell centres):
+ *   E_par = -d_xi Psi,  E_perp = -i k (rho - n_p)/(1+k^2),  B_perp = -i k rho/(1+k^2),
+ *   |E| = sqrt(|E_par|^2 + |E_perp|^2),  A = sqrt(|E|^2 + |B_perp|^2).
+ *
+ * Discretization: cells j = 0..n_xi-1 of width h = length/n_xi; rho and j_perp at cell
+ * centres, j_par on the interior faces (j+1)h (the two outer faces carry no current); the
+ * oscillator is advanced through each cell with its exact solution for a cell-constant
+ * source.  Each mode is renormalized after every step by an exact power of two; every
+ * output already includes that scale.
+ *
+ * Conventions for every entry point:
+ *   - Return value: QS_OK or a negative qs_status.  No entry point aborts, throws or exits.
+ *     The message of the last failure on the calling thread is returned by qs_last_error().
+ *   - Argument errors (QS_ERR_ARG) are detected before any device work and leave every
+ *     buffer and the context unchanged.
+ *   - Pointers documented as "device" must point to device memory of the device that was
+ *     current at qs_init; "host" pointers to host memory.  The caller owns every buffer it
+ *     passes; the library keeps no pointer to them after the call returns, except the
+ *     workspace given to qs_init, which must stay alive until qs_free.
+ *   - Device work is queued on the stream given to qs_init, in call order.  Calls returning
+ *     host data synchronize that stream.  A context may be used by one thread at a time;
+ *     distinct contexts are independent.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QS_ABI_VERSION 1
+
+typedef enum {
+    QS_OK = 0,
+    QS_ERR_ARG = -1,         /* invalid argument (nothing was changed) */
+    QS_ERR_ALLOC = -2,       /* device or host allocation failed, or workspace too small */
+    QS_ERR_HIP = -3,         /* a HIP runtime call failed; the message names it */
+    QS_ERR_NUMERIC = -4,     /* a non-finite value was found when renormalizing */
+    QS_ERR_UNSUPPORTED = -5, /* valid request that this build does not implement */
+    QS_ERR_STATE = -6        /* the context is in a state that does not allow the call */
+} qs_status;
+
+enum { QS_FP64 = 0, QS_FP32 = 1 };           /* FP32: FP32 state, FP64 oscillator carry */
+enum { QS_PROFILE_FLATTOP = 0, QS_PROFILE_GAUSSIAN = 1, QS_PROFILE_TABLE = 2 };
+enum { QS_GEOM_SPECTRAL = 0, QS_GEOM_TRANSVERSE_GRID = 1 };
+enum {
+    QS_SEED_NOISE = 0,         /* rho = amp f(xi_j) exp(i theta), theta uniform from rng_seed */
+    QS_SEED_UNIFORM = 1,       /* rho = amp f(xi_j): the extended disturbance of Appendix C */
+    QS_SEED_FRONT_IMPULSE = 2, /* d_tau rho = amp/h in cell 0 at tau = 0+ (Appendix B impulse) */
+    QS_SEED_CENTROID = 3,      /* transverse-grid runs only (not in this build) */
+    QS_SEED_NONE = 4           /* state is zero until qs_set_state */
+};
+enum {
+    QS_FLAG_DROP_LONGITUDINAL = 1, /* drop the gamma^-2 d_xi^2 term: Eq. CFI_st_master */
+    QS_FLAG_NO_RESTORING = 2,      /* plasma operator d_xi^2 only: Eq. CFI_st_master_front */
+    QS_FLAG_STEADY_INFLOW = 4      /* plasma ahead of the front equals cell 0 (uniform test) */
+};
+
+/*
+ * One problem instance, in the paper's normalized units (Sec. II).
+ *   n_species, q, m, nb_over_np : beam species (charge/e, mass/m_e, peak n_bs/n_p), host
+ *                                 arrays of n_species entries.  Only sum q^2 nb/m enters.
+ *   gamma_b                     : common Lorentz factor (> 1).
+ *   length                      : beam length L; the grid covers 0 <= xi <= L.
+ *   profile                     : longitudinal shape f(xi) <= 1 of n_b0 (Sec. III.D):
+ *                                 FLATTOP f = 1; GAUSSIAN exp(-(xi-xi_center)^2/2 sigma_xi^2);
+ *                                 TABLE profile_table[n_xi] (host) at the cell centres.
+ *   geometry                    : QS_GEOM_SPECTRAL (list of k_perp); TRANSVERSE_GRID is
+ *                                 rejected with QS_ERR_UNSUPPORTED in this build.
+ *   n_modes, kx, ky             : transverse wavevectors, host arrays; ky may be NULL (slab).
+ *                                 Only |k| enters the dynamics.
+ *   nx, ny, lx, ly, sigma_r     : transverse grid (TRANSVERSE_GRID only; ignored otherwise).
+ *   n_xi                        : number of xi cells (>= 1).
+ *   d_tau                       : tau step of the Runge-Kutta push (> 0).
+ *   precision                   : QS_FP64, or QS_FP32 (FP32 state, FP64 oscillator carry).
+ *   seed_kind, seed_amp,        : initial perturbation (see the enum); for NOISE the phase of
+ *   rng_seed                      (instance i, mode m, cell j) is 2 pi u, u the top 53 bits of
+ *                                 output number (i*n_modes + m)*n_xi + j of SplitMix64 started
+ *                                 at rng_seed, over 2^53.
+ *   centroid_offset             : TRANSVERSE_GRID only.
+ *   flags                       : QS_FLAG_* test hooks (0 for the physical model).
+ */
+typedef struct qs_params {
+    int32_t n_species;
+    const double *q;
+    const double *m;
+    const double *nb_over_np;
+    double gamma_b;
+    double length;
+    int32_t profile;
+    double sigma_xi;
+    double xi_center;
+    const double *profile_table;
+    int32_t geometry;
+    int64_t n_modes;
+    const double *kx;
+    const double *ky;
+    int32_t nx, ny;
+    double lx, ly;
+    double sigma_r;
+    int32_t n_xi;
+    double d_tau;
+    int32_t precision;
+    int32_t seed_kind;
+    double seed_amp;
+    uint64_t rng_seed;
+    double centroid_offset;
+    int32_t flags;
+} qs_params;
+
+typedef struct qs_ctx qs_ctx;
+
+/* ABI version of the loaded library (QS_ABI_VERSION at build time). */
+int32_t qs_abi_version(void);
+
+/* Thread-local text of the last failure on this thread ("" if none).  Never NULL. */
+const char *qs_last_error(void);
+
+/*
+ * Bytes of device workspace qs_init needs for these instances (0 on invalid arguments).
+ * params: host array of n_instances problem descriptions.
+ */
+size_t qs_workspace_size(const qs_params *params, int32_t n_instances);
+
+/*
+ * Create a solver context for n_instances >= 1 instances (Sec. II problem statement per
+ * instance), build the per-instance tables (Omega(xi) at centres and faces, per-mode
+ * constants) and write the seed state.  All instances must share one precision; their
+ * n_xi, d_tau, species and modes may differ (a batched sweep).
+ *   hip_stream      : hipStream_t to queue device work on (NULL = the null stream).
+ *   workspace       : device buffer of workspace_bytes >= qs_workspace_size(...), owned by
+ *                     the caller and kept alive until qs_free; or NULL, in which case the
+ *                     library allocates (and frees) its own.
+ *   out             : receives the context (host).  Unchanged on failure.
+ * Errors: QS_ERR_ARG (invalid parameter: the message names it), QS_ERR_UNSUPPORTED,
+ *         QS_ERR_ALLOC, QS_ERR_HIP.
+ */
+qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream,
+                  void *workspace, size_t workspace_bytes, qs_ctx **out);
+
+/*
+ * Advance every instance by n_steps >= 0 tau-steps of its own d_tau (the hot path: one
+ * fused causal march over xi per step carrying all four Runge-Kutta stages).
+ * Outputs (device pointers, each may be NULL; element type double for QS_FP64, float for
+ * QS_FP32), for the modes of all instances concatenated in instance order (mode index
+ * M = sum of n_modes of the earlier instances + m):
+ *   out_ln_e, out_ln_b : field snapshots of the state at the start of every step s of this
+ *                        call with s % out_every == 0; snapshot t of instance i starts at
+ *                        element t * S + off_i with S = sum_i n_xi_i * n_modes_i and
+ *                        off_i = sum_{i'<i} n_xi_i' * n_modes_i', then [n_xi_i][n_modes_i].
+ *                        With n_steps == 0 one snapshot of the current state is written and
+ *                        the state does not change.
+ *   out_max_ln_a       : [n_steps][total modes] max over xi of ln A at the start of each step.
+ *   out_every >= 1 (ignored when both snapshot pointers are NULL).
+ * Errors: QS_ERR_ARG, QS_ERR_HIP.  Does not synchronize.
+ */
+qs_status qs_step_tau(qs_ctx *ctx, int32_t n_steps, int32_t out_every, void *out_ln_e,
+                      void *out_ln_b, void *out_max_ln_a);
+
+/*
+ * Synchronize the context's stream and report whether any renormalization since the last
+ * call met a non-finite value (QS_ERR_NUMERIC; the message names the step and mode).
+ */
+qs_status qs_sync_check(qs_ctx *ctx);
+
+/*
+ * Number of tau-steps taken since qs_init (host).  Returns -1 for a NULL context.
+ */
+int64_t qs_steps_done(const qs_ctx *ctx);
+
+/*
+ * Copy the state out (synchronizes).  Host arrays of 2 * sum_i n_modes_i * n_xi_i doubles
+ * each, complex interleaved, instance-major then mode then cell:
+ *   rho    : beam charge density at the cell centres,
+ *   j_par  : longitudinal beam current density at the rear face of each cell (the last
+ *            cell's entry, the outer face, is 0),
+ *   j_perp : transverse beam current density along k at the cell centres,
+ *   log2_scale : [total modes] the state of mode M is (rho, j_par, j_perp) * 2^log2_scale[M].
+ * Any array may be NULL.  Errors: QS_ERR_ARG, QS_ERR_HIP.
+ */
+qs_status qs_get_state(qs_ctx *ctx, double *rho, double *j_par, double *j_perp,
+                       double *log2_scale);
+
+/*
+ * Replace the state (same layout as qs_get_state; all four arrays required, host).
+ * log2_scale must hold integers.  Values are rounded to the context's precision.
+ * Errors: QS_ERR_ARG, QS_ERR_HIP.
+ */
+qs_status qs_set_state(qs_ctx *ctx, const double *rho, const double *j_par,
+                       const double *j_perp, const double *log2_scale);
+
+/* Release the context and anything the library allocated for it.  NULL is ignored. */
+void qs_free(qs_ctx *ctx);
+
+/*
+ * Diagnostics: output number i (0-based) of the SplitMix64 stream started at `seed`, as the
+ * device seed kernel evaluates it (Steele, Lea and Flood, OOPSLA 2014), computed on the host.
+ */
+uint64_t qs_debug_splitmix64(uint64_t seed, uint64_t i);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

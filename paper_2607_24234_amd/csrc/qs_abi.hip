@@ -1,0 +1,502 @@
+// Host side of libqs: argument validation, per-instance tables, workspace layout, launch
+// sequencing and state import/export.  Every entry point is declared in include/qs.h.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+thread_local std::string g_err;
+
+qs_status fail(qs_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+qs_status hip_fail(hipError_t e, const char *what) {
+    return fail(QS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QS_HIP(call, what)                           \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int env_mpl() {
+    const char *s = std::getenv("QS_MODES_PER_LANE");
+    if (s && (std::atoi(s) == 1 || std::atoi(s) == 2)) return std::atoi(s);
+    return 1;
+}
+
+// Sizes derived from validated parameters.
+struct Plan {
+    int precision = QS_FP32;
+    int mpl = 1;
+    size_t ts = 4;                 // bytes per state element
+    std::vector<InstDev> inst;
+    std::vector<int32_t> blk_inst;
+    int64_t state_elems = 0;
+    int64_t table_elems = 0;       // Omega centres+faces (and shape) elements
+    int64_t total_modes = 0;
+    int64_t total_pmodes = 0;
+    int64_t snap_elems = 0;        // elements of one snapshot over all instances
+    int32_t max_n_xi = 0;
+    // workspace offsets (bytes)
+    size_t off_state, off_omega, off_shape, off_k, off_log2s, off_epend, off_inst, off_blk,
+        off_iidx, off_err, total;
+};
+
+bool finite(double x) { return std::isfinite(x); }
+
+qs_status validate_one(const qs_params &p, int i) {
+    const std::string at = "instance " + std::to_string(i) + ": ";
+    if (p.geometry == QS_GEOM_TRANSVERSE_GRID)
+        return fail(QS_ERR_UNSUPPORTED, at + "geometry TRANSVERSE_GRID is not implemented in this build");
+    if (p.geometry != QS_GEOM_SPECTRAL) return fail(QS_ERR_ARG, at + "unknown geometry");
+    if (p.n_species < 1 || p.n_species > 64) return fail(QS_ERR_ARG, at + "n_species must be in [1, 64]");
+    if (!p.q || !p.m || !p.nb_over_np) return fail(QS_ERR_ARG, at + "q, m and nb_over_np are required");
+    for (int s = 0; s < p.n_species; ++s) {
+        if (!finite(p.q[s]) || !finite(p.m[s]) || !(p.m[s] > 0.0))
+            return fail(QS_ERR_ARG, at + "species " + std::to_string(s) + ": need finite q and m > 0");
+        if (!finite(p.nb_over_np[s]) || p.nb_over_np[s] < 0.0)
+            return fail(QS_ERR_ARG, at + "species " + std::to_string(s) + ": need finite nb_over_np >= 0");
+    }
+    if (!finite(p.gamma_b) || !(p.gamma_b > 1.0)) return fail(QS_ERR_ARG, at + "gamma_b must be finite and > 1");
+    if (!finite(p.length) || !(p.length > 0.0)) return fail(QS_ERR_ARG, at + "length must be finite and > 0");
+    if (p.n_xi < 1 || p.n_xi > (1 << 22)) return fail(QS_ERR_ARG, at + "n_xi must be in [1, 2^22]");
+    if (!finite(p.d_tau) || !(p.d_tau > 0.0)) return fail(QS_ERR_ARG, at + "d_tau must be finite and > 0");
+    if (p.precision != QS_FP64 && p.precision != QS_FP32) return fail(QS_ERR_ARG, at + "unknown precision");
+    if (p.n_modes < 1 || p.n_modes > (int64_t(1) << 26)) return fail(QS_ERR_ARG, at + "n_modes must be in [1, 2^26]");
+    if (!p.kx) return fail(QS_ERR_ARG, at + "kx is required");
+    for (int64_t m = 0; m < p.n_modes; ++m) {
+        if (!finite(p.kx[m]) || (p.ky && !finite(p.ky[m])))
+            return fail(QS_ERR_ARG, at + "non-finite wavenumber at mode " + std::to_string(m));
+    }
+    switch (p.profile) {
+    case QS_PROFILE_FLATTOP: break;
+    case QS_PROFILE_GAUSSIAN:
+        if (!finite(p.sigma_xi) || !(p.sigma_xi > 0.0) || !finite(p.xi_center))
+            return fail(QS_ERR_ARG, at + "GAUSSIAN profile needs sigma_xi > 0 and a finite xi_center");
+        break;
+    case QS_PROFILE_TABLE:
+        if (!p.profile_table) return fail(QS_ERR_ARG, at + "TABLE profile needs profile_table");
+        for (int j = 0; j < p.n_xi; ++j)
+            if (!finite(p.profile_table[j]) || p.profile_table[j] < 0.0)
+                return fail(QS_ERR_ARG, at + "profile_table entries must be finite and >= 0");
+        break;
+    default: return fail(QS_ERR_ARG, at + "unknown profile");
+    }
+    if (p.seed_kind == QS_SEED_CENTROID)
+        return fail(QS_ERR_UNSUPPORTED, at + "CENTROID seed needs the transverse-grid geometry");
+    if (p.seed_kind != QS_SEED_NOISE && p.seed_kind != QS_SEED_UNIFORM &&
+        p.seed_kind != QS_SEED_FRONT_IMPULSE && p.seed_kind != QS_SEED_NONE)
+        return fail(QS_ERR_ARG, at + "unknown seed_kind");
+    if (!finite(p.seed_amp)) return fail(QS_ERR_ARG, at + "seed_amp must be finite");
+    if (p.seed_kind == QS_SEED_FRONT_IMPULSE) {
+        for (int64_t m = 0; m < p.n_modes; ++m) {
+            double k2 = p.kx[m] * p.kx[m] + (p.ky ? p.ky[m] * p.ky[m] : 0.0);
+            if (k2 == 0.0) return fail(QS_ERR_ARG, at + "FRONT_IMPULSE seed needs k != 0 for every mode");
+        }
+    }
+    if (p.flags & ~(QS_FLAG_DROP_LONGITUDINAL | QS_FLAG_NO_RESTORING | QS_FLAG_STEADY_INFLOW))
+        return fail(QS_ERR_ARG, at + "unknown flag bits");
+    return QS_OK;
+}
+
+qs_status make_plan(const qs_params *params, int32_t n, Plan &pl) {
+    if (!params) return fail(QS_ERR_ARG, "params is NULL");
+    if (n < 1 || n > (1 << 20)) return fail(QS_ERR_ARG, "n_instances must be in [1, 2^20]");
+    for (int i = 0; i < n; ++i) {
+        qs_status st = validate_one(params[i], i);
+        if (st != QS_OK) return st;
+        if (params[i].precision != params[0].precision)
+            return fail(QS_ERR_ARG, "all instances must share one precision");
+        if ((params[i].flags & QS_FLAG_NO_RESTORING) != (params[0].flags & QS_FLAG_NO_RESTORING))
+            return fail(QS_ERR_ARG, "all instances must share QS_FLAG_NO_RESTORING");
+    }
+    pl.precision = params[0].precision;
+    pl.mpl = env_mpl();
+    pl.ts = pl.precision == QS_FP64 ? 8 : 4;
+    const int lanes_modes = kWave * pl.mpl;
+    int64_t blocks = 0, pmodes = 0, modes = 0, state = 0, table = 0, snap = 0;
+    pl.inst.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const qs_params &p = params[i];
+        InstDev &d = pl.inst[i];
+        std::memset(&d, 0, sizeof(d));
+        d.n_xi = p.n_xi;
+        d.n_modes = (int32_t)p.n_modes;
+        d.n_blocks = (int32_t)((p.n_modes + lanes_modes - 1) / lanes_modes);
+        d.block0 = (int32_t)blocks;
+        d.pmode0 = (int32_t)pmodes;
+        d.mode0 = (int32_t)modes;
+        d.flags = p.flags;
+        d.state_off = state;
+        d.omega_off = table;
+        d.snap_off = snap;
+        const double h = p.length / p.n_xi;
+        const bool drop = (p.flags & QS_FLAG_DROP_LONGITUDINAL) != 0;
+        d.h = h;
+        d.ih = drop ? 0.0 : 1.0 / h;
+        d.dtau = p.d_tau;
+        d.ginv = 1.0 / p.gamma_b;
+        d.g3inv = drop ? 0.0 : 1.0 / (p.gamma_b * p.gamma_b * p.gamma_b);
+        d.c1 = std::cos(h);
+        d.s1 = std::sin(h);
+        d.c2 = std::cos(0.5 * h);
+        d.s2 = std::sin(0.5 * h);
+        blocks += d.n_blocks;
+        pmodes += (int64_t)d.n_blocks * lanes_modes;
+        modes += p.n_modes;
+        state += (int64_t)d.n_blocks * p.n_xi * 6 * pl.mpl * kWave;
+        table += 2 * (int64_t)p.n_xi;
+        snap += (int64_t)p.n_xi * p.n_modes;
+        pl.max_n_xi = std::max(pl.max_n_xi, p.n_xi);
+    }
+    if (blocks > (int64_t(1) << 31) - 1) return fail(QS_ERR_ARG, "too many blocks");
+    pl.blk_inst.resize(blocks);
+    for (int i = 0; i < n; ++i)
+        for (int b = 0; b < pl.inst[i].n_blocks; ++b) pl.blk_inst[pl.inst[i].block0 + b] = i;
+    pl.state_elems = state;
+    pl.table_elems = table;
+    pl.total_modes = modes;
+    pl.total_pmodes = pmodes;
+    pl.snap_elems = snap;
+    size_t o = 0;
+    pl.off_state = o; o = align_up(o + (size_t)state * pl.ts);
+    pl.off_omega = o; o = align_up(o + (size_t)table * pl.ts);
+    pl.off_shape = o; o = align_up(o + (size_t)table * sizeof(double));
+    pl.off_k = o; o = align_up(o + (size_t)pmodes * sizeof(double));
+    pl.off_log2s = o; o = align_up(o + (size_t)pmodes * sizeof(int32_t));
+    pl.off_epend = o; o = align_up(o + (size_t)pmodes * sizeof(int32_t));
+    pl.off_inst = o; o = align_up(o + (size_t)n * sizeof(InstDev));
+    pl.off_blk = o; o = align_up(o + (size_t)blocks * sizeof(int32_t));
+    pl.off_iidx = o; o = align_up(o + (size_t)n * sizeof(int32_t));
+    pl.off_err = o; o = align_up(o + sizeof(uint32_t) * 4);
+    pl.total = o;
+    return QS_OK;
+}
+
+}  // namespace
+}  // namespace qs
+
+using namespace qs;
+
+struct qs_ctx {
+    Plan pl;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    bool owns_ws = false;
+    int64_t steps_done = 0;
+    char *at(size_t off) const { return ws + off; }
+};
+
+namespace {
+
+qs_status upload_tables(qs_ctx *c, const qs_params *params) {
+    const Plan &pl = c->pl;
+    const int n = (int)pl.inst.size();
+    std::vector<double> shape(pl.table_elems, 0.0);
+    std::vector<double> om64(pl.table_elems, 0.0);
+    std::vector<double> kmode(pl.total_pmodes, 0.0);
+    std::vector<int32_t> iidx(n);
+    for (int i = 0; i < n; ++i) {
+        const qs_params &p = params[i];
+        const InstDev &d = pl.inst[i];
+        const int N = p.n_xi;
+        const double h = p.length / N;
+        double q2nm = 0.0;  // sum_s q_s^2 nb_s / m_s
+        for (int s = 0; s < p.n_species; ++s) q2nm += p.q[s] * p.q[s] * p.nb_over_np[s] / p.m[s];
+        double *f = shape.data() + d.omega_off;
+        double *oc = om64.data() + d.omega_off;
+        double *of = oc + N;
+        for (int j = 0; j < N; ++j) {
+            const double xi = (j + 0.5) * h;
+            if (p.profile == QS_PROFILE_FLATTOP) f[j] = 1.0;
+            else if (p.profile == QS_PROFILE_GAUSSIAN) {
+                const double z = (xi - p.xi_center) / p.sigma_xi;
+                f[j] = std::exp(-0.5 * z * z);
+            } else f[j] = p.profile_table[j];
+            oc[j] = q2nm * f[j];
+        }
+        for (int j = 0; j < N; ++j) of[j] = (j + 1 < N) ? 0.5 * (oc[j] + oc[j + 1]) : 0.0;
+        for (int64_t m = 0; m < p.n_modes; ++m) {
+            const double kx = p.kx[m], ky = p.ky ? p.ky[m] : 0.0;
+            kmode[d.pmode0 + m] = std::sqrt(kx * kx + ky * ky);
+        }
+        iidx[i] = i;
+    }
+    if (pl.precision == QS_FP64) {
+        QS_HIP(hipMemcpyAsync(c->at(pl.off_omega), om64.data(), om64.size() * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream), "copy Omega tables");
+    } else {
+        std::vector<float> om32(om64.begin(), om64.end());
+        QS_HIP(hipMemcpyAsync(c->at(pl.off_omega), om32.data(), om32.size() * sizeof(float),
+                              hipMemcpyHostToDevice, c->stream), "copy Omega tables");
+        QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    }
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_shape), shape.data(), shape.size() * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream), "copy profile");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_k), kmode.data(), kmode.size() * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream), "copy wavenumbers");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_inst), pl.inst.data(), pl.inst.size() * sizeof(InstDev),
+                          hipMemcpyHostToDevice, c->stream), "copy instance table");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_blk), pl.blk_inst.data(), pl.blk_inst.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, c->stream), "copy block table");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_iidx), iidx.data(), iidx.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, c->stream), "copy instance index");
+    QS_HIP(hipMemsetAsync(c->at(pl.off_err), 0, sizeof(uint32_t) * 4, c->stream), "clear error flag");
+    // the host vectors die here: make the copies complete first
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return QS_OK;
+}
+
+qs_status seed_state(qs_ctx *c, const qs_params *params) {
+    const Plan &pl = c->pl;
+    // every instance must share the seed kind/amp/rng_seed within one launch: launch per group
+    const int n = (int)pl.inst.size();
+    QS_HIP(hipMemsetAsync(c->at(pl.off_state), 0, (size_t)pl.state_elems * pl.ts, c->stream), "clear state");
+    QS_HIP(hipMemsetAsync(c->at(pl.off_log2s), 0, (size_t)pl.total_pmodes * sizeof(int32_t), c->stream), "clear scales");
+    QS_HIP(hipMemsetAsync(c->at(pl.off_epend), 0, (size_t)pl.total_pmodes * sizeof(int32_t), c->stream), "clear scales");
+    int i0 = 0;
+    while (i0 < n) {
+        int i1 = i0 + 1;
+        while (i1 < n && params[i1].seed_kind == params[i0].seed_kind &&
+               params[i1].seed_amp == params[i0].seed_amp && params[i1].rng_seed == params[i0].rng_seed)
+            ++i1;
+        if (params[i0].seed_kind != QS_SEED_NONE) {
+            int b0 = pl.inst[i0].block0;
+            int nb = pl.inst[i1 - 1].block0 + pl.inst[i1 - 1].n_blocks - b0;
+            int mx = 0;
+            for (int i = i0; i < i1; ++i) mx = std::max(mx, pl.inst[i].n_xi);
+            SeedArgs a{};
+            a.state = c->at(pl.off_state);
+            a.blk_inst = reinterpret_cast<const int32_t *>(c->at(pl.off_blk));
+            a.block_base = b0;
+            a.inst = reinterpret_cast<const InstDev *>(c->at(pl.off_inst));
+            a.shape = reinterpret_cast<const double *>(c->at(pl.off_shape));
+            a.kmode = reinterpret_cast<const double *>(c->at(pl.off_k));
+            a.log2s = reinterpret_cast<int32_t *>(c->at(pl.off_log2s));
+            a.epend = reinterpret_cast<int32_t *>(c->at(pl.off_epend));
+            a.kind = params[i0].seed_kind;
+            a.amp = params[i0].seed_amp;
+            a.rng_seed = params[i0].rng_seed;
+            a.inst_index = reinterpret_cast<const int32_t *>(c->at(pl.off_iidx));
+            QS_HIP(launch_seed(pl.precision, pl.mpl, nb, mx, a, c->stream), "seed kernel");
+        }
+        i0 = i1;
+    }
+    return QS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t qs_abi_version(void) { return QS_ABI_VERSION; }
+
+const char *qs_last_error(void) { return g_err.c_str(); }
+
+size_t qs_workspace_size(const qs_params *params, int32_t n_instances) {
+    Plan pl;
+    if (make_plan(params, n_instances, pl) != QS_OK) return 0;
+    return pl.total;
+}
+
+qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream, void *workspace,
+                  size_t workspace_bytes, qs_ctx **out) {
+    g_err.clear();
+    if (!out) return fail(QS_ERR_ARG, "out is NULL");
+    Plan pl;
+    qs_status st = make_plan(params, n_instances, pl);
+    if (st != QS_OK) return st;
+    if (workspace && workspace_bytes < pl.total)
+        return fail(QS_ERR_ALLOC, "workspace too small: need " + std::to_string(pl.total) + " bytes");
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+        return fail(QS_ERR_ARG, "workspace must be 256-byte aligned");
+    qs_ctx *c = new (std::nothrow) qs_ctx;
+    if (!c) return fail(QS_ERR_ALLOC, "host allocation of the context failed");
+    c->pl = std::move(pl);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
+    if (workspace) {
+        c->ws = static_cast<char *>(workspace);
+    } else {
+        void *p = nullptr;
+        e = hipMalloc(&p, c->pl.total);
+        if (e != hipSuccess) { delete c; return fail(QS_ERR_ALLOC, "hipMalloc of the workspace failed"); }
+        c->ws = static_cast<char *>(p);
+        c->owns_ws = true;
+    }
+    st = upload_tables(c, params);
+    if (st == QS_OK) st = seed_state(c, params);
+    if (st != QS_OK) { qs_free(c); return st; }
+    *out = c;
+    return QS_OK;
+}
+
+qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_ln_e, void *out_ln_b,
+                      void *out_max_ln_a) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (n_steps < 0) return fail(QS_ERR_ARG, "n_steps must be >= 0");
+    if ((out_ln_e == nullptr) != (out_ln_b == nullptr))
+        return fail(QS_ERR_ARG, "out_ln_e and out_ln_b must both be given or both be NULL");
+    const bool snaps = out_ln_e != nullptr;
+    if (snaps && out_every < 1) return fail(QS_ERR_ARG, "out_every must be >= 1");
+    if (n_steps == 0 && !snaps) return QS_OK;
+    const Plan &pl = c->pl;
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    StepArgs a{};
+    a.state = c->at(pl.off_state);
+    a.blk_inst = reinterpret_cast<const int32_t *>(c->at(pl.off_blk));
+    a.inst = reinterpret_cast<const InstDev *>(c->at(pl.off_inst));
+    a.omega = c->at(pl.off_omega);
+    a.kmode = reinterpret_cast<const double *>(c->at(pl.off_k));
+    a.log2s = reinterpret_cast<int32_t *>(c->at(pl.off_log2s));
+    a.epend = reinterpret_cast<int32_t *>(c->at(pl.off_epend));
+    a.total_modes = (int32_t)pl.total_modes;
+    a.err = reinterpret_cast<uint32_t *>(c->at(pl.off_err));
+    const bool restoring = !(pl.inst[0].flags & QS_FLAG_NO_RESTORING);
+    const int nblk = (int)pl.blk_inst.size();
+    if (n_steps == 0) {
+        a.ln_e = out_ln_e;
+        a.ln_b = out_ln_b;
+        a.update = 0;
+        QS_HIP(launch_step(pl.precision, pl.mpl, restoring, true, nblk, a, c->stream), "step kernel");
+        return QS_OK;
+    }
+    for (int s = 0; s < n_steps; ++s) {
+        const bool snap = snaps && (s % out_every == 0);
+        a.ln_e = snap ? out_ln_e : nullptr;
+        a.ln_b = snap ? out_ln_b : nullptr;
+        a.snap_base = snap ? (int64_t)(s / out_every) * pl.snap_elems : 0;
+        a.max_ln_a = out_max_ln_a;
+        a.max_base = (int64_t)s * pl.total_modes;
+        a.update = 1;
+        const bool fields = snap || out_max_ln_a != nullptr;
+        QS_HIP(launch_step(pl.precision, pl.mpl, restoring, fields, nblk, a, c->stream), "step kernel");
+        ++c->steps_done;
+    }
+    return QS_OK;
+}
+
+qs_status qs_sync_check(qs_ctx *c) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    uint32_t flag = 0;
+    QS_HIP(hipMemcpy(&flag, c->at(c->pl.off_err), sizeof(flag), hipMemcpyDeviceToHost), "read error flag");
+    if (flag) {
+        QS_HIP(hipMemset(c->at(c->pl.off_err), 0, sizeof(uint32_t)), "clear error flag");
+        return fail(QS_ERR_NUMERIC, "non-finite state at renormalization (padded mode " +
+                                        std::to_string(flag - 1) + ") after step " +
+                                        std::to_string(c->steps_done));
+    }
+    return QS_OK;
+}
+
+int64_t qs_steps_done(const qs_ctx *c) { return c ? c->steps_done : -1; }
+
+qs_status qs_get_state(qs_ctx *c, double *rho, double *j_par, double *j_perp, double *log2_scale) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    const Plan &pl = c->pl;
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    std::vector<char> raw((size_t)pl.state_elems * pl.ts);
+    std::vector<int32_t> l2(pl.total_pmodes), ep(pl.total_pmodes);
+    QS_HIP(hipMemcpy(raw.data(), c->at(pl.off_state), raw.size(), hipMemcpyDeviceToHost), "copy state");
+    QS_HIP(hipMemcpy(l2.data(), c->at(pl.off_log2s), l2.size() * 4, hipMemcpyDeviceToHost), "copy scales");
+    QS_HIP(hipMemcpy(ep.data(), c->at(pl.off_epend), ep.size() * 4, hipMemcpyDeviceToHost), "copy scales");
+    const int NC = 2 * pl.mpl, ROW = 3 * NC, LM = kWave * pl.mpl;
+    auto val = [&](int64_t e) -> double {
+        return pl.precision == QS_FP64 ? reinterpret_cast<const double *>(raw.data())[e]
+                                       : (double)reinterpret_cast<const float *>(raw.data())[e];
+    };
+    int64_t out0 = 0;
+    for (const InstDev &d : pl.inst) {
+        const int N = d.n_xi;
+        for (int m = 0; m < d.n_modes; ++m) {
+            const int b = m / LM, q = m % LM, lane = q / pl.mpl, t = q % pl.mpl;
+            const int e = ep[d.pmode0 + m];
+            const double sc = std::ldexp(1.0, -e);
+            if (log2_scale) log2_scale[d.mode0 + m] = (double)l2[d.pmode0 + m] + e;
+            for (int j = 0; j < N; ++j) {
+                const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave + lane;
+                auto x = [&](int var, int part) { return val(cell + (int64_t)(var * NC + 2 * t + part) * kWave) * sc; };
+                const int64_t o = 2 * (out0 + (int64_t)m * N + j);
+                if (rho) { rho[o] = x(0, 0); rho[o + 1] = x(0, 1); }
+                if (j_par) { j_par[o] = x(1, 0); j_par[o + 1] = x(1, 1); }
+                if (j_perp) { j_perp[o] = -x(2, 1); j_perp[o + 1] = x(2, 0); }  // j_perp = i T
+            }
+        }
+        out0 += (int64_t)d.n_modes * N;
+    }
+    return QS_OK;
+}
+
+qs_status qs_set_state(qs_ctx *c, const double *rho, const double *j_par, const double *j_perp,
+                       const double *log2_scale) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (!rho || !j_par || !j_perp || !log2_scale) return fail(QS_ERR_ARG, "all state arrays are required");
+    const Plan &pl = c->pl;
+    for (int64_t M = 0; M < pl.total_modes; ++M)
+        if (!(log2_scale[M] == std::floor(log2_scale[M])) || std::fabs(log2_scale[M]) > 1e9)
+            return fail(QS_ERR_ARG, "log2_scale entries must be integers");
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    std::vector<char> raw((size_t)pl.state_elems * pl.ts, 0);
+    std::vector<int32_t> l2(pl.total_pmodes, 0), ep(pl.total_pmodes, 0);
+    const int NC = 2 * pl.mpl, ROW = 3 * NC, LM = kWave * pl.mpl;
+    auto put = [&](int64_t e, double v) {
+        if (pl.precision == QS_FP64) reinterpret_cast<double *>(raw.data())[e] = v;
+        else reinterpret_cast<float *>(raw.data())[e] = (float)v;
+    };
+    int64_t out0 = 0;
+    for (const InstDev &d : pl.inst) {
+        const int N = d.n_xi;
+        for (int m = 0; m < d.n_modes; ++m) {
+            const int b = m / LM, q = m % LM, lane = q / pl.mpl, t = q % pl.mpl;
+            l2[d.pmode0 + m] = (int32_t)log2_scale[d.mode0 + m];
+            for (int j = 0; j < N; ++j) {
+                const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave + lane;
+                auto at = [&](int var, int part) { return cell + (int64_t)(var * NC + 2 * t + part) * kWave; };
+                const int64_t o = 2 * (out0 + (int64_t)m * N + j);
+                put(at(0, 0), rho[o]); put(at(0, 1), rho[o + 1]);
+                put(at(1, 0), j_par[o]); put(at(1, 1), j_par[o + 1]);
+                put(at(2, 0), j_perp[o + 1]); put(at(2, 1), -j_perp[o]);  // T = -i j_perp
+            }
+        }
+        out0 += (int64_t)d.n_modes * N;
+    }
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    QS_HIP(hipMemcpy(c->at(pl.off_state), raw.data(), raw.size(), hipMemcpyHostToDevice), "copy state");
+    QS_HIP(hipMemcpy(c->at(pl.off_log2s), l2.data(), l2.size() * 4, hipMemcpyHostToDevice), "copy scales");
+    QS_HIP(hipMemcpy(c->at(pl.off_epend), ep.data(), ep.size() * 4, hipMemcpyHostToDevice), "copy scales");
+    return QS_OK;
+}
+
+void qs_free(qs_ctx *c) {
+    if (!c) return;
+    if (c->owns_ws && c->ws) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->ws);
+    }
+    delete c;
+}
+
+// Host evaluation of the device's SplitMix64 (used by the generator cross-check tests).
+uint64_t qs_debug_splitmix64(uint64_t seed, uint64_t i) { return splitmix64_host(seed, i); }
+
+}  // extern "C"

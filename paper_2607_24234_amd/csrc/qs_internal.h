@@ -1,0 +1,77 @@
+// Internal declarations shared by the HIP sources of libqs (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qs.h"
+
+namespace qs {
+
+constexpr int kWave = 64;  // lanes per wavefront on CDNA
+
+// Per-instance constants, read by every workgroup of that instance (wave-uniform).
+struct InstDev {
+    int32_t n_xi;        // cells
+    int32_t n_modes;     // active modes
+    int32_t n_blocks;    // 64-lane blocks of this instance
+    int32_t block0;      // first global block index
+    int32_t pmode0;      // first padded global mode index
+    int32_t mode0;       // first global (unpadded) mode index
+    int32_t flags;       // QS_FLAG_*
+    int32_t pad_;
+    int64_t state_off;   // element offset of block 0 in the state array
+    int64_t omega_off;   // element offset of this instance's Omega tables (centres, then faces)
+    int64_t snap_off;    // element offset of this instance inside one snapshot
+    double h, ih;        // cell width, 1/h (0 when the longitudinal term is dropped)
+    double dtau;
+    double ginv, g3inv;  // gamma^-1, gamma^-3 (g3inv is 0 when the longitudinal term is dropped)
+    double c1, s1;       // cos h, sin h
+    double c2, s2;       // cos h/2, sin h/2
+};
+
+// Arguments of one tau-step launch.
+struct StepArgs {
+    void *state;              // TS elements, layout [block][cell][var 3][col 2*MPL][lane 64]
+    const int32_t *blk_inst;  // global block -> instance
+    const InstDev *inst;
+    const void *omega;        // TC elements: per instance [n_xi] centres then [n_xi] faces
+    const double *kmode;      // |k| per padded mode
+    int32_t *log2s;           // per padded mode: applied power of two (L)
+    int32_t *epend;           // per padded mode: pending exponent (applied at the next load)
+    void *ln_e, *ln_b;        // snapshot outputs (TS) or null
+    void *max_ln_a;           // [step][total modes] (TS) or null
+    int64_t snap_base;        // element offset of this step's snapshot (ln_e/ln_b)
+    int64_t max_base;         // element offset of this step's row in max_ln_a
+    int32_t total_modes;      // unpadded total modes (row length of max_ln_a)
+    int32_t update;           // 1: advance the state; 0: fields only
+    uint32_t *err;            // nonzero after a non-finite renormalization: 1 + padded mode
+};
+
+struct SeedArgs {
+    void *state;
+    const int32_t *blk_inst;
+    const InstDev *inst;
+    const double *shape;      // per instance at omega_off: f(xi_j) (double)
+    const double *kmode;
+    int32_t *log2s, *epend;
+    int32_t kind;
+    double amp;
+    uint64_t rng_seed;
+    const int32_t *inst_index; // instance index per instance (for the RNG counter)
+    int32_t block_base;        // global block index of blockIdx.x == 0
+};
+
+// launchers (qs_spectral.hip)
+hipError_t launch_step(int precision, int mpl, bool restoring, bool fields, int n_blocks,
+                       const StepArgs &a, hipStream_t s);
+hipError_t launch_seed(int precision, int mpl, int n_blocks, int max_n_xi, const SeedArgs &a,
+                       hipStream_t s);
+
+// host helper mirroring the device SplitMix64 (exported for the generator tests)
+uint64_t splitmix64_host(uint64_t seed, uint64_t i);
+
+}  // namespace qs

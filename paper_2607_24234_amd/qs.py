@@ -1,0 +1,265 @@
+"""Python binding of libqs (include/qs.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library.  torch provides device memory (the
+workspace and output buffers) and the HIP stream; if libqs.so is missing or cannot be
+loaded, importing this module's ``lib()`` raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqs.so")
+
+# mirrored from include/qs.h
+QS_OK = 0
+QS_ERR_ARG = -1
+QS_ERR_ALLOC = -2
+QS_ERR_HIP = -3
+QS_ERR_NUMERIC = -4
+QS_ERR_UNSUPPORTED = -5
+QS_ERR_STATE = -6
+QS_FP64 = 0
+QS_FP32 = 1
+PROFILE_FLATTOP, PROFILE_GAUSSIAN, PROFILE_TABLE = 0, 1, 2
+GEOM_SPECTRAL, GEOM_TRANSVERSE_GRID = 0, 1
+SEED_NOISE, SEED_UNIFORM, SEED_FRONT_IMPULSE, SEED_CENTROID, SEED_NONE = 0, 1, 2, 3, 4
+FLAG_DROP_LONGITUDINAL, FLAG_NO_RESTORING, FLAG_STEADY_INFLOW = 1, 2, 4
+
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+class QSParams(ctypes.Structure):
+    _fields_ = [("n_species", ctypes.c_int32),
+                ("q", _D), ("m", _D), ("nb_over_np", _D),
+                ("gamma_b", ctypes.c_double),
+                ("length", ctypes.c_double),
+                ("profile", ctypes.c_int32),
+                ("sigma_xi", ctypes.c_double),
+                ("xi_center", ctypes.c_double),
+                ("profile_table", _D),
+                ("geometry", ctypes.c_int32),
+                ("n_modes", ctypes.c_int64),
+                ("kx", _D), ("ky", _D),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("sigma_r", ctypes.c_double),
+                ("n_xi", ctypes.c_int32),
+                ("d_tau", ctypes.c_double),
+                ("precision", ctypes.c_int32),
+                ("seed_kind", ctypes.c_int32),
+                ("seed_amp", ctypes.c_double),
+                ("rng_seed", ctypes.c_uint64),
+                ("centroid_offset", ctypes.c_double),
+                ("flags", ctypes.c_int32)]
+
+
+class QSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libqs status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_init", "qs_step_tau",
+           "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
+           "qs_debug_splitmix64"]
+
+
+def lib():
+    """Load libqs.so (raises if it is missing: build it with paper_2607_24234_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqs.so not found at %s; run `python -m paper_2607_24234_amd.build` "
+                          "(or __graft_entry__.build())" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(QSParams)
+    vp = ctypes.c_void_p
+    L.qs_abi_version.restype = ctypes.c_int32
+    L.qs_last_error.restype = ctypes.c_char_p
+    L.qs_workspace_size.restype = ctypes.c_size_t
+    L.qs_workspace_size.argtypes = [P, ctypes.c_int32]
+    L.qs_init.restype = ctypes.c_int
+    L.qs_init.argtypes = [P, ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.qs_step_tau.restype = ctypes.c_int
+    L.qs_step_tau.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    L.qs_sync_check.restype = ctypes.c_int
+    L.qs_sync_check.argtypes = [vp]
+    L.qs_steps_done.restype = ctypes.c_int64
+    L.qs_steps_done.argtypes = [vp]
+    L.qs_get_state.restype = ctypes.c_int
+    L.qs_get_state.argtypes = [vp, _D, _D, _D, _D]
+    L.qs_set_state.restype = ctypes.c_int
+    L.qs_set_state.argtypes = [vp, _D, _D, _D, _D]
+    L.qs_free.restype = None
+    L.qs_free.argtypes = [vp]
+    L.qs_debug_splitmix64.restype = ctypes.c_uint64
+    L.qs_debug_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != QS_OK:
+        raise QSError(status, lib().qs_last_error().decode(errors="replace"))
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+class _Instance:
+    """Keeps the numpy arrays behind one QSParams alive."""
+
+    def __init__(self, inst, precision):
+        sp = inst["species"]
+        self.q = np.ascontiguousarray([s[0] for s in sp], np.float64)
+        self.m = np.ascontiguousarray([s[1] for s in sp], np.float64)
+        self.nb = np.ascontiguousarray([s[2] for s in sp], np.float64)
+        self.kx = np.ascontiguousarray(inst["kx"], np.float64)
+        ky = inst.get("ky")
+        self.ky = None if ky is None else np.ascontiguousarray(ky, np.float64)
+        tab = inst.get("profile_table")
+        self.tab = None if tab is None else np.ascontiguousarray(tab, np.float64)
+        p = QSParams()
+        p.n_species = len(sp)
+        p.q, p.m, p.nb_over_np = _dp(self.q), _dp(self.m), _dp(self.nb)
+        p.gamma_b = float(inst["gamma"])
+        p.length = float(inst["length"])
+        p.profile = int(inst.get("profile", PROFILE_TABLE if self.tab is not None else PROFILE_FLATTOP))
+        p.sigma_xi = float(inst.get("sigma_xi", 0.0))
+        p.xi_center = float(inst.get("xi_center", 0.0))
+        p.profile_table = _dp(self.tab)
+        p.geometry = int(inst.get("geometry", GEOM_SPECTRAL))
+        p.n_modes = len(self.kx)
+        p.kx, p.ky = _dp(self.kx), _dp(self.ky)
+        p.n_xi = int(inst["n_xi"])
+        p.d_tau = float(inst["d_tau"])
+        p.precision = precision
+        p.seed_kind = int(inst.get("seed_kind", SEED_NOISE))
+        p.seed_amp = float(inst.get("seed_amp", 1e-6))
+        p.rng_seed = int(inst.get("rng_seed", 0)) & (2**64 - 1)
+        p.flags = int(inst.get("flags", 0))
+        self.p = p
+        self.n_modes = len(self.kx)
+        self.n_xi = p.n_xi
+
+
+def workspace_size(instances, precision=QS_FP32):
+    insts = [_Instance(i, precision) for i in instances]
+    arr = (QSParams * len(insts))(*[x.p for x in insts])
+    return int(lib().qs_workspace_size(arr, len(insts)))
+
+
+class Solver:
+    """A qs_ctx over one or more instances, with torch-owned device memory.
+
+    instances: list of dicts as produced by ``paper_2607_24234_amd.inputs`` (keys species,
+    gamma, length, n_xi, kx, ky, d_tau, seed_kind, seed_amp, rng_seed, flags, ...).
+    """
+
+    def __init__(self, instances, precision=QS_FP32, device=None, stream=None):
+        import torch
+        if isinstance(instances, dict):
+            instances = [instances]
+        L = lib()
+        self.torch = torch
+        self.precision = precision
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._insts = [_Instance(i, precision) for i in instances]
+        self._params = (QSParams * len(self._insts))(*[x.p for x in self._insts])
+        nbytes = int(L.qs_workspace_size(self._params, len(self._insts)))
+        if nbytes == 0:
+            _check(L.qs_init(self._params, len(self._insts), None, None, 0, ctypes.byref(ctypes.c_void_p())))
+        self.n_modes = [x.n_modes for x in self._insts]
+        self.n_xi = [x.n_xi for x in self._insts]
+        self.total_modes = sum(self.n_modes)
+        self.snap_elems = sum(m * n for m, n in zip(self.n_modes, self.n_xi))
+        self.dtype = torch.float64 if precision == QS_FP64 else torch.float32
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream() if stream is None else stream
+            # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            ctx = ctypes.c_void_p()
+            _check(L.qs_init(self._params, len(self._insts), ctypes.c_void_p(self.stream.cuda_stream),
+                             ctypes.c_void_p(self.workspace.data_ptr()), nbytes, ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    # -------------------------------------------------------------- stepping
+    def step(self, n_steps, out_every=1, snapshots=False, max_ln_a=False, out=None):
+        """Advance every instance by n_steps tau-steps.  Returns a dict of torch tensors:
+        'ln_e', 'ln_b' [n_snap, snap_elems] (if snapshots) and 'max_ln_a' [n_steps, total_modes]."""
+        t = self.torch
+        res = {} if out is None else out
+        n_snap = 0
+        if snapshots:
+            n_snap = 1 if n_steps == 0 else -(-n_steps // max(1, out_every))
+            if "ln_e" not in res:
+                res["ln_e"] = t.empty((n_snap, self.snap_elems), dtype=self.dtype, device=self.device)
+                res["ln_b"] = t.empty((n_snap, self.snap_elems), dtype=self.dtype, device=self.device)
+        if max_ln_a and n_steps > 0 and "max_ln_a" not in res:
+            res["max_ln_a"] = t.empty((n_steps, self.total_modes), dtype=self.dtype, device=self.device)
+        pe = ctypes.c_void_p(res["ln_e"].data_ptr()) if snapshots else None
+        pb = ctypes.c_void_p(res["ln_b"].data_ptr()) if snapshots else None
+        pm = ctypes.c_void_p(res["max_ln_a"].data_ptr()) if (max_ln_a and n_steps > 0) else None
+        _check(lib().qs_step_tau(self.ctx, int(n_steps), int(max(1, out_every)), pe, pb, pm))
+        return res
+
+    def snapshot_view(self, flat, instance=0):
+        """View of one instance's block of a snapshot row as [n_xi, n_modes]."""
+        off = sum(m * n for m, n in zip(self.n_modes[:instance], self.n_xi[:instance]))
+        n, m = self.n_xi[instance], self.n_modes[instance]
+        return flat[..., off:off + n * m].reshape(*flat.shape[:-1], n, m)
+
+    def sync_check(self):
+        _check(lib().qs_sync_check(self.ctx))
+
+    @property
+    def steps_done(self):
+        return int(lib().qs_steps_done(self.ctx))
+
+    # -------------------------------------------------------------- state
+    def get_state(self):
+        """Canonical state: list (per instance) of dicts rho, j_par, j_perp [n_modes, n_xi]
+        complex128 and log2_scale [n_modes]."""
+        tot = self.snap_elems
+        rho = np.empty(2 * tot)
+        jpa = np.empty(2 * tot)
+        jpe = np.empty(2 * tot)
+        l2 = np.empty(self.total_modes)
+        _check(lib().qs_get_state(self.ctx, _dp(rho), _dp(jpa), _dp(jpe), _dp(l2)))
+        out, o, mo = [], 0, 0
+        for m, n in zip(self.n_modes, self.n_xi):
+            sl = slice(2 * o, 2 * (o + m * n))
+            out.append({"rho": rho[sl].view(np.complex128).reshape(m, n).copy(),
+                        "j_par": jpa[sl].view(np.complex128).reshape(m, n).copy(),
+                        "j_perp": jpe[sl].view(np.complex128).reshape(m, n).copy(),
+                        "log2_scale": l2[mo:mo + m].copy()})
+            o += m * n
+            mo += m
+        return out
+
+    def set_state(self, states):
+        rho = np.concatenate([np.ascontiguousarray(s["rho"], np.complex128).ravel() for s in states])
+        jpa = np.concatenate([np.ascontiguousarray(s["j_par"], np.complex128).ravel() for s in states])
+        jpe = np.concatenate([np.ascontiguousarray(s["j_perp"], np.complex128).ravel() for s in states])
+        l2 = np.concatenate([np.ascontiguousarray(s["log2_scale"], np.float64).ravel() for s in states])
+        _check(lib().qs_set_state(self.ctx, _dp(rho.view(np.float64)), _dp(jpa.view(np.float64)),
+                                  _dp(jpe.view(np.float64)), _dp(l2)))
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().qs_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,117 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol include/qs.h
+declares, rejects invalid arguments on the host before touching the device, and evaluates
+the same SplitMix64 stream as the oracle (two independent implementations)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2607_24234_amd import build, qs
+    if not os.path.exists(qs.LIB_PATH):
+        build.build()
+    return qs, qs.lib()
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(qs_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    qs, L = _lib()
+    names = declared_functions()
+    assert "qs_init" in names and "qs_step_tau" in names
+    for n in names:
+        assert hasattr(L, n), "libqs.so does not export " + n
+    assert set(names) <= set(qs.EXPORTS)
+
+
+def test_abi_version():
+    qs, L = _lib()
+    assert L.qs_abi_version() == 1
+
+
+def _inst(**kw):
+    from paper_2607_24234_amd import inputs
+    d = inputs.slab(n_modes=4, n_xi=16, n_steps=1)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("bad,needle", [
+    (dict(gamma=0.5), "gamma_b"),
+    (dict(length=-1.0), "length"),
+    (dict(n_xi=0), "n_xi"),
+    (dict(d_tau=0.0), "d_tau"),
+    (dict(d_tau=float("nan")), "d_tau"),
+    (dict(species=[(-1.0, 0.0, 0.01)]), "m > 0"),
+    (dict(species=[(-1.0, 1.0, -0.01)]), "nb_over_np"),
+    (dict(kx=np.array([0.1, float("inf")])), "wavenumber"),
+    (dict(seed_kind=9), "seed_kind"),
+    (dict(flags=64), "flag"),
+    (dict(seed_kind=2, kx=np.array([0.0, 1.0])), "k != 0"),
+])
+def test_invalid_arguments_rejected_on_host(bad, needle):
+    qs, L = _lib()
+    insts = [qs._Instance(_inst(**bad), qs.QS_FP64)]
+    arr = (qs.QSParams * 1)(*[x.p for x in insts])
+    assert L.qs_workspace_size(arr, 1) == 0
+    ctx = ctypes.c_void_p()
+    st = L.qs_init(arr, 1, None, None, 0, ctypes.byref(ctx))
+    assert st == qs.QS_ERR_ARG
+    assert ctx.value is None
+    assert needle in L.qs_last_error().decode()
+
+
+def test_unsupported_geometry_reported():
+    qs, L = _lib()
+    insts = [qs._Instance(_inst(geometry=qs.GEOM_TRANSVERSE_GRID), qs.QS_FP32)]
+    arr = (qs.QSParams * 1)(*[x.p for x in insts])
+    ctx = ctypes.c_void_p()
+    assert L.qs_init(arr, 1, None, None, 0, ctypes.byref(ctx)) == qs.QS_ERR_UNSUPPORTED
+
+
+def test_mixed_precision_rejected():
+    qs, L = _lib()
+    a = qs._Instance(_inst(), qs.QS_FP64)
+    b = qs._Instance(_inst(), qs.QS_FP32)
+    arr = (qs.QSParams * 2)(a.p, b.p)
+    ctx = ctypes.c_void_p()
+    assert L.qs_init(arr, 2, None, None, 0, ctypes.byref(ctx)) == qs.QS_ERR_ARG
+
+
+def test_workspace_size_scales_with_problem():
+    qs, L = _lib()
+    s1 = qs.workspace_size([_inst(n_xi=64)], qs.QS_FP32)
+    s2 = qs.workspace_size([_inst(n_xi=128)], qs.QS_FP32)
+    s3 = qs.workspace_size([_inst(n_xi=64)], qs.QS_FP64)
+    assert 0 < s1 < s2 and s1 < s3
+    # state of 4 modes padded to one 64-lane block: 64 lanes x 6 values x n_xi
+    assert s2 - s1 >= 64 * 6 * 64 * 4
+
+
+def test_null_arguments():
+    qs, L = _lib()
+    assert L.qs_step_tau(None, 1, 1, None, None, None) == qs.QS_ERR_ARG
+    assert L.qs_sync_check(None) == qs.QS_ERR_ARG
+    assert L.qs_steps_done(None) == -1
+    L.qs_free(None)
+    assert L.qs_init(None, 1, None, None, 0, None) == qs.QS_ERR_ARG
+
+
+def test_device_generator_equals_oracle_generator(oracle):
+    qs, L = _lib()
+    for seed in (0, 1, 0xDEADBEEF, 2**64 - 1):
+        for i in (0, 1, 2, 12345, 2**40 + 7):
+            assert L.qs_debug_splitmix64(seed, i) == oracle.splitmix64(seed, i)

@@ -1,0 +1,236 @@
+"""GPU parity of the spectral hot path (through the C ABI) against the FP64 oracle.
+
+Bars: FP64 |d ln| <= 1e-9 (relative amplitude error 1e-9); FP32 (FP32 state, FP64 carry)
+|d ln A| <= 1e-4, on every cell whose amplitude is >= 1e-6 of its mode's maximum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import ln_compare, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+FP32_TOL = 1e-4
+
+
+def _slab(**kw):
+    from paper_2607_24234_amd import inputs
+    d = inputs.slab()
+    d.update(kw)
+    return d
+
+
+def _run_gpu(qs, inst, n_steps, out_every=1, precision=None, final_snapshot=False):
+    precision = qs.QS_FP64 if precision is None else precision
+    s = qs.Solver([inst], precision=precision)
+    out = s.step(n_steps, out_every=out_every, snapshots=True, max_ln_a=True)
+    res = {"ln_e": s.snapshot_view(out["ln_e"]).cpu().numpy(),
+           "ln_b": s.snapshot_view(out["ln_b"]).cpu().numpy(),
+           "max_ln_a": out["max_ln_a"].cpu().numpy() if n_steps > 0 else None}
+    if final_snapshot:
+        f = s.step(0, snapshots=True)
+        res["final_ln_e"] = s.snapshot_view(f["ln_e"]).cpu().numpy()
+    s.sync_check()
+    res["solver"] = s
+    return res
+
+
+def _check_all(g, ln_e, ln_b, mx, tol, what):
+    ln_compare(g["ln_e"], ln_e, tol, what=what + " ln|E|")
+    ln_compare(g["ln_b"], ln_b, tol, what=what + " ln|B|")
+    if mx is not None:
+        ln_compare(g["max_ln_a"], mx, tol, what=what + " max ln A")
+
+
+def test_seed_equals_oracle_seed(qs):
+    inst = _slab(n_xi=64)
+    s = qs.Solver([inst], precision=qs.QS_FP64)
+    st = s.get_state()[0]
+    _, _, _, ost = oracle_run(inst, 0)
+    import oracle as O
+    from helpers import oracle_beam
+    beam = oracle_beam(inst)
+    for m in range(len(inst["kx"])):
+        rho, jpar, jperp = O.collapse(beam, ost, m)
+        assert np.max(np.abs(st["rho"][m] - rho)) <= 1e-15 * np.max(np.abs(rho))
+        assert np.all(st["j_par"][m] == 0) and np.all(st["j_perp"][m] == 0)
+
+
+def test_slab_fp64_parity_full_config(qs):
+    """The slab workload at its full size: 32 modes, 256 cells, 100 steps of 50, every step."""
+    inst = _slab()
+    g = _run_gpu(qs, inst, 100, out_every=1)
+    ln_e, ln_b, mx, _ = oracle_run(inst, 100, out_every=1)
+    _check_all(g, ln_e, ln_b, mx, FP64_TOL, "slab fp64")
+    # the run grows by many e-folds, so the comparison is not on the seed alone
+    assert np.max(mx[-1] - mx[0]) > 5.0
+
+
+def test_slab_fp32_parity_full_config(qs):
+    inst = _slab()
+    g = _run_gpu(qs, inst, 100, out_every=10, precision=qs.QS_FP32)
+    ln_e, ln_b, mx, _ = oracle_run(inst, 100, out_every=10)
+    _check_all(g, ln_e, ln_b, mx, FP32_TOL, "slab fp32")
+
+
+@pytest.mark.parametrize("n_modes,n_xi", [(1, 1), (1, 5), (70, 37), (130, 3), (64, 4), (65, 9)])
+def test_ragged_shapes_fp64(qs, n_modes, n_xi):
+    """Mode counts off the 64-lane blocks and cell counts off the register tile."""
+    inst = _slab(kx=np.linspace(0.05, 4.0, n_modes), n_xi=n_xi, length=n_xi * 0.15,
+                 d_tau=40.0)
+    g = _run_gpu(qs, inst, 12, out_every=3, final_snapshot=True)
+    ln_e, ln_b, mx, st = oracle_run(inst, 12, out_every=3)
+    _check_all(g, ln_e, ln_b, mx, FP64_TOL, "ragged")
+    import oracle as O
+    from helpers import oracle_beam
+    fe, _, _ = O.run(oracle_beam(inst), np.abs(inst["kx"]), inst["d_tau"], 0, st)
+    ln_compare(g["final_ln_e"], fe, FP64_TOL, what="ragged final")
+
+
+@pytest.mark.parametrize("flags,seed", [
+    (1, 2),   # DROP_LONGITUDINAL + front impulse: Eq. CFI_st_master impulse response
+    (3, 2),   # + NO_RESTORING: Eq. CFI_st_master_front
+    (4, 1),   # STEADY_INFLOW + uniform: temporal CFI
+    (0, 2),   # full model, front impulse
+    (0, 1),   # full model, extended disturbance
+])
+def test_model_variants_fp64(qs, flags, seed):
+    inst = _slab(n_xi=96, length=8.0, kx=np.array([0.3, 1.0, 2.5, 4.0]), flags=flags,
+                 seed_kind=seed, seed_amp=1.0, gamma=20.0, d_tau=5.0)
+    g = _run_gpu(qs, inst, 40, out_every=4)
+    ln_e, ln_b, mx, _ = oracle_run(inst, 40, out_every=4)
+    _check_all(g, ln_e, ln_b, mx, FP64_TOL, "variant %d/%d" % (flags, seed))
+
+
+def test_temporal_cfi_closed_form_gpu(qs):
+    """STEADY_INFLOW + uniform seed: rho = S [R(z)^n + R(-z)^n]/2 exactly (RK4 of
+    rho'' = Gamma_CFI^2 rho), on the GPU state itself."""
+    from exact_refs import gamma_cfi, rk4_growth_factor
+    k = np.array([0.5, 2.0, 5.0])
+    inst = _slab(n_xi=8, length=1.0, kx=k, flags=4, seed_kind=1, seed_amp=1e-6, d_tau=20.0)
+    s = qs.Solver([inst], precision=qs.QS_FP64)
+    n = 60
+    s.step(n)
+    st = s.get_state()[0]
+    for m, kk in enumerate(k):
+        G = gamma_cfi(inst["species"], inst["gamma"], kk)
+        z = G * inst["d_tau"]
+        ref = 1e-6 * (rk4_growth_factor(z) ** n + rk4_growth_factor(-z) ** n) / 2
+        rho = st["rho"][m] * 2.0 ** st["log2_scale"][m]
+        assert np.max(np.abs(rho / ref - 1)) < 1e-12
+
+
+def test_gaussian_profile_fp64(qs):
+    from paper_2607_24234_amd import inputs
+    n, L = 120, 30.0
+    prof = inputs.gaussian_profile(n, L, 15.0, 3.5)
+    inst = _slab(n_xi=n, length=L, profile_table=prof, kx=np.array([1.0, 3.0, 5.0]),
+                 species=[(-1.0, 1.0, 0.03), (1.0, 1.0, 0.03)], gamma=2000.0, d_tau=30.0)
+    g = _run_gpu(qs, inst, 30, out_every=5)
+    ln_e, ln_b, mx, _ = oracle_run(inst, 30, out_every=5)
+    _check_all(g, ln_e, ln_b, mx, FP64_TOL, "gaussian")
+
+
+def test_batched_instances_match_single_runs(qs):
+    """Instances of different length, step and species in one context."""
+    from paper_2607_24234_amd import inputs
+    insts = inputs.batched(n_instances=5, n_modes=70, n_steps=10, max_cells=300)
+    s = qs.Solver(insts, precision=qs.QS_FP64)
+    out = s.step(10, out_every=5, snapshots=True, max_ln_a=True)
+    mx_all = out["max_ln_a"].cpu().numpy()
+    o = 0
+    for i, inst in enumerate(insts):
+        ln_e, ln_b, mx, _ = oracle_run(inst, 10, out_every=5, instance=i)
+        ln_compare(s.snapshot_view(out["ln_e"], i).cpu().numpy(), ln_e, FP64_TOL, what="batched e %d" % i)
+        ln_compare(s.snapshot_view(out["ln_b"], i).cpu().numpy(), ln_b, FP64_TOL, what="batched b %d" % i)
+        ln_compare(mx_all[:, o:o + 70], mx, FP64_TOL, what="batched max %d" % i)
+        o += 70
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_determinism_and_resume(qs, precision):
+    """Two runs are bitwise equal (no atomics, fixed order); a state saved with qs_get_state
+    and restored with qs_set_state continues bitwise like the uninterrupted run."""
+    inst = _slab(n_xi=80, kx=np.linspace(0.1, 4, 20))
+    a = qs.Solver([inst], precision=precision)
+    ra = a.step(30, max_ln_a=True)["max_ln_a"].cpu().numpy()
+    sa = a.get_state()[0]
+    b = qs.Solver([inst], precision=precision)
+    b.step(12)
+    saved = b.get_state()
+    c = qs.Solver([inst], precision=precision)
+    c.set_state(saved)
+    rc = c.step(18, max_ln_a=True)["max_ln_a"].cpu().numpy()
+    sc = c.get_state()[0]
+    assert np.array_equal(ra[12:], rc)
+    for key in ("rho", "j_par", "j_perp"):
+        assert np.array_equal(sa[key] * 2.0 ** sa["log2_scale"][:, None],
+                              sc[key] * 2.0 ** sc["log2_scale"][:, None])
+
+
+def test_isotropy_bitwise(qs):
+    """Only |k_perp| enters: (a, b), (b, a), (-a, b), (a, -b) give identical outputs when
+    their seeds are equal (uniform seed)."""
+    a, b = 0.7, 2.9
+    inst = _slab(kx=np.array([a, b, -a, a]), ky=np.array([b, a, b, -b]), seed_kind=1,
+                 n_xi=64, d_tau=40.0)
+    g = _run_gpu(qs, inst, 20, out_every=5, precision=qs.QS_FP32)
+    for m in range(1, 4):
+        assert np.array_equal(g["ln_e"][..., 0], g["ln_e"][..., m])
+        assert np.array_equal(g["max_ln_a"][:, 0], g["max_ln_a"][:, m])
+
+
+def test_nonfinite_state_reported(qs):
+    inst = _slab(n_xi=16, kx=np.array([1.0, 2.0]))
+    s = qs.Solver([inst], precision=qs.QS_FP32)
+    st = s.get_state()
+    st[0]["rho"][1, 3] = np.nan
+    s.set_state(st)
+    s.step(1)
+    with pytest.raises(qs.QSError) as e:
+        s.sync_check()
+    assert e.value.status == qs.QS_ERR_NUMERIC
+    s.sync_check()  # the flag is cleared once reported
+
+
+def test_step_argument_errors(qs):
+    s = qs.Solver([_slab(n_xi=8, kx=np.array([1.0]))], precision=qs.QS_FP32)
+    L = qs.lib()
+    assert L.qs_step_tau(s.ctx, -1, 1, None, None, None) == qs.QS_ERR_ARG
+    import torch
+    t = torch.empty(16, device="cuda")
+    assert L.qs_step_tau(s.ctx, 1, 0, t.data_ptr(), t.data_ptr(), None) == qs.QS_ERR_ARG
+    assert L.qs_step_tau(s.ctx, 1, 1, t.data_ptr(), None, None) == qs.QS_ERR_ARG
+    assert s.steps_done == 0
+
+
+def test_spectral3d_full_size_sampled(qs):
+    """The 3D spectral workload at full size (205,859 modes x 4096 cells, FP32 state) in the
+    launch configuration the benchmark times; sampled modes against the oracle."""
+    import torch
+    from paper_2607_24234_amd import inputs
+    inst = inputs.spectral3d()
+    n_modes = len(inst["kx"])
+    assert n_modes == 205859
+    s = qs.Solver([inst], precision=qs.QS_FP32)
+    n = 3
+    out = s.step(n, max_ln_a=True)
+    fin = s.step(0, snapshots=True)
+    torch.cuda.synchronize()
+    s.sync_check()
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([[0, 1, n_modes // 2, n_modes - 1],
+                                       rng.integers(0, n_modes, 8)]))
+    ln_e, ln_b, mx, st = oracle_run(inst, n, modes=sample, out_every=1)
+    import oracle as O
+    from helpers import mode_k, oracle_beam
+    fe, fb, _ = O.run(oracle_beam(inst), mode_k(inst)[sample], inst["d_tau"], 0, st)
+    ge = s.snapshot_view(fin["ln_e"])[:, :, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    gb = s.snapshot_view(fin["ln_b"])[:, :, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    gm = out["max_ln_a"][:, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    ln_compare(gm, mx, FP32_TOL, what="3d max")
+    ln_compare(ge, fe, FP32_TOL, what="3d ln E")
+    ln_compare(gb, fb, FP32_TOL, what="3d ln B")
