@@ -48,7 +48,8 @@ def read_traffic(precision_name):
 
 def cpu_baseline(inst, seconds=15.0):
     """The FP64 oracle timed on the host cores on a bounded sample of the same workload:
-    `n_modes` modes spread over the mode list, all 4096 cells, a few tau-steps."""
+    modes spread evenly over the mode list, all 4096 cells, a fixed number of tau-steps;
+    the mode count is sized from a short probe so that the timed run takes ~`seconds`."""
     import numpy as np
     import oracle as O
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -57,17 +58,21 @@ def cpu_baseline(inst, seconds=15.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     beam = oracle_beam(inst)
     k_all = mode_k(inst)
-    n_modes = 4 * threads
-    sel = np.linspace(0, len(k_all) - 1, n_modes).astype(int)
-    st = O.seed(beam, k_all[sel], O.SEED_NOISE, inst["seed_amp"], rng_seed=inst["rng_seed"])
-    t = time.perf_counter()
-    O.run(beam, k_all[sel], inst["d_tau"], 1, st, want_fields=False, want_max=True, n_threads=threads)
-    one = time.perf_counter() - t
-    steps = max(1, min(200, int(seconds / max(one, 1e-6))))
-    t = time.perf_counter()
-    O.run(beam, k_all[sel], inst["d_tau"], steps, st, want_fields=False, want_max=True,
-          n_threads=threads)
-    dt = time.perf_counter() - t
+    steps = 10
+
+    def timed(n_modes, n_steps):
+        sel = np.linspace(0, len(k_all) - 1, n_modes).astype(int)
+        st = O.seed(beam, k_all[sel], O.SEED_NOISE, inst["seed_amp"], rng_seed=inst["rng_seed"])
+        t = time.perf_counter()
+        O.run(beam, k_all[sel], inst["d_tau"], n_steps, st, want_fields=False, want_max=True,
+              n_threads=threads)
+        return time.perf_counter() - t
+
+    probe_modes = 2 * threads
+    rate = probe_modes * inst["n_xi"] * 2 / timed(probe_modes, 2)
+    n_modes = int(max(threads, min(len(k_all), seconds * rate / (inst["n_xi"] * steps))))
+    n_modes = max(threads, n_modes // threads * threads)
+    dt = timed(n_modes, steps)
     cells = n_modes * inst["n_xi"] * steps
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": "%d modes evenly spread over the 205,859-mode list x %d cells x %d steps "

@@ -216,6 +216,21 @@ qs_status qs_get_state(qs_ctx *ctx, double *rho, double *j_par, double *j_perp,
 qs_status qs_set_state(qs_ctx *ctx, const double *rho, const double *j_par,
                        const double *j_perp, const double *log2_scale);
 
+/*
+ * Checkpoint: an opaque, bitwise-exact image of the context's state (stored values, per-mode
+ * scale exponents, steps done) in the library's own layout, for resuming the same problem.
+ * qs_checkpoint_size returns its size in bytes (0 for a NULL context).
+ * qs_save_checkpoint writes it to host memory `dst` of `bytes` >= that size (synchronizes).
+ * qs_load_checkpoint restores it from host memory; it must come from a context created with
+ * identical parameters (checked through the stored shape header: QS_ERR_ARG otherwise).
+ * Continuing after a load is bitwise identical to continuing the saved context.
+ * (qs_get_state / qs_set_state instead use the documented canonical layout; a round trip
+ * through them is exact up to one rounding of the stored scaled currents.)
+ */
+size_t qs_checkpoint_size(const qs_ctx *ctx);
+qs_status qs_save_checkpoint(qs_ctx *ctx, void *dst, size_t bytes);
+qs_status qs_load_checkpoint(qs_ctx *ctx, const void *src, size_t bytes);
+
 /* Release the context and anything the library allocated for it.  NULL is ignored. */
 void qs_free(qs_ctx *ctx);
 

@@ -32,8 +32,10 @@ qs_status hip_fail(hipError_t e, const char *what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int env_mpl() {
-    const char *s = std::getenv("QS_MODES_PER_LANE");
+// real columns per lane of the step kernel: 1 (the two parts of a mode in adjacent lanes)
+// or 2 (one mode per lane); QS_COLUMNS_PER_LANE overrides the default of 1
+int env_nc() {
+    const char *s = std::getenv("QS_COLUMNS_PER_LANE");
     if (s && (std::atoi(s) == 1 || std::atoi(s) == 2)) return std::atoi(s);
     return 1;
 }
@@ -41,7 +43,7 @@ int env_mpl() {
 // Sizes derived from validated parameters.
 struct Plan {
     int precision = QS_FP32;
-    int mpl = 1;
+    int nc = 1;                    // real columns per lane
     size_t ts = 4;                 // bytes per state element
     std::vector<InstDev> inst;
     std::vector<int32_t> blk_inst;
@@ -58,6 +60,15 @@ struct Plan {
 
 bool finite(double x) { return std::isfinite(x); }
 
+// Offset inside one cell of a block of the value (var, part) of the block's local mode q,
+// for NC real columns per lane (column lane*NC + c holds part (lane*NC+c) & 1 of local
+// mode (lane*NC+c)/2, stored at row var*NC + c, lane).
+int64_t elem_of(int NC, int q, int var, int part) {
+    const int col = 2 * q + part;
+    const int lane = col / NC, c = col % NC;
+    return (int64_t)(var * NC + c) * kWave + lane;
+}
+
 qs_status validate_one(const qs_params &p, int i) {
     const std::string at = "instance " + std::to_string(i) + ": ";
     if (p.geometry == QS_GEOM_TRANSVERSE_GRID)
@@ -73,7 +84,7 @@ qs_status validate_one(const qs_params &p, int i) {
     }
     if (!finite(p.gamma_b) || !(p.gamma_b > 1.0)) return fail(QS_ERR_ARG, at + "gamma_b must be finite and > 1");
     if (!finite(p.length) || !(p.length > 0.0)) return fail(QS_ERR_ARG, at + "length must be finite and > 0");
-    if (p.n_xi < 1 || p.n_xi > (1 << 22)) return fail(QS_ERR_ARG, at + "n_xi must be in [1, 2^22]");
+    if (p.n_xi < 1 || p.n_xi > (1 << 20)) return fail(QS_ERR_ARG, at + "n_xi must be in [1, 2^20]");
     if (!finite(p.d_tau) || !(p.d_tau > 0.0)) return fail(QS_ERR_ARG, at + "d_tau must be finite and > 0");
     if (p.precision != QS_FP64 && p.precision != QS_FP32) return fail(QS_ERR_ARG, at + "unknown precision");
     if (p.n_modes < 1 || p.n_modes > (int64_t(1) << 26)) return fail(QS_ERR_ARG, at + "n_modes must be in [1, 2^26]");
@@ -125,9 +136,9 @@ qs_status make_plan(const qs_params *params, int32_t n, Plan &pl) {
             return fail(QS_ERR_ARG, "all instances must share QS_FLAG_NO_RESTORING");
     }
     pl.precision = params[0].precision;
-    pl.mpl = env_mpl();
+    pl.nc = env_nc();
     pl.ts = pl.precision == QS_FP64 ? 8 : 4;
-    const int lanes_modes = kWave * pl.mpl;
+    const int lanes_modes = 32 * pl.nc;  // modes per 64-lane block
     int64_t blocks = 0, pmodes = 0, modes = 0, state = 0, table = 0, snap = 0;
     pl.inst.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -140,14 +151,14 @@ qs_status make_plan(const qs_params *params, int32_t n, Plan &pl) {
         d.block0 = (int32_t)blocks;
         d.pmode0 = (int32_t)pmodes;
         d.mode0 = (int32_t)modes;
-        d.flags = p.flags;
+        d.flags = p.flags | (p.profile == QS_PROFILE_FLATTOP ? kFlatProfile : 0);
         d.state_off = state;
         d.omega_off = table;
         d.snap_off = snap;
         const double h = p.length / p.n_xi;
         const bool drop = (p.flags & QS_FLAG_DROP_LONGITUDINAL) != 0;
         d.h = h;
-        d.ih = drop ? 0.0 : 1.0 / h;
+        d.ih = 1.0 / h;
         d.dtau = p.d_tau;
         d.ginv = 1.0 / p.gamma_b;
         d.g3inv = drop ? 0.0 : 1.0 / (p.gamma_b * p.gamma_b * p.gamma_b);
@@ -158,7 +169,7 @@ qs_status make_plan(const qs_params *params, int32_t n, Plan &pl) {
         blocks += d.n_blocks;
         pmodes += (int64_t)d.n_blocks * lanes_modes;
         modes += p.n_modes;
-        state += (int64_t)d.n_blocks * p.n_xi * 6 * pl.mpl * kWave;
+        state += (int64_t)d.n_blocks * p.n_xi * 3 * pl.nc * kWave;
         table += 2 * (int64_t)p.n_xi;
         snap += (int64_t)p.n_xi * p.n_modes;
         pl.max_n_xi = std::max(pl.max_n_xi, p.n_xi);
@@ -293,7 +304,7 @@ qs_status seed_state(qs_ctx *c, const qs_params *params) {
             a.amp = params[i0].seed_amp;
             a.rng_seed = params[i0].rng_seed;
             a.inst_index = reinterpret_cast<const int32_t *>(c->at(pl.off_iidx));
-            QS_HIP(launch_seed(pl.precision, pl.mpl, nb, mx, a, c->stream), "seed kernel");
+            QS_HIP(launch_seed(pl.precision, pl.nc, nb, mx, a, c->stream), "seed kernel");
         }
         i0 = i1;
     }
@@ -374,7 +385,7 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
         a.ln_e = out_ln_e;
         a.ln_b = out_ln_b;
         a.update = 0;
-        QS_HIP(launch_step(pl.precision, pl.mpl, restoring, true, nblk, a, c->stream), "step kernel");
+        QS_HIP(launch_step(pl.precision, pl.nc, restoring, true, nblk, a, c->stream), "step kernel");
         return QS_OK;
     }
     for (int s = 0; s < n_steps; ++s) {
@@ -386,7 +397,7 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
         a.max_base = (int64_t)s * pl.total_modes;
         a.update = 1;
         const bool fields = snap || out_max_ln_a != nullptr;
-        QS_HIP(launch_step(pl.precision, pl.mpl, restoring, fields, nblk, a, c->stream), "step kernel");
+        QS_HIP(launch_step(pl.precision, pl.nc, restoring, fields, nblk, a, c->stream), "step kernel");
         ++c->steps_done;
     }
     return QS_OK;
@@ -419,26 +430,35 @@ qs_status qs_get_state(qs_ctx *c, double *rho, double *j_par, double *j_perp, do
     QS_HIP(hipMemcpy(raw.data(), c->at(pl.off_state), raw.size(), hipMemcpyDeviceToHost), "copy state");
     QS_HIP(hipMemcpy(l2.data(), c->at(pl.off_log2s), l2.size() * 4, hipMemcpyDeviceToHost), "copy scales");
     QS_HIP(hipMemcpy(ep.data(), c->at(pl.off_epend), ep.size() * 4, hipMemcpyDeviceToHost), "copy scales");
-    const int NC = 2 * pl.mpl, ROW = 3 * NC, LM = kWave * pl.mpl;
+    const int NC = pl.nc, ROW = 3 * NC, LM = 32 * NC;
     auto val = [&](int64_t e) -> double {
         return pl.precision == QS_FP64 ? reinterpret_cast<const double *>(raw.data())[e]
                                        : (double)reinterpret_cast<const float *>(raw.data())[e];
     };
+    std::vector<double> kmode(pl.total_pmodes);
+    QS_HIP(hipMemcpy(kmode.data(), c->at(pl.off_k), kmode.size() * sizeof(double), hipMemcpyDeviceToHost),
+           "copy wavenumbers");
     int64_t out0 = 0;
     for (const InstDev &d : pl.inst) {
         const int N = d.n_xi;
         for (int m = 0; m < d.n_modes; ++m) {
-            const int b = m / LM, q = m % LM, lane = q / pl.mpl, t = q % pl.mpl;
+            const int b = m / LM, q = m % LM;
             const int e = ep[d.pmode0 + m];
             const double sc = std::ldexp(1.0, -e);
+            const double k = kmode[d.pmode0 + m];
             if (log2_scale) log2_scale[d.mode0 + m] = (double)l2[d.pmode0 + m] + e;
             for (int j = 0; j < N; ++j) {
-                const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave + lane;
-                auto x = [&](int var, int part) { return val(cell + (int64_t)(var * NC + 2 * t + part) * kWave) * sc; };
+                const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave;
+                auto x = [&](int var, int part) { return val(cell + elem_of(NC, q, var, part)) * sc; };
                 const int64_t o = 2 * (out0 + (int64_t)m * N + j);
                 if (rho) { rho[o] = x(0, 0); rho[o + 1] = x(0, 1); }
-                if (j_par) { j_par[o] = x(1, 0); j_par[o + 1] = x(1, 1); }
-                if (j_perp) { j_perp[o] = -x(2, 1); j_perp[o + 1] = x(2, 0); }  // j_perp = i T
+                // stored P' = j_par / h
+                if (j_par) { j_par[o] = x(1, 0) * d.h; j_par[o + 1] = x(1, 1) * d.h; }
+                // stored T' = k T with T = -i j_perp, i.e. j_perp = i T'/k (identically 0 at k = 0)
+                if (j_perp) {
+                    j_perp[o] = k != 0.0 ? -x(2, 1) / k : 0.0;
+                    j_perp[o + 1] = k != 0.0 ? x(2, 0) / k : 0.0;
+                }
             }
         }
         out0 += (int64_t)d.n_modes * N;
@@ -457,24 +477,31 @@ qs_status qs_set_state(qs_ctx *c, const double *rho, const double *j_par, const 
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     std::vector<char> raw((size_t)pl.state_elems * pl.ts, 0);
     std::vector<int32_t> l2(pl.total_pmodes, 0), ep(pl.total_pmodes, 0);
-    const int NC = 2 * pl.mpl, ROW = 3 * NC, LM = kWave * pl.mpl;
+    const int NC = pl.nc, ROW = 3 * NC, LM = 32 * NC;
     auto put = [&](int64_t e, double v) {
         if (pl.precision == QS_FP64) reinterpret_cast<double *>(raw.data())[e] = v;
         else reinterpret_cast<float *>(raw.data())[e] = (float)v;
     };
+    std::vector<double> kmode(pl.total_pmodes);
+    QS_HIP(hipMemcpy(kmode.data(), c->at(pl.off_k), kmode.size() * sizeof(double), hipMemcpyDeviceToHost),
+           "copy wavenumbers");
     int64_t out0 = 0;
     for (const InstDev &d : pl.inst) {
         const int N = d.n_xi;
+        const bool drop = (d.flags & QS_FLAG_DROP_LONGITUDINAL) != 0;
         for (int m = 0; m < d.n_modes; ++m) {
-            const int b = m / LM, q = m % LM, lane = q / pl.mpl, t = q % pl.mpl;
+            const int b = m / LM, q = m % LM;
+            const double k = kmode[d.pmode0 + m];
             l2[d.pmode0 + m] = (int32_t)log2_scale[d.mode0 + m];
             for (int j = 0; j < N; ++j) {
-                const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave + lane;
-                auto at = [&](int var, int part) { return cell + (int64_t)(var * NC + 2 * t + part) * kWave; };
+                const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave;
+                auto at = [&](int var, int part) { return cell + elem_of(NC, q, var, part); };
                 const int64_t o = 2 * (out0 + (int64_t)m * N + j);
                 put(at(0, 0), rho[o]); put(at(0, 1), rho[o + 1]);
-                put(at(1, 0), j_par[o]); put(at(1, 1), j_par[o + 1]);
-                put(at(2, 0), j_perp[o + 1]); put(at(2, 1), -j_perp[o]);  // T = -i j_perp
+                // P' = j_par/h; the outer rear face and dropped-longitudinal runs carry none
+                const bool zp = drop || j == N - 1;
+                put(at(1, 0), zp ? 0.0 : j_par[o] * d.ih); put(at(1, 1), zp ? 0.0 : j_par[o + 1] * d.ih);
+                put(at(2, 0), k * j_perp[o + 1]); put(at(2, 1), -k * j_perp[o]);  // T' = -i k j_perp
             }
         }
         out0 += (int64_t)d.n_modes * N;
@@ -483,6 +510,74 @@ qs_status qs_set_state(qs_ctx *c, const double *rho, const double *j_par, const 
     QS_HIP(hipMemcpy(c->at(pl.off_state), raw.data(), raw.size(), hipMemcpyHostToDevice), "copy state");
     QS_HIP(hipMemcpy(c->at(pl.off_log2s), l2.data(), l2.size() * 4, hipMemcpyHostToDevice), "copy scales");
     QS_HIP(hipMemcpy(c->at(pl.off_epend), ep.data(), ep.size() * 4, hipMemcpyHostToDevice), "copy scales");
+    return QS_OK;
+}
+
+namespace {
+struct CkptHeader {
+    uint64_t magic;        // "QSCKPT01"
+    uint64_t state_bytes;  // bytes of the state image
+    uint64_t pmodes;       // padded modes
+    uint64_t shape_hash;   // hash of the per-instance shapes and constants
+    int64_t steps_done;
+};
+constexpr uint64_t kCkptMagic = 0x3130544B50435351ull;
+
+uint64_t shape_hash(const Plan &pl) {
+    // FNV-1a over the instance table (sizes, offsets and step constants)
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    };
+    for (const InstDev &d : pl.inst) mix(&d, sizeof(d));
+    mix(&pl.precision, sizeof(pl.precision));
+    mix(&pl.nc, sizeof(pl.nc));
+    return h;
+}
+}  // namespace
+
+size_t qs_checkpoint_size(const qs_ctx *c) {
+    if (!c) return 0;
+    return sizeof(CkptHeader) + (size_t)c->pl.state_elems * c->pl.ts + 2 * (size_t)c->pl.total_pmodes * sizeof(int32_t);
+}
+
+qs_status qs_save_checkpoint(qs_ctx *c, void *dst, size_t bytes) {
+    if (!c || !dst) return fail(QS_ERR_ARG, "ctx and dst are required");
+    if (bytes < qs_checkpoint_size(c)) return fail(QS_ERR_ARG, "checkpoint buffer too small");
+    const Plan &pl = c->pl;
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    CkptHeader hd{kCkptMagic, (uint64_t)pl.state_elems * pl.ts, (uint64_t)pl.total_pmodes, shape_hash(pl), c->steps_done};
+    char *o = static_cast<char *>(dst);
+    std::memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    QS_HIP(hipMemcpy(o, c->at(pl.off_state), hd.state_bytes, hipMemcpyDeviceToHost), "copy state");
+    o += hd.state_bytes;
+    QS_HIP(hipMemcpy(o, c->at(pl.off_log2s), pl.total_pmodes * 4, hipMemcpyDeviceToHost), "copy scales");
+    o += pl.total_pmodes * 4;
+    QS_HIP(hipMemcpy(o, c->at(pl.off_epend), pl.total_pmodes * 4, hipMemcpyDeviceToHost), "copy scales");
+    return QS_OK;
+}
+
+qs_status qs_load_checkpoint(qs_ctx *c, const void *src, size_t bytes) {
+    if (!c || !src) return fail(QS_ERR_ARG, "ctx and src are required");
+    if (bytes < qs_checkpoint_size(c)) return fail(QS_ERR_ARG, "checkpoint too small for this context");
+    const Plan &pl = c->pl;
+    CkptHeader hd;
+    std::memcpy(&hd, src, sizeof(hd));
+    if (hd.magic != kCkptMagic || hd.state_bytes != (uint64_t)pl.state_elems * pl.ts ||
+        hd.pmodes != (uint64_t)pl.total_pmodes || hd.shape_hash != shape_hash(pl))
+        return fail(QS_ERR_ARG, "checkpoint does not match this context's parameters");
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    const char *o = static_cast<const char *>(src) + sizeof(hd);
+    QS_HIP(hipMemcpy(c->at(pl.off_state), o, hd.state_bytes, hipMemcpyHostToDevice), "copy state");
+    o += hd.state_bytes;
+    QS_HIP(hipMemcpy(c->at(pl.off_log2s), o, pl.total_pmodes * 4, hipMemcpyHostToDevice), "copy scales");
+    o += pl.total_pmodes * 4;
+    QS_HIP(hipMemcpy(c->at(pl.off_epend), o, pl.total_pmodes * 4, hipMemcpyHostToDevice), "copy scales");
+    c->steps_done = hd.steps_done;
     return QS_OK;
 }
 

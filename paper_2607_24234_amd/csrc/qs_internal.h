@@ -12,6 +12,7 @@
 namespace qs {
 
 constexpr int kWave = 64;  // lanes per wavefront on CDNA
+constexpr int32_t kFlatProfile = 1 << 16;  // InstDev.flags bit: Omega is constant over the beam
 
 // Per-instance constants, read by every workgroup of that instance (wave-uniform).
 struct InstDev {
@@ -35,7 +36,7 @@ struct InstDev {
 
 // Arguments of one tau-step launch.
 struct StepArgs {
-    void *state;              // TS elements, layout [block][cell][var 3][col 2*MPL][lane 64]
+    void *state;              // TS elements, layout [block][cell][var 3][col NC][lane 64]
     const int32_t *blk_inst;  // global block -> instance
     const InstDev *inst;
     const void *omega;        // TC elements: per instance [n_xi] centres then [n_xi] faces
@@ -66,9 +67,9 @@ struct SeedArgs {
 };
 
 // launchers (qs_spectral.hip)
-hipError_t launch_step(int precision, int mpl, bool restoring, bool fields, int n_blocks,
+hipError_t launch_step(int precision, int nc, bool restoring, bool fields, int n_blocks,
                        const StepArgs &a, hipStream_t s);
-hipError_t launch_seed(int precision, int mpl, int n_blocks, int max_n_xi, const SeedArgs &a,
+hipError_t launch_seed(int precision, int nc, int n_blocks, int max_n_xi, const SeedArgs &a,
                        hipStream_t s);
 
 // host helper mirroring the device SplitMix64 (exported for the generator tests)

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libqs.so")
+LIB_PATH = os.environ.get("QS_LIBRARY", os.path.join(PKG, "libqs.so"))
 
 # mirrored from include/qs.h
 QS_OK = 0
@@ -67,7 +67,7 @@ _lib = None
 
 EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_init", "qs_step_tau",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
-           "qs_debug_splitmix64"]
+           "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint"]
 
 
 def lib():
@@ -99,6 +99,12 @@ def lib():
     L.qs_set_state.argtypes = [vp, _D, _D, _D, _D]
     L.qs_free.restype = None
     L.qs_free.argtypes = [vp]
+    L.qs_checkpoint_size.restype = ctypes.c_size_t
+    L.qs_checkpoint_size.argtypes = [vp]
+    L.qs_save_checkpoint.restype = ctypes.c_int
+    L.qs_save_checkpoint.argtypes = [vp, vp, ctypes.c_size_t]
+    L.qs_load_checkpoint.restype = ctypes.c_int
+    L.qs_load_checkpoint.argtypes = [vp, vp, ctypes.c_size_t]
     L.qs_debug_splitmix64.restype = ctypes.c_uint64
     L.qs_debug_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     _lib = L
@@ -252,6 +258,17 @@ class Solver:
         l2 = np.concatenate([np.ascontiguousarray(s["log2_scale"], np.float64).ravel() for s in states])
         _check(lib().qs_set_state(self.ctx, _dp(rho.view(np.float64)), _dp(jpa.view(np.float64)),
                                   _dp(jpe.view(np.float64)), _dp(l2)))
+
+    def save_checkpoint(self):
+        """Opaque bitwise image of the state (bytes)."""
+        n = int(lib().qs_checkpoint_size(self.ctx))
+        buf = np.empty(n, np.uint8)
+        _check(lib().qs_save_checkpoint(self.ctx, buf.ctypes.data_as(ctypes.c_void_p), n))
+        return buf
+
+    def load_checkpoint(self, buf):
+        buf = np.ascontiguousarray(buf, np.uint8)
+        _check(lib().qs_load_checkpoint(self.ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:

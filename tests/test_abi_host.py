@@ -97,8 +97,8 @@ def test_workspace_size_scales_with_problem():
     s2 = qs.workspace_size([_inst(n_xi=128)], qs.QS_FP32)
     s3 = qs.workspace_size([_inst(n_xi=64)], qs.QS_FP64)
     assert 0 < s1 < s2 and s1 < s3
-    # state of 4 modes padded to one 64-lane block: 64 lanes x 6 values x n_xi
-    assert s2 - s1 >= 64 * 6 * 64 * 4
+    # state of 4 modes padded to one 64-lane block: 64 lanes x 3 values x n_xi
+    assert s2 - s1 >= 64 * 3 * 64 * 4
 
 
 def test_null_arguments():

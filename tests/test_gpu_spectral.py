@@ -152,23 +152,38 @@ def test_batched_instances_match_single_runs(qs):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_determinism_and_resume(qs, precision):
-    """Two runs are bitwise equal (no atomics, fixed order); a state saved with qs_get_state
-    and restored with qs_set_state continues bitwise like the uninterrupted run."""
+    """Two runs are bitwise equal (no atomics, fixed order); a checkpoint saved after 12 steps
+    and loaded into a fresh context continues bitwise like the uninterrupted run; a round trip
+    through the canonical state (qs_get_state/qs_set_state) is exact to one rounding."""
     inst = _slab(n_xi=80, kx=np.linspace(0.1, 4, 20))
     a = qs.Solver([inst], precision=precision)
     ra = a.step(30, max_ln_a=True)["max_ln_a"].cpu().numpy()
     sa = a.get_state()[0]
+    a2 = qs.Solver([inst], precision=precision)
+    ra2 = a2.step(30, max_ln_a=True)["max_ln_a"].cpu().numpy()
+    assert np.array_equal(ra, ra2)
     b = qs.Solver([inst], precision=precision)
     b.step(12)
-    saved = b.get_state()
+    ck = b.save_checkpoint()
     c = qs.Solver([inst], precision=precision)
-    c.set_state(saved)
+    c.load_checkpoint(ck)
+    assert c.steps_done == 12
     rc = c.step(18, max_ln_a=True)["max_ln_a"].cpu().numpy()
     sc = c.get_state()[0]
     assert np.array_equal(ra[12:], rc)
     for key in ("rho", "j_par", "j_perp"):
         assert np.array_equal(sa[key] * 2.0 ** sa["log2_scale"][:, None],
                               sc[key] * 2.0 ** sc["log2_scale"][:, None])
+    # canonical round trip
+    d = qs.Solver([inst], precision=precision)
+    d.set_state(b.get_state())
+    rd = d.step(18, max_ln_a=True)["max_ln_a"].cpu().numpy()
+    tol = 1e-12 if precision == qs.QS_FP64 else 1e-5
+    assert np.max(np.abs(rd - ra[12:])) < tol
+    # a checkpoint of another shape is refused
+    e = qs.Solver([_slab(n_xi=40, kx=np.linspace(0.1, 4, 20))], precision=precision)
+    with pytest.raises(qs.QSError):
+        e.load_checkpoint(ck)
 
 
 def test_isotropy_bitwise(qs):
