@@ -32,12 +32,12 @@ qs_status hip_fail(hipError_t e, const char *what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// real columns per lane of the step kernel: 1 (the two parts of a mode in adjacent lanes)
-// or 2 (one mode per lane); QS_COLUMNS_PER_LANE overrides the default of 1
+// real columns per lane of the step kernel: 2 (one mode per lane, the default) or 1 (the
+// two parts of a mode in adjacent lanes); QS_COLUMNS_PER_LANE overrides the default
 int env_nc() {
     const char *s = std::getenv("QS_COLUMNS_PER_LANE");
     if (s && (std::atoi(s) == 1 || std::atoi(s) == 2)) return std::atoi(s);
-    return 1;
+    return 2;
 }
 
 // Sizes derived from validated parameters.

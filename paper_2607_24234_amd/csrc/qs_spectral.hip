@@ -18,6 +18,8 @@
 // march up to the rear face of cell j (causality in xi).  Each lane therefore carries four
 // oscillator states (n_p, d_xi n_p) per column in FP64 and reads and writes the state of
 // each cell exactly once per tau-step.
+#include <type_traits>
+
 #include "qs_internal.h"
 
 // Tuning knobs of the step kernel (compile time): cells per register tile and the
@@ -27,7 +29,7 @@
 #endif
 // waves per SIMD the register allocator targets, by storage type and columns per lane
 #ifndef QS_WAVES_PER_EU
-#define QS_WAVES_PER_EU(TS, NC) (NC == 1 ? (sizeof(TS) == 8 ? 4 : 5) : 2)
+#define QS_WAVES_PER_EU(TS, NC) (NC == 1 ? (sizeof(TS) == 8 ? 4 : 5) : (sizeof(TS) == 8 ? 2 : 4))
 #endif
 
 namespace qs {
@@ -141,7 +143,6 @@ __global__ void __launch_bounds__(256) seed_kernel(SeedArgs a, int max_n_xi) {
 //
 // TS: storage type, TC: arithmetic type of everything except the oscillator carries
 // (always double).  RESTORING selects the plasma operator (d_xi^2 + 1) or d_xi^2.
-// TJ: cells per register tile (the next tile's loads are in flight while a tile computes).
 // Column layout: a block is 64 lanes x NC real columns; column q = lane*NC + c of block b
 // is part (q & 1) (0 = real, 1 = imaginary) of local mode b*32*NC + q/2.  With NC = 1 the
 // two parts of a mode sit in adjacent lanes and are combined with a lane swap when the
@@ -237,8 +238,10 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const InstDev &I, c
         }
     };
 
-    // one cell: four stages, fields of the state at tau_n (stage-1 values), the update
-    auto cell = [&](const int j, const TS (&x)[XW]) __attribute__((always_inline)) {
+    // one cell: four stages, fields of the state at tau_n (stage-1 values), the update.
+    // FIRST (cell 0 only) applies the steady-inflow front condition of the test hook.
+    auto cell = [&](const int j, const TS (&x)[XW], auto first) __attribute__((always_inline)) {
+        constexpr bool FIRST = decltype(first)::value;
         const bool last = (j == N - 1);
         const TC Oc = FLAT ? om0 : (TC)x[ROW];
         const TC Of = last ? (TC)0 : (FLAT ? om0 : (TC)x[ROW + 1]);
@@ -263,7 +266,7 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const InstDev &I, c
                 const TC Pm = (m == 0) ? P0[c] : P0[c] + cm * dP[c];
                 const TC Tm = (m == 0) ? T0[c] : T0[c] + cm * dT[c];
                 const double rd = (double)rm;
-                if (j == 0 && steady) { y[m][c] = rd; v[m][c] = 0.0; }
+                if (FIRST && steady) { y[m][c] = rd; v[m][c] = 0.0; }
                 double nc, yn, vn, vc;
                 if (RESTORING) {
                     const double u = y[m][c] - rd;
@@ -327,28 +330,26 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const InstDev &I, c
         }
     };
 
-    // register double buffer: tile t+1 is loaded while tile t computes.  The prefetch is
-    // unconditional: past the end of the block's region the bounds-checked buffer loads
-    // return 0 and nothing uses the values.
-    const int nfull = N / TJ * TJ;
-    TS cur[TJ][XW];
-#pragma unroll
-    for (int jj = 0; jj < TJ; ++jj) ldx(jj, cur[jj]);
-    for (int j0 = 0; j0 < nfull; j0 += TJ) {
-        TS nxt[TJ][XW];
-#pragma unroll
-        for (int jj = 0; jj < TJ; ++jj) ldx(j0 + TJ + jj, nxt[jj]);
-#pragma unroll
-        for (int jj = 0; jj < TJ; ++jj) cell(j0 + jj, cur[jj]);
-#pragma unroll
-        for (int jj = 0; jj < TJ; ++jj)
-#pragma unroll
-            for (int r = 0; r < XW; ++r) cur[jj][r] = nxt[jj][r];
+    // Cell 0 first (front condition), then cells 1..N-1 with a one-cell-ahead prefetch
+    // ping-ponged between two register sets, unrolled by two so that neither the buffers
+    // nor the oscillator carries need copies at the loop edge.  Loads past the end of the
+    // block's region are bounds-checked by the buffer descriptor (they return 0, unused).
+    using first_t = std::integral_constant<bool, true>;
+    using rest_t = std::integral_constant<bool, false>;
+    TS xa[XW], xb[XW];
+    ldx(0, xa);
+    ldx(1, xb);
+    cell(0, xa, first_t{});
+    int j = 1;
+    while (j < N) {
+        ldx(j + 1, xa);
+        cell(j, xb, rest_t{});
+        ++j;
+        if (j >= N) break;
+        ldx(j + 1, xb);
+        cell(j, xa, rest_t{});
+        ++j;
     }
-    // ragged tail (N not a multiple of TJ): cur holds cells nfull .. nfull+TJ-1
-#pragma unroll
-    for (int jj = 0; jj < TJ - 1; ++jj)
-        if (nfull + jj < N) cell(nfull + jj, cur[jj]);
 
     constexpr int R = RenormRange<TS>::R;
 #pragma unroll
