@@ -137,6 +137,26 @@ typedef struct qs_params {
 
 typedef struct qs_ctx qs_ctx;
 
+/*
+ * Execution plan of the march kernel (library design choice, not physics):
+ *   columns_per_lane : real columns per SIMD lane, 1 (the two parts of a mode in adjacent
+ *                      lanes) or 2 (one mode per lane); 0 = default (1, or the value of the
+ *                      environment variable QS_COLUMNS_PER_LANE).
+ *   segment_cells    : target cells per xi-segment.  Each 64-lane block of modes is split
+ *                      into ceil(n_xi/segment_cells) segments (at most 16 for FP32 with one
+ *                      column per lane, else 8), one
+ *                      wavefront each, pipelined over tau-steps with the oscillator carries
+ *                      passed between segments in LDS.  0 = automatic (fill one round of
+ *                      workgroups); >= n_xi = no segmentation.
+ *   max_segments     : (output of qs_get_plan) largest segment count of any instance.
+ */
+typedef struct qs_plan {
+    int32_t columns_per_lane;
+    int32_t segment_cells;
+    int32_t max_segments;
+    int32_t reserved;
+} qs_plan;
+
 /* ABI version of the loaded library (QS_ABI_VERSION at build time). */
 int32_t qs_abi_version(void);
 
@@ -148,6 +168,9 @@ const char *qs_last_error(void);
  * params: host array of n_instances problem descriptions.
  */
 size_t qs_workspace_size(const qs_params *params, int32_t n_instances);
+
+/* As qs_workspace_size, for an explicit execution plan (NULL = automatic). */
+size_t qs_workspace_size_ex(const qs_params *params, int32_t n_instances, const qs_plan *plan);
 
 /*
  * Create a solver context for n_instances >= 1 instances (Sec. II problem statement per
@@ -165,9 +188,20 @@ size_t qs_workspace_size(const qs_params *params, int32_t n_instances);
 qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream,
                   void *workspace, size_t workspace_bytes, qs_ctx **out);
 
+/* As qs_init, with an explicit execution plan (NULL = automatic).  QS_ERR_ARG for an invalid
+ * plan.  The plan changes only the schedule: results are identical for every plan. */
+qs_status qs_init_ex(const qs_params *params, int32_t n_instances, const qs_plan *plan,
+                     void *hip_stream, void *workspace, size_t workspace_bytes, qs_ctx **out);
+
+/* The plan in use (host): columns per lane, segment cells, largest segment count; and the
+ * workgroup count and wave slots per workgroup of one march launch.  Any output may be NULL. */
+qs_status qs_get_plan(const qs_ctx *ctx, qs_plan *plan, int32_t *n_workgroups,
+                      int32_t *waves_per_workgroup);
+
 /*
  * Advance every instance by n_steps >= 0 tau-steps of its own d_tau (the hot path: one
- * fused causal march over xi per step carrying all four Runge-Kutta stages).
+ * fused causal march over xi per step carrying all four Runge-Kutta stages; the steps
+ * between two snapshots run in one persistent launch).
  * Outputs (device pointers, each may be NULL; element type double for QS_FP64, float for
  * QS_FP32), for the modes of all instances concatenated in instance order (mode index
  * M = sum of n_modes of the earlier instances + m):

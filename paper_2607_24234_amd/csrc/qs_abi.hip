@@ -1,5 +1,7 @@
 // Host side of libqs: argument validation, per-instance tables, workspace layout, launch
 // sequencing and state import/export.  Every entry point is declared in include/qs.h.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -32,12 +34,12 @@ qs_status hip_fail(hipError_t e, const char *what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// real columns per lane of the step kernel: 2 (one mode per lane, the default) or 1 (the
-// two parts of a mode in adjacent lanes); QS_COLUMNS_PER_LANE overrides the default
+// real columns per lane of the step kernel: 1 (the two parts of a mode in adjacent lanes,
+// the default) or 2 (one mode per lane); QS_COLUMNS_PER_LANE overrides the default
 int env_nc() {
     const char *s = std::getenv("QS_COLUMNS_PER_LANE");
     if (s && (std::atoi(s) == 1 || std::atoi(s) == 2)) return std::atoi(s);
-    return 2;
+    return 1;
 }
 
 // Sizes derived from validated parameters.
@@ -53,10 +55,80 @@ struct Plan {
     int64_t total_pmodes = 0;
     int64_t snap_elems = 0;        // elements of one snapshot over all instances
     int32_t max_n_xi = 0;
+    int32_t seg_target = 0;        // target cells per xi-segment
+    int32_t wg_waves = 16;         // wave slots per workgroup of the march kernel
+    int32_t n_wg = 0;              // workgroups of the march kernel
+    int32_t max_seg = 1;           // largest segment count of any instance
+    int32_t max_seg_len = 0;       // longest segment of any segmented instance (cells)
+    int64_t n_scale = 0;           // entries of the per-(segment, mode) scale arrays
+    std::vector<int2> wave_table;  // [n_wg][wg_waves]: (global block, segment) or (-1, -1)
     // workspace offsets (bytes)
     size_t off_state, off_omega, off_shape, off_k, off_log2s, off_epend, off_inst, off_blk,
-        off_iidx, off_err, total;
+        off_iidx, off_err, off_wtab, total;
 };
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        return cus;
+    (void)hipGetLastError();
+    return 256;  // MI355X
+}
+
+// Segment each instance into ceil(N/seg) pieces (at most max_seg) and pack the (block,
+// segment) waves into workgroups of W slots, first fit by decreasing segment count; a
+// block's segments take consecutive slots of one workgroup.  Returns the workgroup count.
+// Segments of an instance of N cells for a target of seg cells and at most max_seg pieces:
+// equal lengths ceil(N/count), and no empty segment.
+int segments_of(int N, int seg, int max_seg) {
+    const int c = std::min(max_seg, std::max(1, (N + seg - 1) / seg));
+    const int len = (N + c - 1) / c;
+    return (N + len - 1) / len;
+}
+
+int pack(const std::vector<InstDev> &inst, int seg, int W, int max_seg, std::vector<int> *nseg_out,
+         std::vector<int2> *table) {
+    const int n = (int)inst.size();
+    std::vector<int> nseg(n);
+    for (int i = 0; i < n; ++i) nseg[i] = segments_of(inst[i].n_xi, seg, max_seg);
+    std::vector<std::pair<int, int>> items;  // (segments, global block)
+    for (int i = 0; i < n; ++i)
+        for (int b = 0; b < inst[i].n_blocks; ++b) items.push_back({nseg[i], inst[i].block0 + b});
+    std::stable_sort(items.begin(), items.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<int> freeslots;  // per workgroup
+    std::vector<std::vector<int2>> wgs;
+    // workgroups with free slots, bucketed by free count, for a near-linear first fit
+    std::vector<std::vector<int>> by_free(W + 1);
+    for (const auto &it : items) {
+        const int need = it.first;
+        int g = -1;
+        for (int f = need; f <= W && g < 0; ++f) {
+            while (!by_free[f].empty()) {
+                const int cand = by_free[f].back();
+                if (freeslots[cand] != f) { by_free[f].pop_back(); continue; }  // stale entry
+                g = cand;
+                by_free[f].pop_back();
+                break;
+            }
+        }
+        if (g < 0) {
+            g = (int)wgs.size();
+            wgs.emplace_back();
+            freeslots.push_back(W);
+        }
+        for (int s = 0; s < need; ++s) wgs[g].push_back(make_int2(it.second, s));
+        freeslots[g] -= need;
+        by_free[freeslots[g]].push_back(g);
+    }
+    if (nseg_out) *nseg_out = nseg;
+    if (table) {
+        table->assign((size_t)wgs.size() * W, make_int2(-1, -1));
+        for (size_t g = 0; g < wgs.size(); ++g)
+            for (size_t s = 0; s < wgs[g].size(); ++s) (*table)[g * W + s] = wgs[g][s];
+    }
+    return (int)wgs.size();
+}
 
 bool finite(double x) { return std::isfinite(x); }
 
@@ -124,7 +196,7 @@ qs_status validate_one(const qs_params &p, int i) {
     return QS_OK;
 }
 
-qs_status make_plan(const qs_params *params, int32_t n, Plan &pl) {
+qs_status make_plan(const qs_params *params, int32_t n, const qs_plan *plan, Plan &pl) {
     if (!params) return fail(QS_ERR_ARG, "params is NULL");
     if (n < 1 || n > (1 << 20)) return fail(QS_ERR_ARG, "n_instances must be in [1, 2^20]");
     for (int i = 0; i < n; ++i) {
@@ -137,6 +209,12 @@ qs_status make_plan(const qs_params *params, int32_t n, Plan &pl) {
     }
     pl.precision = params[0].precision;
     pl.nc = env_nc();
+    if (plan && plan->columns_per_lane != 0) {
+        if (plan->columns_per_lane != 1 && plan->columns_per_lane != 2)
+            return fail(QS_ERR_ARG, "plan.columns_per_lane must be 0, 1 or 2");
+        pl.nc = plan->columns_per_lane;
+    }
+    if (plan && plan->segment_cells < 0) return fail(QS_ERR_ARG, "plan.segment_cells must be >= 0");
     pl.ts = pl.precision == QS_FP64 ? 8 : 4;
     const int lanes_modes = 32 * pl.nc;  // modes per 64-lane block
     int64_t blocks = 0, pmodes = 0, modes = 0, state = 0, table = 0, snap = 0;
@@ -183,17 +261,96 @@ qs_status make_plan(const qs_params *params, int32_t n, Plan &pl) {
     pl.total_modes = modes;
     pl.total_pmodes = pmodes;
     pl.snap_elems = snap;
+
+    // xi-segmentation and workgroup packing.  Segments of one block share a workgroup; its
+    // size W (>= the largest segment count) is the one that keeps the most waves resident
+    // per CU for the kernel's register and LDS footprint.
+    const int Wmax = march_wg_waves(pl.precision, pl.nc);
+    const bool restoring = !(params[0].flags & QS_FLAG_NO_RESTORING);
+    bool flat = true;
+    for (const InstDev &d : pl.inst) flat = flat && (d.flags & kFlatProfile);
+    std::vector<int> wpc(Wmax + 1, -1);  // resident workgroups per CU by size
+    auto wgs_per_cu = [&](int W, bool segmented) {
+        const int key = segmented ? W : 0;
+        if (key > 0 && wpc[key] >= 0) return wpc[key];
+        int r = march_wgs_per_cu(pl.precision, pl.nc, restoring, flat, W, segmented);
+        if (r <= 0) {
+            // no device to ask: the register budgets the kernels are built for
+            const int per_simd = pl.nc == 1 ? (pl.precision == QS_FP64 ? 4 : 6) : (pl.precision == QS_FP64 ? 2 : 4);
+            r = std::max(1, 4 * per_simd / W);
+        }
+        if (key > 0) wpc[key] = r;
+        return r;
+    };
+    auto pick_w = [&](int mseg, int *per_cu) {
+        int best_w = mseg, best_res = -1;
+        for (int W = mseg; W <= Wmax; ++W) {
+            const int r = wgs_per_cu(W, mseg > 1);
+            if (r * W > best_res) { best_res = r * W; best_w = W; }
+        }
+        *per_cu = std::max(1, best_res / best_w);
+        return best_w;
+    };
+    auto max_segs = [&](int seg) {
+        int m = 1;
+        for (const InstDev &d : pl.inst) m = std::max(m, segments_of(d.n_xi, seg, Wmax));
+        return m;
+    };
+    int seg = 0;
+    if (plan && plan->segment_cells > 0) {
+        seg = plan->segment_cells;
+    } else {
+        // estimated makespan of a long launch: rounds of resident workgroups x longest
+        // segment x (1 + pipeline fill of the tau-skew over ~100 steps)
+        const int cus = device_cus();
+        double best = 1e300;
+        for (int div = 1; div <= Wmax; ++div) {
+            const int cand = (pl.max_n_xi + div - 1) / div;
+            if (cand < 32 && div > 1) break;
+            const int mseg = max_segs(cand);
+            int per_cu = 1;
+            const int W = pick_w(mseg, &per_cu);
+            std::vector<int> ns;
+            const int nwg = pack(pl.inst, cand, W, Wmax, &ns, nullptr);
+            int mlen = 0;
+            for (int i = 0; i < n; ++i) mlen = std::max(mlen, (pl.inst[i].n_xi + ns[i] - 1) / ns[i]);
+            const int64_t conc = (int64_t)cus * per_cu;
+            const double est = (double)((nwg + conc - 1) / conc) * mlen * (1.0 + (mseg - 1) / 100.0);
+            if (est < best * (1.0 - 1e-9)) { best = est; seg = cand; }
+        }
+    }
+    {
+        int per_cu = 1;
+        pl.wg_waves = pick_w(max_segs(seg), &per_cu);
+    }
+    const int W = pl.wg_waves;
+    pl.seg_target = seg;
+    std::vector<int> nseg;
+    pl.n_wg = pack(pl.inst, seg, W, Wmax, &nseg, &pl.wave_table);
+    int64_t nscale = 0;
+    pl.max_seg = 1;
+    for (int i = 0; i < n; ++i) {
+        InstDev &d = pl.inst[i];
+        d.n_seg = nseg[i];
+        d.seg_len = (d.n_xi + d.n_seg - 1) / d.n_seg;  // (n_seg - 1) * seg_len < n_xi
+        d.scale_off = nscale;
+        nscale += (int64_t)d.n_seg * d.n_blocks * lanes_modes;
+        pl.max_seg = std::max(pl.max_seg, d.n_seg);
+        if (d.n_seg > 1) pl.max_seg_len = std::max(pl.max_seg_len, d.seg_len);
+    }
+    pl.n_scale = nscale;
     size_t o = 0;
     pl.off_state = o; o = align_up(o + (size_t)state * pl.ts);
     pl.off_omega = o; o = align_up(o + (size_t)table * pl.ts);
     pl.off_shape = o; o = align_up(o + (size_t)table * sizeof(double));
     pl.off_k = o; o = align_up(o + (size_t)pmodes * sizeof(double));
-    pl.off_log2s = o; o = align_up(o + (size_t)pmodes * sizeof(int32_t));
-    pl.off_epend = o; o = align_up(o + (size_t)pmodes * sizeof(int32_t));
+    pl.off_log2s = o; o = align_up(o + (size_t)nscale * sizeof(int32_t));
+    pl.off_epend = o; o = align_up(o + (size_t)nscale * sizeof(int32_t));
     pl.off_inst = o; o = align_up(o + (size_t)n * sizeof(InstDev));
     pl.off_blk = o; o = align_up(o + (size_t)blocks * sizeof(int32_t));
     pl.off_iidx = o; o = align_up(o + (size_t)n * sizeof(int32_t));
     pl.off_err = o; o = align_up(o + sizeof(uint32_t) * 4);
+    pl.off_wtab = o; o = align_up(o + pl.wave_table.size() * sizeof(int2));
     pl.total = o;
     return QS_OK;
 }
@@ -206,6 +363,7 @@ using namespace qs;
 struct qs_ctx {
     Plan pl;
     int device = 0;
+    double wall_clock_hz = 1e8;  // rate of the device's constant wall clock
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     bool owns_ws = false;
@@ -267,6 +425,8 @@ qs_status upload_tables(qs_ctx *c, const qs_params *params) {
                           hipMemcpyHostToDevice, c->stream), "copy block table");
     QS_HIP(hipMemcpyAsync(c->at(pl.off_iidx), iidx.data(), iidx.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice, c->stream), "copy instance index");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_wtab), pl.wave_table.data(), pl.wave_table.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, c->stream), "copy wave table");
     QS_HIP(hipMemsetAsync(c->at(pl.off_err), 0, sizeof(uint32_t) * 4, c->stream), "clear error flag");
     // the host vectors die here: make the copies complete first
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
@@ -278,8 +438,8 @@ qs_status seed_state(qs_ctx *c, const qs_params *params) {
     // every instance must share the seed kind/amp/rng_seed within one launch: launch per group
     const int n = (int)pl.inst.size();
     QS_HIP(hipMemsetAsync(c->at(pl.off_state), 0, (size_t)pl.state_elems * pl.ts, c->stream), "clear state");
-    QS_HIP(hipMemsetAsync(c->at(pl.off_log2s), 0, (size_t)pl.total_pmodes * sizeof(int32_t), c->stream), "clear scales");
-    QS_HIP(hipMemsetAsync(c->at(pl.off_epend), 0, (size_t)pl.total_pmodes * sizeof(int32_t), c->stream), "clear scales");
+    QS_HIP(hipMemsetAsync(c->at(pl.off_log2s), 0, (size_t)pl.n_scale * sizeof(int32_t), c->stream), "clear scales");
+    QS_HIP(hipMemsetAsync(c->at(pl.off_epend), 0, (size_t)pl.n_scale * sizeof(int32_t), c->stream), "clear scales");
     int i0 = 0;
     while (i0 < n) {
         int i1 = i0 + 1;
@@ -319,18 +479,22 @@ int32_t qs_abi_version(void) { return QS_ABI_VERSION; }
 
 const char *qs_last_error(void) { return g_err.c_str(); }
 
-size_t qs_workspace_size(const qs_params *params, int32_t n_instances) {
+size_t qs_workspace_size_ex(const qs_params *params, int32_t n_instances, const qs_plan *plan) {
     Plan pl;
-    if (make_plan(params, n_instances, pl) != QS_OK) return 0;
+    if (make_plan(params, n_instances, plan, pl) != QS_OK) return 0;
     return pl.total;
 }
 
-qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream, void *workspace,
-                  size_t workspace_bytes, qs_ctx **out) {
+size_t qs_workspace_size(const qs_params *params, int32_t n_instances) {
+    return qs_workspace_size_ex(params, n_instances, nullptr);
+}
+
+qs_status qs_init_ex(const qs_params *params, int32_t n_instances, const qs_plan *plan, void *hip_stream,
+                     void *workspace, size_t workspace_bytes, qs_ctx **out) {
     g_err.clear();
     if (!out) return fail(QS_ERR_ARG, "out is NULL");
     Plan pl;
-    qs_status st = make_plan(params, n_instances, pl);
+    qs_status st = make_plan(params, n_instances, plan, pl);
     if (st != QS_OK) return st;
     if (workspace && workspace_bytes < pl.total)
         return fail(QS_ERR_ALLOC, "workspace too small: need " + std::to_string(pl.total) + " bytes");
@@ -342,6 +506,13 @@ qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream
     c->stream = static_cast<hipStream_t>(hip_stream);
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
+        c->wall_clock_hz = 1e3 * khz;
+    (void)hipGetLastError();
+    const size_t lds = march_lds_bytes(c->pl.precision, c->pl.nc, c->pl.wg_waves, c->pl.max_seg > 1);
+    e = allow_march_lds(c->pl.precision, c->pl.nc, lds);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "allow march kernel LDS"); }
     if (workspace) {
         c->ws = static_cast<char *>(workspace);
     } else {
@@ -355,6 +526,24 @@ qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream
     if (st == QS_OK) st = seed_state(c, params);
     if (st != QS_OK) { qs_free(c); return st; }
     *out = c;
+    return QS_OK;
+}
+
+qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream, void *workspace,
+                  size_t workspace_bytes, qs_ctx **out) {
+    return qs_init_ex(params, n_instances, nullptr, hip_stream, workspace, workspace_bytes, out);
+}
+
+qs_status qs_get_plan(const qs_ctx *c, qs_plan *plan, int32_t *n_workgroups, int32_t *waves_per_workgroup) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (plan) {
+        plan->columns_per_lane = c->pl.nc;
+        plan->segment_cells = c->pl.seg_target;
+        plan->max_segments = c->pl.max_seg;
+        plan->reserved = 0;
+    }
+    if (n_workgroups) *n_workgroups = c->pl.n_wg;
+    if (waves_per_workgroup) *waves_per_workgroup = c->pl.wg_waves;
     return QS_OK;
 }
 
@@ -379,27 +568,52 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     a.epend = reinterpret_cast<int32_t *>(c->at(pl.off_epend));
     a.total_modes = (int32_t)pl.total_modes;
     a.err = reinterpret_cast<uint32_t *>(c->at(pl.off_err));
+    a.wave_table = reinterpret_cast<const int2 *>(c->at(pl.off_wtab));
+    // a segment waits for its predecessor to finish one step of its own cells: allow 2 s
+    // plus 20 us per cell before the wait reports a stall
+    a.wait_ticks = (uint64_t)(c->wall_clock_hz * (2.0 + 20e-6 * pl.max_seg_len));
     const bool restoring = !(pl.inst[0].flags & QS_FLAG_NO_RESTORING);
-    const int nblk = (int)pl.blk_inst.size();
+    bool flat = true;
+    for (const InstDev &d : pl.inst) flat = flat && (d.flags & kFlatProfile);
+    auto launch = [&](bool fields) {
+        return launch_march(pl.precision, pl.nc, restoring, fields, flat, pl.n_wg, pl.wg_waves, pl.max_seg > 1,
+                            a, c->stream);
+    };
     if (n_steps == 0) {
         a.ln_e = out_ln_e;
         a.ln_b = out_ln_b;
         a.update = 0;
-        QS_HIP(launch_step(pl.precision, pl.nc, restoring, true, nblk, a, c->stream), "step kernel");
+        a.n_steps = 1;
+        QS_HIP(launch(true), "march kernel");
         return QS_OK;
     }
-    for (int s = 0; s < n_steps; ++s) {
-        const bool snap = snaps && (s % out_every == 0);
+    // segments of one mode combine their per-step maxima with order-independent atomics
+    const bool keyed = out_max_ln_a != nullptr && pl.max_seg > 1;
+    if (keyed)
+        QS_HIP(launch_key_fill(pl.precision, out_max_ln_a, (int64_t)n_steps * pl.total_modes, c->stream), "key fill");
+    a.max_ln_a = out_max_ln_a;
+    a.keyed = keyed ? 1 : 0;
+    a.update = 1;
+    // snapshot steps run as one-step launches, the steps between them in one launch each
+    int s0 = 0;
+    while (s0 < n_steps) {
+        const bool snap = snaps && (s0 % out_every == 0);
+        int s1 = s0 + 1;
+        if (!snap) {
+            s1 = n_steps;
+            if (snaps) s1 = std::min(n_steps, (s0 / out_every + 1) * out_every);
+        }
         a.ln_e = snap ? out_ln_e : nullptr;
         a.ln_b = snap ? out_ln_b : nullptr;
-        a.snap_base = snap ? (int64_t)(s / out_every) * pl.snap_elems : 0;
-        a.max_ln_a = out_max_ln_a;
-        a.max_base = (int64_t)s * pl.total_modes;
-        a.update = 1;
-        const bool fields = snap || out_max_ln_a != nullptr;
-        QS_HIP(launch_step(pl.precision, pl.nc, restoring, fields, nblk, a, c->stream), "step kernel");
-        ++c->steps_done;
+        a.snap_base = snap ? (int64_t)(s0 / out_every) * pl.snap_elems : 0;
+        a.max_base = (int64_t)s0 * pl.total_modes;
+        a.n_steps = s1 - s0;
+        QS_HIP(launch(snap || out_max_ln_a != nullptr), "march kernel");
+        c->steps_done += s1 - s0;
+        s0 = s1;
     }
+    if (keyed)
+        QS_HIP(launch_key_decode(pl.precision, out_max_ln_a, (int64_t)n_steps * pl.total_modes, c->stream), "key decode");
     return QS_OK;
 }
 
@@ -409,6 +623,12 @@ qs_status qs_sync_check(qs_ctx *c) {
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
     uint32_t flag = 0;
     QS_HIP(hipMemcpy(&flag, c->at(c->pl.off_err), sizeof(flag), hipMemcpyDeviceToHost), "read error flag");
+    uint32_t stall = 0;
+    QS_HIP(hipMemcpy(&stall, c->at(c->pl.off_err) + sizeof(uint32_t), sizeof(stall), hipMemcpyDeviceToHost), "read error flag");
+    if (stall) {
+        QS_HIP(hipMemset(c->at(c->pl.off_err) + sizeof(uint32_t), 0, sizeof(uint32_t)), "clear error flag");
+        return fail(QS_ERR_HIP, "a xi-segment hand-off wait gave up (results of the last launch are invalid)");
+    }
     if (flag) {
         QS_HIP(hipMemset(c->at(c->pl.off_err), 0, sizeof(uint32_t)), "clear error flag");
         return fail(QS_ERR_NUMERIC, "non-finite state at renormalization (padded mode " +
@@ -426,7 +646,7 @@ qs_status qs_get_state(qs_ctx *c, double *rho, double *j_par, double *j_perp, do
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
     std::vector<char> raw((size_t)pl.state_elems * pl.ts);
-    std::vector<int32_t> l2(pl.total_pmodes), ep(pl.total_pmodes);
+    std::vector<int32_t> l2(pl.n_scale), ep(pl.n_scale);
     QS_HIP(hipMemcpy(raw.data(), c->at(pl.off_state), raw.size(), hipMemcpyDeviceToHost), "copy state");
     QS_HIP(hipMemcpy(l2.data(), c->at(pl.off_log2s), l2.size() * 4, hipMemcpyDeviceToHost), "copy scales");
     QS_HIP(hipMemcpy(ep.data(), c->at(pl.off_epend), ep.size() * 4, hipMemcpyDeviceToHost), "copy scales");
@@ -441,13 +661,21 @@ qs_status qs_get_state(qs_ctx *c, double *rho, double *j_par, double *j_perp, do
     int64_t out0 = 0;
     for (const InstDev &d : pl.inst) {
         const int N = d.n_xi;
+        const int64_t pm_inst = (int64_t)d.n_blocks * LM;  // padded modes of the instance
         for (int m = 0; m < d.n_modes; ++m) {
             const int b = m / LM, q = m % LM;
-            const int e = ep[d.pmode0 + m];
-            const double sc = std::ldexp(1.0, -e);
             const double k = kmode[d.pmode0 + m];
-            if (log2_scale) log2_scale[d.mode0 + m] = (double)l2[d.pmode0 + m] + e;
+            // stored values of segment s are the true ones divided by 2^log2s; report them
+            // against the largest applied+pending exponent of the mode (exact rescaling)
+            int32_t lmax = INT32_MIN;
+            for (int sg = 0; sg < d.n_seg; ++sg) {
+                const int64_t si = d.scale_off + sg * pm_inst + m;
+                lmax = std::max(lmax, l2[si] + ep[si]);
+            }
+            if (log2_scale) log2_scale[d.mode0 + m] = (double)lmax;
             for (int j = 0; j < N; ++j) {
+                const int64_t si = d.scale_off + (j / d.seg_len) * pm_inst + m;
+                const double sc = std::ldexp(1.0, l2[si] - lmax);
                 const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave;
                 auto x = [&](int var, int part) { return val(cell + elem_of(NC, q, var, part)) * sc; };
                 const int64_t o = 2 * (out0 + (int64_t)m * N + j);
@@ -476,7 +704,7 @@ qs_status qs_set_state(qs_ctx *c, const double *rho, const double *j_par, const 
             return fail(QS_ERR_ARG, "log2_scale entries must be integers");
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     std::vector<char> raw((size_t)pl.state_elems * pl.ts, 0);
-    std::vector<int32_t> l2(pl.total_pmodes, 0), ep(pl.total_pmodes, 0);
+    std::vector<int32_t> l2(pl.n_scale, 0), ep(pl.n_scale, 0);
     const int NC = pl.nc, ROW = 3 * NC, LM = 32 * NC;
     auto put = [&](int64_t e, double v) {
         if (pl.precision == QS_FP64) reinterpret_cast<double *>(raw.data())[e] = v;
@@ -492,7 +720,8 @@ qs_status qs_set_state(qs_ctx *c, const double *rho, const double *j_par, const 
         for (int m = 0; m < d.n_modes; ++m) {
             const int b = m / LM, q = m % LM;
             const double k = kmode[d.pmode0 + m];
-            l2[d.pmode0 + m] = (int32_t)log2_scale[d.mode0 + m];
+            for (int sg = 0; sg < d.n_seg; ++sg)
+                l2[d.scale_off + (int64_t)sg * d.n_blocks * LM + m] = (int32_t)log2_scale[d.mode0 + m];
             for (int j = 0; j < N; ++j) {
                 const int64_t cell = d.state_off + ((int64_t)b * N + j) * ROW * kWave;
                 auto at = [&](int var, int part) { return cell + elem_of(NC, q, var, part); };
@@ -517,7 +746,7 @@ namespace {
 struct CkptHeader {
     uint64_t magic;        // "QSCKPT01"
     uint64_t state_bytes;  // bytes of the state image
-    uint64_t pmodes;       // padded modes
+    uint64_t pmodes;       // entries of each scale array
     uint64_t shape_hash;   // hash of the per-instance shapes and constants
     int64_t steps_done;
 };
@@ -533,13 +762,14 @@ uint64_t shape_hash(const Plan &pl) {
     for (const InstDev &d : pl.inst) mix(&d, sizeof(d));
     mix(&pl.precision, sizeof(pl.precision));
     mix(&pl.nc, sizeof(pl.nc));
+    mix(pl.wave_table.data(), pl.wave_table.size() * sizeof(int2));
     return h;
 }
 }  // namespace
 
 size_t qs_checkpoint_size(const qs_ctx *c) {
     if (!c) return 0;
-    return sizeof(CkptHeader) + (size_t)c->pl.state_elems * c->pl.ts + 2 * (size_t)c->pl.total_pmodes * sizeof(int32_t);
+    return sizeof(CkptHeader) + (size_t)c->pl.state_elems * c->pl.ts + 2 * (size_t)c->pl.n_scale * sizeof(int32_t);
 }
 
 qs_status qs_save_checkpoint(qs_ctx *c, void *dst, size_t bytes) {
@@ -548,15 +778,15 @@ qs_status qs_save_checkpoint(qs_ctx *c, void *dst, size_t bytes) {
     const Plan &pl = c->pl;
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
-    CkptHeader hd{kCkptMagic, (uint64_t)pl.state_elems * pl.ts, (uint64_t)pl.total_pmodes, shape_hash(pl), c->steps_done};
+    CkptHeader hd{kCkptMagic, (uint64_t)pl.state_elems * pl.ts, (uint64_t)pl.n_scale, shape_hash(pl), c->steps_done};
     char *o = static_cast<char *>(dst);
     std::memcpy(o, &hd, sizeof(hd));
     o += sizeof(hd);
     QS_HIP(hipMemcpy(o, c->at(pl.off_state), hd.state_bytes, hipMemcpyDeviceToHost), "copy state");
     o += hd.state_bytes;
-    QS_HIP(hipMemcpy(o, c->at(pl.off_log2s), pl.total_pmodes * 4, hipMemcpyDeviceToHost), "copy scales");
-    o += pl.total_pmodes * 4;
-    QS_HIP(hipMemcpy(o, c->at(pl.off_epend), pl.total_pmodes * 4, hipMemcpyDeviceToHost), "copy scales");
+    QS_HIP(hipMemcpy(o, c->at(pl.off_log2s), pl.n_scale * 4, hipMemcpyDeviceToHost), "copy scales");
+    o += pl.n_scale * 4;
+    QS_HIP(hipMemcpy(o, c->at(pl.off_epend), pl.n_scale * 4, hipMemcpyDeviceToHost), "copy scales");
     return QS_OK;
 }
 
@@ -567,16 +797,16 @@ qs_status qs_load_checkpoint(qs_ctx *c, const void *src, size_t bytes) {
     CkptHeader hd;
     std::memcpy(&hd, src, sizeof(hd));
     if (hd.magic != kCkptMagic || hd.state_bytes != (uint64_t)pl.state_elems * pl.ts ||
-        hd.pmodes != (uint64_t)pl.total_pmodes || hd.shape_hash != shape_hash(pl))
+        hd.pmodes != (uint64_t)pl.n_scale || hd.shape_hash != shape_hash(pl))
         return fail(QS_ERR_ARG, "checkpoint does not match this context's parameters");
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
     const char *o = static_cast<const char *>(src) + sizeof(hd);
     QS_HIP(hipMemcpy(c->at(pl.off_state), o, hd.state_bytes, hipMemcpyHostToDevice), "copy state");
     o += hd.state_bytes;
-    QS_HIP(hipMemcpy(c->at(pl.off_log2s), o, pl.total_pmodes * 4, hipMemcpyHostToDevice), "copy scales");
-    o += pl.total_pmodes * 4;
-    QS_HIP(hipMemcpy(c->at(pl.off_epend), o, pl.total_pmodes * 4, hipMemcpyHostToDevice), "copy scales");
+    QS_HIP(hipMemcpy(c->at(pl.off_log2s), o, pl.n_scale * 4, hipMemcpyHostToDevice), "copy scales");
+    o += pl.n_scale * 4;
+    QS_HIP(hipMemcpy(c->at(pl.off_epend), o, pl.n_scale * 4, hipMemcpyHostToDevice), "copy scales");
     c->steps_done = hd.steps_done;
     return QS_OK;
 }

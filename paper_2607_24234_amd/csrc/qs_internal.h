@@ -27,6 +27,9 @@ struct InstDev {
     int64_t state_off;   // element offset of block 0 in the state array
     int64_t omega_off;   // element offset of this instance's Omega tables (centres, then faces)
     int64_t snap_off;    // element offset of this instance inside one snapshot
+    int64_t scale_off;   // offset of (segment 0, mode 0) in the per-(mode, segment) scale arrays
+    int32_t n_seg;       // xi-segments (waves per block) of this instance
+    int32_t seg_len;     // cells per segment (the last one may be shorter)
     double h, ih;        // cell width, 1/h (0 when the longitudinal term is dropped)
     double dtau;
     double ginv, g3inv;  // gamma^-1, gamma^-3 (g3inv is 0 when the longitudinal term is dropped)
@@ -41,15 +44,20 @@ struct StepArgs {
     const InstDev *inst;
     const void *omega;        // TC elements: per instance [n_xi] centres then [n_xi] faces
     const double *kmode;      // |k| per padded mode
-    int32_t *log2s;           // per padded mode: applied power of two (L)
-    int32_t *epend;           // per padded mode: pending exponent (applied at the next load)
+    int32_t *log2s;           // per (segment, padded mode): applied power of two (L)
+    int32_t *epend;           // per (segment, padded mode): pending exponent (next step)
     void *ln_e, *ln_b;        // snapshot outputs (TS) or null
     void *max_ln_a;           // [step][total modes] (TS) or null
     int64_t snap_base;        // element offset of this step's snapshot (ln_e/ln_b)
-    int64_t max_base;         // element offset of this step's row in max_ln_a
+    int64_t max_base;         // element offset of the launch's first row in max_ln_a
     int32_t total_modes;      // unpadded total modes (row length of max_ln_a)
     int32_t update;           // 1: advance the state; 0: fields only
-    uint32_t *err;            // nonzero after a non-finite renormalization: 1 + padded mode
+    int32_t n_steps;          // tau-steps of this launch
+    int32_t keyed;            // 1: max_ln_a holds order-preserving keys (combined by atomic max)
+    uint64_t wait_ticks;      // wall-clock ticks a segment hand-off wait allows before giving up
+    const int2 *wave_table;   // per (workgroup, wave slot): (global block, segment) or (-1, -1)
+    uint32_t *err;            // [0]: 1 + padded mode after a non-finite renormalization;
+                              // [1]: 1 if a segment hand-off wait gave up
 };
 
 struct SeedArgs {
@@ -67,8 +75,19 @@ struct SeedArgs {
 };
 
 // launchers (qs_spectral.hip)
-hipError_t launch_step(int precision, int nc, bool restoring, bool fields, int n_blocks,
-                       const StepArgs &a, hipStream_t s);
+constexpr int kMaxSegments = 16;  // most waves per workgroup of the march kernel
+// waves per workgroup of the march kernel: 16 for FP32 with one column per lane, else 8
+// (the register budget of the larger column counts and of FP64 allows half the waves)
+inline int march_wg_waves(int precision, int nc) { return precision == QS_FP32 && nc == 1 ? 16 : 8; }
+hipError_t launch_march(int precision, int nc, bool restoring, bool fields, bool flat, int n_wg,
+                        int wg_waves, bool segmented, const StepArgs &a, hipStream_t s);
+size_t march_lds_bytes(int precision, int nc, int wg_waves, bool segmented);
+// resident workgroups per CU of the march kernel for this shape (-1 if the runtime cannot
+// tell, e.g. without a device)
+int march_wgs_per_cu(int precision, int nc, bool restoring, bool flat, int wg_waves, bool segmented);
+hipError_t allow_march_lds(int precision, int nc, size_t bytes);
+hipError_t launch_key_fill(int precision, void *p, int64_t n, hipStream_t s);
+hipError_t launch_key_decode(int precision, void *p, int64_t n, hipStream_t s);
 hipError_t launch_seed(int precision, int nc, int n_blocks, int max_n_xi, const SeedArgs &a,
                        hipStream_t s);
 

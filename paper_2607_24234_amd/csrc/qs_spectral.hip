@@ -24,13 +24,6 @@
 
 // Tuning knobs of the step kernel (compile time): cells per register tile and the
 // occupancy the register allocator targets (waves per SIMD).
-#ifndef QS_STEP_TJ
-#define QS_STEP_TJ 2
-#endif
-// waves per SIMD the register allocator targets, by storage type and columns per lane
-#ifndef QS_WAVES_PER_EU
-#define QS_WAVES_PER_EU(TS, NC) (NC == 1 ? (sizeof(TS) == 8 ? 4 : 5) : (sizeof(TS) == 8 ? 2 : 4))
-#endif
 
 namespace qs {
 namespace {
@@ -122,8 +115,11 @@ __global__ void __launch_bounds__(256) seed_kernel(SeedArgs a, int max_n_xi) {
             const double am = fabs(a.amp);
             constexpr int R = RenormRange<TS>::R;
             if (am > 0.0 && (am > ldexp(1.0, R) || am < ldexp(1.0, -R))) (void)frexp(am, &e);
-            a.log2s[I.pmode0 + m] = 0;
-            a.epend[I.pmode0 + m] = e;
+            for (int sg = 0; sg < I.n_seg; ++sg) {
+                const int64_t si = I.scale_off + (int64_t)sg * I.n_blocks * Cols<NC>::MODES_PER_BLOCK + m;
+                a.log2s[si] = 0;
+                a.epend[si] = e;
+            }
         }
     }
 }
@@ -173,34 +169,124 @@ template <typename TC> __device__ __forceinline__ TC pair_max(TC x) {
     return (y > x || !(y <= y)) ? y : x;
 }
 
-template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, bool SNAP, int TJ, bool SCALE, bool FLAT>
-__device__ __forceinline__ void step_body(const StepArgs &a, const InstDev &I, const int b) {
+// ------------------------------------------------------------- max over segments
+// Order-preserving integer keys of floating-point values: max of keys = key of the max, so
+// segments of one mode combine their maxima with integer atomics in any order.
+__device__ __forceinline__ uint32_t fkey(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float funkey(uint32_t k) {
+    return __builtin_bit_cast(float, (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+__device__ __forceinline__ uint64_t fkey(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double funkey(uint64_t k) {
+    return __builtin_bit_cast(double, (k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k);
+}
+__device__ __forceinline__ void atomic_max_key(float *dst, float v) {
+    atomicMax(reinterpret_cast<unsigned int *>(dst), fkey(v));
+}
+__device__ __forceinline__ void atomic_max_key(double *dst, double v) {
+    atomicMax(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)fkey(v));
+}
+
+// ----------------------------------------------------------------------------- march
+// One workgroup per 64-lane block of modes, one wave per xi-segment of that block.  Wave s
+// owns cells [s*seg_len, min(N, (s+1)*seg_len)) and runs every tau-step of the launch on
+// them; at a segment boundary it hands the four stage carries (n_p, d_xi n_p) and the stage
+// inputs of P' at the boundary face to wave s+1 through LDS.  Wave s+1 can start step n as
+// soon as wave s has finished step n on its cells, so the segments of one block pipeline
+// over tau-steps (tau-skew).  Each (mode, segment) keeps its own power-of-two scale: carries
+// crossing a boundary are rescaled exactly by the difference of the two exponents.
+//
+// LDS layout (dynamic): int ready[16], taken[16], abort, 3 pad; then per boundary w (0..S-2)
+// the payload double Y[4][NC][64], V[4][NC][64];  TC PP[4][NC][64];  int32 LL[MPL][64].
+constexpr int kMaxSeg = 16;
+constexpr int kFlagInts = 2 * kMaxSeg + 4;
+
+template <typename TC, int NC>
+struct Payload {
+    static constexpr int MPL = NC >= 2 ? NC / 2 : 1;
+    static constexpr int BYTES = kWave * (8 * NC * 8 + 4 * NC * (int)sizeof(TC) + MPL * 4);
+    __device__ static double *Y(char *p) { return reinterpret_cast<double *>(p); }
+    __device__ static double *V(char *p) { return reinterpret_cast<double *>(p) + 4 * NC * kWave; }
+    __device__ static TC *PP(char *p) { return reinterpret_cast<TC *>(p + 8 * NC * kWave * 8); }
+    __device__ static int32_t *LL(char *p) {
+        return reinterpret_cast<int32_t *>(p + 8 * NC * kWave * 8 + 4 * NC * kWave * (int)sizeof(TC));
+    }
+};
+
+// Wait until *flag >= target (LDS, same workgroup).  Gives up (false) when another wave of
+// the workgroup gave up (*abort set) or after `ticks` of the constant-rate wall clock, and
+// then sets *abort so that every other waiting wave of the workgroup stops too.
+__device__ __forceinline__ bool wait_flag(int *flag, int target, int *abort, uint64_t ticks) {
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+        if (wall_clock64() - t0 > ticks) {
+            __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, bool SNAP, bool FLAT>
+__global__ void __launch_bounds__(sizeof(TS) == 4 && NC == 1 ? 1024 : 512)
+__attribute__((amdgpu_waves_per_eu(NC == 1 && !SNAP ? (sizeof(TS) == 8 ? 4 : 5) : 1)))
+march_kernel(StepArgs a) {
     using CL = Cols<NC>;
+    using PL = Payload<TC, NC>;
     constexpr int MPL = CL::MPL;
     constexpr int ROW = 3 * NC;        // rows of 64 values per cell
+    extern __shared__ __align__(16) char lds[];
+    int *ready = reinterpret_cast<int *>(lds);
+    int *taken = ready + kMaxSeg;
+    int *abort = ready + 2 * kMaxSeg;
+    char *payload = lds + kFlagInts * sizeof(int);
+
+    // wave slot -> (block, segment) from the packing table; slots of one block's segments
+    // are consecutive, so the hand-off of slot w goes to slot w+1
+    const int slot = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);  // wave-uniform
+    const int lane = (int)threadIdx.x % kWave;
+    if (threadIdx.x < kFlagInts) ready[threadIdx.x] = 0;  // also clears taken[] and abort
+    __syncthreads();
+    const int2 ent = a.wave_table[(int64_t)blockIdx.x * (blockDim.x / kWave) + slot];
+    if (ent.x < 0) return;  // idle slot
+    const int gb = ent.x, wave = ent.y;  // global block, segment index
+    const int ii = a.blk_inst[gb];
+    const InstDev I = a.inst[ii];
+    const int b = gb - I.block0;
+
     const int N = I.n_xi;
-    const int lane = threadIdx.x;
+    const int c0 = wave * I.seg_len;
+    const int c1 = min(N, c0 + I.seg_len);
+    const bool has_next = wave + 1 < I.n_seg;
     const bool steady = (I.flags & QS_FLAG_STEADY_INFLOW) != 0;
     const bool writer = NC >= 2 || (lane & 1) == 0;   // lane that writes per-mode results
 
-    TC cT[MPL], cP[MPL], kap2[MPL], k2kap2[MPL], scale[MPL];
-    int32_t L[MPL];
-    int pm[MPL], mloc[MPL];
+    TC cT[MPL], cP[MPL], kap2[MPL], k2kap2[MPL];
+    int32_t L[MPL], ep[MPL];
+    int mloc[MPL];
+    int64_t sidx[MPL];  // index of this (mode, segment) in the scale arrays
 #pragma unroll
     for (int t = 0; t < MPL; ++t) {
         mloc[t] = CL::mode(b, lane, t);
-        pm[t] = I.pmode0 + mloc[t];
-        const double k = a.kmode[pm[t]];
+        const double k = a.kmode[I.pmode0 + mloc[t]];
         const double kp = 1.0 / (1.0 + k * k);
         kap2[t] = (TC)(kp * kp);
         k2kap2[t] = (TC)(k * k * kp * kp);
-        const int e = a.epend[pm[t]];
-        L[t] = a.log2s[pm[t]] + e;
-        scale[t] = (TC)ldexp(1.0, -e);
         cT[t] = (TC)(k * k * kp * I.ginv);
         cP[t] = (TC)(-kp * I.g3inv * I.ih);
+        sidx[t] = I.scale_off + (int64_t)wave * I.n_blocks * CL::MODES_PER_BLOCK + mloc[t];
+        L[t] = a.log2s[sidx[t]];
+        ep[t] = a.epend[sidx[t]];
     }
-    const TC c1 = (TC)(0.25 * I.dtau), c2 = (TC)(I.dtau / 3.0), c3 = (TC)(0.5 * I.dtau);
+    const TC c1s = (TC)(0.25 * I.dtau), c2s = (TC)(I.dtau / 3.0), c3s = (TC)(0.5 * I.dtau);
     const TC dt = (TC)I.dtau;
     const double C1 = I.c1, S1 = I.s1, C2 = I.c2, S2 = I.s2, h = I.h;
 
@@ -209,209 +295,285 @@ __device__ __forceinline__ void step_body(const StepArgs &a, const InstDev &I, c
     const rsrc_t ro = make_rsrc(const_cast<TC *>(omc), (uint32_t)(2 * N * sizeof(TC)));
     const TC om0 = omc[0];
 
-    double y[4][NC], v[4][NC];  // oscillator carries per stage: n_p and d_xi n_p at the front face
-    TC pp[4][NC];               // stage inputs of P' at the front face of the current cell
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) { y[m][c] = 0.0; v[m][c] = 0.0; pp[m][c] = (TC)0; }
-
-    TC rmax[MPL], a2max[MPL];
-#pragma unroll
-    for (int t = 0; t < MPL; ++t) { rmax[t] = (TC)0; a2max[t] = (TC)0; }
-
     // this block's region of the state: [cell][row][lane] of TS
     TS *blk = static_cast<TS *>(a.state) + I.state_off + (int64_t)b * N * ROW * kWave;
     const rsrc_t rs = make_rsrc(blk, (uint32_t)((int64_t)N * ROW * kWave * sizeof(TS)));
     const int voff = lane * (int)sizeof(TS);
     constexpr int RB = kWave * (int)sizeof(TS);  // bytes per row
-    auto ld = [&](int j, int r) __attribute__((always_inline)) { return bload<TS>(rs, voff, (j * ROW + r) * RB); };
-
-    // a cell's inputs: its state rows and (non-flat profiles) Omega at its centre and rear face
     constexpr int XW = ROW + (FLAT ? 0 : 2);
     auto ldx = [&](int j, TS (&x)[XW]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int r = 0; r < ROW; ++r) x[r] = ld(j, r);
+        for (int r = 0; r < ROW; ++r) x[r] = bload<TS>(rs, voff, (j * ROW + r) * RB);
         if (!FLAT) {
             x[ROW] = (TS)bload<TC>(ro, 0, j * (int)sizeof(TC));
             x[ROW + 1] = (TS)bload<TC>(ro, 0, (N + j) * (int)sizeof(TC));
         }
     };
 
-    // one cell: four stages, fields of the state at tau_n (stage-1 values), the update.
-    // FIRST (cell 0 only) applies the steady-inflow front condition of the test hook.
-    auto cell = [&](const int j, const TS (&x)[XW], auto first) __attribute__((always_inline)) {
-        constexpr bool FIRST = decltype(first)::value;
-        const bool last = (j == N - 1);
-        const TC Oc = FLAT ? om0 : (TC)x[ROW];
-        const TC Of = last ? (TC)0 : (FLAT ? om0 : (TC)x[ROW + 1]);
-        TC r0[NC], P0[NC], T0[NC], cTO[NC], cPO[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int t = NC >= 2 ? c / 2 : 0;
-            r0[c] = SCALE ? (TC)x[0 * NC + c] * scale[t] : (TC)x[0 * NC + c];
-            P0[c] = SCALE ? (TC)x[1 * NC + c] * scale[t] : (TC)x[1 * NC + c];
-            T0[c] = SCALE ? (TC)x[2 * NC + c] * scale[t] : (TC)x[2 * NC + c];
-            cTO[c] = cT[t] * Oc;
-            cPO[c] = cP[t] * Of;
-        }
-        TC dr[NC], dT[NC], dP[NC];   // A W_m at this cell
-        TC ncf0[NC], vcf0[NC];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const TC cm = (m == 1) ? c1 : (m == 2 ? c2 : c3);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const TC rm = (m == 0) ? r0[c] : r0[c] + cm * dr[c];
-                const TC Pm = (m == 0) ? P0[c] : P0[c] + cm * dP[c];
-                const TC Tm = (m == 0) ? T0[c] : T0[c] + cm * dT[c];
-                const double rd = (double)rm;
-                if (FIRST && steady) { y[m][c] = rd; v[m][c] = 0.0; }
-                double nc, yn, vn, vc;
-                if (RESTORING) {
-                    const double u = y[m][c] - rd;
-                    nc = rd + C2 * u + S2 * v[m][c];
-                    yn = rd + C1 * u + S1 * v[m][c];
-                    vn = C1 * v[m][c] - S1 * u;
-                    if (FIELDS && m == 0) vc = C2 * v[m][c] - S2 * u;
-                } else {
-                    nc = y[m][c] + 0.5 * h * v[m][c] + 0.125 * h * h * rd;
-                    yn = y[m][c] + h * v[m][c] + 0.5 * h * h * rd;
-                    vn = v[m][c] + h * rd;
-                    if (FIELDS && m == 0) vc = v[m][c] + 0.5 * h * rd;
-                }
-                y[m][c] = yn;
-                v[m][c] = vn;
-                if (FIELDS && m == 0) { ncf0[c] = (TC)nc; vcf0[c] = (TC)vc; }
-                dr[c] = (Pm - pp[m][c]) + Tm;
-                pp[m][c] = Pm;
-                dT[c] = cTO[c] * (TC)nc;
-                dP[c] = cPO[c] * (TC)vn;
-            }
-        }
-        if (FIELDS) {
-#pragma unroll
-            for (int t = 0; t < MPL; ++t) {
-                // |E_par|^2 = kappa^2 |n_p'|^2, |E_perp|^2 = k^2 kappa^2 |rho - n_p|^2,
-                // |B_perp|^2 = k^2 kappa^2 |rho|^2, summed over the two parts of the mode
-                TC e2, b2;
-                if (NC >= 2) {
-                    const int c0 = 2 * t, c1i = 2 * t + 1;
-                    const TC en = vcf0[c0] * vcf0[c0] + vcf0[c1i] * vcf0[c1i];
-                    const TC d0 = r0[c0] - ncf0[c0], d1 = r0[c1i] - ncf0[c1i];
-                    e2 = kap2[t] * en + k2kap2[t] * (d0 * d0 + d1 * d1);
-                    b2 = k2kap2[t] * (r0[c0] * r0[c0] + r0[c1i] * r0[c1i]);
-                } else {
-                    const TC d0 = r0[0] - ncf0[0];
-                    e2 = pair_sum(kap2[0] * vcf0[0] * vcf0[0] + k2kap2[0] * d0 * d0);
-                    b2 = pair_sum(k2kap2[0] * r0[0] * r0[0]);
-                }
-                const TC a2 = e2 + b2;
-                a2max[t] = a2 > a2max[t] ? a2 : a2max[t];
-                if (SNAP && writer && mloc[t] < I.n_modes) {
-                    const double sh = (double)L[t] * 0.69314718055994530942;
-                    const int64_t o = a.snap_base + I.snap_off + (int64_t)j * I.n_modes + mloc[t];
-                    static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(e2) + sh);
-                    static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
-                }
-            }
-        }
-        if (a.update) {
+    double y[4][NC], v[4][NC];  // oscillator carries per stage: n_p and d_xi n_p at the front face
+    TC pp[4][NC];               // stage inputs of P' at the front face of the current cell
+    TC scale[MPL], rmax[MPL], a2max[MPL];
+    (void)scale;
+
+    // One segment pass of one tau-step: all four stages per cell, the fields of the state at
+    // tau_n (stage-1 values) and the update.
+    auto pass = [&](const bool init_steady) __attribute__((always_inline)) {
+        auto cell = [&](const int j, const TS (&x)[XW], auto first) __attribute__((always_inline)) {
+            constexpr bool FIRST = decltype(first)::value;
+            const bool last = (j == N - 1);
+            const TC Oc = FLAT ? om0 : (TC)x[ROW];
+            const TC Of = last ? (TC)0 : (FLAT ? om0 : (TC)x[ROW + 1]);
+            TC r0[NC], P0[NC], T0[NC], cTO[NC], cPO[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int t = NC >= 2 ? c / 2 : 0;
-                const TS rn = (TS)(r0[c] + dt * dr[c]);
-                bstore(rn, rs, voff, (j * ROW + 0 * NC + c) * RB);
-                bstore((TS)(P0[c] + dt * dP[c]), rs, voff, (j * ROW + 1 * NC + c) * RB);
-                bstore((TS)(T0[c] + dt * dT[c]), rs, voff, (j * ROW + 2 * NC + c) * RB);
-                const TC ar = (TC)fabs((TC)rn);
-                rmax[t] = (ar > rmax[t] || !(ar <= ar)) ? ar : rmax[t];  // NaN sticks
+                r0[c] = (TC)x[0 * NC + c];
+                P0[c] = (TC)x[1 * NC + c];
+                T0[c] = (TC)x[2 * NC + c];
+                cTO[c] = cT[t] * Oc;
+                cPO[c] = cP[t] * Of;
             }
+            TC dr[NC], dT[NC], dP[NC];   // A W_m at this cell
+            TC ncf0[NC], vcf0[NC];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const TC cm = (m == 1) ? c1s : (m == 2 ? c2s : c3s);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const TC rm = (m == 0) ? r0[c] : r0[c] + cm * dr[c];
+                    const TC Pm = (m == 0) ? P0[c] : P0[c] + cm * dP[c];
+                    const TC Tm = (m == 0) ? T0[c] : T0[c] + cm * dT[c];
+                    const double rd = (double)rm;
+                    if (FIRST && init_steady) { y[m][c] = rd; v[m][c] = 0.0; }
+                    double nc, yn, vn, vc;
+                    if (RESTORING) {
+                        const double u = y[m][c] - rd;
+                        nc = rd + C2 * u + S2 * v[m][c];
+                        yn = rd + C1 * u + S1 * v[m][c];
+                        vn = C1 * v[m][c] - S1 * u;
+                        if (FIELDS && m == 0) vc = C2 * v[m][c] - S2 * u;
+                    } else {
+                        nc = y[m][c] + 0.5 * h * v[m][c] + 0.125 * h * h * rd;
+                        yn = y[m][c] + h * v[m][c] + 0.5 * h * h * rd;
+                        vn = v[m][c] + h * rd;
+                        if (FIELDS && m == 0) vc = v[m][c] + 0.5 * h * rd;
+                    }
+                    y[m][c] = yn;
+                    v[m][c] = vn;
+                    if (FIELDS && m == 0) { ncf0[c] = (TC)nc; vcf0[c] = (TC)vc; }
+                    dr[c] = (Pm - pp[m][c]) + Tm;
+                    pp[m][c] = Pm;
+                    dT[c] = cTO[c] * (TC)nc;
+                    dP[c] = cPO[c] * (TC)vn;
+                }
+            }
+            if (FIELDS) {
+#pragma unroll
+                for (int t = 0; t < MPL; ++t) {
+                    // |E_par|^2 = kappa^2 |n_p'|^2, |E_perp|^2 = k^2 kappa^2 |rho - n_p|^2,
+                    // |B_perp|^2 = k^2 kappa^2 |rho|^2, summed over the two parts of the mode
+                    TC e2, b2;
+                    if (NC >= 2) {
+                        const int ca = 2 * t, cb = 2 * t + 1;
+                        const TC en = vcf0[ca] * vcf0[ca] + vcf0[cb] * vcf0[cb];
+                        const TC d0 = r0[ca] - ncf0[ca], d1 = r0[cb] - ncf0[cb];
+                        e2 = kap2[t] * en + k2kap2[t] * (d0 * d0 + d1 * d1);
+                        b2 = k2kap2[t] * (r0[ca] * r0[ca] + r0[cb] * r0[cb]);
+                    } else {
+                        const TC d0 = r0[0] - ncf0[0];
+                        e2 = pair_sum(kap2[0] * vcf0[0] * vcf0[0] + k2kap2[0] * d0 * d0);
+                        b2 = pair_sum(k2kap2[0] * r0[0] * r0[0]);
+                    }
+                    const TC a2 = e2 + b2;
+                    a2max[t] = a2 > a2max[t] ? a2 : a2max[t];
+                    if (SNAP && writer && mloc[t] < I.n_modes) {
+                        const double sh = (double)L[t] * 0.69314718055994530942;
+                        const int64_t o = a.snap_base + I.snap_off + (int64_t)j * I.n_modes + mloc[t];
+                        static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(e2) + sh);
+                        static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
+                    }
+                }
+            }
+            if (a.update) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const int t = NC >= 2 ? c / 2 : 0;
+                    const TS rn = (TS)(r0[c] + dt * dr[c]);
+                    bstore(rn, rs, voff, (j * ROW + 0 * NC + c) * RB);
+                    bstore((TS)(P0[c] + dt * dP[c]), rs, voff, (j * ROW + 1 * NC + c) * RB);
+                    bstore((TS)(T0[c] + dt * dT[c]), rs, voff, (j * ROW + 2 * NC + c) * RB);
+                    const TC ar = (TC)fabs((TC)rn);
+                    rmax[t] = (ar > rmax[t] || !(ar <= ar)) ? ar : rmax[t];  // NaN sticks
+                }
+            }
+        };
+        // Cell c0 first (it may carry the front condition), then c0+1..c1-1 with a one-cell
+        // prefetch ping-ponged between two register sets, unrolled by two so that neither
+        // the buffers nor the carries need copies at the loop edge.  Loads past the end of
+        // the block's region are bounds-checked by the descriptor (0 returned, unused).
+        using first_t = std::integral_constant<bool, true>;
+        using rest_t = std::integral_constant<bool, false>;
+        TS xa[XW], xb[XW];
+        ldx(c0, xa);
+        ldx(c0 + 1, xb);
+        cell(c0, xa, first_t{});
+        int j = c0 + 1;
+        while (j < c1) {
+            ldx(j + 1, xa);
+            cell(j, xb, rest_t{});
+            ++j;
+            if (j >= c1) break;
+            ldx(j + 1, xb);
+            cell(j, xa, rest_t{});
+            ++j;
         }
     };
 
-    // Cell 0 first (front condition), then cells 1..N-1 with a one-cell-ahead prefetch
-    // ping-ponged between two register sets, unrolled by two so that neither the buffers
-    // nor the oscillator carries need copies at the loop edge.  Loads past the end of the
-    // block's region are bounds-checked by the buffer descriptor (they return 0, unused).
-    using first_t = std::integral_constant<bool, true>;
-    using rest_t = std::integral_constant<bool, false>;
-    TS xa[XW], xb[XW];
-    ldx(0, xa);
-    ldx(1, xb);
-    cell(0, xa, first_t{});
-    int j = 1;
-    while (j < N) {
-        ldx(j + 1, xa);
-        cell(j, xb, rest_t{});
-        ++j;
-        if (j >= N) break;
-        ldx(j + 1, xb);
-        cell(j, xa, rest_t{});
-        ++j;
-    }
-
     constexpr int R = RenormRange<TS>::R;
+    for (int n = 0; n < a.n_steps; ++n) {
+        // apply the pending renormalization of each (mode, segment); a fields-only launch
+        // (no update) reads the stored values with their current exponent
+        bool need = false;
 #pragma unroll
-    for (int t = 0; t < MPL; ++t) {
-        if (NC == 1) rmax[t] = pair_max(rmax[t]);
-        if (!writer || mloc[t] >= I.n_modes) continue;
-        if (FIELDS && a.max_ln_a) {
-            const double sh = (double)L[t] * 0.69314718055994530942;
-            static_cast<TS *>(a.max_ln_a)[a.max_base + I.mode0 + mloc[t]] =
-                (TS)(0.5 * (double)log(a2max[t]) + sh);
-        }
-        if (a.update) {
-            int e = 0;
-            const double mx = (double)rmax[t];
-            if (!isfinite(mx)) {
-                a.err[0] = 1u + (uint32_t)pm[t];
-            } else if (mx > 0.0 && (mx > ldexp(1.0, R) || mx < ldexp(1.0, -R))) {
-                (void)frexp(mx, &e);
+        for (int t = 0; t < MPL; ++t) {
+            if (a.update) {
+                L[t] += ep[t];
+                scale[t] = (TC)ldexp(1.0, -ep[t]);
+                need |= ep[t] != 0;
             }
-            a.log2s[pm[t]] = L[t];
-            a.epend[pm[t]] = e;
+            rmax[t] = (TC)0;
+            a2max[t] = (TC)0;
+        }
+        // carries at the segment's front face: zero at the beam front, else from wave-1
+        if (wave == 0) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) { y[m][c] = 0.0; v[m][c] = 0.0; pp[m][c] = (TC)0; }
+        } else {
+            if (!wait_flag(&ready[slot - 1], n + 1, abort, a.wait_ticks)) { a.err[1] = 1u; return; }
+            char *pl = payload + (slot - 1) * PL::BYTES;
+#pragma unroll
+            for (int t = 0; t < MPL; ++t) {
+                const int lp = PL::LL(pl)[t * kWave + lane];
+                const double f = ldexp(1.0, lp - L[t]);  // predecessor units -> ours (exact)
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int p = 0; p < (NC >= 2 ? 2 : 1); ++p) {
+                        const int c = NC >= 2 ? 2 * t + p : 0;
+                        y[m][c] = PL::Y(pl)[(m * NC + c) * kWave + lane] * f;
+                        v[m][c] = PL::V(pl)[(m * NC + c) * kWave + lane] * f;
+                        pp[m][c] = PL::PP(pl)[(m * NC + c) * kWave + lane] * (TC)f;
+                    }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) __hip_atomic_store(&taken[slot - 1], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        // a mode of this wave left the renormalization range: rescale the segment's stored
+        // state by its exact power of two first (rare; kept out of the hot pass)
+        if (__any(need) && a.update) {
+            for (int j = c0; j < c1; ++j)
+#pragma unroll
+                for (int r = 0; r < ROW; ++r) {
+                    const int t = NC >= 2 ? (r % NC) / 2 : 0;
+                    const int off = (j * ROW + r) * RB;
+                    bstore((TS)((TC)bload<TS>(rs, voff, off) * scale[t]), rs, voff, off);
+                }
+        }
+        pass(wave == 0 && steady);
+
+        // hand the carries at this segment's rear face to the next segment
+        if (has_next) {
+            if (!wait_flag(&taken[slot], n, abort, a.wait_ticks)) { a.err[1] = 1u; return; }
+            char *pl = payload + slot * PL::BYTES;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    PL::Y(pl)[(m * NC + c) * kWave + lane] = y[m][c];
+                    PL::V(pl)[(m * NC + c) * kWave + lane] = v[m][c];
+                    PL::PP(pl)[(m * NC + c) * kWave + lane] = pp[m][c];
+                }
+#pragma unroll
+            for (int t = 0; t < MPL; ++t) PL::LL(pl)[t * kWave + lane] = L[t];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) __hip_atomic_store(&ready[slot], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+
+#pragma unroll
+        for (int t = 0; t < MPL; ++t) {
+            if (NC == 1) rmax[t] = pair_max(rmax[t]);
+            if (FIELDS && a.max_ln_a && writer && mloc[t] < I.n_modes) {
+                const double sh = (double)L[t] * 0.69314718055994530942;
+                const TS val = (TS)(0.5 * (double)log(a2max[t]) + sh);
+                TS *dst = static_cast<TS *>(a.max_ln_a) + a.max_base + (int64_t)n * a.total_modes + I.mode0 + mloc[t];
+                if (a.keyed) atomic_max_key(dst, val);
+                else *dst = val;
+            }
+            int e = 0;
+            if (a.update) {
+                const double mx = (double)rmax[t];
+                if (!isfinite(mx)) {
+                    if (writer) a.err[0] = 1u + (uint32_t)(I.pmode0 + mloc[t]);
+                } else if (mx > 0.0 && (mx > ldexp(1.0, R) || mx < ldexp(1.0, -R))) {
+                    (void)frexp(mx, &e);
+                }
+            }
+            ep[t] = e;
+        }
+    }
+    if (a.update) {
+#pragma unroll
+        for (int t = 0; t < MPL; ++t) {
+            if (!writer) continue;
+            a.log2s[sidx[t]] = L[t];
+            a.epend[sidx[t]] = ep[t];
         }
     }
 }
 
-// FIELDS: compute the fields (max ln A per mode); SNAP: also write ln|E|, ln|B| per cell
-template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, bool SNAP, int TJ>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(QS_WAVES_PER_EU(TS, NC) - (SNAP ? 1 : 0))))
-step_kernel(StepArgs a) {
-    const int gb = blockIdx.x;
-    const int ii = a.blk_inst[gb];
-    const InstDev I = a.inst[ii];
-    const int b = gb - I.block0;
-    // the rescaling path runs only when a mode of this wave left the renormalization range
-    bool need = false;
-#pragma unroll
-    for (int t = 0; t < Cols<NC>::MPL; ++t)
-        need |= a.epend[I.pmode0 + Cols<NC>::mode(b, (int)threadIdx.x, t)] != 0;
-    const bool flat = (I.flags & kFlatProfile) != 0;
-    if (flat) {
-        if (__any(need)) step_body<TS, TC, NC, RESTORING, FIELDS, SNAP, TJ, true, true>(a, I, b);
-        else step_body<TS, TC, NC, RESTORING, FIELDS, SNAP, TJ, false, true>(a, I, b);
-    } else {
-        if (__any(need)) step_body<TS, TC, NC, RESTORING, FIELDS, SNAP, TJ, true, false>(a, I, b);
-        else step_body<TS, TC, NC, RESTORING, FIELDS, SNAP, TJ, false, false>(a, I, b);
+template <typename TS>
+__global__ void __launch_bounds__(256) key_fill(TS *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const auto k = fkey((TS)-INFINITY);
+        p[i] = __builtin_bit_cast(TS, k);
+    }
+}
+template <typename TS>
+__global__ void __launch_bounds__(256) key_decode(TS *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        using K = decltype(fkey((TS)0));
+        p[i] = funkey(__builtin_bit_cast(K, p[i]));
     }
 }
 
 template <typename TS, typename TC, int NC, bool RESTORING>
-hipError_t launch_step_r(bool fields, bool snap, int n_blocks, const StepArgs &a, hipStream_t s) {
-    constexpr int TJ = QS_STEP_TJ;
-    dim3 grid(n_blocks), block(kWave);
-    if (snap) hipLaunchKernelGGL((step_kernel<TS, TC, NC, RESTORING, true, true, TJ>), grid, block, 0, s, a);
-    else if (fields) hipLaunchKernelGGL((step_kernel<TS, TC, NC, RESTORING, true, false, TJ>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((step_kernel<TS, TC, NC, RESTORING, false, false, TJ>), grid, block, 0, s, a);
+hipError_t launch_march_r(bool fields, bool snap, bool flat, int n_wg, int wg_waves, bool segmented,
+                          const StepArgs &a, hipStream_t s) {
+    dim3 grid(n_wg), block(kWave * wg_waves);
+    const size_t lds = march_lds_bytes(sizeof(TS) == 8 ? QS_FP64 : QS_FP32, NC, wg_waves, segmented);
+#define QS_LAUNCH(F, S, FL) hipLaunchKernelGGL((march_kernel<TS, TC, NC, RESTORING, F, S, FL>), grid, block, lds, s, a)
+    if (flat) {
+        if (snap) QS_LAUNCH(true, true, true);
+        else if (fields) QS_LAUNCH(true, false, true);
+        else QS_LAUNCH(false, false, true);
+    } else {
+        if (snap) QS_LAUNCH(true, true, false);
+        else if (fields) QS_LAUNCH(true, false, false);
+        else QS_LAUNCH(false, false, false);
+    }
+#undef QS_LAUNCH
     return hipGetLastError();
 }
 
 template <typename TS, typename TC, int NC>
-hipError_t launch_step_t(bool restoring, bool fields, bool snap, int n_blocks, const StepArgs &a, hipStream_t s) {
-    if (restoring) return launch_step_r<TS, TC, NC, true>(fields, snap, n_blocks, a, s);
-    return launch_step_r<TS, TC, NC, false>(fields, snap, n_blocks, a, s);
+hipError_t launch_march_t(bool restoring, bool fields, bool snap, bool flat, int n_wg, int wg_waves,
+                          bool segmented, const StepArgs &a, hipStream_t s) {
+    if (restoring) return launch_march_r<TS, TC, NC, true>(fields, snap, flat, n_wg, wg_waves, segmented, a, s);
+    return launch_march_r<TS, TC, NC, false>(fields, snap, flat, n_wg, wg_waves, segmented, a, s);
 }
 
 template <typename TS, int NC>
@@ -424,15 +586,92 @@ hipError_t launch_seed_t(int n_blocks, int max_n_xi, const SeedArgs &a, hipStrea
 
 }  // namespace
 
-hipError_t launch_step(int precision, int nc, bool restoring, bool fields, int n_blocks,
-                       const StepArgs &a, hipStream_t s) {
+size_t march_lds_bytes(int precision, int nc, int wg_waves, bool segmented) {
+    if (!segmented) return kFlagInts * sizeof(int);  // no hand-offs: the flags only
+    size_t pay;
+    if (precision == QS_FP64) pay = nc == 1 ? Payload<double, 1>::BYTES : Payload<double, 2>::BYTES;
+    else pay = nc == 1 ? Payload<float, 1>::BYTES : Payload<float, 2>::BYTES;
+    return kFlagInts * sizeof(int) + (size_t)(wg_waves - 1) * pay;
+}
+
+hipError_t launch_march(int precision, int nc, bool restoring, bool fields, bool flat, int n_wg,
+                        int wg_waves, bool segmented, const StepArgs &a, hipStream_t s) {
     const bool snap = a.ln_e != nullptr;
+    if (wg_waves < 1 || wg_waves > march_wg_waves(precision, nc)) return hipErrorInvalidConfiguration;
     if (precision == QS_FP64) {
-        if (nc == 1) return launch_step_t<double, double, 1>(restoring, fields, snap, n_blocks, a, s);
-        return launch_step_t<double, double, 2>(restoring, fields, snap, n_blocks, a, s);
+        if (nc == 1) return launch_march_t<double, double, 1>(restoring, fields, snap, flat, n_wg, wg_waves, segmented, a, s);
+        return launch_march_t<double, double, 2>(restoring, fields, snap, flat, n_wg, wg_waves, segmented, a, s);
     }
-    if (nc == 1) return launch_step_t<float, float, 1>(restoring, fields, snap, n_blocks, a, s);
-    return launch_step_t<float, float, 2>(restoring, fields, snap, n_blocks, a, s);
+    if (nc == 1) return launch_march_t<float, float, 1>(restoring, fields, snap, flat, n_wg, wg_waves, segmented, a, s);
+    return launch_march_t<float, float, 2>(restoring, fields, snap, flat, n_wg, wg_waves, segmented, a, s);
+}
+
+int march_wgs_per_cu(int precision, int nc, bool restoring, bool flat, int wg_waves, bool segmented) {
+    // occupancy of the variant that steps with per-step maxima (fields, no snapshot)
+    const size_t lds = march_lds_bytes(precision, nc, wg_waves, segmented);
+    const void *f = nullptr;
+#define QS_PICK(TS, TC, NCc)                                                                          \
+    f = restoring ? (flat ? reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, true, true, false, true>)   \
+                          : reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, true, true, false, false>)) \
+                  : (flat ? reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, false, true, false, true>)  \
+                          : reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, false, true, false, false>));
+    if (precision == QS_FP64) {
+        if (nc == 1) { QS_PICK(double, double, 1) } else { QS_PICK(double, double, 2) }
+    } else {
+        if (nc == 1) { QS_PICK(float, float, 1) } else { QS_PICK(float, float, 2) }
+    }
+#undef QS_PICK
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kWave * wg_waves, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    return n;
+}
+
+hipError_t allow_march_lds(int precision, int nc, size_t bytes) {
+    // kernels that need more than the default dynamic LDS must opt in
+#define QS_ALLOW(TS, TC, NCc, R, F, S, FL) \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, R, F, S, FL>), \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
+    if (e != hipSuccess) return e;
+#define QS_ALLOW_ALL(TS, TC, NCc) \
+    QS_ALLOW(TS, TC, NCc, true, true, true, true) QS_ALLOW(TS, TC, NCc, true, true, false, true) \
+    QS_ALLOW(TS, TC, NCc, true, false, false, true) QS_ALLOW(TS, TC, NCc, true, true, true, false) \
+    QS_ALLOW(TS, TC, NCc, true, true, false, false) QS_ALLOW(TS, TC, NCc, true, false, false, false) \
+    QS_ALLOW(TS, TC, NCc, false, true, true, true) QS_ALLOW(TS, TC, NCc, false, true, false, true) \
+    QS_ALLOW(TS, TC, NCc, false, false, false, true) QS_ALLOW(TS, TC, NCc, false, true, true, false) \
+    QS_ALLOW(TS, TC, NCc, false, true, false, false) QS_ALLOW(TS, TC, NCc, false, false, false, false)
+    hipError_t e = hipSuccess;
+    if (precision == QS_FP64) {
+        if (nc == 1) { QS_ALLOW_ALL(double, double, 1) } else { QS_ALLOW_ALL(double, double, 2) }
+    } else {
+        if (nc == 1) { QS_ALLOW_ALL(float, float, 1) } else { QS_ALLOW_ALL(float, float, 2) }
+    }
+#undef QS_ALLOW_ALL
+#undef QS_ALLOW
+    return e;
+}
+
+hipError_t launch_key_fill(int precision, void *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (precision == QS_FP64) hipLaunchKernelGGL(key_fill<double>, grid, block, 0, s, static_cast<double *>(p), n);
+    else hipLaunchKernelGGL(key_fill<float>, grid, block, 0, s, static_cast<float *>(p), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_decode(int precision, void *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (precision == QS_FP64) hipLaunchKernelGGL(key_decode<double>, grid, block, 0, s, static_cast<double *>(p), n);
+    else hipLaunchKernelGGL(key_decode<float>, grid, block, 0, s, static_cast<float *>(p), n);
+    return hipGetLastError();
 }
 
 hipError_t launch_seed(int precision, int nc, int n_blocks, int max_n_xi, const SeedArgs &a,

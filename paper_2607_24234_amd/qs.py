@@ -57,6 +57,13 @@ class QSParams(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+class QSPlan(ctypes.Structure):
+    _fields_ = [("columns_per_lane", ctypes.c_int32),
+                ("segment_cells", ctypes.c_int32),
+                ("max_segments", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class QSError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("libqs status %d: %s" % (status, msg))
@@ -65,7 +72,8 @@ class QSError(RuntimeError):
 
 _lib = None
 
-EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_init", "qs_step_tau",
+EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace_size_ex", "qs_init",
+           "qs_init_ex", "qs_get_plan", "qs_step_tau",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint"]
 
@@ -87,6 +95,13 @@ def lib():
     L.qs_workspace_size.argtypes = [P, ctypes.c_int32]
     L.qs_init.restype = ctypes.c_int
     L.qs_init.argtypes = [P, ctypes.c_int32, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    PP = ctypes.POINTER(QSPlan)
+    L.qs_workspace_size_ex.restype = ctypes.c_size_t
+    L.qs_workspace_size_ex.argtypes = [P, ctypes.c_int32, PP]
+    L.qs_init_ex.restype = ctypes.c_int
+    L.qs_init_ex.argtypes = [P, ctypes.c_int32, PP, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.qs_get_plan.restype = ctypes.c_int
+    L.qs_get_plan.argtypes = [vp, PP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     L.qs_step_tau.restype = ctypes.c_int
     L.qs_step_tau.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.qs_sync_check.restype = ctypes.c_int
@@ -157,10 +172,17 @@ class _Instance:
         self.n_xi = p.n_xi
 
 
-def workspace_size(instances, precision=QS_FP32):
+def _plan(columns_per_lane=0, segment_cells=0):
+    if not columns_per_lane and not segment_cells:
+        return None
+    return QSPlan(int(columns_per_lane), int(segment_cells), 0, 0)
+
+
+def workspace_size(instances, precision=QS_FP32, columns_per_lane=0, segment_cells=0):
     insts = [_Instance(i, precision) for i in instances]
     arr = (QSParams * len(insts))(*[x.p for x in insts])
-    return int(lib().qs_workspace_size(arr, len(insts)))
+    pl = _plan(columns_per_lane, segment_cells)
+    return int(lib().qs_workspace_size_ex(arr, len(insts), ctypes.byref(pl) if pl else None))
 
 
 class Solver:
@@ -168,9 +190,11 @@ class Solver:
 
     instances: list of dicts as produced by ``paper_2607_24234_amd.inputs`` (keys species,
     gamma, length, n_xi, kx, ky, d_tau, seed_kind, seed_amp, rng_seed, flags, ...).
+    columns_per_lane / segment_cells: launch plan overrides (0 = the library's choice).
     """
 
-    def __init__(self, instances, precision=QS_FP32, device=None, stream=None):
+    def __init__(self, instances, precision=QS_FP32, device=None, stream=None, columns_per_lane=0,
+                 segment_cells=0):
         import torch
         if isinstance(instances, dict):
             instances = [instances]
@@ -180,9 +204,11 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self._insts = [_Instance(i, precision) for i in instances]
         self._params = (QSParams * len(self._insts))(*[x.p for x in self._insts])
-        nbytes = int(L.qs_workspace_size(self._params, len(self._insts)))
+        self._plan = _plan(columns_per_lane, segment_cells)
+        pp = ctypes.byref(self._plan) if self._plan else None
+        nbytes = int(L.qs_workspace_size_ex(self._params, len(self._insts), pp))
         if nbytes == 0:
-            _check(L.qs_init(self._params, len(self._insts), None, None, 0, ctypes.byref(ctypes.c_void_p())))
+            _check(L.qs_init_ex(self._params, len(self._insts), pp, None, None, 0, ctypes.byref(ctypes.c_void_p())))
         self.n_modes = [x.n_modes for x in self._insts]
         self.n_xi = [x.n_xi for x in self._insts]
         self.total_modes = sum(self.n_modes)
@@ -193,9 +219,18 @@ class Solver:
             # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             ctx = ctypes.c_void_p()
-            _check(L.qs_init(self._params, len(self._insts), ctypes.c_void_p(self.stream.cuda_stream),
-                             ctypes.c_void_p(self.workspace.data_ptr()), nbytes, ctypes.byref(ctx)))
+            _check(L.qs_init_ex(self._params, len(self._insts), pp, ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.c_void_p(self.workspace.data_ptr()), nbytes, ctypes.byref(ctx)))
         self.ctx = ctx
+
+    def plan(self):
+        """Launch plan the library chose: dict columns_per_lane, segment_cells, max_segments,
+        workgroups, waves_per_workgroup."""
+        p = QSPlan()
+        nwg, wpw = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qs_get_plan(self.ctx, ctypes.byref(p), ctypes.byref(nwg), ctypes.byref(wpw)))
+        return {"columns_per_lane": p.columns_per_lane, "segment_cells": p.segment_cells,
+                "max_segments": p.max_segments, "workgroups": nwg.value, "waves_per_workgroup": wpw.value}
 
     # -------------------------------------------------------------- stepping
     def step(self, n_steps, out_every=1, snapshots=False, max_ln_a=False, out=None):

@@ -1,0 +1,149 @@
+"""GPU parity of the batched, xi-segmented launch (many instances in one persistent kernel,
+each 64-lane block of modes split into xi-segments that pass the oscillator carries to each
+other) against the FP64 oracle, and against the unsegmented launch.
+
+Bars as for the single-instance path: FP64 |d ln| <= 1e-9, FP32 |d ln A| <= 1e-4.
+"""
+import numpy as np
+import pytest
+
+from helpers import ln_compare, mode_k, oracle_beam, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-9
+FP32_TOL = 1e-4
+
+
+def _slab(**kw):
+    from paper_2607_24234_amd import inputs
+    d = inputs.slab()
+    d.update(kw)
+    return d
+
+
+def _views(s, out, i):
+    return (s.snapshot_view(out["ln_e"], i).cpu().numpy(), s.snapshot_view(out["ln_b"], i).cpu().numpy())
+
+
+@pytest.mark.parametrize("precision,amp", [(0, 3e6), (1, 3e29)])
+@pytest.mark.parametrize("seg", [1, 7, 37, 299])
+def test_segmented_matches_oracle(qs, precision, amp, seg):
+    """One instance split into segments of `seg` cells (ragged last segment; the segment count
+    is capped by the workgroup size), seeded next to the top of the renormalization range so
+    that segments of one mode change scale at different steps."""
+    inst = _slab(n_xi=300, length=30.0, kx=np.linspace(0.05, 4.0, 45), seed_amp=amp, d_tau=40.0)
+    s = qs.Solver([inst], precision=precision, segment_cells=seg)
+    pl = s.plan()
+    cap = 16 if precision == qs.QS_FP32 else 8
+    assert pl["max_segments"] == min(cap, -(-300 // seg))
+    n = 24
+    out = s.step(n, out_every=4, snapshots=True, max_ln_a=True)
+    fin = s.step(0, snapshots=True)
+    s.sync_check()
+    ln_e, ln_b, mx, st = oracle_run(inst, n, out_every=4)
+    tol = FP64_TOL if precision == qs.QS_FP64 else FP32_TOL
+    ge, gb = _views(s, out, 0)
+    ln_compare(ge, ln_e, tol, what="seg ln E")
+    ln_compare(gb, ln_b, tol, what="seg ln B")
+    ln_compare(out["max_ln_a"].cpu().numpy(), mx, tol, what="seg max ln A")
+    import oracle as O
+    fe, fb, _ = O.run(oracle_beam(inst), mode_k(inst), inst["d_tau"], 0, st)
+    ln_compare(_views(s, fin, 0)[0], fe, tol, what="seg final ln E")
+    # the canonical state agrees with the oracle's (per-segment scales folded in exactly)
+    cs = s.get_state()[0]
+    beam = oracle_beam(inst)
+    for m in (0, 22, 44):
+        rho, _, _ = O.collapse(beam, st, m)
+        g = cs["rho"][m] * 2.0 ** cs["log2_scale"][m]
+        assert np.max(np.abs(g - rho)) <= (1e-9 if precision == qs.QS_FP64 else 1e-4) * np.max(np.abs(rho))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_segmented_equals_unsegmented(qs, precision):
+    """The segmented launch reproduces the unsegmented one: the scales are exact powers of
+    two, so the arithmetic is the same up to the rounding of the log shift."""
+    inst = _slab(n_xi=200, length=25.0, kx=np.linspace(0.1, 3.0, 40), d_tau=30.0)
+    a = qs.Solver([inst], precision=precision, segment_cells=1 << 20)
+    b = qs.Solver([inst], precision=precision, segment_cells=13)
+    assert a.plan()["max_segments"] == 1 and b.plan()["max_segments"] > 1
+    ra = a.step(20, out_every=5, snapshots=True, max_ln_a=True)
+    rb = b.step(20, out_every=5, snapshots=True, max_ln_a=True)
+    tol = 1e-12 if precision == qs.QS_FP64 else 2e-6
+    for key in ("ln_e", "ln_b", "max_ln_a"):
+        x, y = ra[key].cpu().numpy(), rb[key].cpu().numpy()
+        assert np.array_equal(np.isfinite(x), np.isfinite(y))
+        f = np.isfinite(x)
+        assert np.max(np.abs(x[f] - y[f])) <= tol, key
+    a.sync_check()
+    b.sync_check()
+
+
+def test_segmented_deterministic(qs):
+    """Per-step maxima of a mode's segments combine by integer atomic max of order-preserving
+    keys, so repeated runs are bitwise equal."""
+    from paper_2607_24234_amd import inputs
+    insts = inputs.batched(n_instances=12, n_modes=40, n_steps=8, max_cells=700)
+    r = []
+    for _ in range(2):
+        s = qs.Solver(insts, precision=qs.QS_FP32, segment_cells=50)
+        r.append(s.step(8, out_every=4, snapshots=True, max_ln_a=True))
+        s.sync_check()
+    for key in ("ln_e", "ln_b", "max_ln_a"):
+        assert np.array_equal(r[0][key].cpu().numpy(), r[1][key].cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_auto_plan_matches_oracle(qs, precision):
+    """The batched sweep at reduced size (24 instances x 70 modes, 128..900 cells) with the
+    automatic plan: instances with one and with many segments share one launch."""
+    from paper_2607_24234_amd import inputs
+    n_steps = 12
+    insts = inputs.batched(n_instances=24, n_modes=70, n_steps=n_steps, max_cells=900)
+    s = qs.Solver(insts, precision=precision)
+    out = s.step(n_steps, out_every=6, snapshots=True, max_ln_a=True)
+    s.sync_check()
+    mx_all = out["max_ln_a"].cpu().numpy()
+    tol = FP64_TOL if precision == qs.QS_FP64 else FP32_TOL
+    for i in range(0, 24, 3):
+        ln_e, ln_b, mx, _ = oracle_run(insts[i], n_steps, out_every=6, instance=i)
+        ge, gb = _views(s, out, i)
+        ln_compare(ge, ln_e, tol, what="batched e %d" % i)
+        ln_compare(gb, ln_b, tol, what="batched b %d" % i)
+        ln_compare(mx_all[:, 70 * i:70 * (i + 1)], mx, tol, what="batched max %d" % i)
+
+
+def test_batched_full_size_sampled(qs):
+    """The batched sweep at full size (256 instances x 128 modes, 128..8192 cells, 200
+    steps, FP32 state) in the automatic plan; sampled (instance, mode) pairs against the
+    oracle, every step's max ln A."""
+    import torch
+    from paper_2607_24234_amd import inputs
+    insts = inputs.batched()
+    assert len(insts) == 256 and min(i["n_xi"] for i in insts) >= 128 and max(i["n_xi"] for i in insts) <= 8192
+    s = qs.Solver(insts, precision=qs.QS_FP32)
+    assert s.plan()["max_segments"] > 1
+    n_steps = insts[0]["n_steps"]
+    out = s.step(n_steps, max_ln_a=True)
+    torch.cuda.synchronize()
+    s.sync_check()
+    mx_all = out["max_ln_a"].cpu().numpy()
+    assert np.all(np.isfinite(mx_all))
+    lens = np.array([i["n_xi"] for i in insts])
+    pick = sorted({int(np.argmax(lens)), int(np.argmin(lens)), 0, 97, 200})
+    for i in pick:
+        modes = np.array([0, 1, 63, 127])
+        _, _, mx, _ = oracle_run(insts[i], n_steps, modes=modes, instance=i, n_threads=4)
+        ln_compare(mx_all[:, 128 * i + modes], mx, FP32_TOL, what="batched full max %d" % i)
+
+
+def test_plan_arguments(qs):
+    inst = _slab(n_xi=64, kx=np.array([1.0]))
+    with pytest.raises(qs.QSError):
+        qs.Solver([inst], precision=qs.QS_FP32, columns_per_lane=3)
+    with pytest.raises(qs.QSError):
+        qs.Solver([inst], precision=qs.QS_FP32, segment_cells=-1)
+    for nc in (1, 2):
+        s = qs.Solver([inst], precision=qs.QS_FP32, columns_per_lane=nc, segment_cells=16)
+        p = s.plan()
+        assert p["columns_per_lane"] == nc and p["max_segments"] == 4 and p["workgroups"] == 1
