@@ -265,6 +265,41 @@ size_t qs_checkpoint_size(const qs_ctx *ctx);
 qs_status qs_save_checkpoint(qs_ctx *ctx, void *dst, size_t bytes);
 qs_status qs_load_checkpoint(qs_ctx *ctx, const void *src, size_t bytes);
 
+/*
+ * Autotuner (library design choice, not physics): time candidate execution plans for these
+ * instances on the current device and return the fastest for calls of steps_per_call tau-
+ * steps that output the per-step maxima.  Candidates: columns_per_lane 1 and 2, each with
+ * 1, 2, 3, 4, 6, 8, 12 or 16 xi-segments (as many as the workgroup holds) and the automatic
+ * plan.  Each is initialized on a scratch workspace that qs_tune allocates (hipMalloc) and
+ * frees before returning, and timed: directly for steps_per_call <= 40, else as calls of 8
+ * and 40 steps fitted to a + b n (a segmented plan pays a pipeline fill once per call) and
+ * evaluated at n = steps_per_call.  With QS_TUNE_VERBOSE set, each candidate's time is
+ * printed to stderr.  If
+ * the environment variable QS_TUNE_CACHE names a file, a result for the same parameters
+ * (seed excluded), steps_per_call and device is taken from it instead of timing, and new
+ * results are appended to it.
+ *   best        : receives columns_per_lane and segment_cells (pass it to qs_init_ex).
+ *   ms_per_step : optional; the projected time per tau-step of the chosen plan.
+ * Synchronizes the device.  Errors: QS_ERR_ARG (as qs_init), QS_ERR_ALLOC, QS_ERR_HIP.
+ */
+qs_status qs_tune(const qs_params *params, int32_t n_instances, int32_t steps_per_call,
+                  qs_plan *best, double *ms_per_step);
+
+/*
+ * Captured step sequences: qs_graph_create records the kernel launches of one
+ * qs_step_tau(ctx, n_steps, out_every, out_ln_e, out_ln_b, out_max_ln_a) call (same
+ * arguments and meaning) into a HIP graph without running them; qs_graph_launch replays it
+ * on the context's stream, advancing the state by n_steps each time and writing the same
+ * output buffers.  The graph holds only kernel nodes (no memset or copy nodes).  The output
+ * pointers must stay valid while the graph exists; the graph must be freed before its
+ * context.  Errors: QS_ERR_ARG (as qs_step_tau; n_steps >= 1), QS_ERR_HIP.
+ */
+typedef struct qs_graph qs_graph;
+qs_status qs_graph_create(qs_ctx *ctx, int32_t n_steps, int32_t out_every, void *out_ln_e,
+                          void *out_ln_b, void *out_max_ln_a, qs_graph **out);
+qs_status qs_graph_launch(qs_graph *graph);
+void qs_graph_free(qs_graph *graph);
+
 /* Release the context and anything the library allocated for it.  NULL is ignored. */
 void qs_free(qs_ctx *ctx);
 

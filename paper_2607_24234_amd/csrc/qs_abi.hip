@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -819,6 +820,233 @@ void qs_free(qs_ctx *c) {
         (void)hipFree(c->ws);
     }
     delete c;
+}
+
+// ----------------------------------------------------------------------------- autotuner
+}  // extern "C"
+
+namespace {
+
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 0x100000001B3ull; }
+    return h;
+}
+template <typename T> uint64_t fnv_v(uint64_t h, const T &v) { return fnv(h, &v, sizeof(v)); }
+
+// Key of a tuning result: everything that changes the work or its shape (not the seed).
+uint64_t tune_key(const qs_params *p, int n, int steps) {
+    uint64_t h = 0xCBF29CE484222325ull;
+    h = fnv_v(h, n);
+    h = fnv_v(h, steps);
+    for (int i = 0; i < n; ++i) {
+        const qs_params &q = p[i];
+        h = fnv_v(h, q.n_species);
+        h = fnv(h, q.q, sizeof(double) * q.n_species);
+        h = fnv(h, q.m, sizeof(double) * q.n_species);
+        h = fnv(h, q.nb_over_np, sizeof(double) * q.n_species);
+        h = fnv_v(h, q.gamma_b); h = fnv_v(h, q.length); h = fnv_v(h, q.profile);
+        h = fnv_v(h, q.n_xi); h = fnv_v(h, q.d_tau); h = fnv_v(h, q.precision);
+        h = fnv_v(h, q.flags); h = fnv_v(h, q.n_modes);
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        h = fnv(h, prop.gcnArchName, std::strlen(prop.gcnArchName));
+        h = fnv_v(h, prop.multiProcessorCount);
+    }
+    (void)hipGetLastError();
+    return h;
+}
+
+bool cache_lookup(const char *path, uint64_t key, qs_plan *plan, double *ms) {
+    FILE *f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return false;
+    unsigned long long k;
+    int nc, seg;
+    double t;
+    bool hit = false;
+    while (std::fscanf(f, "%llx %d %d %lf", &k, &nc, &seg, &t) == 4) {
+        if (k == key) { plan->columns_per_lane = nc; plan->segment_cells = seg; *ms = t; hit = true; }
+    }
+    std::fclose(f);
+    return hit;
+}
+
+void cache_store(const char *path, uint64_t key, const qs_plan &plan, double ms) {
+    FILE *f = path ? std::fopen(path, "a") : nullptr;
+    if (!f) return;
+    std::fprintf(f, "%016llx %d %d %.17g\n", (unsigned long long)key, plan.columns_per_lane, plan.segment_cells, ms);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_tune(const qs_params *params, int32_t n_instances, int32_t steps_per_call, qs_plan *best,
+                  double *ms_per_step) {
+    g_err.clear();
+    if (!best) return fail(QS_ERR_ARG, "best is NULL");
+    if (steps_per_call < 1) return fail(QS_ERR_ARG, "steps_per_call must be >= 1");
+    Plan base;
+    qs_status st = make_plan(params, n_instances, nullptr, base);
+    if (st != QS_OK) return st;
+    const char *cache = std::getenv("QS_TUNE_CACHE");
+    const uint64_t key = tune_key(params, n_instances, steps_per_call);
+    double cached_ms = 0.0;
+    qs_plan hit{};
+    if (cache_lookup(cache, key, &hit, &cached_ms)) {
+        *best = hit;
+        best->max_segments = 0;
+        best->reserved = 0;
+        if (ms_per_step) *ms_per_step = cached_ms;
+        return QS_OK;
+    }
+    // candidates: columns per lane x segment counts the workgroup allows, plus the automatic
+    // plan of each column count
+    struct Cand { qs_plan plan; Plan pl; };
+    std::vector<Cand> cands;
+    for (int nc = 1; nc <= 2; ++nc) {
+        const int Wmax = march_wg_waves(base.precision, nc);
+        std::vector<int> segs = {0};
+        for (int div : {1, 2, 3, 4, 6, 8, 12, 16})
+            if (div <= Wmax) segs.push_back(div == 1 ? (1 << 20) : (base.max_n_xi + div - 1) / div);
+        for (int seg : segs) {
+            Cand c;
+            c.plan = qs_plan{nc, seg, 0, 0};
+            if (make_plan(params, n_instances, &c.plan, c.pl) != QS_OK) continue;
+            c.plan.segment_cells = c.pl.seg_target;
+            bool dup = false;
+            for (const Cand &o : cands)
+                dup = dup || (o.pl.nc == c.pl.nc && o.pl.wave_table.size() == c.pl.wave_table.size() &&
+                              o.pl.seg_target == c.pl.seg_target && o.pl.wg_waves == c.pl.wg_waves);
+            if (!dup) cands.push_back(std::move(c));
+        }
+    }
+    size_t ws_bytes = 0;
+    for (const Cand &c : cands) ws_bytes = std::max(ws_bytes, c.pl.total);
+    // a call of n steps costs a + b n (a: launch and, for segmented plans, the pipeline
+    // fill); measured directly for short calls, else fitted from calls of 8 and 40 steps
+    const int T1 = 8, T2 = 40;
+    const bool direct = steps_per_call <= T2;
+    const int T = direct ? steps_per_call : T2;
+    const size_t out_bytes = (size_t)T * base.total_modes * base.ts;
+    void *ws = nullptr, *outb = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (ws) (void)hipFree(ws);
+        if (outb) (void)hipFree(outb);
+    };
+    if (hipMalloc(&ws, ws_bytes) != hipSuccess || hipMalloc(&outb, out_bytes) != hipSuccess) {
+        cleanup();
+        return fail(QS_ERR_ALLOC, "autotuner: hipMalloc failed");
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(QS_ERR_HIP, "autotuner: hipEventCreate failed");
+    }
+    double best_t = 1e300;
+    qs_plan best_plan{};
+    const bool verbose = std::getenv("QS_TUNE_VERBOSE") != nullptr;
+    for (Cand &c : cands) {
+        qs_ctx *ctx = nullptr;
+        if (qs_init_ex(params, n_instances, &c.plan, nullptr, ws, ws_bytes, &ctx) != QS_OK) continue;
+        auto timed = [&](int steps, float *ms) {
+            return hipEventRecord(e0, nullptr) == hipSuccess &&
+                   qs_step_tau(ctx, steps, 1, nullptr, nullptr, outb) == QS_OK &&
+                   hipEventRecord(e1, nullptr) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                   hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+        };
+        float m1 = 0.f, m2 = 0.f;
+        bool ok = qs_step_tau(ctx, 2, 1, nullptr, nullptr, outb) == QS_OK && timed(T, &m2);
+        if (ok && !direct) ok = timed(T1, &m1);
+        ok = ok && qs_sync_check(ctx) == QS_OK;
+        qs_free(ctx);
+        if (!ok) continue;
+        double per = (double)m2 / T;
+        if (!direct) {
+            const double b = std::max(0.0, (double)(m2 - m1) / (T2 - T1));
+            const double a0 = std::max(0.0, (double)m1 - T1 * b);
+            per = (a0 + b * steps_per_call) / steps_per_call;
+        }
+        if (verbose)
+            std::fprintf(stderr, "qs_tune: columns_per_lane %d segment_cells %d (segments %d, waves/workgroup %d): "
+                                 "%.4f ms per step\n", c.pl.nc, c.pl.seg_target, c.pl.max_seg, c.pl.wg_waves, per);
+        if (per < best_t) { best_t = per; best_plan = c.plan; }
+    }
+    cleanup();
+    (void)hipGetLastError();
+    if (best_t >= 1e300) return fail(QS_ERR_HIP, "autotuner: no candidate plan ran");
+    best_plan.max_segments = 0;
+    best_plan.reserved = 0;
+    *best = best_plan;
+    if (ms_per_step) *ms_per_step = best_t;
+    cache_store(cache, key, best_plan, best_t);
+    return QS_OK;
+}
+
+// ----------------------------------------------------------------------------- graphs
+struct qs_graph {
+    qs_ctx *ctx = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t n_steps = 0;
+};
+
+qs_status qs_graph_create(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_ln_e, void *out_ln_b,
+                          void *out_max_ln_a, qs_graph **out) {
+    if (!c || !out) return fail(QS_ERR_ARG, "ctx and out are required");
+    if (n_steps < 1) return fail(QS_ERR_ARG, "n_steps must be >= 1");
+    *out = nullptr;
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    // capture the launches of one qs_step_tau call on a private stream (the context's own
+    // stream may be the null stream, which cannot be captured)
+    hipStream_t cap = nullptr;
+    QS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "create capture stream");
+    hipStream_t keep = c->stream;
+    const int64_t done = c->steps_done;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    qs_status st = QS_OK;
+    if (e == hipSuccess) {
+        c->stream = cap;
+        st = qs_step_tau(c, n_steps, out_every, out_ln_e, out_ln_b, out_max_ln_a);
+        c->stream = keep;
+        c->steps_done = done;  // nothing ran
+        e = hipStreamEndCapture(cap, &g);
+    }
+    std::string msg = g_err;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess && st == QS_OK) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (st != QS_OK) return fail(st, msg);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    qs_graph *q = new (std::nothrow) qs_graph;
+    if (!q) { (void)hipGraphExecDestroy(exec); return fail(QS_ERR_ALLOC, "host allocation failed"); }
+    q->ctx = c;
+    q->exec = exec;
+    q->n_steps = n_steps;
+    *out = q;
+    return QS_OK;
+}
+
+qs_status qs_graph_launch(qs_graph *g) {
+    if (!g) return fail(QS_ERR_ARG, "graph is NULL");
+    QS_HIP(hipSetDevice(g->ctx->device), "hipSetDevice");
+    QS_HIP(hipGraphLaunch(g->exec, g->ctx->stream), "graph launch");
+    g->ctx->steps_done += g->n_steps;
+    return QS_OK;
+}
+
+void qs_graph_free(qs_graph *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    (void)hipGraphExecDestroy(g->exec);
+    delete g;
 }
 
 // Host evaluation of the device's SplitMix64 (used by the generator cross-check tests).

@@ -73,7 +73,8 @@ class QSError(RuntimeError):
 _lib = None
 
 EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace_size_ex", "qs_init",
-           "qs_init_ex", "qs_get_plan", "qs_step_tau",
+           "qs_init_ex", "qs_get_plan", "qs_tune", "qs_graph_create", "qs_graph_launch", "qs_graph_free",
+           "qs_step_tau",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint"]
 
@@ -102,6 +103,14 @@ def lib():
     L.qs_init_ex.argtypes = [P, ctypes.c_int32, PP, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     L.qs_get_plan.restype = ctypes.c_int
     L.qs_get_plan.argtypes = [vp, PP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.qs_tune.restype = ctypes.c_int
+    L.qs_tune.argtypes = [P, ctypes.c_int32, ctypes.c_int32, PP, ctypes.POINTER(ctypes.c_double)]
+    L.qs_graph_create.restype = ctypes.c_int
+    L.qs_graph_create.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, ctypes.POINTER(vp)]
+    L.qs_graph_launch.restype = ctypes.c_int
+    L.qs_graph_launch.argtypes = [vp]
+    L.qs_graph_free.restype = None
+    L.qs_graph_free.argtypes = [vp]
     L.qs_step_tau.restype = ctypes.c_int
     L.qs_step_tau.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.qs_sync_check.restype = ctypes.c_int
@@ -183,6 +192,54 @@ def workspace_size(instances, precision=QS_FP32, columns_per_lane=0, segment_cel
     arr = (QSParams * len(insts))(*[x.p for x in insts])
     pl = _plan(columns_per_lane, segment_cells)
     return int(lib().qs_workspace_size_ex(arr, len(insts), ctypes.byref(pl) if pl else None))
+
+
+def tune(instances, precision=QS_FP32, steps_per_call=100):
+    """Autotuned launch plan for these instances (qs_tune): dict with columns_per_lane,
+    segment_cells and ms_per_step; pass the first two to Solver."""
+    insts = [_Instance(i, precision) for i in instances]
+    arr = (QSParams * len(insts))(*[x.p for x in insts])
+    best = QSPlan()
+    ms = ctypes.c_double()
+    _check(lib().qs_tune(arr, len(insts), int(steps_per_call), ctypes.byref(best), ctypes.byref(ms)))
+    return {"columns_per_lane": best.columns_per_lane, "segment_cells": best.segment_cells,
+            "ms_per_step": ms.value}
+
+
+class Graph:
+    """A captured qs_step_tau call (qs_graph_create); replay() advances the solver by
+    n_steps and rewrites the same output tensors."""
+
+    def __init__(self, solver, n_steps, out_every=1, snapshots=False, max_ln_a=False):
+        t = solver.torch
+        self.solver = solver
+        self.out = {}
+        if snapshots:
+            n_snap = -(-n_steps // max(1, out_every))
+            self.out["ln_e"] = t.empty((n_snap, solver.snap_elems), dtype=solver.dtype, device=solver.device)
+            self.out["ln_b"] = t.empty((n_snap, solver.snap_elems), dtype=solver.dtype, device=solver.device)
+        if max_ln_a:
+            self.out["max_ln_a"] = t.empty((n_steps, solver.total_modes), dtype=solver.dtype, device=solver.device)
+        ptr = lambda k: ctypes.c_void_p(self.out[k].data_ptr()) if k in self.out else None
+        g = ctypes.c_void_p()
+        _check(lib().qs_graph_create(solver.ctx, int(n_steps), int(max(1, out_every)), ptr("ln_e"), ptr("ln_b"),
+                                     ptr("max_ln_a"), ctypes.byref(g)))
+        self.g = g
+
+    def replay(self):
+        _check(lib().qs_graph_launch(self.g))
+        return self.out
+
+    def close(self):
+        if getattr(self, "g", None) is not None and self.g.value:
+            lib().qs_graph_free(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Solver:

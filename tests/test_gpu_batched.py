@@ -147,3 +147,46 @@ def test_plan_arguments(qs):
         s = qs.Solver([inst], precision=qs.QS_FP32, columns_per_lane=nc, segment_cells=16)
         p = s.plan()
         assert p["columns_per_lane"] == nc and p["max_segments"] == 4 and p["workgroups"] == 1
+
+
+def test_graph_replays_match_eager(qs):
+    """A captured 7-step call replayed three times, with eager work and synchronizations in
+    between, gives bitwise the outputs of three eager 7-step calls."""
+    import torch
+    from paper_2607_24234_amd import inputs
+    insts = inputs.batched(n_instances=6, n_modes=40, n_steps=21, max_cells=400)
+    a = qs.Solver(insts, precision=qs.QS_FP32, segment_cells=60)
+    b = qs.Solver(insts, precision=qs.QS_FP32, segment_cells=60)
+    g = qs.Graph(b, 7, out_every=3, snapshots=True, max_ln_a=True)
+    for rep in range(3):
+        ra = a.step(7, out_every=3, snapshots=True, max_ln_a=True)
+        rb = g.replay()
+        torch.cuda.synchronize()
+        for key in ("ln_e", "ln_b", "max_ln_a"):
+            assert np.array_equal(ra[key].cpu().numpy(), rb[key].cpu().numpy()), (rep, key)
+        x = torch.randn(1000, device="cuda").sum()  # unrelated eager work between replays
+        assert torch.isfinite(x)
+    assert b.steps_done == 21
+    b.sync_check()
+    g.close()
+
+
+def test_tuner_and_cache(qs, tmp_path, monkeypatch):
+    from paper_2607_24234_amd import inputs
+    insts = inputs.batched(n_instances=10, n_modes=70, n_steps=20, max_cells=1500)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("QS_TUNE_CACHE", str(cache))
+    t1 = qs.tune(insts, qs.QS_FP32, steps_per_call=20)
+    assert t1["columns_per_lane"] in (1, 2) and t1["segment_cells"] > 0 and t1["ms_per_step"] > 0
+    assert len(cache.read_text().splitlines()) == 1
+    t2 = qs.tune(insts, qs.QS_FP32, steps_per_call=20)
+    assert t2 == t1 and len(cache.read_text().splitlines()) == 1  # served from the cache
+    # the tuned plan is a valid plan: parity against the oracle on two instances
+    s = qs.Solver(insts, precision=qs.QS_FP32, columns_per_lane=t1["columns_per_lane"],
+                  segment_cells=t1["segment_cells"])
+    out = s.step(20, max_ln_a=True)
+    s.sync_check()
+    mx_all = out["max_ln_a"].cpu().numpy()
+    for i in (0, 7):
+        _, _, mx, _ = oracle_run(insts[i], 20, instance=i)
+        ln_compare(mx_all[:, 70 * i:70 * (i + 1)], mx, FP32_TOL, what="tuned %d" % i)
