@@ -22,6 +22,12 @@ qs_status fail(qs_status st, const std::string &msg) {
     return st;
 }
 
+}  // namespace
+
+void set_last_error(const std::string &msg) { g_err = msg; }
+
+namespace {
+
 qs_status hip_fail(hipError_t e, const char *what) {
     return fail(QS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }

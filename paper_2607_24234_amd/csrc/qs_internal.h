@@ -91,6 +91,9 @@ hipError_t launch_key_decode(int precision, void *p, int64_t n, hipStream_t s);
 hipError_t launch_seed(int precision, int nc, int n_blocks, int max_n_xi, const SeedArgs &a,
                        hipStream_t s);
 
+// text returned by qs_last_error on this thread
+void set_last_error(const std::string &msg);
+
 // host helper mirroring the device SplitMix64 (exported for the generator tests)
 uint64_t splitmix64_host(uint64_t seed, uint64_t i);
 

@@ -1,0 +1,660 @@
+// Growth-map surrogate network (include/qs_mlp.h): 5 -> 512 x4 -> 1 MLP with exact GELU,
+// MSE loss and AdamW, for gfx950.
+//
+// The three 512 x 512 layers and their backward products are one kernel, gemm_nt:
+// C[M][N] = A[M][K] B[N][K]^T with bfloat16 operands (both K-contiguous) on the matrix cores
+// (v_mfma_f32_32x32x16_bf16, float32 accumulation), 128 x 128 tiles per workgroup of four
+// waves, each wave 64 x 64 (2 x 2 MFMA tiles), operands read as 16-byte fragments.  The
+// three uses differ only in operands and epilogue:
+//   forward      z = h W^T + b             A = h [rows][in],      B = W [out][in]
+//   input grad   dh = dz W                 A = dz [rows][out],    B = W^T [in][out]
+//   weight grad  dW = dz^T h (split over rows) A = dz^T [out][rows], B = h^T [in][rows]
+// so the forward pass also stores h^T and the backward pass dz^T (bfloat16) for the weight
+// gradients.  The first layer (5 inputs) and the last (1 output) are float32 VALU kernels.
+// Reductions over rows (bias and first/last-layer weight gradients, the loss) write
+// per-tile partial sums that a second kernel adds in a fixed order: the gradients are
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qs_mlp.h"
+#include "qs_internal.h"
+
+namespace {
+
+constexpr int D = 512;   // hidden width
+constexpr int DIN = 5;   // inputs
+constexpr int kWave = 64;
+
+// flat parameter layout
+constexpr int64_t OFF_W1 = 0;
+constexpr int64_t OFF_B1 = OFF_W1 + (int64_t)D * DIN;
+constexpr int64_t OFF_W2 = OFF_B1 + D;
+constexpr int64_t OFF_B2 = OFF_W2 + (int64_t)D * D;
+constexpr int64_t OFF_W3 = OFF_B2 + D;
+constexpr int64_t OFF_B3 = OFF_W3 + (int64_t)D * D;
+constexpr int64_t OFF_W4 = OFF_B3 + D;
+constexpr int64_t OFF_B4 = OFF_W4 + (int64_t)D * D;
+constexpr int64_t OFF_W5 = OFF_B4 + D;
+constexpr int64_t OFF_B5 = OFF_W5 + D;
+constexpr int64_t N_PARAMS = OFF_B5 + 1;
+// W2..W4 and b2..b4 are evenly spaced
+__host__ __device__ constexpr int64_t off_w(int l) { return OFF_W2 + (int64_t)l * (OFF_W3 - OFF_W2); }
+__host__ __device__ constexpr int64_t off_b(int l) { return OFF_B2 + (int64_t)l * (OFF_W3 - OFF_W2); }
+static_assert(off_w(2) == OFF_W4 && off_b(2) == OFF_B4, "layer spacing");
+
+using bf16_t = uint16_t;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+
+// float32 -> bfloat16, round to nearest, ties to even (NaN kept quiet)
+__device__ __forceinline__ bf16_t f2bf(float x) {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (bf16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+// exact GELU x Phi(x) and its derivative Phi(x) + x phi(x)
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_d(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// ----------------------------------------------------------------------------- layer 1
+// z1 = W1 x + b1 for a tile of 64 rows x 64 outputs per 256 threads: thread t owns output
+// o0 + t%64 and 16 consecutive rows, so both h (row-major) and h^T rows are contiguous.
+__global__ void __launch_bounds__(256) l1_fwd(const float *__restrict__ x, int64_t n_valid, const float *__restrict__ P,
+                                              float *__restrict__ z, bf16_t *__restrict__ h, bf16_t *__restrict__ hT,
+                                              int64_t ldT) {
+    const int o = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int64_t r0 = (int64_t)blockIdx.y * 64 + 16 * (threadIdx.x >> 6);
+    float w[DIN];
+#pragma unroll
+    for (int i = 0; i < DIN; ++i) w[i] = P[OFF_W1 + (int64_t)o * DIN + i];
+    const float b = P[OFF_B1 + o];
+    bf16_t col[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t m = r0 + r;
+        float s = b;
+        if (m < n_valid) {
+#pragma unroll
+            for (int i = 0; i < DIN; ++i) s += w[i] * x[m * DIN + i];
+        }
+        if (z) z[m * D + o] = s;
+        const bf16_t hb = f2bf(gelu(s));
+        h[m * D + o] = hb;
+        col[r] = hb;
+    }
+    if (hT) {
+        uint4 *dst = reinterpret_cast<uint4 *>(hT + (int64_t)o * ldT + r0);
+        uint32_t p[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) p[q] = (uint32_t)col[2 * q] | ((uint32_t)col[2 * q + 1] << 16);
+        dst[0] = make_uint4(p[0], p[1], p[2], p[3]);
+        dst[1] = make_uint4(p[4], p[5], p[6], p[7]);
+    }
+}
+
+// dW1[o][i] = sum_m dz1[m][o] x[m][i] and db1[o] = sum_m dz1[m][o]: partial sums per tile of
+// 64 rows, part[tile][o][6]
+__global__ void __launch_bounds__(256) l1_wgrad(const float *__restrict__ dz1, const float *__restrict__ x,
+                                                float *__restrict__ part) {
+    __shared__ float red[4][64][DIN + 1];
+    const int ol = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + ol;
+    const int64_t r0 = (int64_t)blockIdx.y * 64 + 16 * g;
+    float acc[DIN + 1] = {};
+    for (int r = 0; r < 16; ++r) {
+        const int64_t m = r0 + r;
+        const float d = dz1[m * D + o];
+#pragma unroll
+        for (int i = 0; i < DIN; ++i) acc[i] += d * x[m * DIN + i];
+        acc[DIN] += d;
+    }
+#pragma unroll
+    for (int i = 0; i <= DIN; ++i) red[g][ol][i] = acc[i];
+    __syncthreads();
+    if (g == 0) {
+#pragma unroll
+        for (int i = 0; i <= DIN; ++i)
+            part[((int64_t)blockIdx.y * D + o) * (DIN + 1) + i] = ((red[0][ol][i] + red[1][ol][i]) + red[2][ol][i]) + red[3][ol][i];
+    }
+}
+
+// ----------------------------------------------------------------------------- layer 5
+// y[m] = W5 . h4[m] + b5: one wave per row (8 bfloat16 per lane); with targets also
+// dy[m] = 2 (y - t)/batch and per-block partials of sum (y - t)^2 and sum dy.
+__global__ void __launch_bounds__(256) l5_fwd(const bf16_t *__restrict__ h4, const float *__restrict__ P,
+                                              int64_t n_valid, float *__restrict__ y, const float *__restrict__ t,
+                                              float inv_batch2, float *__restrict__ dy, float *__restrict__ lossp) {
+    __shared__ float sl[4], sd[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t m = (int64_t)blockIdx.x * 4 + wv;
+    const uint4 v = *reinterpret_cast<const uint4 *>(h4 + m * D + 8 * lane);
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        s += bf2f((bf16_t)(u[q] & 0xFFFFu)) * P[OFF_W5 + 8 * lane + 2 * q];
+        s += bf2f((bf16_t)(u[q] >> 16)) * P[OFF_W5 + 8 * lane + 2 * q + 1];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    s += P[OFF_B5];
+    float e2 = 0.f, d = 0.f;
+    if (lane == 0) {
+        if (m < n_valid) y[m] = s;
+        if (t) {
+            const float e = s - t[m];
+            d = e * inv_batch2;
+            dy[m] = d;
+            e2 = e * e;
+        }
+    }
+    if (t) {
+        if (lane == 0) { sl[wv] = e2; sd[wv] = d; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            lossp[2 * blockIdx.x] = ((sl[0] + sl[1]) + sl[2]) + sl[3];
+            lossp[2 * blockIdx.x + 1] = ((sd[0] + sd[1]) + sd[2]) + sd[3];
+        }
+    }
+}
+
+// dz4 = (dy W5) * GELU'(z4), stored as bfloat16 (row-major and transposed); partials per
+// 64-row tile of db4 = sum dz4 (colpart) and dW5 = sum dy h4 (w5part)
+__global__ void __launch_bounds__(256) l5_bwd(const float *__restrict__ dy, const float *__restrict__ P,
+                                              const float *__restrict__ z4, const bf16_t *__restrict__ h4,
+                                              bf16_t *__restrict__ dzb, bf16_t *__restrict__ dzT, int64_t ldT,
+                                              float *__restrict__ colpart, float *__restrict__ w5part) {
+    __shared__ float red[2][4][64];
+    const int ol = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + ol;
+    const int64_t r0 = (int64_t)blockIdx.y * 64 + 16 * g;
+    const float w = P[OFF_W5 + o];
+    bf16_t col[16];
+    float sb = 0.f, sw = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t m = r0 + r;
+        const float dyv = dy[m];
+        const float d = dyv * w * gelu_d(z4[m * D + o]);
+        const bf16_t b = f2bf(d);
+        dzb[m * D + o] = b;
+        col[r] = b;
+        sb += d;
+        sw += dyv * bf2f(h4[m * D + o]);
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(dzT + (int64_t)o * ldT + r0);
+    uint32_t p[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) p[q] = (uint32_t)col[2 * q] | ((uint32_t)col[2 * q + 1] << 16);
+    dst[0] = make_uint4(p[0], p[1], p[2], p[3]);
+    dst[1] = make_uint4(p[4], p[5], p[6], p[7]);
+    red[0][g][ol] = sb;
+    red[1][g][ol] = sw;
+    __syncthreads();
+    if (g == 0) {
+        colpart[(int64_t)blockIdx.y * D + o] = ((red[0][0][ol] + red[0][1][ol]) + red[0][2][ol]) + red[0][3][ol];
+        w5part[(int64_t)blockIdx.y * D + o] = ((red[1][0][ol] + red[1][1][ol]) + red[1][2][ol]) + red[1][3][ol];
+    }
+}
+
+// ----------------------------------------------------------------------------- gemm_nt
+enum Epi { EPI_FWD = 0, EPI_BWD = 1, EPI_PART = 2 };
+
+struct GemmArgs {
+    const bf16_t *A;
+    int64_t lda;
+    const bf16_t *B;
+    int64_t ldb;
+    int64_t k_len;        // reduction length per split (multiple of 16)
+    int64_t M, N;         // C extent (multiples of 128)
+    // EPI_FWD
+    const float *bias;    // [N]
+    float *z;             // [M][N] or null
+    bf16_t *h;            // [M][N]
+    bf16_t *hT;           // [N][ldT] or null
+    int64_t ldT;
+    // EPI_BWD
+    const float *zprev;   // [M][N]
+    float *dzf;           // [M][N] float32 or null
+    bf16_t *dzb;          // [M][N] or null
+    bf16_t *dzT;          // [N][ldT] or null
+    float *colpart;       // [M/64][N] or null
+    // EPI_PART
+    float *part;          // [split][M][N]
+};
+
+__device__ __forceinline__ bf16x8 frag(const bf16_t *p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256) gemm_nt(GemmArgs g) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int wm = wv >> 1, wn = wv & 1;
+    const int64_t m0 = (int64_t)blockIdx.y * 128 + 64 * wm;
+    const int64_t n0 = (int64_t)blockIdx.x * 128 + 64 * wn;
+    const int64_t kb = (int64_t)blockIdx.z * g.k_len;
+    const int lr = lane & 31, lk = 8 * (lane >> 5);
+    const bf16_t *pa0 = g.A + (m0 + lr) * g.lda + kb + lk;
+    const bf16_t *pa1 = pa0 + 32 * g.lda;
+    const bf16_t *pb0 = g.B + (n0 + lr) * g.ldb + kb + lk;
+    const bf16_t *pb1 = pb0 + 32 * g.ldb;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    bf16x8 a0 = frag(pa0), a1 = frag(pa1), b0 = frag(pb0), b1 = frag(pb1);
+    for (int64_t k = 16; k < g.k_len; k += 16) {
+        const bf16x8 na0 = frag(pa0 + k), na1 = frag(pa1 + k), nb0 = frag(pb0 + k), nb1 = frag(pb1 + k);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        a0 = na0; a1 = na1; b0 = nb0; b1 = nb1;
+    }
+    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+
+    // result element r of lane: row 8(r/4) + 4(lane/32) + r%4, column lane%32 of each tile
+    const int rb = 4 * (lane >> 5);
+    float csum[2] = {0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t n = n0 + 32 * j + lr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t mq = m0 + 32 * i + 8 * q + rb;  // four consecutive rows mq..mq+3
+                bf16_t t4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t m = mq + e;
+                    const float v = acc[i][j][4 * q + e];
+                    if (EPI == EPI_FWD) {
+                        const float zz = v + g.bias[n];
+                        if (g.z) g.z[m * g.N + n] = zz;
+                        const bf16_t hb = f2bf(gelu(zz));
+                        g.h[m * g.N + n] = hb;
+                        t4[e] = hb;
+                    } else if (EPI == EPI_BWD) {
+                        const float d = v * gelu_d(g.zprev[m * g.N + n]);
+                        if (g.dzf) g.dzf[m * g.N + n] = d;
+                        const bf16_t db = f2bf(d);
+                        if (g.dzb) g.dzb[m * g.N + n] = db;
+                        t4[e] = db;
+                        csum[j] += d;
+                    } else {
+                        g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = v;
+                        t4[e] = 0;
+                    }
+                }
+                bf16_t *tr = EPI == EPI_FWD ? g.hT : (EPI == EPI_BWD ? g.dzT : nullptr);
+                if (tr) {
+                    const uint2 pk = make_uint2((uint32_t)t4[0] | ((uint32_t)t4[1] << 16),
+                                                (uint32_t)t4[2] | ((uint32_t)t4[3] << 16));
+                    *reinterpret_cast<uint2 *>(tr + n * g.ldT + mq) = pk;
+                }
+            }
+        }
+    if (EPI == EPI_BWD && g.colpart) {
+        // this wave's 64 rows: lanes l and l + 32 hold the two halves of each column
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float s = csum[j] + __shfl_xor(csum[j], 32);
+            if (lane < 32) g.colpart[((m0 >> 6)) * g.N + n0 + 32 * j + lr] = s;
+        }
+    }
+}
+
+// out[i] = sum_{s < S} part[s * stride + i * step] (fixed order)
+__global__ void __launch_bounds__(256) reduce_parts(const float *__restrict__ part, int S, int64_t stride,
+                                                    int64_t count, int64_t step, float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int k = 0; k < S; ++k) s += part[(int64_t)k * stride + i * step];
+    out[i] = s;
+}
+
+// first-layer partials [tiles][o][6] -> dW1 [o][5], db1 [o]
+__global__ void __launch_bounds__(256) reduce_l1(const float *__restrict__ part, int tiles, float *__restrict__ G) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= D * (DIN + 1)) return;
+    const int o = i / (DIN + 1), c = i % (DIN + 1);
+    float s = 0.f;
+    for (int k = 0; k < tiles; ++k) s += part[((int64_t)k * D + o) * (DIN + 1) + c];
+    if (c < DIN) G[OFF_W1 + (int64_t)o * DIN + c] = s;
+    else G[OFF_B1 + o] = s;
+}
+
+// sum over blocks of the (loss, dy) partial pairs -> db5 (device) ; loss is read by the host
+__global__ void reduce_db5(const float *__restrict__ lossp, int blocks, float *__restrict__ G, float *__restrict__ loss_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float sl = 0.f, sd = 0.f;
+    for (int b = 0; b < blocks; ++b) { sl += lossp[2 * b]; sd += lossp[2 * b + 1]; }
+    G[OFF_B5] = sd;
+    loss_out[0] = sl;
+}
+
+// ----------------------------------------------------------------------------- optimizer
+__global__ void __launch_bounds__(256) adamw(float *__restrict__ w, const float *__restrict__ gr, float *__restrict__ m,
+                                             float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                                             float wd, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * g;
+    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] = w[i] - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * w[i]);
+}
+
+// bfloat16 copies of W2..W4 ([out][in]) and their transposes ([in][out])
+__global__ void __launch_bounds__(256) convert_weights(const float *__restrict__ P, bf16_t *__restrict__ Wb,
+                                                       bf16_t *__restrict__ WTb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * (int64_t)D * D) return;
+    const int l = (int)(i / ((int64_t)D * D));
+    const int64_t e = i % ((int64_t)D * D);
+    const int o = (int)(e / D), in = (int)(e % D);
+    const bf16_t b = f2bf(P[off_w(l) + e]);
+    Wb[(int64_t)l * D * D + e] = b;
+    WTb[(int64_t)l * D * D + (int64_t)in * D + o] = b;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- host
+struct qs_mlp {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int32_t max_batch = 0;
+    int64_t t = 0;          // AdamW steps taken
+    void *mem = nullptr;    // one allocation for everything below
+    float *P, *G, *Mo, *Vo;
+    bf16_t *Wb, *WTb;       // [3][D][D]
+    float *z[4];            // [B][D]
+    bf16_t *h[4];           // [B][D]
+    bf16_t *hT[3];          // [D][B]
+    bf16_t *dzb[2], *dzT[2];
+    float *dz1, *y, *dy;
+    float *part;            // split-K partials [16][D][D]
+    float *colpart;         // [B/64][D]
+    float *w5part;          // [B/64][D]
+    float *l1part;          // [B/64][D][6]
+    float *lossp;           // [B/4][2]
+    float *loss;            // [1]
+};
+
+namespace {
+
+qs_status mfail(qs_status st, const std::string &m) {
+    qs::set_last_error(m);
+    return st;
+}
+#define MLP_HIP(call, what)                                                                  \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) return mfail(QS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t mlp_bytes(int64_t B, std::vector<size_t> *offs) {
+    std::vector<size_t> sz = {
+        (size_t)N_PARAMS * 4, (size_t)N_PARAMS * 4, (size_t)N_PARAMS * 4, (size_t)N_PARAMS * 4,
+        (size_t)3 * D * D * 2, (size_t)3 * D * D * 2};
+    for (int i = 0; i < 4; ++i) sz.push_back((size_t)B * D * 4);   // z
+    for (int i = 0; i < 4; ++i) sz.push_back((size_t)B * D * 2);   // h
+    for (int i = 0; i < 3; ++i) sz.push_back((size_t)B * D * 2);   // hT
+    for (int i = 0; i < 4; ++i) sz.push_back((size_t)B * D * 2);   // dzb[2], dzT[2]
+    sz.push_back((size_t)B * D * 4);                                 // dz1
+    sz.push_back((size_t)B * 4);                                     // y
+    sz.push_back((size_t)B * 4);                                     // dy
+    sz.push_back((size_t)16 * D * D * 4);                            // part
+    sz.push_back((size_t)(B / 64) * D * 4);                          // colpart
+    sz.push_back((size_t)(B / 64) * D * 4);                          // w5part
+    sz.push_back((size_t)(B / 64) * D * (DIN + 1) * 4);              // l1part
+    sz.push_back((size_t)(B / 4) * 2 * 4);                           // lossp
+    sz.push_back(256);                                               // loss
+    size_t o = 0;
+    offs->clear();
+    for (size_t s : sz) {
+        offs->push_back(o);
+        o += (s + 255) / 256 * 256;
+    }
+    return o;
+}
+
+void gemm_launch(int epi, const GemmArgs &a, int splits, hipStream_t s) {
+    dim3 grid((unsigned)(a.N / 128), (unsigned)(a.M / 128), (unsigned)splits), block(256);
+    if (epi == EPI_FWD) hipLaunchKernelGGL(gemm_nt<EPI_FWD>, grid, block, 0, s, a);
+    else if (epi == EPI_BWD) hipLaunchKernelGGL(gemm_nt<EPI_BWD>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(gemm_nt<EPI_PART>, grid, block, 0, s, a);
+}
+
+// forward pass over `rows` (multiple of 128) rows; training stores z and the transposes
+void forward_rows(qs_mlp *c, const float *x, int64_t rows, int64_t n_valid, bool train, float *y,
+                  const float *t, float inv_batch2) {
+    hipStream_t s = c->stream;
+    const int64_t ldT = c->max_batch;
+    bf16_t *hin[4] = {c->h[0], c->h[1], c->h[2], c->h[3]};
+    if (!train) { hin[2] = c->h[0]; hin[3] = c->h[1]; }  // inference ping-pongs two buffers
+    hipLaunchKernelGGL(l1_fwd, dim3(D / 64, (unsigned)(rows / 64)), dim3(256), 0, s, x, n_valid, c->P,
+                       train ? c->z[0] : nullptr, hin[0], train ? c->hT[0] : nullptr, ldT);
+    for (int l = 0; l < 3; ++l) {
+        GemmArgs a{};
+        a.A = hin[l]; a.lda = D;
+        a.B = c->Wb + (int64_t)l * D * D; a.ldb = D;
+        a.k_len = D; a.M = rows; a.N = D;
+        a.bias = c->P + off_b(l);
+        a.z = train ? c->z[l + 1] : nullptr;
+        a.h = hin[l + 1];
+        a.hT = (train && l < 2) ? c->hT[l + 1] : nullptr;
+        a.ldT = ldT;
+        gemm_launch(EPI_FWD, a, 1, s);
+    }
+    hipLaunchKernelGGL(l5_fwd, dim3((unsigned)(rows / 4)), dim3(256), 0, s, hin[3], c->P, n_valid, y, t,
+                       inv_batch2, c->dy, c->lossp);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t qs_mlp_param_count(void) { return N_PARAMS; }
+
+qs_status qs_mlp_create(int32_t max_batch, void *hip_stream, qs_mlp **out) {
+    if (!out) return mfail(QS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_batch < 128 || max_batch % 128 != 0 || max_batch > (1 << 20))
+        return mfail(QS_ERR_ARG, "max_batch must be a positive multiple of 128, at most 2^20");
+    qs_mlp *c = new (std::nothrow) qs_mlp;
+    if (!c) return mfail(QS_ERR_ALLOC, "host allocation failed");
+    c->max_batch = max_batch;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return mfail(QS_ERR_HIP, "hipGetDevice failed"); }
+    std::vector<size_t> o;
+    const size_t bytes = mlp_bytes(max_batch, &o);
+    if (hipMalloc(&c->mem, bytes) != hipSuccess) { delete c; return mfail(QS_ERR_ALLOC, "hipMalloc of the network buffers failed"); }
+    char *b = static_cast<char *>(c->mem);
+    int k = 0;
+    c->P = (float *)(b + o[k++]); c->G = (float *)(b + o[k++]); c->Mo = (float *)(b + o[k++]); c->Vo = (float *)(b + o[k++]);
+    c->Wb = (bf16_t *)(b + o[k++]); c->WTb = (bf16_t *)(b + o[k++]);
+    for (int i = 0; i < 4; ++i) c->z[i] = (float *)(b + o[k++]);
+    for (int i = 0; i < 4; ++i) c->h[i] = (bf16_t *)(b + o[k++]);
+    for (int i = 0; i < 3; ++i) c->hT[i] = (bf16_t *)(b + o[k++]);
+    c->dzb[0] = (bf16_t *)(b + o[k++]); c->dzb[1] = (bf16_t *)(b + o[k++]);
+    c->dzT[0] = (bf16_t *)(b + o[k++]); c->dzT[1] = (bf16_t *)(b + o[k++]);
+    c->dz1 = (float *)(b + o[k++]); c->y = (float *)(b + o[k++]); c->dy = (float *)(b + o[k++]);
+    c->part = (float *)(b + o[k++]); c->colpart = (float *)(b + o[k++]); c->w5part = (float *)(b + o[k++]);
+    c->l1part = (float *)(b + o[k++]); c->lossp = (float *)(b + o[k++]); c->loss = (float *)(b + o[k++]);
+    hipError_t e = hipMemsetAsync(c->mem, 0, bytes, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { (void)hipFree(c->mem); delete c; return mfail(QS_ERR_HIP, "clearing the network buffers failed"); }
+    *out = c;
+    return QS_OK;
+}
+
+qs_status qs_mlp_set_params(qs_mlp *c, const float *host) {
+    if (!c || !host) return mfail(QS_ERR_ARG, "net and params are required");
+    MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
+    MLP_HIP(hipMemcpyAsync(c->P, host, N_PARAMS * 4, hipMemcpyHostToDevice, c->stream), "copy params");
+    MLP_HIP(hipMemsetAsync(c->Mo, 0, N_PARAMS * 4, c->stream), "clear moments");
+    MLP_HIP(hipMemsetAsync(c->Vo, 0, N_PARAMS * 4, c->stream), "clear moments");
+    hipLaunchKernelGGL(convert_weights, dim3((unsigned)((3 * D * D + 255) / 256)), dim3(256), 0, c->stream, c->P, c->Wb,
+                       c->WTb);
+    MLP_HIP(hipGetLastError(), "convert weights");
+    MLP_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    c->t = 0;
+    return QS_OK;
+}
+
+qs_status qs_mlp_get_params(qs_mlp *c, float *host) {
+    if (!c || !host) return mfail(QS_ERR_ARG, "net and params are required");
+    MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
+    MLP_HIP(hipMemcpyAsync(host, c->P, N_PARAMS * 4, hipMemcpyDeviceToHost, c->stream), "copy params");
+    MLP_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return QS_OK;
+}
+
+qs_status qs_mlp_get_grads(qs_mlp *c, float *host) {
+    if (!c || !host) return mfail(QS_ERR_ARG, "net and grads are required");
+    MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
+    MLP_HIP(hipMemcpyAsync(host, c->G, N_PARAMS * 4, hipMemcpyDeviceToHost, c->stream), "copy grads");
+    MLP_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return QS_OK;
+}
+
+qs_status qs_mlp_set_grads(qs_mlp *c, const float *host) {
+    if (!c || !host) return mfail(QS_ERR_ARG, "net and grads are required");
+    MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
+    MLP_HIP(hipMemcpyAsync(c->G, host, N_PARAMS * 4, hipMemcpyHostToDevice, c->stream), "copy grads");
+    MLP_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return QS_OK;
+}
+
+qs_status qs_mlp_forward(qs_mlp *c, const float *x, int64_t n, float *y) {
+    if (!c) return mfail(QS_ERR_ARG, "net is NULL");
+    if (n < 0) return mfail(QS_ERR_ARG, "n must be >= 0");
+    if (n > 0 && (!x || !y)) return mfail(QS_ERR_ARG, "x and y are required");
+    MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
+    for (int64_t r0 = 0; r0 < n; r0 += c->max_batch) {
+        const int64_t valid = std::min<int64_t>(c->max_batch, n - r0);
+        const int64_t rows = (valid + 127) / 128 * 128;
+        forward_rows(c, x + r0 * DIN, rows, valid, false, y + r0, nullptr, 0.f);
+    }
+    MLP_HIP(hipGetLastError(), "forward kernels");
+    return QS_OK;
+}
+
+qs_status qs_mlp_grads(qs_mlp *c, const float *x, const float *t, int32_t batch, double *loss) {
+    if (!c || !x || !t) return mfail(QS_ERR_ARG, "net, x and t are required");
+    if (batch < 128 || batch % 128 != 0 || batch > c->max_batch)
+        return mfail(QS_ERR_ARG, "batch must be a positive multiple of 128 and <= max_batch");
+    MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t s = c->stream;
+    const int64_t B = batch, ldT = c->max_batch, tiles = B / 64;
+    forward_rows(c, x, B, B, true, c->y, t, 2.0f / (float)B);
+    // last layer
+    hipLaunchKernelGGL(l5_bwd, dim3(D / 64, (unsigned)tiles), dim3(256), 0, s, c->dy, c->P, c->z[3], c->h[3],
+                       c->dzb[0], c->dzT[0], ldT, c->colpart, c->w5part);
+    hipLaunchKernelGGL(reduce_parts, dim3(2), dim3(256), 0, s, c->colpart, (int)tiles, (int64_t)D, (int64_t)D,
+                       (int64_t)1, c->G + OFF_B4);
+    hipLaunchKernelGGL(reduce_parts, dim3(2), dim3(256), 0, s, c->w5part, (int)tiles, (int64_t)D, (int64_t)D,
+                       (int64_t)1, c->G + OFF_W5);
+    hipLaunchKernelGGL(reduce_db5, dim3(1), dim3(64), 0, s, c->lossp, (int)(B / 4), c->G, c->loss);
+    // layers 4, 3, 2: weight gradient (split over rows), then the input gradient
+    // row splits of the weight gradients: at most 16, >= 512 rows each, dividing B/16
+    int splits = (int)std::max<int64_t>(1, std::min<int64_t>(16, B / 512));
+    while ((B / 16) % splits != 0) --splits;
+    int cur = 0;
+    for (int l = 2; l >= 0; --l) {
+        GemmArgs w{};
+        w.A = c->dzT[cur]; w.lda = ldT;
+        w.B = c->hT[l]; w.ldb = ldT;
+        w.k_len = B / splits; w.M = D; w.N = D;
+        w.part = c->part;
+        gemm_launch(EPI_PART, w, splits, s);
+        hipLaunchKernelGGL(reduce_parts, dim3(D * D / 256), dim3(256), 0, s, c->part, splits, (int64_t)D * D,
+                           (int64_t)D * D, (int64_t)1, c->G + off_w(l));
+        GemmArgs d{};
+        d.A = c->dzb[cur]; d.lda = D;
+        d.B = c->WTb + (int64_t)l * D * D; d.ldb = D;
+        d.k_len = D; d.M = B; d.N = D;
+        d.zprev = c->z[l];
+        d.ldT = ldT;
+        if (l > 0) {
+            d.dzb = c->dzb[cur ^ 1];
+            d.dzT = c->dzT[cur ^ 1];
+            d.colpart = c->colpart;
+        } else {
+            d.dzf = c->dz1;
+        }
+        gemm_launch(EPI_BWD, d, 1, s);
+        if (l > 0)
+            hipLaunchKernelGGL(reduce_parts, dim3(2), dim3(256), 0, s, c->colpart, (int)tiles, (int64_t)D, (int64_t)D,
+                               (int64_t)1, c->G + off_b(l - 1));
+        cur ^= 1;
+    }
+    // first layer
+    hipLaunchKernelGGL(l1_wgrad, dim3(D / 64, (unsigned)tiles), dim3(256), 0, s, c->dz1, x, c->l1part);
+    hipLaunchKernelGGL(reduce_l1, dim3((D * (DIN + 1) + 255) / 256), dim3(256), 0, s, c->l1part, (int)tiles, c->G);
+    MLP_HIP(hipGetLastError(), "gradient kernels");
+    if (loss) {
+        float l = 0.f;
+        MLP_HIP(hipMemcpyAsync(&l, c->loss, 4, hipMemcpyDeviceToHost, s), "copy loss");
+        MLP_HIP(hipStreamSynchronize(s), "synchronize");
+        *loss = (double)l / (double)B;
+    }
+    return QS_OK;
+}
+
+qs_status qs_mlp_adamw(qs_mlp *c, double lr, double beta1, double beta2, double eps, double wd) {
+    if (!c) return mfail(QS_ERR_ARG, "net is NULL");
+    if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0) || !(wd >= 0))
+        return mfail(QS_ERR_ARG, "invalid AdamW hyperparameters");
+    MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
+    c->t += 1;
+    const double c1 = 1.0 - std::pow(beta1, (double)c->t), c2 = 1.0 - std::pow(beta2, (double)c->t);
+    hipLaunchKernelGGL(adamw, dim3((unsigned)((N_PARAMS + 255) / 256)), dim3(256), 0, c->stream, c->P, c->G, c->Mo, c->Vo,
+                       N_PARAMS, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)wd, (float)c1, (float)c2);
+    hipLaunchKernelGGL(convert_weights, dim3((unsigned)((3 * D * D + 255) / 256)), dim3(256), 0, c->stream, c->P, c->Wb,
+                       c->WTb);
+    MLP_HIP(hipGetLastError(), "optimizer kernels");
+    return QS_OK;
+}
+
+qs_status qs_mlp_train_step(qs_mlp *c, const float *x, const float *t, int32_t batch, double lr, double *loss) {
+    qs_status st = qs_mlp_grads(c, x, t, batch, loss);
+    if (st != QS_OK) return st;
+    return qs_mlp_adamw(c, lr, 0.9, 0.999, 1e-8, 0.01);
+}
+
+void qs_mlp_free(qs_mlp *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->mem);
+    delete c;
+}
+
+}  // extern "C"

@@ -74,7 +74,9 @@ _lib = None
 
 EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace_size_ex", "qs_init",
            "qs_init_ex", "qs_get_plan", "qs_tune", "qs_graph_create", "qs_graph_launch", "qs_graph_free",
-           "qs_step_tau",
+           "qs_step_tau", "qs_mlp_param_count", "qs_mlp_create", "qs_mlp_set_params", "qs_mlp_get_params",
+           "qs_mlp_forward", "qs_mlp_grads", "qs_mlp_get_grads", "qs_mlp_set_grads", "qs_mlp_adamw",
+           "qs_mlp_train_step", "qs_mlp_free",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint"]
 
@@ -111,6 +113,23 @@ def lib():
     L.qs_graph_launch.argtypes = [vp]
     L.qs_graph_free.restype = None
     L.qs_graph_free.argtypes = [vp]
+    L.qs_mlp_param_count.restype = ctypes.c_int64
+    L.qs_mlp_create.restype = ctypes.c_int
+    L.qs_mlp_create.argtypes = [ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    F = ctypes.POINTER(ctypes.c_float)
+    for name in ("qs_mlp_set_params", "qs_mlp_get_params", "qs_mlp_get_grads", "qs_mlp_set_grads"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [vp, F]
+    L.qs_mlp_forward.restype = ctypes.c_int
+    L.qs_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp]
+    L.qs_mlp_grads.restype = ctypes.c_int
+    L.qs_mlp_grads.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    L.qs_mlp_adamw.restype = ctypes.c_int
+    L.qs_mlp_adamw.argtypes = [vp] + [ctypes.c_double] * 5
+    L.qs_mlp_train_step.restype = ctypes.c_int
+    L.qs_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    L.qs_mlp_free.restype = None
+    L.qs_mlp_free.argtypes = [vp]
     L.qs_step_tau.restype = ctypes.c_int
     L.qs_step_tau.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.qs_sync_check.restype = ctypes.c_int
@@ -192,6 +211,97 @@ def workspace_size(instances, precision=QS_FP32, columns_per_lane=0, segment_cel
     arr = (QSParams * len(insts))(*[x.p for x in insts])
     pl = _plan(columns_per_lane, segment_cells)
     return int(lib().qs_workspace_size_ex(arr, len(insts), ctypes.byref(pl) if pl else None))
+
+
+MLP_DIMS = (5, 512, 512, 512, 512, 1)
+
+
+def pack_params(params):
+    """[(W [out, in], b [out]), ...] -> flat float32 array in the library's layout."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                           for W, b in params]).astype(np.float32)
+
+
+def unpack_params(flat, dims=MLP_DIMS):
+    out, o = [], 0
+    for i in range(len(dims) - 1):
+        n_w = dims[i + 1] * dims[i]
+        W = np.asarray(flat[o:o + n_w], np.float64).reshape(dims[i + 1], dims[i])
+        o += n_w
+        b = np.asarray(flat[o:o + dims[i + 1]], np.float64)
+        o += dims[i + 1]
+        out.append((W, b))
+    return out
+
+
+class MLP:
+    """The surrogate network (include/qs_mlp.h) on one device; tensors are torch CUDA
+    float32 tensors, parameters host numpy arrays."""
+
+    def __init__(self, max_batch=65536, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        _check(lib().qs_mlp_create(int(max_batch), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.max_batch = int(max_batch)
+        self.n_params = int(lib().qs_mlp_param_count())
+
+    def _f(self, a):
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(params if isinstance(params, np.ndarray) else pack_params(params), np.float32)
+        assert flat.size == self.n_params
+        _check(lib().qs_mlp_set_params(self.h, self._f(flat)))
+
+    def get_params(self):
+        flat = np.empty(self.n_params, np.float32)
+        _check(lib().qs_mlp_get_params(self.h, self._f(flat)))
+        return flat
+
+    def get_grads(self):
+        flat = np.empty(self.n_params, np.float32)
+        _check(lib().qs_mlp_get_grads(self.h, self._f(flat)))
+        return flat
+
+    def set_grads(self, flat):
+        flat = np.ascontiguousarray(flat, np.float32)
+        _check(lib().qs_mlp_set_grads(self.h, self._f(flat)))
+
+    def forward(self, x, out=None):
+        t = self.torch
+        x = x.contiguous()
+        y = t.empty(x.shape[0], dtype=t.float32, device=x.device) if out is None else out
+        _check(lib().qs_mlp_forward(self.h, ctypes.c_void_p(x.data_ptr()), int(x.shape[0]), ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def grads(self, x, target, want_loss=True):
+        loss = ctypes.c_double()
+        _check(lib().qs_mlp_grads(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                  int(x.shape[0]), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def adamw(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.01):
+        _check(lib().qs_mlp_adamw(self.h, lr, beta1, beta2, eps, weight_decay))
+
+    def train_step(self, x, target, lr, want_loss=False):
+        loss = ctypes.c_double()
+        _check(lib().qs_mlp_train_step(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                       int(x.shape[0]), lr, ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().qs_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune(instances, precision=QS_FP32, steps_per_call=100):
