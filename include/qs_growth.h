@@ -1,0 +1,103 @@
+/*
+ * Growth maps: answers to scattered queries of how much a mode has grown, from the solver
+ * or from the learned surrogate (qs_mlp.h), with a held-out error table deciding which.
+ *
+ * A query is q = (ln n_b, ln gamma, k, xi, tau) for a single electron beam of density n_b
+ * (in units of n_p) and Lorentz factor gamma, flat-top in xi, seeded with the uniform
+ * extended disturbance S (Appendix C), inside the box
+ *   n_b in [1e-3, 1e-1],  gamma in [10, 1e4],  k in [0.05, 4],  xi in [0, 200],
+ *   tau in [0, tau_f],  tau_f = 10 sqrt(gamma / n_b)
+ * (tau_f: ten e-folds of the temporal CFI rate sqrt(n_b/gamma) at large k, Eq. CFI_temporal).
+ * Its answer is the growth of the windowed field amplitude over the seed,
+ *   G = 1/2 ln( mean over the cells with centres in (xi - 2 pi, xi] of A^2 ) - ln S,
+ *   A^2 = |E|^2 + |B|^2,
+ * i.e. the log amplitude averaged over one plasma wavelength behind xi (A itself carries
+ * the plasma-period ripple of the response).  The solver answer uses the discretization of
+ * the batched sweep: an instance of length L (the largest xi of its group of queries) with
+ * N = round(128 + 8064 (L - 5)/195) cells (N = max(1, round(128 L/5)) below L = 5),
+ * d_tau = tau_f/200, FP32 state; tau is rounded to whole steps.
+ *
+ * Network inputs (features) of a query:
+ *   x = ( log10 n_b + 2, (log10 gamma - 2.5)/1.5, (k - 2.025)/1.975, xi/100 - 1,
+ *         2 tau/tau_f - 1 ),   each in [-1, 1] inside the box.
+ *
+ * Device arrays are float32 and caller-owned; calls are ordered on `hip_stream` (NULL =
+ * null stream).  Errors: QS_ERR_ARG, QS_ERR_ALLOC, QS_ERR_HIP (qs_last_error has the text).
+ */
+#ifndef QS_GROWTH_H
+#define QS_GROWTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "qs.h"
+#include "qs_mlp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { QS_GROWTH_SURROGATE = 0, QS_GROWTH_SOLVER = 1, QS_GROWTH_AUTO = 2 };
+
+/* Bins of the held-out error table: 8 per feature, 8^5 in all, row-major in feature order. */
+enum { QS_GROWTH_BINS = 32768 };
+
+/* One solver instance whose snapshots feed qs_growth_targets / qs_growth_sample. */
+typedef struct qs_growth_instance {
+    double nb_over_np;   /* electron beam density n_b / n_p */
+    double gamma_b;
+    double length;       /* beam length L; cells of width h = L / n_xi */
+    double d_tau;
+    double seed_amp;     /* S of the uniform seed */
+    int32_t n_xi;
+    int32_t n_modes;
+    const double *k;     /* host: |k| of each mode */
+} qs_growth_instance;
+
+/*
+ * Training targets from solver snapshots (qs_step_tau layout, FP32): for every snapshot
+ * t < n_snap, instance i, cell j and mode m, G[t][i][j][m] = the windowed growth above.
+ * ln_e, ln_b, G: device [n_snap][sum_i n_xi_i n_modes_i] with instance i's block
+ * [n_xi][n_modes] at the running offset.  inst: host array of n_inst descriptions.
+ */
+qs_status qs_growth_targets(const qs_growth_instance *inst, int32_t n_inst, const float *ln_e,
+                            const float *ln_b, int32_t n_snap, float *G, void *hip_stream);
+
+/*
+ * Draw n training examples uniformly over all (snapshot, instance, cell, mode) entries of G
+ * (entry number floor(u * total), u = top 53 bits of SplitMix64 output i of `seed`, over
+ * 2^53).  snap_step: host [n_snap] step index of each snapshot (tau = step * d_tau).
+ * X: device [n][5] features; T: device [n] targets.
+ */
+qs_status qs_growth_sample(const qs_growth_instance *inst, int32_t n_inst, const float *G,
+                           int32_t n_snap, const int32_t *snap_step, uint64_t seed, int64_t n,
+                           float *X, float *T, void *hip_stream);
+
+/* Features x (device [n][5]) of queries q (device [n][5]). */
+qs_status qs_growth_features(const float *q, int64_t n, float *x, void *hip_stream);
+
+/*
+ * Held-out error table: table[bin] = max |network(x) - t| over the examples in each bin
+ * (-1 where a bin holds none).  X, T: device held-out examples; table: device
+ * [QS_GROWTH_BINS].  Uses the network's stream.
+ */
+qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64_t n, float *table);
+
+/*
+ * Answer n queries (device q [n][5]) into out (device [n]).
+ *   QS_GROWTH_SURROGATE : the network for every query (net required).
+ *   QS_GROWTH_SOLVER    : the solver for every query (net and table ignored; may be NULL).
+ *   QS_GROWTH_AUTO      : the network where the query is inside the box and its bin's
+ *                         held-out error is in [0, tol]; the solver elsewhere.
+ * used_solver (device [n] bytes, optional): 1 where the solver answered.  The solver path
+ * copies the selected queries to the host, groups them by (n_b, gamma), runs one batched
+ * solver context (one instance per group, its distinct k as modes) and synchronizes.
+ */
+qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float *q, int64_t n,
+                        int32_t mode, float *out, uint8_t *used_solver, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_GROWTH_H */

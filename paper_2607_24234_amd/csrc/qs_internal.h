@@ -9,6 +9,8 @@
 
 #include "../../include/qs.h"
 
+struct qs_mlp;
+
 namespace qs {
 
 constexpr int kWave = 64;  // lanes per wavefront on CDNA
@@ -93,6 +95,9 @@ hipError_t launch_seed(int precision, int nc, int n_blocks, int max_n_xi, const 
 
 // text returned by qs_last_error on this thread
 void set_last_error(const std::string &msg);
+
+// stream a surrogate network was created with (qs_mlp.hip)
+hipStream_t mlp_stream(const qs_mlp *net);
 
 // host helper mirroring the device SplitMix64 (exported for the generator tests)
 uint64_t splitmix64_host(uint64_t seed, uint64_t i);

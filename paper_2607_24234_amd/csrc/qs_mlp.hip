@@ -478,6 +478,10 @@ void forward_rows(qs_mlp *c, const float *x, int64_t rows, int64_t n_valid, bool
 
 }  // namespace
 
+namespace qs {
+hipStream_t mlp_stream(const qs_mlp *net) { return net->stream; }
+}  // namespace qs
+
 extern "C" {
 
 int64_t qs_mlp_param_count(void) { return N_PARAMS; }

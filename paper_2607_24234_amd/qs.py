@@ -64,6 +64,17 @@ class QSPlan(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class QSGrowthInstance(ctypes.Structure):
+    _fields_ = [("nb_over_np", ctypes.c_double), ("gamma_b", ctypes.c_double),
+                ("length", ctypes.c_double), ("d_tau", ctypes.c_double),
+                ("seed_amp", ctypes.c_double), ("n_xi", ctypes.c_int32),
+                ("n_modes", ctypes.c_int32), ("k", _D)]
+
+
+GROWTH_SURROGATE, GROWTH_SOLVER, GROWTH_AUTO = 0, 1, 2
+GROWTH_BINS = 32768
+
+
 class QSError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("libqs status %d: %s" % (status, msg))
@@ -76,7 +87,8 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_init_ex", "qs_get_plan", "qs_tune", "qs_graph_create", "qs_graph_launch", "qs_graph_free",
            "qs_step_tau", "qs_mlp_param_count", "qs_mlp_create", "qs_mlp_set_params", "qs_mlp_get_params",
            "qs_mlp_forward", "qs_mlp_grads", "qs_mlp_get_grads", "qs_mlp_set_grads", "qs_mlp_adamw",
-           "qs_mlp_train_step", "qs_mlp_free",
+           "qs_mlp_train_step", "qs_mlp_free", "qs_growth_targets", "qs_growth_sample",
+           "qs_growth_features", "qs_growth_calibrate", "qs_growth_map",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint"]
 
@@ -130,6 +142,18 @@ def lib():
     L.qs_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
     L.qs_mlp_free.restype = None
     L.qs_mlp_free.argtypes = [vp]
+    GI = ctypes.POINTER(QSGrowthInstance)
+    L.qs_growth_targets.restype = ctypes.c_int
+    L.qs_growth_targets.argtypes = [GI, ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp]
+    L.qs_growth_sample.restype = ctypes.c_int
+    L.qs_growth_sample.argtypes = [GI, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.c_uint64, ctypes.c_int64, vp, vp, vp]
+    L.qs_growth_features.restype = ctypes.c_int
+    L.qs_growth_features.argtypes = [vp, ctypes.c_int64, vp, vp]
+    L.qs_growth_calibrate.restype = ctypes.c_int
+    L.qs_growth_calibrate.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+    L.qs_growth_map.restype = ctypes.c_int
+    L.qs_growth_map.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp]
     L.qs_step_tau.restype = ctypes.c_int
     L.qs_step_tau.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.qs_sync_check.restype = ctypes.c_int
@@ -302,6 +326,57 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+class GrowthInstances:
+    """qs_growth_instance descriptions of solver instances (dicts from inputs.py with a
+    single species); keeps the k arrays alive."""
+
+    def __init__(self, instances):
+        self._k = []
+        arr = (QSGrowthInstance * len(instances))()
+        for i, inst in enumerate(instances):
+            (q, m, nb), = inst["species"]
+            k = np.asarray(inst["kx"], np.float64)
+            ky = inst.get("ky")
+            kk = np.ascontiguousarray(np.abs(k) if ky is None else np.hypot(k, np.asarray(ky, np.float64)), np.float64)
+            self._k.append(kk)
+            arr[i] = QSGrowthInstance(nb, inst["gamma"], inst["length"], inst["d_tau"], inst.get("seed_amp", 1e-6),
+                                      inst["n_xi"], len(kk), _dp(kk))
+        self.arr = arr
+        self.n = len(instances)
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_ptr(stream):
+    return ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+
+
+def growth_targets(gi, ln_e, ln_b, G, stream=None):
+    n_snap = ln_e.shape[0]
+    _check(lib().qs_growth_targets(gi.arr, gi.n, _vp(ln_e), _vp(ln_b), int(n_snap), _vp(G), _stream_ptr(stream)))
+
+
+def growth_sample(gi, G, snap_steps, seed, n, X, T, stream=None):
+    st = np.ascontiguousarray(snap_steps, np.int32)
+    _check(lib().qs_growth_sample(gi.arr, gi.n, _vp(G), len(st), st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  int(seed), int(n), _vp(X), _vp(T), _stream_ptr(stream)))
+
+
+def growth_features(q, x, stream=None):
+    _check(lib().qs_growth_features(_vp(q), int(q.shape[0]), _vp(x), _stream_ptr(stream)))
+
+
+def growth_calibrate(net, X, T, table):
+    _check(lib().qs_growth_calibrate(net.h, _vp(X), _vp(T), int(X.shape[0]), _vp(table)))
+
+
+def growth_map(net, table, tol, q, mode, out, used_solver=None, stream=None):
+    _check(lib().qs_growth_map(net.h if net is not None else None, _vp(table), float(tol), _vp(q), int(q.shape[0]),
+                               int(mode), _vp(out), _vp(used_solver), _stream_ptr(stream)))
 
 
 def tune(instances, precision=QS_FP32, steps_per_call=100):

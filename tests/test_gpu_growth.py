@@ -1,0 +1,228 @@
+"""GPU parity of the growth-map path (include/qs_growth.h) against the oracles: windowed
+growth targets, training-example draws, the feature map, the held-out error table, and the
+three answer modes of qs_growth_map (surrogate, solver, automatic routing)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import growth as Gr
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+
+def _synthetic_instances():
+    from paper_2607_24234_amd import inputs
+    out = []
+    for (n_xi, n_modes, L, nb, g) in [(40, 3, 30.0, 0.01, 100.0), (70, 2, 8.0, 0.05, 2000.0), (5, 4, 60.0, 0.002, 30.0)]:
+        d = dict(species=[inputs.ELECTRON + (nb,)], gamma=g, length=L, n_xi=n_xi,
+                 kx=np.linspace(0.3, 3.0, n_modes), ky=None, d_tau=0.5 * math.sqrt(g / nb) / 20,
+                 seed_kind=1, seed_amp=1e-6, rng_seed=0)
+        out.append(d)
+    return out
+
+
+def _synthetic_fields(insts, n_snap, seed):
+    rng = np.random.default_rng(seed)
+    S = sum(d["n_xi"] * len(d["kx"]) for d in insts)
+    le = rng.uniform(-16, -5, (n_snap, S))
+    lb = rng.uniform(-16, -5, (n_snap, S))
+    return le.astype(np.float32), lb.astype(np.float32)
+
+
+def _oracle_targets(insts, le, lb):
+    G = np.empty(le.shape)
+    for t in range(le.shape[0]):
+        off = 0
+        for d in insts:
+            N, Mm = d["n_xi"], len(d["kx"])
+            for m in range(Mm):
+                idx = off + np.arange(N) * Mm + m
+                G[t, idx] = Gr.windowed_growth(le[t, idx].astype(np.float64), lb[t, idx].astype(np.float64),
+                                               d["length"] / N, d["seed_amp"])
+            off += N * Mm
+    return G
+
+
+def test_targets_match_oracle(qs):
+    import torch
+    insts = _synthetic_instances()
+    le, lb = _synthetic_fields(insts, 2, 1)
+    gi = qs.GrowthInstances(insts)
+    G = torch.empty(le.shape, dtype=torch.float32, device="cuda")
+    qs.growth_targets(gi, torch.as_tensor(le, device="cuda"), torch.as_tensor(lb, device="cuda"), G)
+    ref = _oracle_targets(insts, le, lb)
+    # float32 output of values of magnitude <= ~12: a few float32 units
+    assert np.max(np.abs(G.cpu().numpy() - ref)) <= 1e-5
+
+
+def test_sample_draws_match_oracle(qs):
+    import torch
+    insts = _synthetic_instances()
+    le, lb = _synthetic_fields(insts, 3, 2)
+    gi = qs.GrowthInstances(insts)
+    Gd = torch.empty(le.shape, dtype=torch.float32, device="cuda")
+    qs.growth_targets(gi, torch.as_tensor(le, device="cuda"), torch.as_tensor(lb, device="cuda"), Gd)
+    ref = _oracle_targets(insts, le, lb)
+    steps = np.array([0, 7, 19], np.int32)
+    n, seed = 3000, 12345
+    X = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+    T = torch.empty(n, dtype=torch.float32, device="cuda")
+    qs.growth_sample(gi, Gd, steps, seed, n, X, T)
+    X, T = X.cpu().numpy(), T.cpu().numpy()
+    S = le.shape[1]
+    total = S * 3
+    offs = np.cumsum([0] + [d["n_xi"] * len(d["kx"]) for d in insts])
+    for i in range(n):
+        u = O.u53(O.splitmix64(seed, i))
+        e = min(int(u * total), total - 1)
+        t, r = divmod(e, S)
+        ii = int(np.searchsorted(offs, r, side="right") - 1)
+        d = insts[ii]
+        Mm = len(d["kx"])
+        j, m = divmod(r - offs[ii], Mm)
+        nb = d["species"][0][2]
+        h = d["length"] / d["n_xi"]
+        q = np.array([[math.log(nb), math.log(d["gamma"]), d["kx"][m], (j + 0.5) * h, steps[t] * d["d_tau"]]])
+        assert np.max(np.abs(X[i] - Gr.features(q)[0])) <= 2e-6, i
+        assert abs(T[i] - ref[t, r]) <= 1e-5, i
+
+
+def test_features_match_oracle(qs):
+    import torch
+    rng = np.random.default_rng(3)
+    n = 1000
+    nb = 10 ** rng.uniform(-3, -1, n)
+    g = 10 ** rng.uniform(1, 4, n)
+    q = np.stack([np.log(nb), np.log(g), rng.uniform(0.05, 4, n), rng.uniform(0, 200, n),
+                  rng.uniform(0, 1, n) * 10 * np.sqrt(g / nb)], axis=1).astype(np.float32)
+    x = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+    qs.growth_features(torch.as_tensor(q, device="cuda"), x)
+    assert np.max(np.abs(x.cpu().numpy() - Gr.features(q.astype(np.float64)))) <= 2e-6
+
+
+def _net(qs, seed):
+    rng = np.random.default_rng(seed)
+    P = [(np.float32(W).astype(np.float64), np.float32(b).astype(np.float64)) for W, b in M.init_params(rng)]
+    net = qs.MLP(max_batch=2048)
+    net.set_params(qs.pack_params(P))
+    return net, P
+
+
+def test_calibration_table_matches_oracle(qs):
+    import torch
+    net, P = _net(qs, 4)
+    rng = np.random.default_rng(5)
+    n = 5000
+    X = rng.uniform(-1.1, 1.1, (n, 5)).astype(np.float32)
+    X[:, 1] = rng.choice([-0.9, 0.3], n)          # leaves most bins empty
+    T = rng.standard_normal(n).astype(np.float32)
+    table = torch.empty(qs.GROWTH_BINS, dtype=torch.float32, device="cuda")
+    qs.growth_calibrate(net, torch.as_tensor(X, device="cuda"), torch.as_tensor(T, device="cuda"), table)
+    y, cache = M.forward(P, X.astype(np.float64), rounding="bf16")
+    err = np.abs(y - T)
+    ref = np.full(qs.GROWTH_BINS, -1.0)
+    np.maximum.at(ref, Gr.bin_of(X.astype(np.float64)), err)
+    got = table.cpu().numpy()
+    assert np.array_equal(got < 0, ref < 0)
+    # per-bin maxima of |y - t| move by at most the network's own difference from the oracle
+    scale = np.max(np.abs(cache["h"][-1]) @ np.abs(P[-1][0][0]))
+    assert np.max(np.abs(got - ref)[ref >= 0]) <= 2.0 ** -8 * scale
+
+
+def _queries():
+    """Two (n_b, gamma) groups, several k, xi and whole-step tau each."""
+    rows = []
+    for nb, g in [(0.0113, 137.0), (0.047, 310.0)]:   # features away from bin edges
+        tf = 10 * math.sqrt(g / nb)
+        dt = tf / 200
+        for k, xi, s in [(0.5, 12.0, 40), (2.0, 12.0, 40), (2.0, 3.3, 199), (3.5, 7.9, 0), (0.5, 0.4, 120)]:
+            rows.append([math.log(nb), math.log(g), k, xi, s * dt])
+    return np.array(rows, np.float32)
+
+
+def _cells_for(L):
+    return int(round(128 + 8064 * (L - 5) / 195)) if L >= 5 else max(1, int(round(128 * L / 5)))
+
+
+def _oracle_solver_answers(q):
+    from paper_2607_24234_amd import inputs
+    from helpers import oracle_run
+    out = np.empty(len(q))
+    q = q.astype(np.float64)
+    groups = {}
+    for i, row in enumerate(q):
+        groups.setdefault((np.float32(row[0]).tobytes(), np.float32(row[1]).tobytes()), []).append(i)
+    for key, idx in groups.items():
+        nb, g = math.exp(float(np.float32(q[idx[0], 0]))), math.exp(float(np.float32(q[idx[0], 1])))
+        L = max(float(np.float32(q[i, 3])) for i in idx)
+        ks = np.unique(np.float32(q[idx, 2]).astype(np.float64))
+        N = _cells_for(L)
+        dt = 10 * math.sqrt(g / nb) / 200
+        inst = dict(species=[inputs.ELECTRON + (nb,)], gamma=g, length=L, n_xi=N, kx=ks, ky=None, d_tau=dt,
+                    seed_kind=1, seed_amp=1e-6, rng_seed=0)
+        steps = [int(round(min(max(float(np.float32(q[i, 4])) / dt, 0), 200))) for i in idx]
+        ln_e, ln_b, _, _ = oracle_run(inst, max(steps) + 1, out_every=1)
+        h = L / N
+        for i, s in zip(idx, steps):
+            m = int(np.searchsorted(ks, float(np.float32(q[i, 2]))))
+            j = min(N - 1, max(0, math.ceil(float(np.float32(q[i, 3])) / h) - 1))
+            G = Gr.windowed_growth(ln_e[s, :, m], ln_b[s, :, m], h, 1e-6)
+            out[i] = G[j]
+    return out
+
+
+def test_growth_map_solver_matches_oracle(qs):
+    import torch
+    q = _queries()
+    out = torch.empty(len(q), dtype=torch.float32, device="cuda")
+    used = torch.zeros(len(q), dtype=torch.uint8, device="cuda")
+    qs.growth_map(None, None, 0.0, torch.as_tensor(q, device="cuda"), qs.GROWTH_SOLVER, out, used)
+    ref = _oracle_solver_answers(q)
+    got = out.cpu().numpy()
+    assert np.all(used.cpu().numpy() == 1)
+    # FP32 solver state against the FP64 oracle: the bar of ln A
+    assert np.max(np.abs(got - ref)) <= 1e-4, np.abs(got - ref)
+
+
+def test_growth_map_surrogate_and_auto(qs):
+    import torch
+    net, P = _net(qs, 6)
+    q = _queries()
+    qd = torch.as_tensor(q, device="cuda")
+    n = len(q)
+    sur = torch.empty(n, dtype=torch.float32, device="cuda")
+    qs.growth_map(net, None, 0.0, qd, qs.GROWTH_SURROGATE, sur)
+    x = Gr.features(q.astype(np.float64)).astype(np.float32).astype(np.float64)
+    y, cache = M.forward(P, x, rounding="bf16")
+    scale = np.abs(cache["h"][-1]) @ np.abs(P[-1][0][0]) + abs(P[-1][1][0])
+    assert np.all(np.abs(sur.cpu().numpy() - y) <= 2.0 ** -8 * scale + 1e-5)
+    # routing: a table trusting every bin except those of queries 1 and 6
+    table = torch.zeros(qs.GROWTH_BINS, dtype=torch.float32, device="cuda")
+    bins = Gr.bin_of(x)
+    table[int(bins[1])] = 0.5
+    table[int(bins[6])] = -1.0                       # no held-out data there
+    auto = torch.empty(n, dtype=torch.float32, device="cuda")
+    used = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    qs.growth_map(net, table, 1e-2, qd, qs.GROWTH_AUTO, auto, used)
+    solver = torch.empty(n, dtype=torch.float32, device="cuda")
+    qs.growth_map(None, None, 0.0, qd, qs.GROWTH_SOLVER, solver)
+    expect = np.zeros(n, np.uint8)
+    expect[[i for i in range(n) if bins[i] in (bins[1], bins[6])]] = 1
+    u = used.cpu().numpy()
+    assert np.array_equal(u, expect)
+    a, s_, su = auto.cpu().numpy(), solver.cpu().numpy(), sur.cpu().numpy()
+    assert np.array_equal(a[u == 0], su[u == 0])
+    # solver answers of a subset come from a context over the subset's groups: same
+    # discretization when the group keeps its largest xi, so compare to the oracle instead
+    ref = _oracle_solver_answers(q[u == 1])
+    assert np.max(np.abs(a[u == 1] - ref)) <= 1e-4
+    # queries outside the box always go to the solver
+    q2 = q.copy()
+    q2[:, 2] = 4.5
+    used2 = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    out2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    qs.growth_map(net, table, 1e-2, torch.as_tensor(q2, device="cuda"), qs.GROWTH_AUTO, out2, used2)
+    assert np.all(used2.cpu().numpy() == 1)
