@@ -77,9 +77,12 @@ qs_status qs_growth_sample(const qs_growth_instance *inst, int32_t n_inst, const
 qs_status qs_growth_features(const float *q, int64_t n, float *x, void *hip_stream);
 
 /*
- * Held-out error table: table[bin] = max |network(x) - t| over the examples in each bin
- * (-1 where a bin holds none).  X, T: device held-out examples; table: device
- * [QS_GROWTH_BINS].  Uses the network's stream.
+ * Held-out error table: per bin, an upper estimate of the 99th percentile of
+ * |network(x) - t| over the held-out examples in the bin: the upper edge of the histogram
+ * bucket that holds it, buckets (1e-4 2^((b-1)/4), 1e-4 2^(b/4)] (b = 1..62; bucket 0 is
+ * [0, 1e-4], bucket 63 everything above 1e-4 2^15.5, reported as 3e38).  -1 where a bin
+ * holds fewer than 32 examples.  X, T: device held-out examples; table: device
+ * [QS_GROWTH_BINS].  Uses the network's stream; allocates an 8 MB histogram.
  */
 qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64_t n, float *table);
 
@@ -90,8 +93,9 @@ qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64
  *   QS_GROWTH_AUTO      : the network where the query is inside the box and its bin's
  *                         held-out error is in [0, tol]; the solver elsewhere.
  * used_solver (device [n] bytes, optional): 1 where the solver answered.  The solver path
- * copies the selected queries to the host, groups them by (n_b, gamma), runs one batched
- * solver context (one instance per group, its distinct k as modes) and synchronizes.
+ * copies the selected queries to the host, groups them by (n_b, gamma), runs batched solver
+ * contexts (one instance per group, its distinct k as modes; groups chunked so that one
+ * context holds at most 8 GB of state), allocates its buffers, and synchronizes.
  */
 qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float *q, int64_t n,
                         int32_t mode, float *out, uint8_t *used_solver, void *hip_stream);

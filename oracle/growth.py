@@ -55,3 +55,39 @@ def bin_of(x):
     for d in range(5):
         b = b * 8 + c[:, d]
     return b
+
+
+E0 = 1e-4
+BUCKETS = 64
+MIN_COUNT = 32
+
+
+def bucket(e):
+    """Histogram bucket of an error: 0 for e <= 1e-4, else 1 + floor(4 log2(e / 1e-4)),
+    at most 63 (also for non-finite errors)."""
+    e = float(e)
+    if not (e <= 3.0e38):
+        return BUCKETS - 1
+    if e <= E0:
+        return 0
+    return min(BUCKETS - 1, 1 + int(math.floor(4.0 * math.log2(e / E0))))
+
+
+def bucket_edge(b):
+    return 3.0e38 if b >= BUCKETS - 1 else E0 * 2.0 ** (0.25 * b)
+
+
+def p99_table(x, err):
+    """Per bin: the upper edge of the bucket holding the ceil(0.99 n)-th smallest error of the
+    bin's n examples, or -1 when n < 32."""
+    bins = bin_of(x)
+    out = np.full(8 ** 5, -1.0)
+    for b in np.unique(bins):
+        e = np.asarray(err)[bins == b]
+        if len(e) < MIN_COUNT:
+            continue
+        k = int(math.ceil(0.99 * len(e)))
+        counts = np.bincount([bucket(v) for v in e], minlength=BUCKETS)
+        acc = np.cumsum(counts)
+        out[b] = bucket_edge(int(np.argmax(acc >= k)))
+    return out

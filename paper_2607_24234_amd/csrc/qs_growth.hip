@@ -149,15 +149,44 @@ __global__ void __launch_bounds__(256) fill_kernel(float *p, int64_t n, float v)
     if (i < n) p[i] = v;
 }
 
-// table[bin] = max |y - t| (non-negative floats order as their bit patterns as signed ints;
-// the table starts at -1, below every non-negative value)
-__global__ void __launch_bounds__(256) calib_kernel(const float *__restrict__ x, const float *__restrict__ y,
-                                                    const float *__restrict__ t, int64_t n, float *__restrict__ table) {
+// Held-out error histogram: bucket 0 holds |y - t| <= e0, bucket b >= 1 the range
+// (e0 2^((b-1)/4), e0 2^(b/4)], the last bucket everything above (and non-finite errors).
+constexpr int kBuckets = 64;
+constexpr float kE0 = 1e-4f;
+constexpr int kMinCount = 32;  // fewer held-out examples in a bin: no estimate
+
+__host__ __device__ inline float bucket_edge(int b) {
+    return b >= kBuckets - 1 ? 3.0e38f : kE0 * exp2f(0.25f * (float)b);
+}
+
+__global__ void __launch_bounds__(256) hist_kernel(const float *__restrict__ x, const float *__restrict__ y,
+                                                   const float *__restrict__ t, int64_t n, uint32_t *__restrict__ cnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float e = fabsf(y[i] - t[i]);
-    if (!(e <= 3.0e38f)) e = 3.0e38f;  // a non-finite error marks the bin as untrusted
-    atomicMax(reinterpret_cast<int *>(table) + bin_of(x + 5 * i), __builtin_bit_cast(int, e));
+    const float e = fabsf(y[i] - t[i]);
+    int b;
+    if (!(e <= 3.0e38f)) b = kBuckets - 1;
+    else if (e <= kE0) b = 0;
+    else b = min(kBuckets - 1, 1 + (int)floorf(4.0f * log2f(e / kE0)));
+    atomicAdd(cnt + (int64_t)bin_of(x + 5 * i) * kBuckets + b, 1u);
+}
+
+// table[bin] = upper edge of the bucket holding the 99th percentile, -1 below kMinCount
+__global__ void __launch_bounds__(256) p99_kernel(const uint32_t *__restrict__ cnt, float *__restrict__ table) {
+    const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bin >= QS_GROWTH_BINS) return;
+    const uint32_t *c = cnt + (int64_t)bin * kBuckets;
+    uint32_t total = 0;
+    for (int b = 0; b < kBuckets; ++b) total += c[b];
+    if (total < (uint32_t)kMinCount) { table[bin] = -1.0f; return; }
+    const uint32_t need = (uint32_t)ceil(0.99 * (double)total);
+    uint32_t acc = 0;
+    int b = 0;
+    for (; b < kBuckets; ++b) {
+        acc += c[b];
+        if (acc >= need) break;
+    }
+    table[bin] = bucket_edge(min(b, kBuckets - 1));
 }
 
 // 1 where the solver must answer: outside the box, no held-out data in the bin, or the
@@ -238,13 +267,105 @@ int cells_for(double L) {
 }
 
 // Solver answers for the queries hq[5 i..] at positions sel; values returned in vals.
+struct Group {
+    double nb, g, L = 0.0;
+    std::vector<double> ks;
+    std::vector<int64_t> members;  // positions in the selection
+};
+
+// Solver answers for the selected queries of groups [g0, g1): one batched context, one
+// instance per group, marched to each distinct step in turn.
+qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> &sel,
+                       const std::vector<Group> &groups, size_t g0, size_t g1, hipStream_t s,
+                       std::vector<float> *vals) {
+    const double S = 1e-6;
+    const int n_steps_max = 200;
+    const size_t ng = g1 - g0;
+    std::vector<qs_params> params(ng);
+    std::vector<double> qv(1, -1.0), mv(1, 1.0);
+    std::vector<std::vector<double>> nbv(ng);
+    std::vector<qs_growth_instance> gis(ng);
+    for (size_t i = 0; i < ng; ++i) {
+        const Group &G = groups[g0 + i];
+        nbv[i] = {G.nb};
+        qs_params &p = params[i];
+        std::memset(&p, 0, sizeof(p));
+        p.n_species = 1;
+        p.q = qv.data();
+        p.m = mv.data();
+        p.nb_over_np = nbv[i].data();
+        p.gamma_b = G.g;
+        p.length = G.L;
+        p.profile = QS_PROFILE_FLATTOP;
+        p.geometry = QS_GEOM_SPECTRAL;
+        p.n_modes = (int64_t)G.ks.size();
+        p.kx = const_cast<double *>(G.ks.data());
+        p.n_xi = cells_for(G.L);
+        p.d_tau = tau_final(G.nb, G.g) / n_steps_max;
+        p.precision = QS_FP32;
+        p.seed_kind = QS_SEED_UNIFORM;
+        p.seed_amp = S;
+        gis[i] = qs_growth_instance{G.nb, G.g, G.L, p.d_tau, S, p.n_xi, (int32_t)p.n_modes, p.kx};
+    }
+    qs_ctx *ctx = nullptr;
+    qs_status st = qs_init(params.data(), (int32_t)params.size(), s, nullptr, 0, &ctx);
+    if (st != QS_OK) return st;
+    int64_t snap = 0;
+    for (const qs_growth_instance &g : gis) snap += (int64_t)g.n_xi * g.n_modes;
+    float *buf = nullptr;
+    if (hipMalloc(&buf, (size_t)snap * 3 * sizeof(float)) != hipSuccess) {
+        qs_free(ctx);
+        return gfail(QS_ERR_ALLOC, "growth map: snapshot buffers");
+    }
+    float *le = buf, *lb = buf + snap, *Gd = buf + 2 * snap;
+    // queries by step
+    std::vector<std::pair<int, int64_t>> order;  // (step, position in sel)
+    std::map<int64_t, int> gof;  // position in sel -> local group
+    for (size_t i = 0; i < ng; ++i)
+        for (int64_t p : groups[g0 + i].members) {
+            gof[p] = (int)i;
+            const float *q = &hq[5 * (size_t)sel[p]];
+            const int stp = (int)std::lround(std::min(std::max((double)q[4] / params[i].d_tau, 0.0), (double)n_steps_max));
+            order.push_back({stp, p});
+        }
+    std::sort(order.begin(), order.end());
+    std::vector<int64_t> goff(ng);
+    {
+        int64_t o = 0;
+        for (size_t i = 0; i < ng; ++i) { goff[i] = o; o += (int64_t)gis[i].n_xi * gis[i].n_modes; }
+    }
+    std::vector<float> hG(snap);
+    int done = 0;
+    size_t a = 0;
+    while (a < order.size() && st == QS_OK) {
+        const int stp = order[a].first;
+        if (stp > done) st = qs_step_tau(ctx, stp - done, 1, nullptr, nullptr, nullptr);
+        done = stp;
+        if (st == QS_OK) st = qs_step_tau(ctx, 0, 1, le, lb, nullptr);
+        if (st == QS_OK) st = qs_growth_targets(gis.data(), (int32_t)gis.size(), le, lb, 1, Gd, s);
+        if (st == QS_OK && hipMemcpyAsync(hG.data(), Gd, (size_t)snap * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = gfail(QS_ERR_HIP, "growth map: copy targets");
+        if (st == QS_OK && hipStreamSynchronize(s) != hipSuccess) st = gfail(QS_ERR_HIP, "growth map: synchronize");
+        for (; st == QS_OK && a < order.size() && order[a].first == stp; ++a) {
+            const int64_t p = order[a].second;
+            const int i = gof.at(p);
+            const float *q = &hq[5 * (size_t)sel[p]];
+            const double h = gis[i].length / gis[i].n_xi;
+            const int j = std::min(gis[i].n_xi - 1, std::max(0, (int)std::ceil((double)q[3] / h) - 1));
+            const auto &ks = groups[g0 + i].ks;
+            const int m = (int)(std::lower_bound(ks.begin(), ks.end(), (double)q[2]) - ks.begin());
+            (*vals)[p] = hG[goff[i] + (int64_t)j * gis[i].n_modes + m];
+        }
+    }
+    if (st == QS_OK) st = qs_sync_check(ctx);
+    (void)hipFree(buf);
+    qs_free(ctx);
+    return st;
+}
+
+
 qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t> &sel, hipStream_t s,
                         std::vector<float> *vals) {
-    struct Group {
-        double nb, g, L = 0.0;
-        std::vector<double> ks;
-        std::vector<int64_t> members;  // positions in sel
-    };
     std::map<std::pair<uint32_t, uint32_t>, int> gid;
     std::vector<Group> groups;
     for (size_t p = 0; p < sel.size(); ++p) {
@@ -266,91 +387,29 @@ qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t>
         G.ks.push_back((double)q[2]);
         G.members.push_back((int64_t)p);
     }
-    const double S = 1e-6;
-    const int n_steps_max = 200;
-    std::vector<qs_params> params(groups.size());
-    std::vector<double> qv(1, -1.0), mv(1, 1.0);
-    std::vector<std::vector<double>> nbv(groups.size());
-    std::vector<qs_growth_instance> gis(groups.size());
-    for (size_t i = 0; i < groups.size(); ++i) {
-        Group &G = groups[i];
+    vals->assign(sel.size(), 0.f);
+    for (Group &G : groups) {
         std::sort(G.ks.begin(), G.ks.end());
         G.ks.erase(std::unique(G.ks.begin(), G.ks.end()), G.ks.end());
         G.L = std::max(G.L, 1e-3);
-        nbv[i] = {G.nb};
-        qs_params &p = params[i];
-        std::memset(&p, 0, sizeof(p));
-        p.n_species = 1;
-        p.q = qv.data();
-        p.m = mv.data();
-        p.nb_over_np = nbv[i].data();
-        p.gamma_b = G.g;
-        p.length = G.L;
-        p.profile = QS_PROFILE_FLATTOP;
-        p.geometry = QS_GEOM_SPECTRAL;
-        p.n_modes = (int64_t)G.ks.size();
-        p.kx = G.ks.data();
-        p.n_xi = cells_for(G.L);
-        p.d_tau = tau_final(G.nb, G.g) / n_steps_max;
-        p.precision = QS_FP32;
-        p.seed_kind = QS_SEED_UNIFORM;
-        p.seed_amp = S;
-        gis[i] = qs_growth_instance{G.nb, G.g, G.L, p.d_tau, S, p.n_xi, (int32_t)p.n_modes, G.ks.data()};
     }
-    qs_ctx *ctx = nullptr;
-    qs_status st = qs_init(params.data(), (int32_t)params.size(), s, nullptr, 0, &ctx);
-    if (st != QS_OK) return st;
-    int64_t snap = 0;
-    for (const qs_growth_instance &g : gis) snap += (int64_t)g.n_xi * g.n_modes;
-    float *buf = nullptr;
-    if (hipMalloc(&buf, (size_t)snap * 3 * sizeof(float)) != hipSuccess) {
-        qs_free(ctx);
-        return gfail(QS_ERR_ALLOC, "growth map: snapshot buffers");
-    }
-    float *le = buf, *lb = buf + snap, *Gd = buf + 2 * snap;
-    // queries by step
-    std::vector<std::pair<int, int64_t>> order;  // (step, position in sel)
-    std::vector<int> gof(sel.size());
-    for (size_t i = 0; i < groups.size(); ++i)
-        for (int64_t p : groups[i].members) {
-            gof[p] = (int)i;
-            const float *q = &hq[5 * (size_t)sel[p]];
-            const int stp = (int)std::lround(std::min(std::max((double)q[4] / params[i].d_tau, 0.0), (double)n_steps_max));
-            order.push_back({stp, p});
+    // run the groups in chunks whose solver state stays within a fixed budget
+    const size_t kBudget = size_t(8) << 30;  // bytes of FP32 state per chunk
+    size_t g0 = 0;
+    while (g0 < groups.size()) {
+        size_t g1 = g0, bytes = 0;
+        while (g1 < groups.size()) {
+            const size_t blocks = (groups[g1].ks.size() + 31) / 32;
+            const size_t b = blocks * (size_t)cells_for(groups[g1].L) * 3 * 64 * 4;
+            if (g1 > g0 && (bytes + b > kBudget || g1 - g0 >= 65536)) break;
+            bytes += b;
+            ++g1;
         }
-    std::sort(order.begin(), order.end());
-    std::vector<int64_t> goff(groups.size());
-    {
-        int64_t o = 0;
-        for (size_t i = 0; i < groups.size(); ++i) { goff[i] = o; o += (int64_t)gis[i].n_xi * gis[i].n_modes; }
+        qs_status st = solve_groups(hq, sel, groups, g0, g1, s, vals);
+        if (st != QS_OK) return st;
+        g0 = g1;
     }
-    vals->assign(sel.size(), 0.f);
-    std::vector<float> hG(snap);
-    int done = 0;
-    size_t a = 0;
-    while (a < order.size() && st == QS_OK) {
-        const int stp = order[a].first;
-        if (stp > done) st = qs_step_tau(ctx, stp - done, 1, nullptr, nullptr, nullptr);
-        done = stp;
-        if (st == QS_OK) st = qs_step_tau(ctx, 0, 1, le, lb, nullptr);
-        if (st == QS_OK) st = qs_growth_targets(gis.data(), (int32_t)gis.size(), le, lb, 1, Gd, s);
-        if (st == QS_OK && hipMemcpyAsync(hG.data(), Gd, (size_t)snap * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
-            st = gfail(QS_ERR_HIP, "growth map: copy targets");
-        if (st == QS_OK && hipStreamSynchronize(s) != hipSuccess) st = gfail(QS_ERR_HIP, "growth map: synchronize");
-        for (; st == QS_OK && a < order.size() && order[a].first == stp; ++a) {
-            const int64_t p = order[a].second;
-            const int i = gof[p];
-            const float *q = &hq[5 * (size_t)sel[p]];
-            const double h = gis[i].length / gis[i].n_xi;
-            const int j = std::min(gis[i].n_xi - 1, std::max(0, (int)std::ceil((double)q[3] / h) - 1));
-            const int m = (int)(std::lower_bound(groups[i].ks.begin(), groups[i].ks.end(), (double)q[2]) - groups[i].ks.begin());
-            (*vals)[p] = hG[goff[i] + (int64_t)j * gis[i].n_modes + m];
-        }
-    }
-    if (st == QS_OK) st = qs_sync_check(ctx);
-    (void)hipFree(buf);
-    qs_free(ctx);
-    return st;
+    return QS_OK;
 }
 
 }  // namespace
@@ -417,16 +476,24 @@ qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64
     if (!net || !table || n < 0 || (n > 0 && (!X || !T))) return gfail(QS_ERR_ARG, "net, X, T and table are required");
     hipStream_t s = qs::mlp_stream(net);
     float *y = nullptr;
+    uint32_t *cnt = nullptr;
     if (n > 0) G_HIP(hipMalloc(&y, n * sizeof(float)), "allocate predictions");
-    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(QS_GROWTH_BINS)), dim3(256), 0, s, table, (int64_t)QS_GROWTH_BINS, -1.0f);
+    if (hipMalloc(&cnt, (size_t)QS_GROWTH_BINS * kBuckets * sizeof(uint32_t)) != hipSuccess) {
+        if (y) (void)hipFree(y);
+        return gfail(QS_ERR_ALLOC, "allocate histogram");
+    }
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks_for((int64_t)QS_GROWTH_BINS * kBuckets)), dim3(256), 0, s,
+                       reinterpret_cast<float *>(cnt), (int64_t)QS_GROWTH_BINS * kBuckets, 0.0f);
     qs_status st = QS_OK;
     if (n > 0) {
         st = qs_mlp_forward(net, X, n, y);
-        if (st == QS_OK) hipLaunchKernelGGL(calib_kernel, dim3(blocks_for(n)), dim3(256), 0, s, X, y, T, n, table);
+        if (st == QS_OK) hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(n)), dim3(256), 0, s, X, y, T, n, cnt);
     }
+    if (st == QS_OK) hipLaunchKernelGGL(p99_kernel, dim3(blocks_for(QS_GROWTH_BINS)), dim3(256), 0, s, cnt, table);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (y) (void)hipFree(y);
+    (void)hipFree(cnt);
     if (st != QS_OK) return st;
     if (e != hipSuccess) return gfail(QS_ERR_HIP, std::string("calibration: ") + hipGetErrorString(e));
     return QS_OK;

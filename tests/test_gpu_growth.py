@@ -115,21 +115,22 @@ def test_calibration_table_matches_oracle(qs):
     import torch
     net, P = _net(qs, 4)
     rng = np.random.default_rng(5)
-    n = 5000
+    n = 20000
     X = rng.uniform(-1.1, 1.1, (n, 5)).astype(np.float32)
     X[:, 1] = rng.choice([-0.9, 0.3], n)          # leaves most bins empty
+    X[:, 2] = rng.choice([-0.5, 0.6], n)
+    X[:, 3] = rng.choice([0.1, 0.9], n)
     T = rng.standard_normal(n).astype(np.float32)
     table = torch.empty(qs.GROWTH_BINS, dtype=torch.float32, device="cuda")
     qs.growth_calibrate(net, torch.as_tensor(X, device="cuda"), torch.as_tensor(T, device="cuda"), table)
     y, cache = M.forward(P, X.astype(np.float64), rounding="bf16")
-    err = np.abs(y - T)
-    ref = np.full(qs.GROWTH_BINS, -1.0)
-    np.maximum.at(ref, Gr.bin_of(X.astype(np.float64)), err)
+    ref = Gr.p99_table(X.astype(np.float64), np.abs(y - T))
     got = table.cpu().numpy()
     assert np.array_equal(got < 0, ref < 0)
-    # per-bin maxima of |y - t| move by at most the network's own difference from the oracle
-    scale = np.max(np.abs(cache["h"][-1]) @ np.abs(P[-1][0][0]))
-    assert np.max(np.abs(got - ref)[ref >= 0]) <= 2.0 ** -8 * scale
+    assert np.sum(ref >= 0) >= 20
+    # the network's own difference from the oracle can move an error across one bucket edge
+    f = ref >= 0
+    assert np.max(np.abs(np.log2(got[f]) - np.log2(ref[f]))) <= 0.25 + 1e-6
 
 
 def _queries():

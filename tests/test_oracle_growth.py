@@ -47,3 +47,21 @@ def test_features_box_corners():
 def test_bin_order():
     x = np.array([[-1, -1, -1, -1, -1], [1, 1, 1, 1, 1], [-1, -1, -1, -1, -0.74], [-0.74, -1, -1, -1, -1]], float)
     assert list(Gr.bin_of(x)) == [0, 8 ** 5 - 1, 1, 8 ** 4]
+
+
+def test_p99_table_definition():
+    # 100 errors 1e-3 .. 0.1 in one bin: the 99th smallest is 0.099, whose bucket
+    # (1e-4 2^(39/4), 1e-4 2^10] = (0.0861, 0.1024] reports 0.1024
+    x = np.zeros((100, 5))
+    err = np.arange(1, 101) * 1e-3
+    t = Gr.p99_table(x, err)
+    b = int(Gr.bin_of(x[:1])[0])
+    assert abs(t[b] - 1e-4 * 2 ** 10) < 1e-15
+    assert np.sum(t >= 0) == 1
+    # fewer than 32 examples: no estimate
+    assert np.all(Gr.p99_table(x[:31], err[:31]) == -1)
+    # bucket edges bracket their errors
+    for e in (1e-5, 1e-4, 1.0001e-4, 3e-3, 0.5, 7.0):
+        bb = Gr.bucket(e)
+        assert e <= Gr.bucket_edge(bb) and (bb == 0 or e > Gr.bucket_edge(bb - 1))
+    assert Gr.bucket(np.inf) == Gr.bucket(np.nan) == Gr.bucket(1e30) == 63
