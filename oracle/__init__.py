@@ -16,6 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(HERE, "qs_oracle.c")
+_SRC_GRID = os.path.join(HERE, "qs_grid_oracle.c")
 _LIB = os.path.join(HERE, "liborc.so")
 
 DROP_LONGITUDINAL = 1
@@ -28,11 +29,13 @@ SEED_FRONT_IMPULSE = 2
 
 
 def build(force: bool = False) -> str:
-    """Compile qs_oracle.c into liborc.so with gcc (-O2, IEEE arithmetic, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile qs_oracle.c and qs_grid_oracle.c into liborc.so with gcc (-O2, IEEE
+    arithmetic, OpenMP)."""
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in (_SRC, _SRC_GRID))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC_GRID, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -227,3 +230,100 @@ def splitmix64(seed, i):
 
 def u53(x):
     return float(lib().orc_u53(int(x)))
+
+
+# ----------------------------------------------------------------------------- finite width
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("n_xi", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("h", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("omega", ctypes.POINTER(ctypes.c_double)),
+                ("flags", ctypes.c_int)]
+
+
+class Grid:
+    """A finite-width problem: nx x ny periodic transverse grid over lx x ly, n_xi cells of
+    width h, Omega at cell centres [n_xi, ny, nx]."""
+
+    def __init__(self, nx, ny, n_xi, lx, ly, h, gamma, omega, flags=0):
+        self.omega = np.ascontiguousarray(omega, np.float64).reshape(n_xi, ny, nx)
+        self.nx, self.ny, self.n_xi, self.lx, self.ly, self.h, self.gamma = nx, ny, n_xi, lx, ly, h, gamma
+        self.flags = flags
+        self.c = _Grid(nx, ny, n_xi, lx, ly, h, gamma, _dp(self.omega), flags)
+
+    @property
+    def shape(self):
+        return (self.n_xi, self.ny, self.nx)
+
+    def coords(self):
+        x = (np.arange(self.nx) - self.nx // 2) * self.lx / self.nx
+        y = (np.arange(self.ny) - self.ny // 2) * self.ly / self.ny
+        return x, y
+
+
+def _glib():
+    L = lib()
+    if not getattr(L, "_grid_ready", False):
+        D = ctypes.POINTER(ctypes.c_double)
+        G = ctypes.POINTER(_Grid)
+        L.ogr_fft2.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.ogr_rates.argtypes = [G, D, D, D, D, D, D, D, D]
+        L.ogr_step.argtypes = [G, ctypes.c_double, D, D, D, D]
+        L.ogr_fields.argtypes = [G, D, D, D]
+        L.ogr_run.argtypes = [G, ctypes.c_double, ctypes.c_int, ctypes.c_int, D, D, D, D, D, D, D]
+        L.ogr_seed.argtypes = [G, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, D,
+                               ctypes.c_uint64, D]
+        L._grid_ready = True
+    return L
+
+
+def fft2(a, inverse=False):
+    """The oracle's own 2D FFT of a complex array [ny, nx] (inverse includes 1/(nx ny))."""
+    z = np.ascontiguousarray(a, np.complex128).copy()
+    _glib().ogr_fft2(z.ctypes.data, z.shape[1], z.shape[0], 1 if inverse else 0)
+    return z
+
+
+class GridState:
+    def __init__(self, grid):
+        self.rho = np.zeros(grid.shape)
+        self.jpar = np.zeros(grid.shape)
+        self.jx = np.zeros(grid.shape)
+        self.jy = np.zeros(grid.shape)
+
+    def arrays(self):
+        return self.rho, self.jpar, self.jx, self.jy
+
+
+def grid_seed(grid, kind, amp, offset=0.0, sigma_r=0.0, f=None, rng_seed=0):
+    st = GridState(grid)
+    fa = None if f is None else np.ascontiguousarray(f, np.float64)
+    _glib().ogr_seed(ctypes.byref(grid.c), int(kind), amp, offset, sigma_r, _dp(fa) if fa is not None else None,
+                     int(rng_seed), _dp(st.rho))
+    return st
+
+
+def grid_rates(grid, st):
+    out = GridState(grid)
+    _glib().ogr_rates(ctypes.byref(grid.c), *[_dp(a) for a in st.arrays()], *[_dp(a) for a in out.arrays()])
+    return out
+
+
+def grid_fields(grid, rho):
+    e2 = np.empty(grid.shape)
+    b2 = np.empty(grid.shape)
+    _glib().ogr_fields(ctypes.byref(grid.c), _dp(np.ascontiguousarray(rho, np.float64)), _dp(e2), _dp(b2))
+    return e2, b2
+
+
+def grid_run(grid, dtau, n_steps, st, out_every=1, want_fields=True, want_max=True):
+    """Advance `st` in place; returns (ln_e, ln_b [n_snap, n_xi, ny, nx], max_ln_a [n_steps])."""
+    out_every = max(1, int(out_every))
+    n_snap = -(-n_steps // out_every) if n_steps > 0 else 0
+    T = grid.n_xi * grid.ny * grid.nx
+    ln_e = np.empty((n_snap,) + grid.shape) if want_fields else None
+    ln_b = np.empty((n_snap,) + grid.shape) if want_fields else None
+    mx = np.empty(n_steps) if want_max else None
+    _glib().ogr_run(ctypes.byref(grid.c), dtau, int(n_steps), out_every, *[_dp(a) for a in st.arrays()],
+                    _dp(ln_e) if want_fields else None, _dp(ln_b) if want_fields else None,
+                    _dp(mx) if want_max else None)
+    return ln_e, ln_b, mx
