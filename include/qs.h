@@ -74,7 +74,7 @@ enum {
     QS_SEED_NOISE = 0,         /* rho = amp f(xi_j) exp(i theta), theta uniform from rng_seed */
     QS_SEED_UNIFORM = 1,       /* rho = amp f(xi_j): the extended disturbance of Appendix C */
     QS_SEED_FRONT_IMPULSE = 2, /* d_tau rho = amp/h in cell 0 at tau = 0+ (Appendix B impulse) */
-    QS_SEED_CENTROID = 3,      /* transverse-grid runs only (not in this build) */
+    QS_SEED_CENTROID = 3,      /* transverse-grid runs only: displaced beam plus noise */
     QS_SEED_NONE = 4           /* state is zero until qs_set_state */
 };
 enum {
@@ -92,11 +92,19 @@ enum {
  *   profile                     : longitudinal shape f(xi) <= 1 of n_b0 (Sec. III.D):
  *                                 FLATTOP f = 1; GAUSSIAN exp(-(xi-xi_center)^2/2 sigma_xi^2);
  *                                 TABLE profile_table[n_xi] (host) at the cell centres.
- *   geometry                    : QS_GEOM_SPECTRAL (list of k_perp); TRANSVERSE_GRID is
- *                                 rejected with QS_ERR_UNSUPPORTED in this build.
+ *   geometry                    : QS_GEOM_SPECTRAL (list of k_perp), or
+ *                                 QS_GEOM_TRANSVERSE_GRID (finite-width beam, Sec. IV.B: the
+ *                                 perturbations on a periodic nx x ny grid per xi cell; one
+ *                                 instance per context, QS_FP32 only, flags DROP_LONGITUDINAL
+ *                                 and NO_RESTORING only; see "Finite-width contexts" below).
  *   n_modes, kx, ky             : transverse wavevectors, host arrays; ky may be NULL (slab).
- *                                 Only |k| enters the dynamics.
- *   nx, ny, lx, ly, sigma_r     : transverse grid (TRANSVERSE_GRID only; ignored otherwise).
+ *                                 Only |k| enters the dynamics.  Ignored for TRANSVERSE_GRID.
+ *   nx, ny, lx, ly, sigma_r     : transverse grid (TRANSVERSE_GRID only; ignored otherwise):
+ *                                 nx, ny powers of two in [2, 256], n_xi <= 65535, periodic
+ *                                 box lx x ly,
+ *                                 points x_i = (i - nx/2) lx/nx (likewise y); the beam's
+ *                                 transverse profile g = exp(-(x^2+y^2)/(2 sigma_r^2)), or
+ *                                 g = 1 for sigma_r = 0, so n_b0 = nb f(xi) g(x, y).
  *   n_xi                        : number of xi cells (>= 1).
  *   d_tau                       : tau step of the Runge-Kutta push (> 0).
  *   precision                   : QS_FP64, or QS_FP32 (FP32 state, FP64 oscillator carry).
@@ -104,7 +112,12 @@ enum {
  *   rng_seed                      (instance i, mode m, cell j) is 2 pi u, u the top 53 bits of
  *                                 output number (i*n_modes + m)*n_xi + j of SplitMix64 started
  *                                 at rng_seed, over 2^53.
- *   centroid_offset             : TRANSVERSE_GRID only.
+ *   centroid_offset             : TRANSVERSE_GRID only: the CENTROID seed is
+ *                                 rho = (centroid_offset x / sigma_r^2 + seed_amp (2u - 1)) f g,
+ *                                 the first-order density change of a beam displaced by
+ *                                 centroid_offset in x plus uniform noise (u as for NOISE with
+ *                                 index (j ny + iy) nx + ix); NOISE is seed_amp (2u - 1) f g,
+ *                                 UNIFORM seed_amp f g.
  *   flags                       : QS_FLAG_* test hooks (0 for the physical model).
  */
 typedef struct qs_params {
@@ -299,6 +312,21 @@ qs_status qs_graph_create(qs_ctx *ctx, int32_t n_steps, int32_t out_every, void 
                           void *out_ln_b, void *out_max_ln_a, qs_graph **out);
 qs_status qs_graph_launch(qs_graph *graph);
 void qs_graph_free(qs_graph *graph);
+
+/*
+ * Finite-width contexts (geometry QS_GEOM_TRANSVERSE_GRID).  qs_step_tau advances them like
+ * spectral ones; its outputs are float32 with snapshots laid out [snap][n_xi][ny][nx] and
+ * out_max_ln_a [step] holding ln of the largest (|E|^2 + |B|^2)^(1/2) over the whole grid at
+ * the start of each step.  The state (host, float64, [n_xi][ny][nx] each): rho at cell
+ * centres, j_par on the rear face of each cell (the last face carries none), j_x and j_y at
+ * centres.  qs_grid_get_state / qs_grid_set_state read and replace it (set: all four
+ * arrays required; get: any may be NULL).  The spectral state calls, checkpoints and
+ * qs_tune return QS_ERR_UNSUPPORTED for these contexts, and the grid calls for spectral
+ * ones.  Errors: QS_ERR_ARG, QS_ERR_UNSUPPORTED, QS_ERR_HIP.
+ */
+qs_status qs_grid_get_state(qs_ctx *ctx, double *rho, double *j_par, double *j_x, double *j_y);
+qs_status qs_grid_set_state(qs_ctx *ctx, const double *rho, const double *j_par, const double *j_x,
+                            const double *j_y);
 
 /* Release the context and anything the library allocated for it.  NULL is ignored. */
 void qs_free(qs_ctx *ctx);

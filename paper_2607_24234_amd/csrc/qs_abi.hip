@@ -150,9 +150,8 @@ int64_t elem_of(int NC, int q, int var, int part) {
 
 qs_status validate_one(const qs_params &p, int i) {
     const std::string at = "instance " + std::to_string(i) + ": ";
-    if (p.geometry == QS_GEOM_TRANSVERSE_GRID)
-        return fail(QS_ERR_UNSUPPORTED, at + "geometry TRANSVERSE_GRID is not implemented in this build");
-    if (p.geometry != QS_GEOM_SPECTRAL) return fail(QS_ERR_ARG, at + "unknown geometry");
+    if (p.geometry != QS_GEOM_SPECTRAL && p.geometry != QS_GEOM_TRANSVERSE_GRID)
+        return fail(QS_ERR_ARG, at + "unknown geometry");
     if (p.n_species < 1 || p.n_species > 64) return fail(QS_ERR_ARG, at + "n_species must be in [1, 64]");
     if (!p.q || !p.m || !p.nb_over_np) return fail(QS_ERR_ARG, at + "q, m and nb_over_np are required");
     for (int s = 0; s < p.n_species; ++s) {
@@ -166,11 +165,25 @@ qs_status validate_one(const qs_params &p, int i) {
     if (p.n_xi < 1 || p.n_xi > (1 << 20)) return fail(QS_ERR_ARG, at + "n_xi must be in [1, 2^20]");
     if (!finite(p.d_tau) || !(p.d_tau > 0.0)) return fail(QS_ERR_ARG, at + "d_tau must be finite and > 0");
     if (p.precision != QS_FP64 && p.precision != QS_FP32) return fail(QS_ERR_ARG, at + "unknown precision");
-    if (p.n_modes < 1 || p.n_modes > (int64_t(1) << 26)) return fail(QS_ERR_ARG, at + "n_modes must be in [1, 2^26]");
-    if (!p.kx) return fail(QS_ERR_ARG, at + "kx is required");
-    for (int64_t m = 0; m < p.n_modes; ++m) {
-        if (!finite(p.kx[m]) || (p.ky && !finite(p.ky[m])))
-            return fail(QS_ERR_ARG, at + "non-finite wavenumber at mode " + std::to_string(m));
+    if (p.geometry == QS_GEOM_TRANSVERSE_GRID) {
+        auto pow2 = [](int v) { return v >= 2 && v <= 256 && (v & (v - 1)) == 0; };
+        if (!pow2(p.nx) || !pow2(p.ny)) return fail(QS_ERR_ARG, at + "nx and ny must be powers of two in [2, 256]");
+        if (p.n_xi > 65535) return fail(QS_ERR_ARG, at + "n_xi must be at most 65535 on the transverse grid");
+        if (!finite(p.lx) || !(p.lx > 0.0) || !finite(p.ly) || !(p.ly > 0.0))
+            return fail(QS_ERR_ARG, at + "lx and ly must be finite and > 0");
+        if (!finite(p.sigma_r) || p.sigma_r < 0.0) return fail(QS_ERR_ARG, at + "sigma_r must be finite and >= 0");
+        if (!finite(p.centroid_offset)) return fail(QS_ERR_ARG, at + "centroid_offset must be finite");
+        if ((int64_t)p.nx * p.ny * (int64_t)p.n_xi > (int64_t(1) << 31))
+            return fail(QS_ERR_ARG, at + "nx * ny * n_xi must be at most 2^31");
+        if (p.precision != QS_FP32) return fail(QS_ERR_UNSUPPORTED, at + "the transverse grid runs in FP32 only");
+        if (p.flags & QS_FLAG_STEADY_INFLOW) return fail(QS_ERR_UNSUPPORTED, at + "STEADY_INFLOW is spectral only");
+    } else {
+        if (p.n_modes < 1 || p.n_modes > (int64_t(1) << 26)) return fail(QS_ERR_ARG, at + "n_modes must be in [1, 2^26]");
+        if (!p.kx) return fail(QS_ERR_ARG, at + "kx is required");
+        for (int64_t m = 0; m < p.n_modes; ++m) {
+            if (!finite(p.kx[m]) || (p.ky && !finite(p.ky[m])))
+                return fail(QS_ERR_ARG, at + "non-finite wavenumber at mode " + std::to_string(m));
+        }
     }
     switch (p.profile) {
     case QS_PROFILE_FLATTOP: break;
@@ -186,13 +199,15 @@ qs_status validate_one(const qs_params &p, int i) {
         break;
     default: return fail(QS_ERR_ARG, at + "unknown profile");
     }
-    if (p.seed_kind == QS_SEED_CENTROID)
+    if (p.seed_kind == QS_SEED_CENTROID && p.geometry != QS_GEOM_TRANSVERSE_GRID)
         return fail(QS_ERR_UNSUPPORTED, at + "CENTROID seed needs the transverse-grid geometry");
-    if (p.seed_kind != QS_SEED_NOISE && p.seed_kind != QS_SEED_UNIFORM &&
+    if (p.seed_kind == QS_SEED_FRONT_IMPULSE && p.geometry == QS_GEOM_TRANSVERSE_GRID)
+        return fail(QS_ERR_UNSUPPORTED, at + "FRONT_IMPULSE seed is spectral only");
+    if (p.seed_kind != QS_SEED_NOISE && p.seed_kind != QS_SEED_UNIFORM && p.seed_kind != QS_SEED_CENTROID &&
         p.seed_kind != QS_SEED_FRONT_IMPULSE && p.seed_kind != QS_SEED_NONE)
         return fail(QS_ERR_ARG, at + "unknown seed_kind");
     if (!finite(p.seed_amp)) return fail(QS_ERR_ARG, at + "seed_amp must be finite");
-    if (p.seed_kind == QS_SEED_FRONT_IMPULSE) {
+    if (p.seed_kind == QS_SEED_FRONT_IMPULSE && p.geometry == QS_GEOM_SPECTRAL) {
         for (int64_t m = 0; m < p.n_modes; ++m) {
             double k2 = p.kx[m] * p.kx[m] + (p.ky ? p.ky[m] * p.ky[m] : 0.0);
             if (k2 == 0.0) return fail(QS_ERR_ARG, at + "FRONT_IMPULSE seed needs k != 0 for every mode");
@@ -209,6 +224,8 @@ qs_status make_plan(const qs_params *params, int32_t n, const qs_plan *plan, Pla
     for (int i = 0; i < n; ++i) {
         qs_status st = validate_one(params[i], i);
         if (st != QS_OK) return st;
+        if (params[i].geometry != QS_GEOM_SPECTRAL)
+            return fail(QS_ERR_ARG, "a TRANSVERSE_GRID instance must be the only instance of its context");
         if (params[i].precision != params[0].precision)
             return fail(QS_ERR_ARG, "all instances must share one precision");
         if ((params[i].flags & QS_FLAG_NO_RESTORING) != (params[0].flags & QS_FLAG_NO_RESTORING))
@@ -369,6 +386,7 @@ using namespace qs;
 
 struct qs_ctx {
     Plan pl;
+    GridCtx *grid = nullptr;   // finite-width context (then pl is unused)
     int device = 0;
     double wall_clock_hz = 1e8;  // rate of the device's constant wall clock
     hipStream_t stream = nullptr;
@@ -478,6 +496,15 @@ qs_status seed_state(qs_ctx *c, const qs_params *params) {
     return QS_OK;
 }
 
+bool is_grid(const qs_params *params, int32_t n) {
+    return params && n >= 1 && params[0].geometry == QS_GEOM_TRANSVERSE_GRID;
+}
+
+qs_status check_grid(const qs_params *params, int32_t n) {
+    if (n != 1) return fail(QS_ERR_ARG, "a TRANSVERSE_GRID instance must be the only instance of its context");
+    return validate_one(params[0], 0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -487,6 +514,7 @@ int32_t qs_abi_version(void) { return QS_ABI_VERSION; }
 const char *qs_last_error(void) { return g_err.c_str(); }
 
 size_t qs_workspace_size_ex(const qs_params *params, int32_t n_instances, const qs_plan *plan) {
+    if (is_grid(params, n_instances)) return check_grid(params, n_instances) == QS_OK ? grid_workspace_size(params[0]) : 0;
     Plan pl;
     if (make_plan(params, n_instances, plan, pl) != QS_OK) return 0;
     return pl.total;
@@ -500,6 +528,21 @@ qs_status qs_init_ex(const qs_params *params, int32_t n_instances, const qs_plan
                      void *workspace, size_t workspace_bytes, qs_ctx **out) {
     g_err.clear();
     if (!out) return fail(QS_ERR_ARG, "out is NULL");
+    if (is_grid(params, n_instances)) {
+        qs_status st = check_grid(params, n_instances);
+        if (st != QS_OK) return st;
+        if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+            return fail(QS_ERR_ARG, "workspace must be 256-byte aligned");
+        qs_ctx *c = new (std::nothrow) qs_ctx;
+        if (!c) return fail(QS_ERR_ALLOC, "host allocation of the context failed");
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(QS_ERR_HIP, "hipGetDevice failed"); }
+        std::string msg;
+        st = grid_create(params[0], workspace, workspace_bytes, c->stream, &c->grid, &msg);
+        if (st != QS_OK) { delete c; return fail(st, msg); }
+        *out = c;
+        return QS_OK;
+    }
     Plan pl;
     qs_status st = make_plan(params, n_instances, plan, pl);
     if (st != QS_OK) return st;
@@ -543,6 +586,7 @@ qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream
 
 qs_status qs_get_plan(const qs_ctx *c, qs_plan *plan, int32_t *n_workgroups, int32_t *waves_per_workgroup) {
     if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "transverse-grid contexts have no march plan");
     if (plan) {
         plan->columns_per_lane = c->pl.nc;
         plan->segment_cells = c->pl.seg_target;
@@ -563,8 +607,15 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     const bool snaps = out_ln_e != nullptr;
     if (snaps && out_every < 1) return fail(QS_ERR_ARG, "out_every must be >= 1");
     if (n_steps == 0 && !snaps) return QS_OK;
-    const Plan &pl = c->pl;
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    if (c->grid) {
+        std::string msg;
+        qs_status st = grid_step(c->grid, n_steps, out_every, out_ln_e, out_ln_b, out_max_ln_a, c->stream, &msg);
+        if (st != QS_OK) return fail(st, msg);
+        c->steps_done += n_steps;
+        return QS_OK;
+    }
+    const Plan &pl = c->pl;
     StepArgs a{};
     a.state = c->at(pl.off_state);
     a.blk_inst = reinterpret_cast<const int32_t *>(c->at(pl.off_blk));
@@ -627,6 +678,11 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
 qs_status qs_sync_check(qs_ctx *c) {
     if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    if (c->grid) {
+        std::string msg;
+        qs_status st = grid_sync_check(c->grid, c->stream, &msg);
+        return st == QS_OK ? QS_OK : fail(st, msg + " after step " + std::to_string(c->steps_done));
+    }
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
     uint32_t flag = 0;
     QS_HIP(hipMemcpy(&flag, c->at(c->pl.off_err), sizeof(flag), hipMemcpyDeviceToHost), "read error flag");
@@ -649,6 +705,7 @@ int64_t qs_steps_done(const qs_ctx *c) { return c ? c->steps_done : -1; }
 
 qs_status qs_get_state(qs_ctx *c, double *rho, double *j_par, double *j_perp, double *log2_scale) {
     if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "transverse-grid context: use qs_grid_get_state");
     const Plan &pl = c->pl;
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
@@ -704,6 +761,7 @@ qs_status qs_get_state(qs_ctx *c, double *rho, double *j_par, double *j_perp, do
 qs_status qs_set_state(qs_ctx *c, const double *rho, const double *j_par, const double *j_perp,
                        const double *log2_scale) {
     if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "transverse-grid context: use qs_grid_set_state");
     if (!rho || !j_par || !j_perp || !log2_scale) return fail(QS_ERR_ARG, "all state arrays are required");
     const Plan &pl = c->pl;
     for (int64_t M = 0; M < pl.total_modes; ++M)
@@ -775,12 +833,13 @@ uint64_t shape_hash(const Plan &pl) {
 }  // namespace
 
 size_t qs_checkpoint_size(const qs_ctx *c) {
-    if (!c) return 0;
+    if (!c || c->grid) return 0;
     return sizeof(CkptHeader) + (size_t)c->pl.state_elems * c->pl.ts + 2 * (size_t)c->pl.n_scale * sizeof(int32_t);
 }
 
 qs_status qs_save_checkpoint(qs_ctx *c, void *dst, size_t bytes) {
     if (!c || !dst) return fail(QS_ERR_ARG, "ctx and dst are required");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "checkpoints of transverse-grid contexts are not supported");
     if (bytes < qs_checkpoint_size(c)) return fail(QS_ERR_ARG, "checkpoint buffer too small");
     const Plan &pl = c->pl;
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
@@ -799,6 +858,7 @@ qs_status qs_save_checkpoint(qs_ctx *c, void *dst, size_t bytes) {
 
 qs_status qs_load_checkpoint(qs_ctx *c, const void *src, size_t bytes) {
     if (!c || !src) return fail(QS_ERR_ARG, "ctx and src are required");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "checkpoints of transverse-grid contexts are not supported");
     if (bytes < qs_checkpoint_size(c)) return fail(QS_ERR_ARG, "checkpoint too small for this context");
     const Plan &pl = c->pl;
     CkptHeader hd;
@@ -820,6 +880,12 @@ qs_status qs_load_checkpoint(qs_ctx *c, const void *src, size_t bytes) {
 
 void qs_free(qs_ctx *c) {
     if (!c) return;
+    if (c->grid) {
+        (void)hipSetDevice(c->device);
+        grid_free(c->grid, c->stream);
+        delete c;
+        return;
+    }
     if (c->owns_ws && c->ws) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
@@ -895,6 +961,7 @@ qs_status qs_tune(const qs_params *params, int32_t n_instances, int32_t steps_pe
     g_err.clear();
     if (!best) return fail(QS_ERR_ARG, "best is NULL");
     if (steps_per_call < 1) return fail(QS_ERR_ARG, "steps_per_call must be >= 1");
+    if (is_grid(params, n_instances)) return fail(QS_ERR_UNSUPPORTED, "the autotuner plans spectral contexts only");
     Plan base;
     qs_status st = make_plan(params, n_instances, nullptr, base);
     if (st != QS_OK) return st;
@@ -992,6 +1059,25 @@ qs_status qs_tune(const qs_params *params, int32_t n_instances, int32_t steps_pe
     if (ms_per_step) *ms_per_step = best_t;
     cache_store(cache, key, best_plan, best_t);
     return QS_OK;
+}
+
+qs_status qs_grid_get_state(qs_ctx *c, double *rho, double *j_par, double *j_x, double *j_y) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (!c->grid) return fail(QS_ERR_UNSUPPORTED, "not a transverse-grid context");
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    std::string msg;
+    qs_status st = grid_get_state(c->grid, rho, j_par, j_x, j_y, c->stream, &msg);
+    return st == QS_OK ? QS_OK : fail(st, msg);
+}
+
+qs_status qs_grid_set_state(qs_ctx *c, const double *rho, const double *j_par, const double *j_x, const double *j_y) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (!c->grid) return fail(QS_ERR_UNSUPPORTED, "not a transverse-grid context");
+    if (!rho || !j_par || !j_x || !j_y) return fail(QS_ERR_ARG, "all state arrays are required");
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    std::string msg;
+    qs_status st = grid_set_state(c->grid, rho, j_par, j_x, j_y, c->stream, &msg);
+    return st == QS_OK ? QS_OK : fail(st, msg);
 }
 
 // ----------------------------------------------------------------------------- graphs

@@ -1,0 +1,688 @@
+// Finite-width (transverse-grid) path for gfx950: the beam perturbations live on a periodic
+// nx x ny grid in each xi cell (Sec. IV.B, the full transverse Laplacian of Eq.
+// poisson_QSA), FP32 state with FP64 oscillator carries.
+//
+// One application of the model operator A to a state W = (rho, j_par, j_x, j_y) runs as
+// four fully parallel passes instead of a sequential slice-by-slice chain:
+//   march    : (d_xi^2 + 1) n_p = rho down every transverse column (65,536 independent
+//              columns for 256^2), exact cell propagator, FP64 carries: n_p at centres,
+//              d_xi n_p at the rear faces (and at centres for the fields);
+//   rows     : per xi slice, FFT along x of z1 = n_p + i d_xi n_p and z2 = j_x + i j_y,
+//              written transposed ([slice][kx][y]) through LDS so the next pass reads
+//              contiguous columns;
+//   columns  : per slice and column pair (kx, -kx): FFT along y, the spectral operators
+//              (Helmholtz inverse 1/(1 + k^2), gradient, divergence) using the conjugate
+//              partner at -k to split the two real fields packed in each complex transform,
+//              inverse FFT along y, in place;
+//   rows^-1  : inverse FFT along x and the pointwise rates
+//                d_tau rho = d_xi j_par - div j_perp,  d_tau j_par = -gamma^-3 Omega d_xi Psi,
+//                d_tau j_perp = gamma^-1 Omega grad Psi,
+//              fused with the Runge-Kutta stage update (Horner form W_{m+1} = U + c_m A W_m).
+// The fields for snapshots and per-step maxima take the same three transform passes on
+// (rho - n_p) + i rho and d_xi n_p.  FFTs are radix-2 Stockham (Govindaraju et al., SC'08)
+// in LDS with a twiddle table computed in FP64 on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qs_internal.h"
+
+namespace qs {
+namespace {
+
+constexpr int kRows = 8;  // rows per workgroup of the row passes
+
+struct GridArgs {
+    int nx, ny, n_xi, log_nx, log_ny;
+    int64_t P, T;          // points per slice, points in all
+    double lx, ly, h, ih;
+    double C1, S1, C2, S2;
+    bool restoring;
+    float om0;             // sum q^2 n_b / m
+    float ginv, g3inv;
+    const float *f;        // longitudinal profile [n_xi]
+    const float *g;        // transverse profile [P]
+    const float2 *twx, *twy;  // exp(-2 pi i m / n), m < n
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// Radix-2 Stockham FFTs of `cnt` transforms of length n = 2^logn stored back to back in
+// buf[0] (ping-pong with buf[1]), by all threads of the workgroup.  Forward uses
+// exp(-2 pi i k / n).  Returns the buffer index (0 or 1) that holds the result.
+__device__ int block_fft(float2 *__restrict__ b0, float2 *__restrict__ b1, int n, int logn, int cnt,
+                         const float2 *__restrict__ tw, bool inverse) {
+    float2 *in = b0, *out = b1;
+    const int half = n >> 1;
+    for (int s = 0; s < logn; ++s) {
+        const int Ns = 1 << s;
+        const int stride = n >> (s + 1);  // twiddle index step: n / (2 Ns)
+        for (int t = threadIdx.x; t < cnt * half; t += blockDim.x) {
+            const int tr = t / half, j = t % half;
+            const int k = j & (Ns - 1);
+            const float2 *src = in + tr * n;
+            float2 *dst = out + tr * n;
+            float2 w = tw[k * stride];
+            if (inverse) w.y = -w.y;
+            const float2 x0 = src[j];
+            const float2 x1 = cmul(src[j + half], w);
+            const int o = ((j - k) << 1) + k;
+            dst[o] = cadd(x0, x1);
+            dst[o + Ns] = csub(x0, x1);
+        }
+        __syncthreads();
+        float2 *tmp = in;
+        in = out;
+        out = tmp;
+    }
+    return (logn & 1) ? 1 : 0;
+}
+
+// ----------------------------------------------------------------------------- march
+// One thread per transverse point: FP64 carries down the column, loads one cell ahead.
+__global__ void __launch_bounds__(256) grid_march(GridArgs a, const float *__restrict__ rho, float *__restrict__ np_c,
+                                                  float *__restrict__ v_f, float *__restrict__ v_c) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    double y = 0.0, v = 0.0;
+    float nxt = rho[p];
+    for (int j = 0; j < a.n_xi; ++j) {
+        const float cur = nxt;
+        if (j + 1 < a.n_xi) nxt = rho[(int64_t)(j + 1) * a.P + p];
+        const double r = (double)cur;
+        double nc, yn, vn, vc;
+        if (a.restoring) {
+            const double u = y - r;
+            nc = r + a.C2 * u + a.S2 * v;
+            vc = a.C2 * v - a.S2 * u;
+            yn = r + a.C1 * u + a.S1 * v;
+            vn = a.C1 * v - a.S1 * u;
+        } else {
+            nc = y + 0.5 * a.h * v + 0.125 * a.h * a.h * r;
+            vc = v + 0.5 * a.h * r;
+            yn = y + a.h * v + 0.5 * a.h * a.h * r;
+            vn = v + a.h * r;
+        }
+        y = yn;
+        v = vn;
+        const int64_t o = (int64_t)j * a.P + p;
+        np_c[o] = (float)nc;
+        v_f[o] = (float)vn;
+        if (v_c) v_c[o] = (float)vc;
+    }
+}
+
+// ----------------------------------------------------------------------------- rows
+// mode 0 (stage): z1 = np_c + i v_f, z2 = jx + i jy
+// mode 1 (fields): z1 = (rho - np_c) + i rho, z2 = v_c
+// Output Z1, Z2: [slice][kx][y] complex.
+__global__ void __launch_bounds__(256) grid_rows_fwd(GridArgs a, int mode, const float *__restrict__ A0,
+                                                     const float *__restrict__ A1, const float *__restrict__ B0,
+                                                     const float *__restrict__ B1, float2 *__restrict__ Z1,
+                                                     float2 *__restrict__ Z2) {
+    extern __shared__ float2 sm[];
+    const int nx = a.nx, ny = a.ny;
+    const int R = min(kRows, ny);
+    const int j = blockIdx.y;
+    const int y0 = blockIdx.x * R;
+    float2 *b0 = sm, *b1 = sm + 2 * R * nx;
+    float2 *tw = sm + 4 * R * nx;
+    for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = a.twx[t];
+    const int64_t base = (int64_t)j * a.P + (int64_t)y0 * nx;
+    for (int t = threadIdx.x; t < R * nx; t += blockDim.x) {
+        const int64_t o = base + t;
+        float2 z1, z2;
+        if (mode == 0) {
+            z1 = make_float2(A0[o], A1[o]);
+            z2 = make_float2(B0[o], B1[o]);
+        } else {
+            const float r = A1[o];
+            z1 = make_float2(r - A0[o], r);
+            z2 = make_float2(B0[o], 0.f);
+        }
+        b0[t] = z1;
+        b0[R * nx + t] = z2;
+    }
+    __syncthreads();
+    const int res = block_fft(b0, b1, nx, a.log_nx, 2 * R, tw, false);
+    const float2 *o = res ? b1 : b0;
+    // transposed store: for each kx the R consecutive y values are contiguous
+    for (int t = threadIdx.x; t < nx * R; t += blockDim.x) {
+        const int kx = t / R, r = t % R;
+        const int64_t d = ((int64_t)j * nx + kx) * ny + y0 + r;
+        Z1[d] = o[r * nx + kx];
+        Z2[d] = o[(R + r) * nx + kx];
+    }
+}
+
+// ----------------------------------------------------------------------------- columns
+__device__ __forceinline__ float wavenum(int i, int n, double l) {
+    return (float)(6.283185307179586 * (double)(i <= n / 2 ? i : i - n) / l);
+}
+__device__ __forceinline__ float dwavenum(int i, int n, double l) { return i == n / 2 ? 0.f : wavenum(i, n, l); }
+
+// One workgroup per (slice, column pair kx, nx - kx), in place over Z1, Z2.  mode 0:
+// O1 = d_xi Psi + i div j, O2 = d_x Psi + i d_y Psi; mode 1: O1 = grad phi_E, O2 = grad
+// phi_B (as x + i y components), phi_E = H(rho - n_p), phi_B = H rho (all still transformed
+// along x).
+__global__ void __launch_bounds__(256) grid_cols(GridArgs a, int mode, float2 *__restrict__ Z1,
+                                                 float2 *__restrict__ Z2) {
+    extern __shared__ float2 sm[];
+    const int nx = a.nx, ny = a.ny;
+    const int j = blockIdx.y;
+    const int kxa = blockIdx.x;                 // 0 .. nx/2
+    const int kxb = (nx - kxa) % nx;            // its conjugate partner column
+    const int ncol = (kxb == kxa) ? 1 : 2;
+    float2 *b0 = sm, *b1 = sm + 4 * ny;
+    float2 *tw = sm + 8 * ny;
+    for (int t = threadIdx.x; t < ny; t += blockDim.x) tw[t] = a.twy[t];
+    // transforms: [col 0 Z1][col 0 Z2][col 1 Z1][col 1 Z2]
+    for (int t = threadIdx.x; t < 2 * ncol * ny; t += blockDim.x) {
+        const int tr = t / ny, y = t % ny;
+        const int kx = (tr >> 1) ? kxb : kxa;
+        const int64_t d = ((int64_t)j * nx + kx) * ny + y;
+        b0[t] = (tr & 1) ? Z2[d] : Z1[d];
+    }
+    __syncthreads();
+    int res = block_fft(b0, b1, ny, a.log_ny, 2 * ncol, tw, false);
+    float2 *F = res ? b1 : b0;   // spectra
+    float2 *G = res ? b0 : b1;   // outputs
+    const float inv = 1.0f / ((float)nx * (float)ny);
+    for (int t = threadIdx.x; t < ncol * ny; t += blockDim.x) {
+        const int c = t / ny, ky = t % ny;
+        const int kx = c ? kxb : kxa;
+        const int cp = (ncol == 1) ? 0 : 1 - c;          // column holding -kx
+        const int kyp = (ny - ky) % ny;
+        const float2 z1 = F[(2 * c) * ny + ky], z1p = cconj(F[(2 * cp) * ny + kyp]);
+        const float2 z2 = F[(2 * c + 1) * ny + ky], z2p = cconj(F[(2 * cp + 1) * ny + kyp]);
+        const float kxv = wavenum(kx, nx, a.lx), kyv = wavenum(ky, ny, a.ly);
+        const float kap = 1.0f / (1.0f + kxv * kxv + kyv * kyv);
+        const float dx = dwavenum(kx, nx, a.lx), dy = dwavenum(ky, ny, a.ly);
+        // the two real fields packed in z: F(re) = (z + conj z(-k))/2, F(im) = (z - conj z(-k))/(2i)
+        const float2 re1 = make_float2(0.5f * (z1.x + z1p.x), 0.5f * (z1.y + z1p.y));
+        const float2 im1 = make_float2(0.5f * (z1.y - z1p.y), -0.5f * (z1.x - z1p.x));
+        float2 o1, o2;
+        if (mode == 0) {
+            const float2 jxh = make_float2(0.5f * (z2.x + z2p.x), 0.5f * (z2.y + z2p.y));
+            const float2 jyh = make_float2(0.5f * (z2.y - z2p.y), -0.5f * (z2.x - z2p.x));
+            // kappa F(v_f) + i (i dx Jx + i dy Jy) = kappa V - (dx Jx + dy Jy)
+            o1 = make_float2(kap * im1.x - (dx * jxh.x + dy * jyh.x), kap * im1.y - (dx * jxh.y + dy * jyh.y));
+            // (i dx - dy) kappa N
+            const float2 nk = make_float2(kap * re1.x, kap * re1.y);
+            o2 = make_float2(-dx * nk.y - dy * nk.x, dx * nk.x - dy * nk.y);
+        } else {
+            const float2 dk = make_float2(kap * re1.x, kap * re1.y);   // kappa F(rho - n_p)
+            const float2 rk = make_float2(kap * im1.x, kap * im1.y);   // kappa F(rho)
+            o1 = make_float2(-dx * dk.y - dy * dk.x, dx * dk.x - dy * dk.y);
+            o2 = make_float2(-dx * rk.y - dy * rk.x, dx * rk.x - dy * rk.y);
+        }
+        G[(2 * c) * ny + ky] = make_float2(o1.x * inv, o1.y * inv);
+        G[(2 * c + 1) * ny + ky] = make_float2(o2.x * inv, o2.y * inv);
+    }
+    __syncthreads();
+    // inverse along y, in place over the inputs
+    res = block_fft(G, F, ny, a.log_ny, 2 * ncol, tw, true);
+    const float2 *R0 = res ? F : G;
+    for (int t = threadIdx.x; t < 2 * ncol * ny; t += blockDim.x) {
+        const int tr = t / ny, y = t % ny;
+        const int kx = (tr >> 1) ? kxb : kxa;
+        const int64_t d = ((int64_t)j * nx + kx) * ny + y;
+        if (tr & 1) Z2[d] = R0[t];
+        else Z1[d] = R0[t];
+    }
+}
+
+// Fields: O3 = (y-transform, kappa / (nx ny), inverse y-transform) of one x-transformed column
+// of v_c, before grid_cols reuses that buffer.
+// mode-1 helper: O3 columns were kept in F slots; a separate small pass transforms them.
+__global__ void __launch_bounds__(256) grid_cols_o3(GridArgs a, const float2 *__restrict__ Z2in, float2 *__restrict__ Z3) {
+    extern __shared__ float2 sm[];
+    const int nx = a.nx, ny = a.ny;
+    const int j = blockIdx.y, kx = blockIdx.x;
+    float2 *b0 = sm, *b1 = sm + ny, *tw = sm + 2 * ny;
+    for (int t = threadIdx.x; t < ny; t += blockDim.x) tw[t] = a.twy[t];
+    const int64_t base = ((int64_t)j * nx + kx) * ny;
+    for (int t = threadIdx.x; t < ny; t += blockDim.x) b0[t] = Z2in[base + t];
+    __syncthreads();
+    int res = block_fft(b0, b1, ny, a.log_ny, 1, tw, false);
+    float2 *F = res ? b1 : b0, *G = res ? b0 : b1;
+    const float inv = 1.0f / ((float)nx * (float)ny);
+    for (int ky = threadIdx.x; ky < ny; ky += blockDim.x) {
+        const float kxv = wavenum(kx, nx, a.lx), kyv = wavenum(ky, ny, a.ly);
+        const float kap = inv / (1.0f + kxv * kxv + kyv * kyv);
+        G[ky] = make_float2(kap * F[ky].x, kap * F[ky].y);
+    }
+    __syncthreads();
+    res = block_fft(G, F, ny, a.log_ny, 1, tw, true);
+    const float2 *R0 = res ? F : G;
+    for (int t = threadIdx.x; t < ny; t += blockDim.x) Z3[base + t] = R0[t];
+}
+
+// ----------------------------------------------------------------------------- rows^-1
+__device__ __forceinline__ uint32_t fkey_pos(float x) { return __builtin_bit_cast(uint32_t, x); }
+
+// mode 0: rates and the stage update.  W_in: the stage input (its j_par for the face
+// difference); U: the step's start state; W_out = U + c A W_in, or (final) U += dtau A W_in.
+// mode 1: fields: snapshot ln|E|, ln|B| and the box maximum of |E|^2 + |B|^2.
+struct RowInvArgs {
+    int mode;
+    const float2 *O1, *O2, *O3;
+    const float *in_jpar;
+    const float *U[4];
+    float *out[4];
+    float coef;
+    int final_update;
+    float *ln_e, *ln_b;        // snapshot (mode 1) or null
+    uint32_t *max_key;         // one entry (mode 1) or null
+    uint32_t *err;             // non-finite flag (final update)
+};
+
+__global__ void __launch_bounds__(256) grid_rows_inv(GridArgs a, RowInvArgs r) {
+    extern __shared__ float2 sm[];
+    const int nx = a.nx, ny = a.ny;
+    const int R = min(kRows, ny);
+    const int j = blockIdx.y;
+    const int y0 = blockIdx.x * R;
+    const int ntr = r.mode == 1 ? 3 : 2;
+    float2 *b0 = sm, *b1 = sm + ntr * R * nx, *tw = sm + 2 * ntr * R * nx;
+    for (int t = threadIdx.x; t < nx; t += blockDim.x) tw[t] = a.twx[t];
+    for (int t = threadIdx.x; t < nx * R; t += blockDim.x) {
+        const int kx = t / R, rr = t % R;
+        const int64_t d = ((int64_t)j * nx + kx) * ny + y0 + rr;
+        b0[rr * nx + kx] = r.O1[d];
+        b0[(R + rr) * nx + kx] = r.O2[d];
+        if (ntr == 3) b0[(2 * R + rr) * nx + kx] = r.O3[d];
+    }
+    __syncthreads();
+    const int res = block_fft(b0, b1, nx, a.log_nx, ntr * R, tw, true);
+    const float2 *o = res ? b1 : b0;
+    float amax = 0.f;
+    const float fj = a.f[j];
+    const float fn = j + 1 < a.n_xi ? a.f[j + 1] : 0.f;
+    for (int t = threadIdx.x; t < R * nx; t += blockDim.x) {
+        const int rr = t / nx, x = t % nx;
+        const int64_t pt = (int64_t)(y0 + rr) * nx + x;
+        const int64_t e = (int64_t)j * a.P + pt;
+        const float2 v1 = o[rr * nx + x], v2 = o[(R + rr) * nx + x];
+        if (r.mode == 0) {
+            const float gp = a.g[pt];
+            const float om_c = a.om0 * fj * gp;
+            const float om_f = j + 1 < a.n_xi ? a.om0 * gp * 0.5f * (fj + fn) : 0.f;
+            const float pin = r.in_jpar[e];
+            const float pprev = j > 0 ? r.in_jpar[e - a.P] : 0.f;
+            float rate[4];
+            rate[0] = (pin - pprev) * (float)a.ih - v1.y;
+            rate[1] = j + 1 < a.n_xi ? -a.g3inv * om_f * v1.x : 0.f;
+            rate[2] = a.ginv * om_c * v2.x;
+            rate[3] = a.ginv * om_c * v2.y;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float nv = r.U[q][e] + r.coef * rate[q];
+                r.out[q][e] = nv;
+                if (q == 0 && r.final_update && !(fabsf(nv) <= 3.0e38f)) r.err[0] = 1u;
+            }
+        } else {
+            const float2 v3 = o[(2 * R + rr) * nx + x];
+            const float e2 = v3.x * v3.x + v1.x * v1.x + v1.y * v1.y;
+            const float b2 = v2.x * v2.x + v2.y * v2.y;
+            if (r.ln_e) {
+                r.ln_e[e] = 0.5f * logf(e2);
+                r.ln_b[e] = 0.5f * logf(b2);
+            }
+            const float a2 = e2 + b2;
+            amax = (a2 > amax || !(a2 <= a2)) ? a2 : amax;
+        }
+    }
+    if (r.mode == 1 && r.max_key) {
+        // wave maximum, then one atomic per wave (non-negative floats order as unsigned ints)
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float other = __shfl_xor(amax, off);
+            amax = (other > amax || !(other <= other)) ? other : amax;
+        }
+        if ((threadIdx.x & 63) == 0) atomicMax(r.max_key, fkey_pos(amax));
+    }
+}
+
+__global__ void grid_max_finish(uint32_t *keys, float *out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = 0.5f * logf(__builtin_bit_cast(float, keys[i]));
+}
+
+__global__ void __launch_bounds__(256) grid_zero_u32(uint32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__device__ inline uint64_t gsm64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// seeds: 0 noise amp (2u-1) f g, 1 uniform amp f g, 3 centroid offset x/sigma^2 f g + noise
+__global__ void __launch_bounds__(256) grid_seed(GridArgs a, int kind, double amp, double offset, double sigma_r,
+                                                 uint64_t seed, float *__restrict__ rho) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.T) return;
+    const int j = (int)(i / a.P);
+    const int64_t pt = i % a.P;
+    const int ix = (int)(pt % a.nx);
+    const double x = (double)(ix - a.nx / 2) * a.lx / a.nx;
+    const double fg = (double)a.f[j] * (double)a.g[pt];
+    const double u = (double)(gsm64(seed, (uint64_t)i) >> 11) * (1.0 / 9007199254740992.0);
+    double r = 0.0;
+    if (kind == QS_SEED_NOISE) r = amp * (2.0 * u - 1.0) * fg;
+    else if (kind == QS_SEED_UNIFORM) r = amp * fg;
+    else if (kind == QS_SEED_CENTROID) r = (sigma_r > 0.0 ? offset * x / (sigma_r * sigma_r) : 0.0) * fg + amp * (2.0 * u - 1.0) * fg;
+    rho[i] = (float)r;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- host
+struct GridCtx {
+    GridArgs a{};
+    double dtau = 0.0;
+    void *mem = nullptr;
+    bool owns = false;
+    float *U[4], *Wa[4], *Wb[4];
+    float *np_c, *v_f, *v_c;
+    float2 *Z1, *Z2, *Z3;
+    float *f, *g;
+    float2 *twx, *twy;
+    uint32_t *err, *keys;
+    int max_keys = 0;
+};
+
+namespace {
+
+unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+size_t grid_bytes(int64_t T, int64_t P, int n_xi, int nx, int ny, size_t *offs) {
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += (b + 255) / 256 * 256; return r; };
+    int k = 0;
+    for (int i = 0; i < 12; ++i) offs[k++] = take((size_t)T * 4);        // U, Wa, Wb
+    for (int i = 0; i < 3; ++i) offs[k++] = take((size_t)T * 4);         // np_c, v_f, v_c
+    for (int i = 0; i < 3; ++i) offs[k++] = take((size_t)T * 8);         // Z1, Z2, Z3
+    offs[k++] = take((size_t)n_xi * 4);                                  // f
+    offs[k++] = take((size_t)P * 4);                                     // g
+    offs[k++] = take((size_t)nx * 8);                                    // twx
+    offs[k++] = take((size_t)ny * 8);                                    // twy
+    offs[k++] = take(16);                                                // err
+    offs[k++] = take(4096 * 4);                                          // keys (per-step maxima)
+    return o;
+}
+
+int ilog2(int n) { int l = 0; while ((1 << l) < n) ++l; return l; }
+
+size_t lds_rows(const GridArgs &a, int ntr) {
+    const int R = std::min(kRows, a.ny);
+    return (size_t)(2 * ntr * R * a.nx + a.nx) * sizeof(float2);
+}
+size_t lds_cols(const GridArgs &a) { return (size_t)(8 * a.ny + a.ny) * sizeof(float2); }
+
+// one application of A to W_in, combined with the stage update
+hipError_t apply(GridCtx *c, float *const *Win, float *const *Wout, float coef, bool final_update, hipStream_t s) {
+    const GridArgs &a = c->a;
+    const int R = std::min(kRows, a.ny);
+    hipLaunchKernelGGL(grid_march, dim3(nblk(a.P)), dim3(256), 0, s, a, Win[0], c->np_c, c->v_f, (float *)nullptr);
+    hipLaunchKernelGGL(grid_rows_fwd, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, 0, c->np_c, c->v_f,
+                       Win[2], Win[3], c->Z1, c->Z2);
+    hipLaunchKernelGGL(grid_cols, dim3(a.nx / 2 + 1, a.n_xi), dim3(256), lds_cols(a), s, a, 0, c->Z1, c->Z2);
+    RowInvArgs r{};
+    r.mode = 0;
+    r.O1 = c->Z1;
+    r.O2 = c->Z2;
+    r.in_jpar = Win[1];
+    for (int q = 0; q < 4; ++q) { r.U[q] = c->U[q]; r.out[q] = Wout[q]; }
+    r.coef = coef;
+    r.final_update = final_update ? 1 : 0;
+    r.err = c->err;
+    hipLaunchKernelGGL(grid_rows_inv, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, r);
+    return hipGetLastError();
+}
+
+// fields of the state U: snapshot (ln_e/ln_b may be null) and/or the maximum into key
+hipError_t fields(GridCtx *c, float *ln_e, float *ln_b, uint32_t *key, hipStream_t s) {
+    const GridArgs &a = c->a;
+    const int R = std::min(kRows, a.ny);
+    hipLaunchKernelGGL(grid_march, dim3(nblk(a.P)), dim3(256), 0, s, a, c->U[0], c->np_c, c->v_f, c->v_c);
+    hipLaunchKernelGGL(grid_rows_fwd, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, 1, c->np_c, c->U[0],
+                       c->v_c, (const float *)nullptr, c->Z1, c->Z2);
+    // O3 = H v_c from the untouched Z2 spectrum column by column, before grid_cols
+    // overwrites Z2
+    hipLaunchKernelGGL(grid_cols_o3, dim3(a.nx, a.n_xi), dim3(256), (size_t)3 * a.ny * sizeof(float2), s, a, c->Z2,
+                       c->Z3);
+    hipLaunchKernelGGL(grid_cols, dim3(a.nx / 2 + 1, a.n_xi), dim3(256), lds_cols(a), s, a, 1, c->Z1, c->Z2);
+    RowInvArgs r{};
+    r.mode = 1;
+    r.O1 = c->Z1;
+    r.O2 = c->Z2;
+    r.O3 = c->Z3;
+    r.ln_e = ln_e;
+    r.ln_b = ln_b;
+    r.max_key = key;
+    hipLaunchKernelGGL(grid_rows_inv, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 3), s, a, r);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t grid_allow_lds(const GridCtx *c) {
+    const size_t rows = lds_rows(c->a, 3), cols = lds_cols(c->a);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&grid_rows_fwd),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)rows);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&grid_rows_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)rows);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&grid_cols), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)cols);
+    return e;
+}
+
+size_t grid_workspace_size(const qs_params &p) {
+    size_t offs[32];
+    const int64_t P = (int64_t)p.nx * p.ny;
+    return grid_bytes(P * p.n_xi, P, p.n_xi, p.nx, p.ny, offs);
+}
+
+qs_status grid_create(const qs_params &p, void *workspace, size_t ws_bytes, hipStream_t s, GridCtx **out,
+                      std::string *err) {
+    GridCtx *c = new (std::nothrow) GridCtx;
+    if (!c) { *err = "host allocation failed"; return QS_ERR_ALLOC; }
+    GridArgs &a = c->a;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.n_xi = p.n_xi;
+    a.log_nx = ilog2(p.nx);
+    a.log_ny = ilog2(p.ny);
+    a.P = (int64_t)p.nx * p.ny;
+    a.T = a.P * p.n_xi;
+    a.lx = p.lx;
+    a.ly = p.ly;
+    a.h = p.length / p.n_xi;
+    a.ih = 1.0 / a.h;
+    a.C1 = std::cos(a.h);
+    a.S1 = std::sin(a.h);
+    a.C2 = std::cos(0.5 * a.h);
+    a.S2 = std::sin(0.5 * a.h);
+    a.restoring = !(p.flags & QS_FLAG_NO_RESTORING);
+    double om0 = 0.0;
+    for (int sp = 0; sp < p.n_species; ++sp) om0 += p.q[sp] * p.q[sp] * p.nb_over_np[sp] / p.m[sp];
+    a.om0 = (float)om0;
+    a.ginv = (float)(1.0 / p.gamma_b);
+    a.g3inv = (p.flags & QS_FLAG_DROP_LONGITUDINAL) ? 0.f : (float)(1.0 / (p.gamma_b * p.gamma_b * p.gamma_b));
+    c->dtau = p.d_tau;
+    size_t offs[32];
+    const size_t bytes = grid_bytes(a.T, a.P, a.n_xi, a.nx, a.ny, offs);
+    if (workspace) {
+        if (ws_bytes < bytes) { delete c; *err = "workspace too small"; return QS_ERR_ALLOC; }
+        c->mem = workspace;
+    } else {
+        if (hipMalloc(&c->mem, bytes) != hipSuccess) { delete c; *err = "hipMalloc of the grid buffers failed"; return QS_ERR_ALLOC; }
+        c->owns = true;
+    }
+    char *b = static_cast<char *>(c->mem);
+    int k = 0;
+    for (int q = 0; q < 4; ++q) c->U[q] = (float *)(b + offs[k++]);
+    for (int q = 0; q < 4; ++q) c->Wa[q] = (float *)(b + offs[k++]);
+    for (int q = 0; q < 4; ++q) c->Wb[q] = (float *)(b + offs[k++]);
+    c->np_c = (float *)(b + offs[k++]);
+    c->v_f = (float *)(b + offs[k++]);
+    c->v_c = (float *)(b + offs[k++]);
+    c->Z1 = (float2 *)(b + offs[k++]);
+    c->Z2 = (float2 *)(b + offs[k++]);
+    c->Z3 = (float2 *)(b + offs[k++]);
+    c->f = (float *)(b + offs[k++]);
+    c->g = (float *)(b + offs[k++]);
+    c->twx = (float2 *)(b + offs[k++]);
+    c->twy = (float2 *)(b + offs[k++]);
+    c->err = (uint32_t *)(b + offs[k++]);
+    c->keys = (uint32_t *)(b + offs[k++]);
+    c->max_keys = 4096;
+    a.f = c->f;
+    a.g = c->g;
+    a.twx = c->twx;
+    a.twy = c->twy;
+    // tables
+    std::vector<float> f(p.n_xi), g(a.P);
+    for (int j = 0; j < p.n_xi; ++j) {
+        const double xi = (j + 0.5) * a.h;
+        if (p.profile == QS_PROFILE_FLATTOP) f[j] = 1.f;
+        else if (p.profile == QS_PROFILE_GAUSSIAN) {
+            const double z = (xi - p.xi_center) / p.sigma_xi;
+            f[j] = (float)std::exp(-0.5 * z * z);
+        } else f[j] = (float)p.profile_table[j];
+    }
+    for (int iy = 0; iy < p.ny; ++iy)
+        for (int ix = 0; ix < p.nx; ++ix) {
+            const double x = (ix - p.nx / 2) * p.lx / p.nx, y = (iy - p.ny / 2) * p.ly / p.ny;
+            g[(size_t)iy * p.nx + ix] =
+                p.sigma_r > 0.0 ? (float)std::exp(-(x * x + y * y) / (2.0 * p.sigma_r * p.sigma_r)) : 1.f;
+        }
+    auto table = [](int n) {
+        std::vector<float2> t(n);
+        for (int m = 0; m < n; ++m) t[m] = make_float2((float)std::cos(-2.0 * M_PI * m / n), (float)std::sin(-2.0 * M_PI * m / n));
+        return t;
+    };
+    const std::vector<float2> tx = table(p.nx), ty = table(p.ny);
+    hipError_t e = hipMemcpyAsync(c->f, f.data(), f.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->g, g.data(), g.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->twx, tx.data(), tx.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->twy, ty.data(), ty.size() * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(c->err, 0, 16, s);
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) e = hipMemsetAsync(c->U[q], 0, (size_t)a.T * 4, s);
+    if (e == hipSuccess) e = grid_allow_lds(c);
+    if (e == hipSuccess && p.seed_kind != QS_SEED_NONE) {
+        hipLaunchKernelGGL(grid_seed, dim3(nblk(a.T)), dim3(256), 0, s, a, p.seed_kind, p.seed_amp, p.centroid_offset,
+                           p.sigma_r, p.rng_seed, c->U[0]);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host tables die here
+    if (e != hipSuccess) {
+        if (c->owns) (void)hipFree(c->mem);
+        delete c;
+        *err = std::string("grid set-up: ") + hipGetErrorString(e);
+        return QS_ERR_HIP;
+    }
+    *out = c;
+    return QS_OK;
+}
+
+void grid_free(GridCtx *c, hipStream_t s) {
+    if (!c) return;
+    (void)hipStreamSynchronize(s);
+    if (c->owns) (void)hipFree(c->mem);
+    delete c;
+}
+
+qs_status grid_step(GridCtx *c, int32_t n_steps, int32_t out_every, void *ln_e, void *ln_b, void *max_ln_a,
+                    hipStream_t s, std::string *err) {
+    const GridArgs &a = c->a;
+    const float dt = (float)c->dtau;
+    const float cm[3] = {(float)(0.25 * c->dtau), (float)(c->dtau / 3.0), (float)(0.5 * c->dtau)};
+    hipError_t e = hipSuccess;
+    if (n_steps == 0) {
+        e = fields(c, static_cast<float *>(ln_e), static_cast<float *>(ln_b), nullptr, s);
+        if (e != hipSuccess) { *err = std::string("grid fields: ") + hipGetErrorString(e); return QS_ERR_HIP; }
+        return QS_OK;
+    }
+    for (int s0 = 0; s0 < n_steps && e == hipSuccess; s0 += c->max_keys) {
+        const int cnt = std::min(c->max_keys, n_steps - s0);
+        if (max_ln_a) hipLaunchKernelGGL(grid_zero_u32, dim3(nblk(cnt)), dim3(256), 0, s, c->keys, cnt);
+        for (int i = 0; i < cnt && e == hipSuccess; ++i) {
+            const int st = s0 + i;
+            const bool snap = ln_e && (st % out_every == 0);
+            if (snap || max_ln_a) {
+                const int64_t so = snap ? (int64_t)(st / out_every) * a.T : 0;
+                e = fields(c, snap ? static_cast<float *>(ln_e) + so : nullptr, snap ? static_cast<float *>(ln_b) + so : nullptr,
+                           max_ln_a ? c->keys + i : nullptr, s);
+            }
+            // Horner-form RK4: W1 = U, W_{m+1} = U + c_m A W_m, U' = U + dtau A W4
+            if (e == hipSuccess) e = apply(c, c->U, c->Wa, cm[0], false, s);
+            if (e == hipSuccess) e = apply(c, c->Wa, c->Wb, cm[1], false, s);
+            if (e == hipSuccess) e = apply(c, c->Wb, c->Wa, cm[2], false, s);
+            if (e == hipSuccess) e = apply(c, c->Wa, c->U, dt, true, s);
+        }
+        if (e == hipSuccess && max_ln_a) {
+            hipLaunchKernelGGL(grid_max_finish, dim3(nblk(cnt)), dim3(256), 0, s, c->keys,
+                               static_cast<float *>(max_ln_a) + s0, cnt);
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) { *err = std::string("grid step: ") + hipGetErrorString(e); return QS_ERR_HIP; }
+    return QS_OK;
+}
+
+qs_status grid_sync_check(GridCtx *c, hipStream_t s, std::string *err) {
+    uint32_t flag = 0;
+    if (hipStreamSynchronize(s) != hipSuccess || hipMemcpy(&flag, c->err, 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        *err = "grid: synchronize";
+        return QS_ERR_HIP;
+    }
+    if (flag) {
+        (void)hipMemset(c->err, 0, 4);
+        *err = "non-finite state on the transverse grid";
+        return QS_ERR_NUMERIC;
+    }
+    return QS_OK;
+}
+
+qs_status grid_get_state(GridCtx *c, double *rho, double *jpar, double *jx, double *jy, hipStream_t s, std::string *err) {
+    double *dst[4] = {rho, jpar, jx, jy};
+    std::vector<float> tmp(c->a.T);
+    if (hipStreamSynchronize(s) != hipSuccess) { *err = "synchronize"; return QS_ERR_HIP; }
+    for (int q = 0; q < 4; ++q) {
+        if (!dst[q]) continue;
+        if (hipMemcpy(tmp.data(), c->U[q], tmp.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) { *err = "copy state"; return QS_ERR_HIP; }
+        for (int64_t i = 0; i < c->a.T; ++i) dst[q][i] = tmp[i];
+    }
+    return QS_OK;
+}
+
+qs_status grid_set_state(GridCtx *c, const double *rho, const double *jpar, const double *jx, const double *jy,
+                         hipStream_t s, std::string *err) {
+    const double *src[4] = {rho, jpar, jx, jy};
+    std::vector<float> tmp(c->a.T);
+    if (hipStreamSynchronize(s) != hipSuccess) { *err = "synchronize"; return QS_ERR_HIP; }
+    for (int q = 0; q < 4; ++q) {
+        for (int64_t i = 0; i < c->a.T; ++i) tmp[i] = (float)src[q][i];
+        if (q == 1)  // no flux through the rear face of the beam
+            for (int64_t i = (int64_t)(c->a.n_xi - 1) * c->a.P; i < c->a.T; ++i) tmp[i] = 0.f;
+        if (hipMemcpy(c->U[q], tmp.data(), tmp.size() * 4, hipMemcpyHostToDevice) != hipSuccess) { *err = "copy state"; return QS_ERR_HIP; }
+    }
+    return QS_OK;
+}
+
+}  // namespace qs

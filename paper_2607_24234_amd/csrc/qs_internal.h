@@ -93,6 +93,20 @@ hipError_t launch_key_decode(int precision, void *p, int64_t n, hipStream_t s);
 hipError_t launch_seed(int precision, int nc, int n_blocks, int max_n_xi, const SeedArgs &a,
                        hipStream_t s);
 
+// finite-width (transverse-grid) contexts (qs_grid.hip)
+struct GridCtx;
+size_t grid_workspace_size(const qs_params &p);
+qs_status grid_create(const qs_params &p, void *workspace, size_t ws_bytes, hipStream_t s, GridCtx **out,
+                      std::string *err);
+void grid_free(GridCtx *c, hipStream_t s);
+qs_status grid_step(GridCtx *c, int32_t n_steps, int32_t out_every, void *ln_e, void *ln_b, void *max_ln_a,
+                    hipStream_t s, std::string *err);
+qs_status grid_sync_check(GridCtx *c, hipStream_t s, std::string *err);
+qs_status grid_get_state(GridCtx *c, double *rho, double *jpar, double *jx, double *jy, hipStream_t s,
+                         std::string *err);
+qs_status grid_set_state(GridCtx *c, const double *rho, const double *jpar, const double *jx, const double *jy,
+                         hipStream_t s, std::string *err);
+
 // text returned by qs_last_error on this thread
 void set_last_error(const std::string &msg);
 

@@ -86,3 +86,15 @@ def gaussian_profile(n_xi, length, center, sigma):
     h = length / n_xi
     xi = (np.arange(n_xi) + 0.5) * h
     return np.exp(-0.5 * ((xi - center) / sigma) ** 2)
+
+
+SEED_CENTROID = 3
+
+
+def finite_width(nx=256, ny=256, n_xi=8192, n_steps=500, length=200.0, box=16.0, sigma_r=0.5,
+                 nb=0.05, gamma=2000.0, d_tau=2.0, seed=0):
+    """Narrow electron beam on a transverse grid: Gaussian radial profile, flat top in xi,
+    seeded by a centroid offset of 1e-3 sigma_r (hosing) plus 1e-6 density noise."""
+    return dict(species=[ELECTRON + (nb,)], gamma=gamma, length=length, n_xi=n_xi,
+                nx=nx, ny=ny, lx=box, ly=box, sigma_r=sigma_r, d_tau=d_tau, n_steps=n_steps,
+                seed_kind=SEED_CENTROID, seed_amp=1e-6, centroid_offset=1e-3 * sigma_r, rng_seed=seed)

@@ -85,7 +85,7 @@ _lib = None
 
 EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace_size_ex", "qs_init",
            "qs_init_ex", "qs_get_plan", "qs_tune", "qs_graph_create", "qs_graph_launch", "qs_graph_free",
-           "qs_step_tau", "qs_mlp_param_count", "qs_mlp_create", "qs_mlp_set_params", "qs_mlp_get_params",
+           "qs_step_tau", "qs_grid_get_state", "qs_grid_set_state", "qs_mlp_param_count", "qs_mlp_create", "qs_mlp_set_params", "qs_mlp_get_params",
            "qs_mlp_forward", "qs_mlp_grads", "qs_mlp_get_grads", "qs_mlp_set_grads", "qs_mlp_adamw",
            "qs_mlp_train_step", "qs_mlp_free", "qs_growth_targets", "qs_growth_sample",
            "qs_growth_features", "qs_growth_calibrate", "qs_growth_map",
@@ -154,6 +154,9 @@ def lib():
     L.qs_growth_calibrate.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     L.qs_growth_map.restype = ctypes.c_int
     L.qs_growth_map.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp]
+    for name in ("qs_grid_get_state", "qs_grid_set_state"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [vp, _D, _D, _D, _D]
     L.qs_step_tau.restype = ctypes.c_int
     L.qs_step_tau.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.qs_sync_check.restype = ctypes.c_int
@@ -195,7 +198,7 @@ class _Instance:
         self.q = np.ascontiguousarray([s[0] for s in sp], np.float64)
         self.m = np.ascontiguousarray([s[1] for s in sp], np.float64)
         self.nb = np.ascontiguousarray([s[2] for s in sp], np.float64)
-        self.kx = np.ascontiguousarray(inst["kx"], np.float64)
+        self.kx = np.ascontiguousarray(inst.get("kx", np.zeros(0)), np.float64)
         ky = inst.get("ky")
         self.ky = None if ky is None else np.ascontiguousarray(ky, np.float64)
         tab = inst.get("profile_table")
@@ -219,6 +222,10 @@ class _Instance:
         p.seed_amp = float(inst.get("seed_amp", 1e-6))
         p.rng_seed = int(inst.get("rng_seed", 0)) & (2**64 - 1)
         p.flags = int(inst.get("flags", 0))
+        p.nx, p.ny = int(inst.get("nx", 0)), int(inst.get("ny", 0))
+        p.lx, p.ly = float(inst.get("lx", 0.0)), float(inst.get("ly", 0.0))
+        p.sigma_r = float(inst.get("sigma_r", 0.0))
+        p.centroid_offset = float(inst.get("centroid_offset", 0.0))
         self.p = p
         self.n_modes = len(self.kx)
         self.n_xi = p.n_xi
@@ -377,6 +384,72 @@ def growth_calibrate(net, X, T, table):
 def growth_map(net, table, tol, q, mode, out, used_solver=None, stream=None):
     _check(lib().qs_growth_map(net.h if net is not None else None, _vp(table), float(tol), _vp(q), int(q.shape[0]),
                                int(mode), _vp(out), _vp(used_solver), _stream_ptr(stream)))
+
+
+class GridSolver:
+    """A finite-width context (geometry TRANSVERSE_GRID, FP32) over one instance dict with
+    keys nx, ny, lx, ly, sigma_r, centroid_offset besides the usual ones."""
+
+    def __init__(self, inst, device=None, stream=None):
+        import torch
+        self.torch = torch
+        inst = dict(inst)
+        inst["geometry"] = GEOM_TRANSVERSE_GRID
+        self._inst = _Instance(inst, QS_FP32)
+        self._params = (QSParams * 1)(self._inst.p)
+        self.shape = (int(inst["n_xi"]), int(inst["ny"]), int(inst["nx"]))
+        self.cells = int(np.prod(self.shape))
+        L = lib()
+        nbytes = int(L.qs_workspace_size(self._params, 1))
+        if nbytes == 0:
+            _check(L.qs_init(self._params, 1, None, None, 0, ctypes.byref(ctypes.c_void_p())))
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream() if stream is None else stream
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            ctx = ctypes.c_void_p()
+            _check(L.qs_init(self._params, 1, ctypes.c_void_p(self.stream.cuda_stream),
+                             ctypes.c_void_p(self.workspace.data_ptr()), nbytes, ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    def step(self, n_steps, out_every=1, snapshots=False, max_ln_a=False, out=None):
+        t = self.torch
+        res = {} if out is None else out
+        if snapshots:
+            n_snap = 1 if n_steps == 0 else -(-n_steps // max(1, out_every))
+            if "ln_e" not in res:
+                res["ln_e"] = t.empty((n_snap,) + self.shape, dtype=t.float32, device=self.device)
+                res["ln_b"] = t.empty((n_snap,) + self.shape, dtype=t.float32, device=self.device)
+        if max_ln_a and n_steps > 0 and "max_ln_a" not in res:
+            res["max_ln_a"] = t.empty(n_steps, dtype=t.float32, device=self.device)
+        pe = ctypes.c_void_p(res["ln_e"].data_ptr()) if snapshots else None
+        pb = ctypes.c_void_p(res["ln_b"].data_ptr()) if snapshots else None
+        pm = ctypes.c_void_p(res["max_ln_a"].data_ptr()) if (max_ln_a and n_steps > 0) else None
+        _check(lib().qs_step_tau(self.ctx, int(n_steps), int(max(1, out_every)), pe, pb, pm))
+        return res
+
+    def sync_check(self):
+        _check(lib().qs_sync_check(self.ctx))
+
+    def get_state(self):
+        arrs = [np.empty(self.shape) for _ in range(4)]
+        _check(lib().qs_grid_get_state(self.ctx, *[_dp(a) for a in arrs]))
+        return dict(zip(("rho", "j_par", "j_x", "j_y"), arrs))
+
+    def set_state(self, st):
+        arrs = [np.ascontiguousarray(st[k], np.float64).reshape(self.shape) for k in ("rho", "j_par", "j_x", "j_y")]
+        _check(lib().qs_grid_set_state(self.ctx, *[_dp(a) for a in arrs]))
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().qs_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune(instances, precision=QS_FP32, steps_per_call=100):

@@ -74,12 +74,41 @@ def test_invalid_arguments_rejected_on_host(bad, needle):
     assert needle in L.qs_last_error().decode()
 
 
-def test_unsupported_geometry_reported():
+def _grid_inst(**kw):
+    from paper_2607_24234_amd import inputs
+    d = inputs.finite_width(nx=16, ny=8, n_xi=32, n_steps=2)
+    d.update(kw)
+    return d
+
+
+def test_transverse_grid_arguments():
     qs, L = _lib()
-    insts = [qs._Instance(_inst(geometry=qs.GEOM_TRANSVERSE_GRID), qs.QS_FP32)]
-    arr = (qs.QSParams * 1)(*[x.p for x in insts])
-    ctx = ctypes.c_void_p()
-    assert L.qs_init(arr, 1, None, None, 0, ctypes.byref(ctx)) == qs.QS_ERR_UNSUPPORTED
+    ok = qs._Instance(_grid_inst(geometry=qs.GEOM_TRANSVERSE_GRID), qs.QS_FP32)
+    arr = (qs.QSParams * 1)(ok.p)
+    # state (4 x 3 FP32 fields) + fields scratch: at least 19 floats per point
+    assert L.qs_workspace_size(arr, 1) >= 16 * 8 * 32 * 4 * 19
+    cases = [(dict(nx=12), qs.QS_ERR_ARG, "powers of two"), (dict(lx=0.0), qs.QS_ERR_ARG, "lx"),
+             (dict(sigma_r=-1.0), qs.QS_ERR_ARG, "sigma_r"), (dict(flags=4), qs.QS_ERR_UNSUPPORTED, "STEADY"),
+             (dict(seed_kind=2), qs.QS_ERR_UNSUPPORTED, "spectral only")]
+    for kw, status, needle in cases:
+        inst = qs._Instance(_grid_inst(geometry=qs.GEOM_TRANSVERSE_GRID, **kw), qs.QS_FP32)
+        arr = (qs.QSParams * 1)(inst.p)
+        ctx = ctypes.c_void_p()
+        assert L.qs_init(arr, 1, None, None, 0, ctypes.byref(ctx)) == status, kw
+        assert needle in L.qs_last_error().decode(), kw
+    # FP64 is not offered on the grid; a grid instance cannot share a context
+    inst = qs._Instance(_grid_inst(geometry=qs.GEOM_TRANSVERSE_GRID), qs.QS_FP64)
+    arr = (qs.QSParams * 1)(inst.p)
+    assert L.qs_init(arr, 1, None, None, 0, ctypes.byref(ctypes.c_void_p())) == qs.QS_ERR_UNSUPPORTED
+    two = (qs.QSParams * 2)(ok.p, ok.p)
+    assert L.qs_init(two, 2, None, None, 0, ctypes.byref(ctypes.c_void_p())) == qs.QS_ERR_ARG
+    spec = qs._Instance(_inst(), qs.QS_FP32)
+    mixed = (qs.QSParams * 2)(spec.p, ok.p)
+    assert L.qs_init(mixed, 2, None, None, 0, ctypes.byref(ctypes.c_void_p())) == qs.QS_ERR_ARG
+    # the centroid seed needs the grid
+    bad = qs._Instance(_inst(seed_kind=3), qs.QS_FP32)
+    arr = (qs.QSParams * 1)(bad.p)
+    assert L.qs_init(arr, 1, None, None, 0, ctypes.byref(ctypes.c_void_p())) == qs.QS_ERR_UNSUPPORTED
 
 
 def test_mixed_precision_rejected():
