@@ -80,6 +80,191 @@ def cpu_baseline(inst, seconds=15.0):
                       "(FP64, per-step max ln A output), %.1f s wall" % (n_modes, inst["n_xi"], steps, dt)}
 
 
+def _line(metric, value, unit, K, W, ms, dtype, config, roofline, cpu, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """The 256-instance parameter sweep (128 modes each, 128..8192 cells, 200 steps) as one
+    library call of 200 steps (one persistent launch) with per-step max ln A."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import inputs, qs
+    insts = inputs.batched()
+    K = insts[0]["n_steps"]
+    s = qs.Solver(insts, precision=qs.QS_FP32)
+    buf = torch.empty((K, s.total_modes), dtype=torch.float32, device="cuda")
+    L = qs.lib()
+    qs._check(L.qs_step_tau(s.ctx, 5, 1, None, None, buf.data_ptr()))
+    torch.cuda.synchronize()
+    s2 = qs.Solver(insts, precision=qs.QS_FP32)       # timed from the initial state
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(s2.stream)
+    qs._check(L.qs_step_tau(s2.ctx, K, 1, None, None, buf.data_ptr()))
+    e1.record(s2.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s2.sync_check()
+    cells = sum(len(d["kx"]) * d["n_xi"] for d in insts)
+    launch = e0.elapsed_time(e1) * 1e-3
+    achieved = 48 * cells * K / launch / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from helpers import oracle_run
+        O.build()
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+        pick = [0, 64, 128, 192]
+        t = time.perf_counter()
+        done = 0
+        for i in pick:
+            oracle_run(insts[i], 20, instance=i, n_threads=threads)
+            done += len(insts[i]["kx"]) * insts[i]["n_xi"] * 20
+        dt = time.perf_counter() - t
+        cpu = {"value": done / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+               "sample": "instances 0, 64, 128, 192 (all 128 modes, all cells) x 20 steps, FP64, "
+                         "per-step max ln A; %.1f s wall" % dt}
+    _line(METRIC, cells * K / wall, "cell-updates/s", K, 0, wall / K * 1e3, "f32",
+          {"workload": "batched sweep: 256 instances x 128 modes, log-uniform n_b in [1e-3, 1e-1], "
+                       "gamma in [10, 1e4], L in [5, 200], 128..8192 cells, 200 steps, noise seed 1e-6",
+           "cells_per_step": cells, "plan": s2.plan()},
+          {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+           "kernel": "march_kernel (persistent, xi-segmented), one launch = 200 steps of all instances",
+           "algorithmic_bytes_per_launch": 48 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
+
+
+GRID_FLOPS_PER_CELL = 1330.0   # four 2D FFTs per slice per stage (5 N log2 N each) x 4 stages
+
+
+def bench_finite_width(args):
+    """The finite-width narrow beam: 256 x 256 transverse grid over 16 c/w_p, 8192 cells,
+    Gaussian sigma_r = 0.5, n_b = 0.05, gamma = 2000, centroid seed; K steps with per-step
+    max ln A over the grid."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import inputs, qs
+    K = 10 if args.steps == 2000 else args.steps
+    W = 1
+    d = inputs.finite_width()
+    s = qs.GridSolver(d)
+    s.step(W, max_ln_a=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s.stream)
+    out = s.step(K, max_ln_a=True)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.sync_check()
+    cells = s.cells
+    step_s = e0.elapsed_time(e1) * 1e-3 / K
+    achieved = GRID_FLOPS_PER_CELL * cells / step_s / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        O.build()
+        n = 8
+        x = (np.arange(256) - 128) * 16 / 256
+        g = np.exp(-(x[None, :] ** 2 + x[:, None] ** 2) / (2 * 0.5 ** 2))
+        G = O.Grid(256, 256, n, 16.0, 16.0, 200.0 / 8192, 2000.0, np.broadcast_to(0.05 * g, (n, 256, 256)).copy())
+        st = O.grid_seed(G, 3, 1e-6, offset=5e-4, sigma_r=0.5)
+        t = time.perf_counter()
+        O.grid_run(G, 2.0, 1, st, want_fields=False, want_max=True)
+        dt = time.perf_counter() - t
+        cpu = {"value": 256 * 256 * n / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+               "sample": "256 x 256 grid x %d cells x 1 step with the field evaluation, FP64, "
+                         "single thread; %.1f s wall" % (n, dt)}
+    _line(METRIC, cells * K / wall, "cell-updates/s", K, W, wall / K * 1e3, "f32",
+          {"workload": "finite width: 256x256 grid over 16 c/w_p, 8192 xi cells (L = 200), Gaussian "
+                       "sigma_r = 0.5, n_b/n_p = 0.05, gamma_b = 2000, d_tau = 2, centroid 1e-3 sigma_r "
+                       "+ 1e-6 noise", "cells_per_step": cells,
+           "max_ln_a_last": float(out["max_ln_a"][-1].item())},
+          {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
+           "frac": achieved / 157.3, "traffic": None,
+           "kernel": "one tau-step (4 stage evaluations: march, row FFT, column FFT + spectral "
+                     "operators, inverse row FFT + update; plus the field pass)",
+           "algorithmic_flops_per_cell": GRID_FLOPS_PER_CELL, "gpu_ms_per_step": step_s * 1e3}, cpu)
+
+
+def bench_surrogate(args):
+    """Growth-map queries: the network trained on the batched uniform-seed sweep against the
+    solver, with the held-out error table that routes queries."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import qs, surrogate as S
+
+    def log(msg):
+        print("[surrogate] %s" % msg, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    X, T = S.examples(S.sweep_instances(seed=0), int(1e7), 1)
+    Xh, Th = S.examples(S.sweep_instances(seed=1), int(2e6), 2)
+    ts = T[:200000].cpu().numpy()
+    net = qs.MLP(max_batch=65536)
+    net.set_params(qs.pack_params(S.initial_params(0, float(ts.mean()), float(ts.std()))))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log("data %.1f s" % (t1 - t0))
+    S.train(net, X, T, epochs=args.epochs, batch=8192, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log("trained %.1f s" % (t2 - t1))
+    err = S.held_out_errors(net, Xh, Th)
+    table = S.calibrate(net, Xh, Th)
+    n_q = int(1e8)
+    chunk = int(1e7)
+    q = torch.as_tensor(S.query_box(chunk, 3), device="cuda")
+    out = torch.empty(chunk, device="cuda")
+    qs.growth_map(net, table, 1e-2, q[:1024], qs.GROWTH_SURROGATE, out[:1024])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n_q // chunk):
+        qs.growth_map(net, table, 1e-2, q, qs.GROWTH_SURROGATE, out)
+    e1.record()
+    torch.cuda.synchronize()
+    sur_s = e0.elapsed_time(e1) * 1e-3
+    log("surrogate %.3f s for %d queries" % (sur_s, n_q))
+    n_s = 64
+    t = time.perf_counter()
+    qs.growth_map(None, None, 0.0, q[:n_s], qs.GROWTH_SOLVER, out[:n_s])
+    torch.cuda.synchronize()
+    sol_s = (time.perf_counter() - t) / n_s
+    log("solver %.3f s per scattered query" % sol_s)
+    n_a = 512
+    used = torch.zeros(n_a, dtype=torch.uint8, device="cuda")
+    auto = torch.empty(n_a, device="cuda")
+    t = time.perf_counter()
+    qs.growth_map(net, table, 1e-2, q[:n_a], qs.GROWTH_AUTO, auto, used)
+    torch.cuda.synchronize()
+    auto_s = (time.perf_counter() - t) / n_a
+    log("auto %.4f s per query" % auto_s)
+    frac = float(used.float().mean().item())
+    qps = n_q / sur_s
+    tf = 1.58e6 * qps / 1e12
+    _line(METRIC, qps, "queries/s", args.epochs, 0, sur_s / (n_q // chunk) * 1e3, "bf16",
+          {"workload": "growth-map queries uniform over log n_b in [-3, -1], log gamma in [1, 4], k in "
+                       "[0.05, 4], xi in [0, 200], tau in [0, tau_f]; network 5-512x4-1 trained on the "
+                       "batched uniform-seed sweep (1e7 examples), held out: a second sweep (2e6)",
+           "queries": n_q, "train_s": t2 - t1, "data_s": t1 - t0, "held_out": err},
+          {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,
+           "traffic": None, "kernel": "network forward (3 bf16 512x512 layers on the matrix cores, "
+                                      "fp32 first/last layers), 1.58 MFLOP per query"},
+          None,
+          surrogate_s_per_query=sur_s / n_q, solver_s_per_query=sol_s,
+          speedup_vs_solver=sol_s / (sur_s / n_q),
+          auto_tol=1e-2, auto_fraction_to_solver=frac, auto_s_per_query=auto_s)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +274,12 @@ def main():
     ap.add_argument("--snapshot-every", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate"],
+                    default="spectral3d",
+                    help="spectral3d (default, the headline line); batched: 256-instance sweep in "
+                         "one persistent launch; finite_width: 256^2 transverse grid x 8192 cells; "
+                         "surrogate: growth-map queries, network against solver")
+    ap.add_argument("--epochs", type=int, default=40, help="surrogate training epochs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (x3) and exit: "
                          "the reference reading for HBM traffic counters")
@@ -115,6 +306,10 @@ def main():
     from paper_2607_24234_amd import inputs, qs
 
     torch.cuda.set_device(0)
+    if args.workload != "spectral3d":
+        {"batched": bench_batched, "finite_width": bench_finite_width,
+         "surrogate": bench_surrogate}[args.workload](args)
+        return
     inst = inputs.spectral3d()
     prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64
     solver = qs.Solver([inst], precision=prec)
