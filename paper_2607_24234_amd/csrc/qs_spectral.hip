@@ -22,8 +22,10 @@
 
 #include "qs_internal.h"
 
-// Tuning knobs of the step kernel (compile time): cells per register tile and the
-// occupancy the register allocator targets (waves per SIMD).
+// Cells of state loads the march keeps in flight ahead of the one it computes.
+#ifndef QS_PREFETCH
+#define QS_PREFETCH 3
+#endif
 
 namespace qs {
 namespace {
@@ -313,7 +315,6 @@ march_kernel(StepArgs a) {
     double y[4][NC], v[4][NC];  // oscillator carries per stage: n_p and d_xi n_p at the front face
     TC pp[4][NC];               // stage inputs of P' at the front face of the current cell
     TC scale[MPL], rmax[MPL], a2max[MPL];
-    (void)scale;
 
     // One segment pass of one tau-step: all four stages per cell, the fields of the state at
     // tau_n (stage-1 values) and the update.
@@ -327,9 +328,10 @@ march_kernel(StepArgs a) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int t = NC >= 2 ? c / 2 : 0;
-                r0[c] = (TC)x[0 * NC + c];
-                P0[c] = (TC)x[1 * NC + c];
-                T0[c] = (TC)x[2 * NC + c];
+                // stored values times the pending exact power of two (1 when none)
+                r0[c] = (TC)x[0 * NC + c] * scale[t];
+                P0[c] = (TC)x[1 * NC + c] * scale[t];
+                T0[c] = (TC)x[2 * NC + c] * scale[t];
                 cTO[c] = cT[t] * Oc;
                 cPO[c] = cP[t] * Of;
             }
@@ -407,39 +409,45 @@ march_kernel(StepArgs a) {
                 }
             }
         };
-        // Cell c0 first (it may carry the front condition), then c0+1..c1-1 with a one-cell
-        // prefetch ping-ponged between two register sets, unrolled by two so that neither
-        // the buffers nor the carries need copies at the loop edge.  Loads past the end of
-        // the block's region are bounds-checked by the descriptor (0 returned, unused).
+        // Cell c0 first (it may carry the front condition), then c0+1..c1-1 with the loads
+        // of cell j+D issued before cell j is computed, into a ring of D+1 register sets
+        // indexed by compile-time constants (the loop is unrolled D+1 times), so neither
+        // the buffers nor the carries are copied at the loop edge and every wait covers only
+        // the oldest loads.  Loads past the end of the block's region are bounds-checked by
+        // the descriptor (0 returned, unused).
         using first_t = std::integral_constant<bool, true>;
         using rest_t = std::integral_constant<bool, false>;
-        TS xa[XW], xb[XW];
-        ldx(c0, xa);
-        ldx(c0 + 1, xb);
-        cell(c0, xa, first_t{});
+        constexpr int D = QS_PREFETCH;
+        TS xs[D + 1][XW];
+#pragma unroll
+        for (int d = 0; d <= D; ++d) ldx(c0 + d, xs[d]);
+        cell(c0, xs[0], first_t{});
         int j = c0 + 1;
-        while (j < c1) {
-            ldx(j + 1, xa);
-            cell(j, xb, rest_t{});
-            ++j;
-            if (j >= c1) break;
-            ldx(j + 1, xb);
-            cell(j, xa, rest_t{});
-            ++j;
+        // whole groups of D+1 cells: ring slot (k+1) mod (D+1) holds cell j+k
+        for (; j + D < c1; j += D + 1) {
+#pragma unroll
+            for (int k = 0; k <= D; ++k) {
+                ldx(j + k + D, xs[k]);
+                cell(j + k, xs[(k + 1) % (D + 1)], rest_t{});
+            }
         }
+        // the last (at most D) cells are already loaded
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            if (j + k < c1) cell(j + k, xs[(k + 1) % (D + 1)], rest_t{});
     };
 
     constexpr int R = RenormRange<TS>::R;
     for (int n = 0; n < a.n_steps; ++n) {
-        // apply the pending renormalization of each (mode, segment); a fields-only launch
-        // (no update) reads the stored values with their current exponent
-        bool need = false;
+        // apply the pending renormalization of each (mode, segment): this step's loads are
+        // multiplied by 2^-e; a fields-only launch (no update) reads the stored values with
+        // their current exponent
 #pragma unroll
         for (int t = 0; t < MPL; ++t) {
+            scale[t] = (TC)1;
             if (a.update) {
                 L[t] += ep[t];
                 scale[t] = (TC)ldexp(1.0, -ep[t]);
-                need |= ep[t] != 0;
             }
             rmax[t] = (TC)0;
             a2max[t] = (TC)0;
@@ -469,17 +477,6 @@ march_kernel(StepArgs a) {
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) __hip_atomic_store(&taken[slot - 1], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        // a mode of this wave left the renormalization range: rescale the segment's stored
-        // state by its exact power of two first (rare; kept out of the hot pass)
-        if (__any(need) && a.update) {
-            for (int j = c0; j < c1; ++j)
-#pragma unroll
-                for (int r = 0; r < ROW; ++r) {
-                    const int t = NC >= 2 ? (r % NC) / 2 : 0;
-                    const int off = (j * ROW + r) * RB;
-                    bstore((TS)((TC)bload<TS>(rs, voff, off) * scale[t]), rs, voff, off);
-                }
         }
         pass(wave == 0 && steady);
 
