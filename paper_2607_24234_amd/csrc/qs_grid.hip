@@ -19,7 +19,7 @@
 //                d_tau j_perp = gamma^-1 Omega grad Psi,
 //              fused with the Runge-Kutta stage update (Horner form W_{m+1} = U + c_m A W_m).
 // The fields for snapshots and per-step maxima take the same three transform passes on
-// (rho - n_p) + i rho and d_xi n_p.  FFTs are radix-2 Stockham (Govindaraju et al., SC'08)
+// (rho - n_p) + i rho and d_xi n_p.  FFTs are radix-4 Stockham (Govindaraju et al., SC'08)
 // in LDS with a twiddle table computed in FP64 on the host.
 #include <hip/hip_runtime.h>
 
@@ -55,35 +55,77 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
-// Radix-2 Stockham FFTs of `cnt` transforms of length n = 2^logn stored back to back in
-// buf[0] (ping-pong with buf[1]), by all threads of the workgroup.  Forward uses
-// exp(-2 pi i k / n).  Returns the buffer index (0 or 1) that holds the result.
-__device__ int block_fft(float2 *__restrict__ b0, float2 *__restrict__ b1, int n, int logn, int cnt,
-                         const float2 *__restrict__ tw, bool inverse) {
+// Stockham FFTs (Govindaraju et al., SC'08) of `cnt` transforms of length N = 2^LOGN stored
+// back to back in b0, ping-ponging with b1, by all threads of the workgroup: one radix-2
+// stage first when LOGN is odd, then radix-4 stages (4 points, 3 twiddles per butterfly,
+// half the passes and barriers of radix 2).  Forward uses exp(-2 pi i k / N) from the
+// table tw[N].  Returns 1 if the result is in b1, else 0.
+template <int LOGN>
+__device__ int fft_stockham(float2 *__restrict__ b0, float2 *__restrict__ b1, int cnt,
+                            const float2 *__restrict__ tw, bool inverse) {
+    constexpr int N = 1 << LOGN;
     float2 *in = b0, *out = b1;
-    const int half = n >> 1;
-    for (int s = 0; s < logn; ++s) {
-        const int Ns = 1 << s;
-        const int stride = n >> (s + 1);  // twiddle index step: n / (2 Ns)
-        for (int t = threadIdx.x; t < cnt * half; t += blockDim.x) {
-            const int tr = t / half, j = t % half;
-            const int k = j & (Ns - 1);
-            const float2 *src = in + tr * n;
-            float2 *dst = out + tr * n;
-            float2 w = tw[k * stride];
-            if (inverse) w.y = -w.y;
-            const float2 x0 = src[j];
-            const float2 x1 = cmul(src[j + half], w);
-            const int o = ((j - k) << 1) + k;
-            dst[o] = cadd(x0, x1);
-            dst[o + Ns] = csub(x0, x1);
+    int res = 0;
+    if (LOGN & 1) {
+        constexpr int H = N / 2;
+        for (int t = threadIdx.x; t < cnt * H; t += blockDim.x) {
+            const int tr = t >> (LOGN - 1), j = t & (H - 1);
+            const float2 x0 = in[tr * N + j], x1 = in[tr * N + j + H];
+            out[tr * N + 2 * j] = cadd(x0, x1);
+            out[tr * N + 2 * j + 1] = csub(x0, x1);
         }
         __syncthreads();
-        float2 *tmp = in;
-        in = out;
-        out = tmp;
+        float2 *tmp = in; in = out; out = tmp;
+        res ^= 1;
     }
-    return (logn & 1) ? 1 : 0;
+    if (LOGN >= 2) {
+        constexpr int Q = N / 4;
+#pragma unroll
+        for (int s = (LOGN & 1); s < LOGN; s += 2) {
+            const int Ns = 1 << s;
+            for (int t = threadIdx.x; t < cnt * Q; t += blockDim.x) {
+                const int tr = t >> (LOGN - 2), j = t & (Q - 1);
+                const int k = j & (Ns - 1);
+                const float2 *src = in + tr * N;
+                float2 *dst = out + tr * N;
+                float2 v0 = src[j], v1 = src[j + Q], v2 = src[j + 2 * Q], v3 = src[j + 3 * Q];
+                if (k) {
+                    const int ts = k * (N >> (s + 2));   // k N / (4 Ns)
+                    float2 w1 = tw[ts], w2 = tw[2 * ts], w3 = tw[3 * ts];
+                    if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+                    v1 = cmul(v1, w1);
+                    v2 = cmul(v2, w2);
+                    v3 = cmul(v3, w3);
+                }
+                const float2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3), d = csub(v1, v3);
+                // forward: -i d; inverse: +i d
+                const float2 a3 = inverse ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+                const int o = ((j - k) << 2) + k;
+                dst[o] = cadd(a0, a2);
+                dst[o + Ns] = cadd(a1, a3);
+                dst[o + 2 * Ns] = csub(a0, a2);
+                dst[o + 3 * Ns] = csub(a1, a3);
+            }
+            __syncthreads();
+            float2 *tmp = in; in = out; out = tmp;
+            res ^= 1;
+        }
+    }
+    return res;
+}
+
+__device__ int block_fft(float2 *__restrict__ b0, float2 *__restrict__ b1, int n, int logn, int cnt,
+                         const float2 *__restrict__ tw, bool inverse) {
+    switch (logn) {
+    case 1: return fft_stockham<1>(b0, b1, cnt, tw, inverse);
+    case 2: return fft_stockham<2>(b0, b1, cnt, tw, inverse);
+    case 3: return fft_stockham<3>(b0, b1, cnt, tw, inverse);
+    case 4: return fft_stockham<4>(b0, b1, cnt, tw, inverse);
+    case 5: return fft_stockham<5>(b0, b1, cnt, tw, inverse);
+    case 6: return fft_stockham<6>(b0, b1, cnt, tw, inverse);
+    case 7: return fft_stockham<7>(b0, b1, cnt, tw, inverse);
+    default: return fft_stockham<8>(b0, b1, cnt, tw, inverse);
+    }
 }
 
 // ----------------------------------------------------------------------------- march
