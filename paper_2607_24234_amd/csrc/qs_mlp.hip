@@ -382,6 +382,236 @@ __global__ void __launch_bounds__(256) convert_weights(const float *__restrict__
     WTb[(int64_t)l * D * D + (int64_t)in * D + o] = b;
 }
 
+
+// bfloat16 W2..W4 in matrix-core A-fragment order, [3][16][32][64][8]: block (fb, ks) holds
+// W[32 fb + lane%32][16 ks + 8 (lane/32) + i] for lane < 64, i < 8, one contiguous KiB
+__global__ void __launch_bounds__(256) pack_weights(const float *__restrict__ P, bf16_t *__restrict__ Wp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * (int64_t)D * D) return;
+    const int l = (int)(i / ((int64_t)D * D));
+    const int64_t e = i % ((int64_t)D * D);
+    const int o = (int)(e / D), in = (int)(e % D);
+    const int fb = o / 32, ks = in / 16, lane = o % 32 + 32 * ((in % 16) / 8);
+    Wp[((((int64_t)l * 16 + fb) * 32 + ks) * 64 + lane) * 8 + in % 8] = f2bf(P[off_w(l) + e]);
+}
+
+// ----------------------------------------------------------------------------- fused inference
+// One persistent kernel runs the whole network on tiles of 64 queries; only x and y touch
+// memory outside the workgroup.  The tile's activations stay in LDS as bfloat16
+// [64 queries][512 features] with a row pitch of 520 elements (the 32 rows of a fragment
+// read then fall on distinct banks).  Wave w of the four computes output features
+// 128 w .. 128 w + 127 of each layer for all 64 queries as the transposed product
+// z^T = W h^T: the weights are the A operand, read from L2 in fragment order (Wp), the
+// activations the B operand, read from LDS.  The first layer is a float32 matrix-core
+// product with the bias as a sixth input of value 1; the last layer is a float32 dot
+// product per query, summed over the four waves in a fixed order.  GELU takes Phi from a
+// table of cubic Hermite pieces (phi_table below).  Two workgroups share a compute unit, so
+// one's activation work overlaps the other's matrix products.
+constexpr int FT = 64;              // queries per tile
+constexpr int ALD = D + 8;          // LDS row pitch of the activation tile (bfloat16 elements)
+constexpr int KS = D / 16;          // k-steps of a 512-long product
+constexpr int PHI_N = 192;          // cubic pieces of Phi on [-6, 6], 16 per unit of x
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+struct InferArgs {
+    const float *x;       // [n][5], n <= kInferChunk
+    int32_t n;
+    const float *P;       // float32 parameters
+    const bf16x8 *Wp;     // packed W2..W4
+    const f32x4 *phi;     // [PHI_N] (c0, c1, c2, c3) per piece
+    float *y;             // [n]
+};
+constexpr int32_t kInferChunk = 1 << 25;   // queries per launch (byte offsets stay 32-bit)
+
+// raw buffer access: a 128-bit descriptor (base, size in bytes), a per-lane VGPR offset and a
+// wave-uniform SGPR offset; where the per-lane offset (which the range check covers) is past
+// the size, loads return 0 and stores are dropped
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+
+// x Phi(x): piece i = floor(16 x + 96) (clamped), Phi = c0 + f (c1 + f (c2 + f c3)) with
+// f the position in the piece; beyond [-6, 6] Phi is taken at the end of the range
+// (|Phi - 0| or |Phi - 1| < 1e-9 there).  NaN propagates through the final product.
+__device__ __forceinline__ float gelu_tab(float v, const f32x4 *tab) {
+    const float t = fminf(fmaxf(fmaf(v, 16.f, 0.5f * PHI_N), 0.f), (float)PHI_N);
+    const int i = min((int)t, PHI_N - 1);
+    const float f = t - (float)i;
+    const f32x4 c = tab[i];
+    return v * fmaf(f, fmaf(f, fmaf(f, c.w, c.z), c.y), c.x);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ float bf_lo(uint32_t p) { return __builtin_bit_cast(float, p << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t p) { return __builtin_bit_cast(float, p & 0xFFFF0000u); }
+
+__global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
+    __shared__ __attribute__((aligned(16))) bf16_t act[FT * ALD];
+    __shared__ f32x4 tab[PHI_N];
+    __shared__ f32x4 bw[D];              // b2, b3, b4, W5: four rows of 512 floats
+    __shared__ float red[4][FT];
+    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 31, lh = lane >> 5;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int i = tid; i < PHI_N; i += 256) tab[i] = a.phi[i];
+    for (int i = tid; i < D; i += 256) {
+        const int r = i / (D / 4), e = i % (D / 4);
+        const float *src = r < 3 ? a.P + off_b(r) : a.P + OFF_W5;
+        bw[i] = *reinterpret_cast<const f32x4 *>(src + 4 * e);
+    }
+    const rsrc_t rx = make_rsrc(a.x, (uint32_t)a.n * DIN * 4);
+    const rsrc_t ry = make_rsrc(a.y, (uint32_t)a.n * 4);
+    const rsrc_t rw = make_rsrc(a.Wp, 3u * D * D * 2);
+    // first layer (32 x 32 x 2 float32 products, k = inputs 0..4 and the bias): lane holds
+    // W1[32 (4 w + fb) + lane%32][2 s + lane/32], the sixth column being b1
+    float w1[4][3];
+#pragma unroll
+    for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int f = 32 * (4 * w + fb) + lr, c = 2 * s + lh;
+            w1[fb][s] = c < DIN ? a.P[OFF_W1 + (int64_t)f * DIN + c] : a.P[OFF_B1 + f];
+        }
+    const int tiles = (a.n + FT - 1) / FT;
+    // inputs of tile t for the B operand: query 32 qb + lane%32, input 2 s + lane/32 (the
+    // sixth input is 1).  The whole byte offset is in the per-lane operand, which the
+    // descriptor's range check covers: queries past n read 0.  Tiles past the last are not read.
+    auto load_x = [&](int t, float (&xb)[2][3]) {
+        if (t >= tiles) return;
+        const int voff = t * FT * DIN * 4 + (lr * DIN + lh) * 4;
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const float v = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rx, voff + (32 * qb * DIN + 2 * s) * 4, 0, 0));
+                xb[qb][s] = (s < 2 || lh == 0) ? v : 1.f;
+            }
+    };
+    // bias (or W5) row r for the four consecutive features of accumulator group (fb, j)
+    auto brow = [&](int r, int fb, int j) { return bw[r * (D / 4) + (32 * (4 * w + fb) + 8 * j + 4 * lh) / 4]; };
+    // GELU of acc (+ bias row r unless r < 0) as bfloat16 into the activation tile: element
+    // 4 j + e of acc[fb][qb] is feature 32 (4 w + fb) + 8 j + 4 (lane/32) + e of query
+    // 32 qb + lane%32
+    auto store = [&](f32x16 (&acc)[4][2], int r) {
+        bf16_t *row = act + lr * ALD + 128 * w + 4 * lh;
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const f32x4 b = r >= 0 ? brow(r, fb, j) : f32x4{0.f, 0.f, 0.f, 0.f};
+                    float h[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) h[e] = gelu_tab(acc[fb][qb][4 * j + e] + b[e], tab);
+                    const uint2 pk = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
+                    *reinterpret_cast<uint2 *>(row + 32 * qb * ALD + 32 * fb + 8 * j) = pk;
+                    __builtin_amdgcn_sched_barrier(0);   // bounds the table reads in flight
+                }
+    };
+    float xn[2][3] = {};
+    load_x(blockIdx.x, xn);
+    __syncthreads();
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        f32x16 acc[4][2];
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+            for (int qb = 0; qb < 2; ++qb) {
+                f32x16 z = {};
+#pragma unroll
+                for (int s = 0; s < 3; ++s) z = __builtin_amdgcn_mfma_f32_32x32x2f32(w1[fb][s], xn[qb][s], z, 0, 0, 0);
+                acc[fb][qb] = z;
+            }
+        load_x(t + gridDim.x, xn);   // next tile's inputs, in flight during this tile
+        store(acc, -1);
+        __syncthreads();
+        for (int l = 0; l < 3; ++l) {
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[fb][qb][r] = 0.f;
+            // weight fragment (fb, ks) of this wave: 1 KiB block ((l 16 + 4 w + fb) KS + ks)
+            const int wbase = (l * 16 + 4 * w) * KS * 1024;
+            auto wload = [&](int fb, int ks) {
+                return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rw, lane * 16, wbase + (fb * KS + ks) * 1024, 0));
+            };
+            auto aload = [&](int qb, int ks) {
+                return *reinterpret_cast<const bf16x8 *>(act + (32 * qb + lr) * ALD + 16 * ks + 8 * lh);
+            };
+            // weight fragments in a ring of four k-steps, each loaded two k-steps ahead, and
+            // activation fragments one k-step ahead; the group barriers keep that order
+            bf16x8 A[4][4], B[2][2];
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb) {
+                A[0][fb] = wload(fb, 0);
+                A[1][fb] = wload(fb, 1);
+            }
+            B[0][0] = aload(0, 0);
+            B[0][1] = aload(1, 0);
+#pragma nounroll
+            for (int kk = 0; kk < KS; kk += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ks = kk + u;
+                    const int kn = min(ks + 2, KS - 1), kb = min(ks + 1, KS - 1);   // the tail reloads the last step
+#pragma unroll
+                    for (int fb = 0; fb < 4; ++fb) A[(u + 2) % 4][fb] = wload(fb, kn);
+#pragma unroll
+                    for (int qb = 0; qb < 2; ++qb) B[(u + 1) % 2][qb] = aload(qb, kb);
+#pragma unroll
+                    for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+                        for (int qb = 0; qb < 2; ++qb)
+                            acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], acc[fb][qb], 0, 0, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);   // 4 global (buffer) reads
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // 2 LDS reads
+                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // 8 matrix products
+                }
+            }
+            if (l < 2) {
+                __syncthreads();     // every wave has read this layer's input
+                store(acc, l);
+                __syncthreads();
+            } else {
+                // last layer: y = W5 . bf16(GELU(z4)) + b5
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) {
+                    float sum = 0.f;
+#pragma unroll
+                    for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const f32x4 b = brow(2, fb, j), w5 = brow(3, fb, j);
+                            const uint32_t p0 = pack_bf16(gelu_tab(acc[fb][qb][4 * j] + b[0], tab),
+                                                          gelu_tab(acc[fb][qb][4 * j + 1] + b[1], tab));
+                            const uint32_t p1 = pack_bf16(gelu_tab(acc[fb][qb][4 * j + 2] + b[2], tab),
+                                                          gelu_tab(acc[fb][qb][4 * j + 3] + b[3], tab));
+                            sum += w5[0] * bf_lo(p0) + w5[1] * bf_hi(p0) + w5[2] * bf_lo(p1) + w5[3] * bf_hi(p1);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    sum += __shfl_xor(sum, 32);
+                    if (lh == 0) red[w][32 * qb + lr] = sum;
+                }
+                __syncthreads();     // also: every wave has read the last layer's input
+                if (tid < FT) {
+                    const float v = (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) + a.P[OFF_B5];
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ry, (t * FT + tid) * 4, 0, 0);
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------- host
@@ -393,6 +623,9 @@ struct qs_mlp {
     void *mem = nullptr;    // one allocation for everything below
     float *P, *G, *Mo, *Vo;
     bf16_t *Wb, *WTb;       // [3][D][D]
+    bf16_t *Wp;             // [3][D][D] in fragment order (inference)
+    float *phi;             // [PHI_N][4] GELU table
+    int cus = 0;            // compute units of the device
     float *z[4];            // [B][D]
     bf16_t *h[4];           // [B][D]
     bf16_t *hT[3];          // [D][B]
@@ -421,7 +654,7 @@ qs_status mfail(qs_status st, const std::string &m) {
 size_t mlp_bytes(int64_t B, std::vector<size_t> *offs) {
     std::vector<size_t> sz = {
         (size_t)N_PARAMS * 4, (size_t)N_PARAMS * 4, (size_t)N_PARAMS * 4, (size_t)N_PARAMS * 4,
-        (size_t)3 * D * D * 2, (size_t)3 * D * D * 2};
+        (size_t)3 * D * D * 2, (size_t)3 * D * D * 2, (size_t)3 * D * D * 2, (size_t)PHI_N * 16};
     for (int i = 0; i < 4; ++i) sz.push_back((size_t)B * D * 4);   // z
     for (int i = 0; i < 4; ++i) sz.push_back((size_t)B * D * 2);   // h
     for (int i = 0; i < 3; ++i) sz.push_back((size_t)B * D * 2);   // hT
@@ -451,29 +684,54 @@ void gemm_launch(int epi, const GemmArgs &a, int splits, hipStream_t s) {
     else hipLaunchKernelGGL(gemm_nt<EPI_PART>, grid, block, 0, s, a);
 }
 
-// forward pass over `rows` (multiple of 128) rows; training stores z and the transposes
-void forward_rows(qs_mlp *c, const float *x, int64_t rows, int64_t n_valid, bool train, float *y,
-                  const float *t, float inv_batch2) {
+// training forward pass over a batch of `rows` (multiple of 128) rows: stores z, h and the
+// transposes h^T for the weight gradients, the outputs y, dy and the loss partials
+void forward_train(qs_mlp *c, const float *x, int64_t rows, const float *t, float inv_batch2) {
     hipStream_t s = c->stream;
     const int64_t ldT = c->max_batch;
-    bf16_t *hin[4] = {c->h[0], c->h[1], c->h[2], c->h[3]};
-    if (!train) { hin[2] = c->h[0]; hin[3] = c->h[1]; }  // inference ping-pongs two buffers
-    hipLaunchKernelGGL(l1_fwd, dim3(D / 64, (unsigned)(rows / 64)), dim3(256), 0, s, x, n_valid, c->P,
-                       train ? c->z[0] : nullptr, hin[0], train ? c->hT[0] : nullptr, ldT);
+    hipLaunchKernelGGL(l1_fwd, dim3(D / 64, (unsigned)(rows / 64)), dim3(256), 0, s, x, rows, c->P, c->z[0], c->h[0],
+                       c->hT[0], ldT);
     for (int l = 0; l < 3; ++l) {
         GemmArgs a{};
-        a.A = hin[l]; a.lda = D;
+        a.A = c->h[l]; a.lda = D;
         a.B = c->Wb + (int64_t)l * D * D; a.ldb = D;
         a.k_len = D; a.M = rows; a.N = D;
         a.bias = c->P + off_b(l);
-        a.z = train ? c->z[l + 1] : nullptr;
-        a.h = hin[l + 1];
-        a.hT = (train && l < 2) ? c->hT[l + 1] : nullptr;
+        a.z = c->z[l + 1];
+        a.h = c->h[l + 1];
+        a.hT = l < 2 ? c->hT[l + 1] : nullptr;
         a.ldT = ldT;
         gemm_launch(EPI_FWD, a, 1, s);
     }
-    hipLaunchKernelGGL(l5_fwd, dim3((unsigned)(rows / 4)), dim3(256), 0, s, hin[3], c->P, n_valid, y, t,
-                       inv_batch2, c->dy, c->lossp);
+    hipLaunchKernelGGL(l5_fwd, dim3((unsigned)(rows / 4)), dim3(256), 0, s, c->h[3], c->P, rows, c->y, t, inv_batch2,
+                       c->dy, c->lossp);
+}
+
+// bfloat16 copies of W2..W4 for training (row-major and transposed) and inference (packed)
+void convert(qs_mlp *c) {
+    const dim3 grid((unsigned)((3 * D * D + 255) / 256)), block(256);
+    hipLaunchKernelGGL(convert_weights, grid, block, 0, c->stream, c->P, c->Wb, c->WTb);
+    hipLaunchKernelGGL(pack_weights, grid, block, 0, c->stream, c->P, c->Wp);
+}
+
+// Cubic Hermite pieces of Phi (standard normal distribution function) on [-6, 6], 16 per
+// unit: on piece i, x = -6 + (i + f)/16 with f in [0, 1],
+//   Phi = c0 + c1 f + c2 f^2 + c3 f^3, matching Phi and its derivative phi at both ends.
+// Interpolation error h^4/384 max|Phi''''| < 3e-8 for h = 1/16, plus float32 rounding.
+std::vector<float> phi_table() {
+    std::vector<float> t(4 * PHI_N);
+    const double h = 1.0 / 16.0;
+    auto Phi = [](double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); };
+    auto phi = [](double x) { return std::exp(-0.5 * x * x) / std::sqrt(2.0 * M_PI); };
+    for (int i = 0; i < PHI_N; ++i) {
+        const double x0 = -6.0 + i * h, x1 = x0 + h;
+        const double p0 = Phi(x0), p1 = Phi(x1), d0 = h * phi(x0), d1 = h * phi(x1);
+        t[4 * i + 0] = (float)p0;
+        t[4 * i + 1] = (float)d0;
+        t[4 * i + 2] = (float)(3.0 * (p1 - p0) - 2.0 * d0 - d1);
+        t[4 * i + 3] = (float)(2.0 * (p0 - p1) + d0 + d1);
+    }
+    return t;
 }
 
 }  // namespace
@@ -503,6 +761,7 @@ qs_status qs_mlp_create(int32_t max_batch, void *hip_stream, qs_mlp **out) {
     int k = 0;
     c->P = (float *)(b + o[k++]); c->G = (float *)(b + o[k++]); c->Mo = (float *)(b + o[k++]); c->Vo = (float *)(b + o[k++]);
     c->Wb = (bf16_t *)(b + o[k++]); c->WTb = (bf16_t *)(b + o[k++]);
+    c->Wp = (bf16_t *)(b + o[k++]); c->phi = (float *)(b + o[k++]);
     for (int i = 0; i < 4; ++i) c->z[i] = (float *)(b + o[k++]);
     for (int i = 0; i < 4; ++i) c->h[i] = (bf16_t *)(b + o[k++]);
     for (int i = 0; i < 3; ++i) c->hT[i] = (bf16_t *)(b + o[k++]);
@@ -513,7 +772,12 @@ qs_status qs_mlp_create(int32_t max_batch, void *hip_stream, qs_mlp **out) {
     c->l1part = (float *)(b + o[k++]); c->lossp = (float *)(b + o[k++]); c->loss = (float *)(b + o[k++]);
     hipError_t e = hipMemsetAsync(c->mem, 0, bytes, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) { (void)hipFree(c->mem); delete c; return mfail(QS_ERR_HIP, "clearing the network buffers failed"); }
+    if (e == hipSuccess) {
+        const std::vector<float> tab = phi_table();
+        e = hipMemcpy(c->phi, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e != hipSuccess) { (void)hipFree(c->mem); delete c; return mfail(QS_ERR_HIP, "initializing the network buffers failed"); }
     *out = c;
     return QS_OK;
 }
@@ -524,8 +788,7 @@ qs_status qs_mlp_set_params(qs_mlp *c, const float *host) {
     MLP_HIP(hipMemcpyAsync(c->P, host, N_PARAMS * 4, hipMemcpyHostToDevice, c->stream), "copy params");
     MLP_HIP(hipMemsetAsync(c->Mo, 0, N_PARAMS * 4, c->stream), "clear moments");
     MLP_HIP(hipMemsetAsync(c->Vo, 0, N_PARAMS * 4, c->stream), "clear moments");
-    hipLaunchKernelGGL(convert_weights, dim3((unsigned)((3 * D * D + 255) / 256)), dim3(256), 0, c->stream, c->P, c->Wb,
-                       c->WTb);
+    convert(c);
     MLP_HIP(hipGetLastError(), "convert weights");
     MLP_HIP(hipStreamSynchronize(c->stream), "synchronize");
     c->t = 0;
@@ -561,12 +824,16 @@ qs_status qs_mlp_forward(qs_mlp *c, const float *x, int64_t n, float *y) {
     if (n < 0) return mfail(QS_ERR_ARG, "n must be >= 0");
     if (n > 0 && (!x || !y)) return mfail(QS_ERR_ARG, "x and y are required");
     MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
-    for (int64_t r0 = 0; r0 < n; r0 += c->max_batch) {
-        const int64_t valid = std::min<int64_t>(c->max_batch, n - r0);
-        const int64_t rows = (valid + 127) / 128 * 128;
-        forward_rows(c, x + r0 * DIN, rows, valid, false, y + r0, nullptr, 0.f);
+    if (n == 0) return QS_OK;
+    for (int64_t r0 = 0; r0 < n; r0 += kInferChunk) {
+        const int32_t m = (int32_t)std::min<int64_t>(kInferChunk, n - r0);
+        const int64_t tiles = (m + FT - 1) / FT;
+        const unsigned grid = (unsigned)std::min<int64_t>(tiles, 2 * (int64_t)std::max(c->cus, 1));
+        InferArgs a{x + r0 * DIN, m, c->P, reinterpret_cast<const bf16x8 *>(c->Wp),
+                    reinterpret_cast<const f32x4 *>(c->phi), y + r0};
+        hipLaunchKernelGGL(mlp_infer, dim3(grid), dim3(256), 0, c->stream, a);
     }
-    MLP_HIP(hipGetLastError(), "forward kernels");
+    MLP_HIP(hipGetLastError(), "forward kernel");
     return QS_OK;
 }
 
@@ -577,7 +844,7 @@ qs_status qs_mlp_grads(qs_mlp *c, const float *x, const float *t, int32_t batch,
     MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = c->stream;
     const int64_t B = batch, ldT = c->max_batch, tiles = B / 64;
-    forward_rows(c, x, B, B, true, c->y, t, 2.0f / (float)B);
+    forward_train(c, x, B, t, 2.0f / (float)B);
     // last layer
     hipLaunchKernelGGL(l5_bwd, dim3(D / 64, (unsigned)tiles), dim3(256), 0, s, c->dy, c->P, c->z[3], c->h[3],
                        c->dzb[0], c->dzT[0], ldT, c->colpart, c->w5part);
@@ -641,8 +908,7 @@ qs_status qs_mlp_adamw(qs_mlp *c, double lr, double beta1, double beta2, double 
     const double c1 = 1.0 - std::pow(beta1, (double)c->t), c2 = 1.0 - std::pow(beta2, (double)c->t);
     hipLaunchKernelGGL(adamw, dim3((unsigned)((N_PARAMS + 255) / 256)), dim3(256), 0, c->stream, c->P, c->G, c->Mo, c->Vo,
                        N_PARAMS, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)wd, (float)c1, (float)c2);
-    hipLaunchKernelGGL(convert_weights, dim3((unsigned)((3 * D * D + 255) / 256)), dim3(256), 0, c->stream, c->P, c->Wb,
-                       c->WTb);
+    convert(c);
     MLP_HIP(hipGetLastError(), "optimizer kernels");
     return QS_OK;
 }
