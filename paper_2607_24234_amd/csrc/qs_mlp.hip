@@ -21,6 +21,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/qs_mlp.h"
@@ -434,14 +435,14 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
 
-// x Phi(x): piece i = floor(16 x + 96) (clamped), Phi = c0 + f (c1 + f (c2 + f c3)) with
-// f the position in the piece; beyond [-6, 6] Phi is taken at the end of the range
-// (|Phi - 0| or |Phi - 1| < 1e-9 there).  NaN propagates through the final product.
+// x Phi(x): t = 16 x + 96 clamped to [0, 192 - 1/64], piece floor(t), position f = t - floor(t),
+// Phi = c0 + f (c1 + f (c2 + f c3)).  Beyond [-6, 6] Phi is taken at the end of the range
+// (|Phi - 0| or |Phi - 1| < 1e-9 there); a NaN input clamps to piece 0 and propagates
+// through the final product.
 __device__ __forceinline__ float gelu_tab(float v, const f32x4 *tab) {
-    const float t = fminf(fmaxf(fmaf(v, 16.f, 0.5f * PHI_N), 0.f), (float)PHI_N);
-    const int i = min((int)t, PHI_N - 1);
-    const float f = t - (float)i;
-    const f32x4 c = tab[i];
+    const float t = fminf(fmaxf(fmaf(v, 16.f, 0.5f * PHI_N), 0.f), PHI_N - 0.015625f);
+    const float f = __builtin_amdgcn_fractf(t);
+    const f32x4 c = tab[(int)t];
     return v * fmaf(f, fmaf(f, fmaf(f, c.w, c.z), c.y), c.x);
 }
 
@@ -496,10 +497,9 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
     };
     // bias (or W5) row r for the four consecutive features of accumulator group (fb, j)
     auto brow = [&](int r, int fb, int j) { return bw[r * (D / 4) + (32 * (4 * w + fb) + 8 * j + 4 * lh) / 4]; };
-    // GELU of acc (+ bias row r unless r < 0) as bfloat16 into the activation tile: element
-    // 4 j + e of acc[fb][qb] is feature 32 (4 w + fb) + 8 j + 4 (lane/32) + e of query
-    // 32 qb + lane%32
-    auto store = [&](f32x16 (&acc)[4][2], int r) {
+    // GELU of acc as bfloat16 into the activation tile: element 4 j + e of acc[fb][qb] is
+    // feature 32 (4 w + fb) + 8 j + 4 (lane/32) + e of query 32 qb + lane%32
+    auto store = [&](f32x16 (&acc)[4][2]) {
         bf16_t *row = act + lr * ALD + 128 * w + 4 * lh;
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
@@ -507,10 +507,9 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
             for (int fb = 0; fb < 4; ++fb)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const f32x4 b = r >= 0 ? brow(r, fb, j) : f32x4{0.f, 0.f, 0.f, 0.f};
                     float h[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) h[e] = gelu_tab(acc[fb][qb][4 * j + e] + b[e], tab);
+                    for (int e = 0; e < 4; ++e) h[e] = gelu_tab(acc[fb][qb][4 * j + e], tab);
                     const uint2 pk = make_uint2(pack_bf16(h[0], h[1]), pack_bf16(h[2], h[3]));
                     *reinterpret_cast<uint2 *>(row + 32 * qb * ALD + 32 * fb + 8 * j) = pk;
                     __builtin_amdgcn_sched_barrier(0);   // bounds the table reads in flight
@@ -531,15 +530,9 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
                 acc[fb][qb] = z;
             }
         load_x(t + gridDim.x, xn);   // next tile's inputs, in flight during this tile
-        store(acc, -1);
+        store(acc);
         __syncthreads();
         for (int l = 0; l < 3; ++l) {
-#pragma unroll
-            for (int fb = 0; fb < 4; ++fb)
-#pragma unroll
-                for (int qb = 0; qb < 2; ++qb)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[fb][qb][r] = 0.f;
             // weight fragment (fb, ks) of this wave: 1 KiB block ((l 16 + 4 w + fb) KS + ks)
             const int wbase = (l * 16 + 4 * w) * KS * 1024;
             auto wload = [&](int fb, int ks) {
@@ -548,9 +541,48 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
             auto aload = [&](int qb, int ks) {
                 return *reinterpret_cast<const bf16x8 *>(act + (32 * qb + lr) * ALD + 16 * ks + 8 * lh);
             };
-            // weight fragments in a ring of four k-steps, each loaded two k-steps ahead, and
-            // activation fragments one k-step ahead; the group barriers keep that order
+            // weight fragments in a ring of four k-steps (slot ks % 4), each loaded two k-steps
+            // ahead, activation fragments one k-step ahead (slot ks % 2); the group barriers
+            // keep that order.  The first k-step starts the sums from the bias.
             bf16x8 A[4][4], B[2][2];
+            auto step = [&](int ks, auto slot, auto first) {
+                constexpr int u = decltype(slot)::value;
+                const int kn = min(ks + 2, KS - 1), kb = min(ks + 1, KS - 1);   // the end reloads the last step
+#pragma unroll
+                for (int fb = 0; fb < 4; ++fb) A[(u + 2) % 4][fb] = wload(fb, kn);
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) B[(u + 1) % 2][qb] = aload(qb, kb);
+#pragma unroll
+                for (int fb = 0; fb < 4; ++fb) {
+                    if constexpr (decltype(first)::value) {
+                        f32x16 bias;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const f32x4 b = brow(l, fb, j);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) bias[4 * j + e] = b[e];
+                        }
+#pragma unroll
+                        for (int qb = 0; qb < 2; ++qb)
+                            acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], bias, 0, 0, 0);
+                    } else {
+#pragma unroll
+                        for (int qb = 0; qb < 2; ++qb)
+                            acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], acc[fb][qb], 0, 0, 0);
+                    }
+                }
+                if constexpr (!decltype(first)::value) {
+                    __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);   // 4 global (buffer) reads
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // 2 LDS reads
+                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // 8 matrix products
+                }
+            };
+            using I0 = std::integral_constant<int, 0>;
+            using I1 = std::integral_constant<int, 1>;
+            using I2 = std::integral_constant<int, 2>;
+            using I3 = std::integral_constant<int, 3>;
+            using T = std::true_type;
+            using F = std::false_type;
 #pragma unroll
             for (int fb = 0; fb < 4; ++fb) {
                 A[0][fb] = wload(fb, 0);
@@ -558,29 +590,20 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
             }
             B[0][0] = aload(0, 0);
             B[0][1] = aload(1, 0);
+            step(0, I0{}, T{});
 #pragma nounroll
-            for (int kk = 0; kk < KS; kk += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int ks = kk + u;
-                    const int kn = min(ks + 2, KS - 1), kb = min(ks + 1, KS - 1);   // the tail reloads the last step
-#pragma unroll
-                    for (int fb = 0; fb < 4; ++fb) A[(u + 2) % 4][fb] = wload(fb, kn);
-#pragma unroll
-                    for (int qb = 0; qb < 2; ++qb) B[(u + 1) % 2][qb] = aload(qb, kb);
-#pragma unroll
-                    for (int fb = 0; fb < 4; ++fb)
-#pragma unroll
-                        for (int qb = 0; qb < 2; ++qb)
-                            acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], acc[fb][qb], 0, 0, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);   // 4 global (buffer) reads
-                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // 2 LDS reads
-                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // 8 matrix products
-                }
+            for (int kk = 1; kk < KS - 3; kk += 4) {   // k-steps 1 .. 28
+                step(kk, I1{}, F{});
+                step(kk + 1, I2{}, F{});
+                step(kk + 2, I3{}, F{});
+                step(kk + 3, I0{}, F{});
             }
+            step(KS - 3, I1{}, F{});
+            step(KS - 2, I2{}, F{});
+            step(KS - 1, I3{}, F{});
             if (l < 2) {
                 __syncthreads();     // every wave has read this layer's input
-                store(acc, l);
+                store(acc);
                 __syncthreads();
             } else {
                 // last layer: y = W5 . bf16(GELU(z4)) + b5
@@ -591,11 +614,9 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
                     for (int fb = 0; fb < 4; ++fb)
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            const f32x4 b = brow(2, fb, j), w5 = brow(3, fb, j);
-                            const uint32_t p0 = pack_bf16(gelu_tab(acc[fb][qb][4 * j] + b[0], tab),
-                                                          gelu_tab(acc[fb][qb][4 * j + 1] + b[1], tab));
-                            const uint32_t p1 = pack_bf16(gelu_tab(acc[fb][qb][4 * j + 2] + b[2], tab),
-                                                          gelu_tab(acc[fb][qb][4 * j + 3] + b[3], tab));
+                            const f32x4 w5 = brow(3, fb, j);
+                            const uint32_t p0 = pack_bf16(gelu_tab(acc[fb][qb][4 * j], tab), gelu_tab(acc[fb][qb][4 * j + 1], tab));
+                            const uint32_t p1 = pack_bf16(gelu_tab(acc[fb][qb][4 * j + 2], tab), gelu_tab(acc[fb][qb][4 * j + 3], tab));
                             sum += w5[0] * bf_lo(p0) + w5[1] * bf_hi(p0) + w5[2] * bf_lo(p1) + w5[3] * bf_hi(p1);
                             __builtin_amdgcn_sched_barrier(0);
                         }
