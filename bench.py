@@ -257,8 +257,9 @@ def bench_surrogate(args):
                        "batched uniform-seed sweep (1e7 examples), held out: a second sweep (2e6)",
            "queries": n_q, "train_s": t2 - t1, "data_s": t1 - t0, "held_out": err},
           {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,
-           "traffic": None, "kernel": "network forward (3 bf16 512x512 layers on the matrix cores, "
-                                      "fp32 first/last layers), 1.58 MFLOP per query"},
+           "traffic": None, "kernel": "fused network forward (one persistent kernel, activations in LDS; "
+                                      "3 bf16 512x512 layers on the matrix cores, fp32 first/last "
+                                      "layers), 1.58 MFLOP per query"},
           None,
           surrogate_s_per_query=sur_s / n_q, solver_s_per_query=sol_s,
           speedup_vs_solver=sol_s / (sur_s / n_q),

@@ -10,7 +10,10 @@
  * (round to nearest even from float32) and float32 accumulation; the first layer (5
  * inputs) and the last (1 output), the bias additions, the activation and all reductions
  * are float32.  Stored activations h1..h4 are bfloat16.  Master weights and the AdamW
- * moments are float32.
+ * moments are float32.  Training evaluates Phi with the float32 error function; inference
+ * (qs_mlp_forward) reads Phi from a table of cubic Hermite pieces (16 per unit on [-6, 6],
+ * interpolation error below 3e-8), so the two forward passes agree to float32 rounding
+ * except where an activation lands on a bfloat16 rounding boundary.
  *
  * Parameter layout (float32, host arrays of qs_mlp_param_count() elements), in order:
  *   W1 [512][5], b1 [512], W2 [512][512], b2 [512], W3 [512][512], b3 [512],
@@ -53,8 +56,9 @@ qs_status qs_mlp_set_params(qs_mlp *net, const float *host_params);
 qs_status qs_mlp_get_params(qs_mlp *net, float *host_params);
 
 /*
- * Inference: y[i] = network(x[i]) for i < n (n >= 0, any size; processed in chunks of
- * max_batch rows).  x: device float32 [n][5]; y: device float32 [n].
+ * Inference: y[i] = network(x[i]) for i < n (n >= 0, any size, independent of max_batch).
+ * x: device float32 [n][5]; y: device float32 [n].  One persistent kernel per 2^25 queries
+ * keeps every activation on chip; it uses no buffer of the network besides its parameters.
  */
 qs_status qs_mlp_forward(qs_mlp *net, const float *x, int64_t n, float *y);
 
