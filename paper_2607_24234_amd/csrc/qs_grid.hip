@@ -129,24 +129,25 @@ __device__ int block_fft(float2 *__restrict__ b0, float2 *__restrict__ b1, int n
 }
 
 // ----------------------------------------------------------------------------- march
-// One thread per transverse point: FP64 carries down the column, loads one cell ahead.
+// One thread per transverse point: FP64 carries down the column.  The 65,536 columns of a
+// 256^2 grid are one wave per SIMD, so the loads run kMarchAhead cells ahead in a register
+// ring (slot j % kMarchAhead; no copies at the loop edge) to keep enough bytes in flight.
+constexpr int kMarchAhead = 16;
+
 __global__ void __launch_bounds__(256) grid_march(GridArgs a, const float *__restrict__ rho, float *__restrict__ np_c,
                                                   float *__restrict__ v_f, float *__restrict__ v_c) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.P) return;
     double y = 0.0, v = 0.0;
-    float nxt = rho[p];
-    for (int j = 0; j < a.n_xi; ++j) {
-        const float cur = nxt;
-        if (j + 1 < a.n_xi) nxt = rho[(int64_t)(j + 1) * a.P + p];
-        const double r = (double)cur;
+    auto cell = [&](int j, float rf) {
+        const double r = (double)rf;
         double nc, yn, vn, vc;
         if (a.restoring) {
-            const double u = y - r;
-            nc = r + a.C2 * u + a.S2 * v;
-            vc = a.C2 * v - a.S2 * u;
-            yn = r + a.C1 * u + a.S1 * v;
-            vn = a.C1 * v - a.S1 * u;
+            const double w = y - r;
+            nc = r + a.C2 * w + a.S2 * v;
+            vc = a.C2 * v - a.S2 * w;
+            yn = r + a.C1 * w + a.S1 * v;
+            vn = a.C1 * v - a.S1 * w;
         } else {
             nc = y + 0.5 * a.h * v + 0.125 * a.h * a.h * r;
             vc = v + 0.5 * a.h * r;
@@ -159,7 +160,23 @@ __global__ void __launch_bounds__(256) grid_march(GridArgs a, const float *__res
         np_c[o] = (float)nc;
         v_f[o] = (float)vn;
         if (v_c) v_c[o] = (float)vc;
+    };
+    const int last = a.n_xi - 1;
+    float ring[kMarchAhead];
+#pragma unroll
+    for (int d = 0; d < kMarchAhead; ++d) ring[d] = rho[(int64_t)min(d, last) * a.P + p];
+    int jb = 0;
+    for (; jb + kMarchAhead <= a.n_xi; jb += kMarchAhead) {
+#pragma unroll
+        for (int u = 0; u < kMarchAhead; ++u) {
+            const float r = ring[u];
+            ring[u] = rho[(int64_t)min(jb + u + kMarchAhead, last) * a.P + p];   // the end reloads the last cell
+            cell(jb + u, r);
+        }
     }
+#pragma unroll
+    for (int u = 0; u < kMarchAhead; ++u)
+        if (jb + u < a.n_xi) cell(jb + u, ring[u]);
 }
 
 // ----------------------------------------------------------------------------- rows
@@ -393,6 +410,296 @@ __global__ void __launch_bounds__(256) grid_rows_inv(GridArgs a, RowInvArgs r) {
     }
 }
 
+// ----------------------------------------------------------------------------- 256-point passes
+// For 256 x 256 grids every transform runs in registers.  The 16 lanes of a group hold a
+// transform as x[q + 16 r] in v[r] (lane q); the split 256 = 16 x 16 (four-step FFT) takes a
+// 16-point FFT in registers, the twiddle W256^(q k), one exchange through LDS inside the
+// wave, and a second 16-point FFT, after which lane q holds X[q + 16 r] in v[r] again.  The
+// passes keep the data layouts of the general kernels above; the transposed loads and
+// stores go through LDS in runs of 16 rows (128 B).
+
+// cos(2 pi k / 16)
+__host__ __device__ constexpr float cos16(int k) {
+    constexpr float c[5] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f, 0.0f};
+    k &= 15;
+    return k <= 4 ? c[k] : k <= 8 ? -c[8 - k] : k <= 12 ? -c[k - 8] : c[16 - k];
+}
+
+// t W16^e, W16 = exp(-2 pi i / 16) (its conjugate for the inverse), 0 <= e < 8
+template <bool INV> __device__ __forceinline__ float2 rot16(float2 t, int e) {
+    if (e == 0) return t;
+    if (e == 4) return INV ? make_float2(-t.y, t.x) : make_float2(t.y, -t.x);
+    const float c = cos16(e), sn = INV ? cos16(e + 12) : -cos16(e + 12);
+    return make_float2(t.x * c - t.y * sn, t.x * sn + t.y * c);
+}
+
+__host__ __device__ constexpr int brev4(int i) { return ((i & 1) << 3) | ((i & 2) << 1) | ((i & 4) >> 1) | ((i & 8) >> 3); }
+
+// 16-point FFT in registers, natural order in and out (radix-2, decimation in time)
+template <bool INV> __device__ __forceinline__ void fft16(float2 (&v)[16]) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int k = brev4(i);
+        if (i < k) {
+            const float2 t = v[i];
+            v[i] = v[k];
+            v[k] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= 16; len <<= 1)
+#pragma unroll
+        for (int i = 0; i < 16; i += len)
+#pragma unroll
+            for (int k = 0; k < len / 2; ++k) {
+                const float2 t = rot16<INV>(v[i + k + len / 2], k * (16 / len));
+                const float2 u = v[i + k];
+                v[i + k] = cadd(u, t);
+                v[i + k + len / 2] = csub(u, t);
+            }
+}
+
+// LDS written by lanes of this wave is visible to its other lanes after this point
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 256-point FFT by a group of 16 lanes (lane q); ex: the group's 16 x 17 exchange area;
+// tw: W256^m, m < 256
+template <bool INV>
+__device__ __forceinline__ void fft256(float2 (&v)[16], int q, float2 *ex, const float2 *tw) {
+    fft16<INV>(v);                      // over r: Y[q][k] in v[k]
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+        float2 w = tw[q * k];
+        if (INV) w.y = -w.y;
+        v[k] = cmul(v[k], w);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ex[k * 17 + q] = v[k];
+    wave_sync();
+#pragma unroll
+    for (int n = 0; n < 16; ++n) v[n] = ex[q * 17 + n];   // column k = q: Y[n][q]
+    wave_sync();
+    fft16<INV>(v);                      // X[16 k1 + q] in v[k1]
+}
+
+// rows: as grid_rows_fwd for 256 x 256; 16 rows per workgroup, a 16-lane group per row
+// holding both transforms
+template <int MODE>
+__global__ void __launch_bounds__(256) grid_rows_fwd256(GridArgs a, const float *__restrict__ A0,
+                                                        const float *__restrict__ A1, const float *__restrict__ B0,
+                                                        const float *__restrict__ B1, float2 *__restrict__ Z1,
+                                                        float2 *__restrict__ Z2) {
+    constexpr int R = 16, XP = R + 1;
+    __shared__ float2 tw[256];
+    __shared__ float2 sm[2 * 256 * XP];   // [transform][kx][row]; the exchange areas alias it
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, q = lane & 15, grp = lane >> 4;
+    const int rr = 4 * wv + grp;
+    const int j = blockIdx.y, y0 = blockIdx.x * R;
+    tw[tid] = a.twx[tid];
+    const int64_t rowb = (int64_t)j * a.P + (int64_t)(y0 + rr) * 256;
+    float2 z1[16], z2[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t o = rowb + q + 16 * r;
+        if (MODE == 0) {
+            z1[r] = make_float2(A0[o], A1[o]);
+            z2[r] = make_float2(B0[o], B1[o]);
+        } else {
+            const float rho = A1[o];
+            z1[r] = make_float2(rho - A0[o], rho);
+            z2[r] = make_float2(B0[o], 0.f);
+        }
+    }
+    __syncthreads();
+    float2 *ex = sm + (4 * wv + grp) * 272;
+    fft256<false>(z1, q, ex, tw);
+    fft256<false>(z2, q, ex, tw);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int kx = q + 16 * r;
+        sm[kx * XP + rr] = z1[r];
+        sm[(256 + kx) * XP + rr] = z2[r];
+    }
+    __syncthreads();
+    for (int t = tid; t < 2 * 256 * R; t += 256) {
+        const int f = t / (256 * R), kx = (t / R) & 255, r = t % R;
+        const int64_t d = ((int64_t)j * 256 + kx) * a.ny + y0 + r;
+        (f ? Z2 : Z1)[d] = sm[(f * 256 + kx) * XP + r];
+    }
+}
+
+// columns: as grid_cols for 256 x 256; a workgroup takes 8 column pairs (kx, -kx) of a
+// slice, pair 0 being the two self-conjugate columns 0 and 128; a 16-lane group per column
+// holding both transforms; the partner column is in the same wave.  MODE 1 (fields) also
+// writes Z3 = H v_c (the work of grid_cols_o3) from the Z2 spectrum it replaces.
+template <int MODE>
+__global__ void __launch_bounds__(256) grid_cols256(GridArgs a, float2 *__restrict__ Z1, float2 *__restrict__ Z2,
+                                                    float2 *__restrict__ Z3) {
+    __shared__ float2 tw[256];
+    __shared__ float2 spec[16][2][256];   // the 16 columns' spectra; each group's exchange area aliases its own
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, q = lane & 15, grp = lane >> 4;
+    const int slot = 4 * wv + grp;
+    const int s = blockIdx.x * 8 + (slot >> 1);
+    const int kx = s == 0 ? (slot & 1) * 128 : ((slot & 1) ? 256 - s : s);
+    const int ps = s == 0 ? slot : (slot ^ 1);
+    const int j = blockIdx.y;
+    tw[tid] = a.twy[tid];
+    const int64_t cb = ((int64_t)j * 256 + kx) * 256;
+    float2 z1[16], z2[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        z1[r] = Z1[cb + q + 16 * r];
+        z2[r] = Z2[cb + q + 16 * r];
+    }
+    __syncthreads();
+    float2 *ex = &spec[slot][0][0];
+    fft256<false>(z1, q, ex, tw);
+    fft256<false>(z2, q, ex, tw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        spec[slot][0][q + 16 * r] = z1[r];
+        spec[slot][1][q + 16 * r] = z2[r];
+    }
+    wave_sync();
+    const float inv = 1.0f / 65536.0f;
+    const float kxv = wavenum(kx, 256, a.lx), dx = dwavenum(kx, 256, a.lx);
+    float2 z3[MODE == 1 ? 16 : 1];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int ky = q + 16 * r, kyp = (256 - ky) & 255;
+        const float2 z1p = cconj(spec[ps][0][kyp]), z2p = cconj(spec[ps][1][kyp]);
+        const float kyv = wavenum(ky, 256, a.ly), dy = dwavenum(ky, 256, a.ly);
+        const float kap = 1.0f / (1.0f + kxv * kxv + kyv * kyv);
+        const float2 re1 = make_float2(0.5f * (z1[r].x + z1p.x), 0.5f * (z1[r].y + z1p.y));
+        const float2 im1 = make_float2(0.5f * (z1[r].y - z1p.y), -0.5f * (z1[r].x - z1p.x));
+        float2 o1, o2;
+        if (MODE == 0) {
+            const float2 jxh = make_float2(0.5f * (z2[r].x + z2p.x), 0.5f * (z2[r].y + z2p.y));
+            const float2 jyh = make_float2(0.5f * (z2[r].y - z2p.y), -0.5f * (z2[r].x - z2p.x));
+            o1 = make_float2(kap * im1.x - (dx * jxh.x + dy * jyh.x), kap * im1.y - (dx * jxh.y + dy * jyh.y));
+            const float2 nk = make_float2(kap * re1.x, kap * re1.y);
+            o2 = make_float2(-dx * nk.y - dy * nk.x, dx * nk.x - dy * nk.y);
+        } else {
+            const float2 dk = make_float2(kap * re1.x, kap * re1.y);
+            const float2 rk = make_float2(kap * im1.x, kap * im1.y);
+            o1 = make_float2(-dx * dk.y - dy * dk.x, dx * dk.x - dy * dk.y);
+            o2 = make_float2(-dx * rk.y - dy * rk.x, dx * rk.x - dy * rk.y);
+            if constexpr (MODE == 1) z3[r] = make_float2(kap * inv * z2[r].x, kap * inv * z2[r].y);
+        }
+        z1[r] = make_float2(o1.x * inv, o1.y * inv);
+        z2[r] = make_float2(o2.x * inv, o2.y * inv);
+    }
+    wave_sync();   // the partner's spectrum is read before the exchange areas are reused
+    fft256<true>(z1, q, ex, tw);
+    fft256<true>(z2, q, ex, tw);
+    if constexpr (MODE == 1) fft256<true>(z3, q, ex, tw);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        Z1[cb + q + 16 * r] = z1[r];
+        Z2[cb + q + 16 * r] = z2[r];
+        if constexpr (MODE == 1) Z3[cb + q + 16 * r] = z3[r];
+    }
+}
+
+// inverse rows: as grid_rows_inv for 256 x 256 (NTR = 2: rates and stage update; 3: fields)
+template <int NTR>
+__global__ void __launch_bounds__(256) grid_rows_inv256(GridArgs a, RowInvArgs r) {
+    constexpr int R = 16, XP = R + 1;
+    __shared__ float2 tw[256];
+    __shared__ float2 sm[2 * 256 * XP];   // [transform][kx][row], two at a time; the exchange areas alias it
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, q = lane & 15, grp = lane >> 4;
+    const int rr = 4 * wv + grp;
+    const int j = blockIdx.y, y0 = blockIdx.x * R;
+    tw[tid] = a.twx[tid];
+    float2 v[NTR][16];
+#pragma unroll
+    for (int f0 = 0; f0 < NTR; f0 += 2) {
+        const int nf = NTR - f0 < 2 ? NTR - f0 : 2;
+        for (int t = tid; t < nf * 256 * R; t += 256) {
+            const int f = t / (256 * R), kx = (t / R) & 255, rw = t % R;
+            const int64_t d = ((int64_t)j * 256 + kx) * a.ny + y0 + rw;
+            const int fi = f0 + f;
+            sm[(f * 256 + kx) * XP + rw] = fi == 0 ? r.O1[d] : (fi == 1 ? r.O2[d] : r.O3[d]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+            if (f < nf)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) v[f0 + f][i] = sm[(f * 256 + q + 16 * i) * XP + rr];
+        __syncthreads();
+    }
+    float2 *ex = sm + (4 * wv + grp) * 272;
+#pragma unroll
+    for (int f = 0; f < NTR; ++f) fft256<true>(v[f], q, ex, tw);
+    const int64_t rowp = (int64_t)(y0 + rr) * 256;
+    float amax = 0.f;
+    const float fj = a.f[j];
+    const float fn = j + 1 < a.n_xi ? a.f[j + 1] : 0.f;
+    if (NTR == 2) {
+        // the update may write where it reads (the last stage updates U in place): each half
+        // of the row's points loads all its inputs before any of its stores
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float u[4][8], pin[8], pprev[8], gp[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t pt = rowp + q + 16 * (8 * h + i);
+                const int64_t e = (int64_t)j * a.P + pt;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) u[c][i] = r.U[c][e];
+                pin[i] = r.in_jpar[e];
+                pprev[i] = j > 0 ? r.in_jpar[e - a.P] : 0.f;
+                gp[i] = a.g[pt];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t e = (int64_t)j * a.P + rowp + q + 16 * (8 * h + i);
+                const float2 v1 = v[0][8 * h + i], v2 = v[1][8 * h + i];
+                const float om_c = a.om0 * fj * gp[i];
+                const float om_f = j + 1 < a.n_xi ? a.om0 * gp[i] * 0.5f * (fj + fn) : 0.f;
+                float rate[4];
+                rate[0] = (pin[i] - pprev[i]) * (float)a.ih - v1.y;
+                rate[1] = j + 1 < a.n_xi ? -a.g3inv * om_f * v1.x : 0.f;
+                rate[2] = a.ginv * om_c * v2.x;
+                rate[3] = a.ginv * om_c * v2.y;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float nv = u[c][i] + r.coef * rate[c];
+                    r.out[c][e] = nv;
+                    if (c == 0 && r.final_update && !(fabsf(nv) <= 3.0e38f)) r.err[0] = 1u;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t e = (int64_t)j * a.P + rowp + q + 16 * i;
+            const float2 v1 = v[0][i], v2 = v[1][i], v3 = v[NTR - 1][i];
+            const float e2 = v3.x * v3.x + v1.x * v1.x + v1.y * v1.y;
+            const float b2 = v2.x * v2.x + v2.y * v2.y;
+            if (r.ln_e) {
+                r.ln_e[e] = 0.5f * logf(e2);
+                r.ln_b[e] = 0.5f * logf(b2);
+            }
+            const float a2 = e2 + b2;
+            amax = (a2 > amax || !(a2 <= a2)) ? a2 : amax;
+        }
+    }
+    if (NTR == 3 && r.max_key) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float other = __shfl_xor(amax, off);
+            amax = (other > amax || !(other <= other)) ? other : amax;
+        }
+        if (lane == 0) atomicMax(r.max_key, fkey_pos(amax));
+    }
+}
+
 __global__ void grid_max_finish(uint32_t *keys, float *out, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = 0.5f * logf(__builtin_bit_cast(float, keys[i]));
@@ -473,14 +780,24 @@ size_t lds_rows(const GridArgs &a, int ntr) {
 }
 size_t lds_cols(const GridArgs &a) { return (size_t)(8 * a.ny + a.ny) * sizeof(float2); }
 
+// 256 x 256 grids take the register-FFT passes
+bool is256(const GridArgs &a) { return a.nx == 256 && a.ny == 256; }
+
 // one application of A to W_in, combined with the stage update
 hipError_t apply(GridCtx *c, float *const *Win, float *const *Wout, float coef, bool final_update, hipStream_t s) {
     const GridArgs &a = c->a;
     const int R = std::min(kRows, a.ny);
+    const bool r256 = is256(a);
     hipLaunchKernelGGL(grid_march, dim3(nblk(a.P)), dim3(256), 0, s, a, Win[0], c->np_c, c->v_f, (float *)nullptr);
-    hipLaunchKernelGGL(grid_rows_fwd, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, 0, c->np_c, c->v_f,
-                       Win[2], Win[3], c->Z1, c->Z2);
-    hipLaunchKernelGGL(grid_cols, dim3(a.nx / 2 + 1, a.n_xi), dim3(256), lds_cols(a), s, a, 0, c->Z1, c->Z2);
+    if (r256) {
+        hipLaunchKernelGGL(grid_rows_fwd256<0>, dim3(16, a.n_xi), dim3(256), 0, s, a, c->np_c, c->v_f, Win[2], Win[3],
+                           c->Z1, c->Z2);
+        hipLaunchKernelGGL(grid_cols256<0>, dim3(16, a.n_xi), dim3(256), 0, s, a, c->Z1, c->Z2, (float2 *)nullptr);
+    } else {
+        hipLaunchKernelGGL(grid_rows_fwd, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, 0, c->np_c, c->v_f,
+                           Win[2], Win[3], c->Z1, c->Z2);
+        hipLaunchKernelGGL(grid_cols, dim3(a.nx / 2 + 1, a.n_xi), dim3(256), lds_cols(a), s, a, 0, c->Z1, c->Z2);
+    }
     RowInvArgs r{};
     r.mode = 0;
     r.O1 = c->Z1;
@@ -490,7 +807,8 @@ hipError_t apply(GridCtx *c, float *const *Win, float *const *Wout, float coef, 
     r.coef = coef;
     r.final_update = final_update ? 1 : 0;
     r.err = c->err;
-    hipLaunchKernelGGL(grid_rows_inv, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, r);
+    if (r256) hipLaunchKernelGGL(grid_rows_inv256<2>, dim3(16, a.n_xi), dim3(256), 0, s, a, r);
+    else hipLaunchKernelGGL(grid_rows_inv, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, r);
     return hipGetLastError();
 }
 
@@ -498,14 +816,23 @@ hipError_t apply(GridCtx *c, float *const *Win, float *const *Wout, float coef, 
 hipError_t fields(GridCtx *c, float *ln_e, float *ln_b, uint32_t *key, hipStream_t s) {
     const GridArgs &a = c->a;
     const int R = std::min(kRows, a.ny);
+    const bool r256 = is256(a);
     hipLaunchKernelGGL(grid_march, dim3(nblk(a.P)), dim3(256), 0, s, a, c->U[0], c->np_c, c->v_f, c->v_c);
-    hipLaunchKernelGGL(grid_rows_fwd, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, 1, c->np_c, c->U[0],
-                       c->v_c, (const float *)nullptr, c->Z1, c->Z2);
-    // O3 = H v_c from the untouched Z2 spectrum column by column, before grid_cols
-    // overwrites Z2
-    hipLaunchKernelGGL(grid_cols_o3, dim3(a.nx, a.n_xi), dim3(256), (size_t)3 * a.ny * sizeof(float2), s, a, c->Z2,
-                       c->Z3);
-    hipLaunchKernelGGL(grid_cols, dim3(a.nx / 2 + 1, a.n_xi), dim3(256), lds_cols(a), s, a, 1, c->Z1, c->Z2);
+    if (r256)
+        hipLaunchKernelGGL(grid_rows_fwd256<1>, dim3(16, a.n_xi), dim3(256), 0, s, a, c->np_c, c->U[0], c->v_c,
+                           (const float *)nullptr, c->Z1, c->Z2);
+    else
+        hipLaunchKernelGGL(grid_rows_fwd, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 2), s, a, 1, c->np_c, c->U[0],
+                           c->v_c, (const float *)nullptr, c->Z1, c->Z2);
+    // O3 = H v_c from the untouched Z2 spectrum column by column, before the column pass
+    // overwrites Z2 (the 256-point column pass does both)
+    if (r256) {
+        hipLaunchKernelGGL(grid_cols256<1>, dim3(16, a.n_xi), dim3(256), 0, s, a, c->Z1, c->Z2, c->Z3);
+    } else {
+        hipLaunchKernelGGL(grid_cols_o3, dim3(a.nx, a.n_xi), dim3(256), (size_t)3 * a.ny * sizeof(float2), s, a,
+                           c->Z2, c->Z3);
+        hipLaunchKernelGGL(grid_cols, dim3(a.nx / 2 + 1, a.n_xi), dim3(256), lds_cols(a), s, a, 1, c->Z1, c->Z2);
+    }
     RowInvArgs r{};
     r.mode = 1;
     r.O1 = c->Z1;
@@ -514,7 +841,8 @@ hipError_t fields(GridCtx *c, float *ln_e, float *ln_b, uint32_t *key, hipStream
     r.ln_e = ln_e;
     r.ln_b = ln_b;
     r.max_key = key;
-    hipLaunchKernelGGL(grid_rows_inv, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 3), s, a, r);
+    if (r256) hipLaunchKernelGGL(grid_rows_inv256<3>, dim3(16, a.n_xi), dim3(256), 0, s, a, r);
+    else hipLaunchKernelGGL(grid_rows_inv, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 3), s, a, r);
     return hipGetLastError();
 }
 

@@ -106,6 +106,49 @@ def test_grid_larger_matches_oracle(qs):
     assert np.max(np.abs(st["rho"] - ost.rho)) <= TOL * sc
 
 
+def _compare_ln_large(gpu, ref, what):
+    """On a 256 x 256 slice the float32 transforms leave an absolute error of a few
+    eps log2(65536) ~ 1e-6 of the slice maximum at every point (the error of a float32 FFT is
+    absolute, not relative), so the 1e-4 bound in ln holds where the field is at least 1e-3
+    of the snapshot maximum; below that the field itself is checked against
+    4 eps log2(65536) = 3.8e-6 of the maximum."""
+    gpu = np.asarray(gpu, np.float64)
+    for t in range(ref.shape[0]):
+        r, g = ref[t], gpu[t]
+        top = np.max(r)
+        m = r >= top + math.log(1e-3)
+        err = np.max(np.abs(g[m] - r[m]))
+        assert err <= TOL, "%s snapshot %d: %.3e" % (what, t, err)
+        absdev = np.max(np.abs(np.exp(g - top) - np.exp(r - top)))
+        assert absdev <= 4 * 2.0 ** -24 * 16, "%s snapshot %d: absolute %.3e of the maximum" % (what, t, absdev)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_grid_256_matches_oracle(qs, flags):
+    """The 256 x 256 grid of the finite-width workload (its transforms take the register-FFT
+    passes) over 6 cells, 2 steps, snapshots and per-step maxima, against the oracle."""
+    from paper_2607_24234_amd import inputs
+    d = inputs.finite_width(n_xi=6, n_steps=2, seed=5)
+    d["length"] = 3.0                   # h = 0.5: the march carries real phase per cell
+    d["flags"] = flags
+    d["seed_amp"] = 1e-4
+    n = d["n_steps"]
+    s = qs.GridSolver(d)
+    out = s.step(n, out_every=1, snapshots=True, max_ln_a=True)
+    s.sync_check()
+    st = s.get_state()
+    G = _oracle_grid(d)
+    ost = O.grid_seed(G, d["seed_kind"], d["seed_amp"], offset=d["centroid_offset"], sigma_r=d["sigma_r"],
+                      rng_seed=d["rng_seed"])
+    ln_e, ln_b, mx = O.grid_run(G, d["d_tau"], n, ost, out_every=1)
+    _compare_ln_large(out["ln_e"].cpu().numpy(), ln_e, "ln|E|")
+    _compare_ln_large(out["ln_b"].cpu().numpy(), ln_b, "ln|B|")
+    assert np.max(np.abs(out["max_ln_a"].cpu().numpy() - mx)) <= TOL
+    for key, ref in zip(("rho", "j_par", "j_x", "j_y"), ost.arrays()):
+        sc = np.max(np.abs(ref))
+        assert np.max(np.abs(st[key] - ref)) <= TOL * sc, key
+
+
 def test_full_size_odd_symmetry(qs):
     """The finite-width workload at its full size (256 x 256 x 8192 cells) for two steps with
     the centroid seed alone: the state stays odd in x (a property of the model that holds at
