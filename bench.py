@@ -142,6 +142,11 @@ def bench_batched(args):
 
 
 GRID_FLOPS_PER_CELL = 1330.0   # four 2D FFTs per slice per stage (5 N log2 N each) x 4 stages
+# HBM bytes per cell-update of the 256 x 256 pass structure: per stage the march (4 read,
+# 8 written), the row transform (16 + 16), the column pass (16 + 16) and the inverse rows with
+# the update (36 read, 16 written) = 128 B, four stages, plus the per-step field pass (march
+# 4 + 12, rows 12 + 16, columns 16 + 24, inverse rows 24) = 108 B
+GRID_BYTES_PER_CELL = 4 * 128.0 + 108.0
 
 
 def bench_finite_width(args):
@@ -167,7 +172,8 @@ def bench_finite_width(args):
     s.sync_check()
     cells = s.cells
     step_s = e0.elapsed_time(e1) * 1e-3 / K
-    achieved = GRID_FLOPS_PER_CELL * cells / step_s / 1e12
+    achieved = GRID_BYTES_PER_CELL * cells / step_s / 1e9
+    flops = GRID_FLOPS_PER_CELL * cells / step_s / 1e12
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -188,11 +194,12 @@ def bench_finite_width(args):
                        "sigma_r = 0.5, n_b/n_p = 0.05, gamma_b = 2000, d_tau = 2, centroid 1e-3 sigma_r "
                        "+ 1e-6 noise", "cells_per_step": cells,
            "max_ln_a_last": float(out["max_ln_a"][-1].item())},
-          {"bound": "alu", "achieved": achieved, "peak": 157.3, "unit": "TFLOP/s",
-           "frac": achieved / 157.3, "traffic": None,
-           "kernel": "one tau-step (4 stage evaluations: march, row FFT, column FFT + spectral "
-                     "operators, inverse row FFT + update; plus the field pass)",
-           "algorithmic_flops_per_cell": GRID_FLOPS_PER_CELL, "gpu_ms_per_step": step_s * 1e3}, cpu)
+          {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+           "kernel": "one tau-step of launches (4 stage evaluations: march, row FFT, column FFT + spectral "
+                     "operators, inverse row FFT + update; plus the field pass for the per-step maximum)",
+           "bytes_per_cell_update": GRID_BYTES_PER_CELL, "algorithmic_flops_per_cell": GRID_FLOPS_PER_CELL,
+           "tflops": flops, "valu_frac": flops / 157.3, "gpu_ms_per_step": step_s * 1e3}, cpu)
 
 
 def bench_surrogate(args):

@@ -526,7 +526,9 @@ __global__ void __launch_bounds__(256) grid_rows_fwd256(GridArgs a, const float 
         sm[(256 + kx) * XP + rr] = z2[r];
     }
     __syncthreads();
-    for (int t = tid; t < 2 * 256 * R; t += 256) {
+#pragma unroll
+    for (int it = 0; it < 2 * R; ++it) {
+        const int t = tid + 256 * it;
         const int f = t / (256 * R), kx = (t / R) & 255, r = t % R;
         const int64_t d = ((int64_t)j * 256 + kx) * a.ny + y0 + r;
         (f ? Z2 : Z1)[d] = sm[(f * 256 + kx) * XP + r];
@@ -620,7 +622,9 @@ __global__ void __launch_bounds__(256) grid_rows_inv256(GridArgs a, RowInvArgs r
 #pragma unroll
     for (int f0 = 0; f0 < NTR; f0 += 2) {
         const int nf = NTR - f0 < 2 ? NTR - f0 : 2;
-        for (int t = tid; t < nf * 256 * R; t += 256) {
+#pragma unroll
+        for (int it = 0; it < nf * R; ++it) {   // all loads in flight before the LDS stores
+            const int t = tid + 256 * it;
             const int f = t / (256 * R), kx = (t / R) & 255, rw = t % R;
             const int64_t d = ((int64_t)j * 256 + kx) * a.ny + y0 + rw;
             const int fi = f0 + f;
