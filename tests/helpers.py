@@ -2,6 +2,8 @@
 compare log-field outputs with the GPU path.  (Test infrastructure: imports the oracle.)"""
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 import oracle as O
@@ -49,3 +51,15 @@ def ln_compare(gpu, ref, tol, rel_floor=1e-6, what=""):
     err = float(np.max(np.abs(gpu[mask] - ref[mask]))) if mask.any() else 0.0
     assert err <= tol, "%s: max |d ln| = %.3e > %.1e" % (what, err, tol)
     return err
+
+
+def windowed_log_ratio(ln_e, ln_b, h, xi):
+    """1/2 ln( sum |E|^2 / sum |B|^2 ) over the cells within half a plasma wavelength of xi."""
+    ln_e = np.asarray(ln_e, np.float64)
+    ln_b = np.asarray(ln_b, np.float64)
+    n = len(ln_e)
+    c = np.arange(n)
+    x = (c + 0.5) * h
+    m = np.abs(x - xi) <= math.pi
+    top = max(np.max(ln_e[m]), np.max(ln_b[m]))
+    return 0.5 * math.log(np.sum(np.exp(2 * (ln_e[m] - top))) / np.sum(np.exp(2 * (ln_b[m] - top))))

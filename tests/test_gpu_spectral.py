@@ -249,3 +249,32 @@ def test_spectral3d_full_size_sampled(qs):
     ln_compare(gm, mx, FP32_TOL, what="3d max")
     ln_compare(ge, fe, FP32_TOL, what="3d ln E")
     ln_compare(gb, fb, FP32_TOL, what="3d ln B")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_field_hierarchy_behind_the_front_gpu(qs, precision):
+    """The Fig. 2 configuration (pair beam, n_b = 0.02 per species, gamma = 2e4, k = 3,
+    front impulse) to Gamma_CFI tau = 5.63 on the GPU: snapshots match the oracle and the
+    wavelength-averaged field energies show |B| dominant at xi = 2, |E| at xi = 20."""
+    import oracle as O
+    from exact_refs import gamma_cfi
+    from helpers import windowed_log_ratio
+    sp = [(-1.0, 1.0, 0.02), (1.0, 1.0, 0.02)]
+    G = gamma_cfi(sp, 2e4, 3.0)
+    n_xi, L = 512, 40.0
+    n = 256
+    inst = _slab(species=sp, gamma=2e4, length=L, n_xi=n_xi, kx=np.array([3.0]), d_tau=5.63 / G / n, n_steps=n,
+                 seed_kind=O.SEED_FRONT_IMPULSE)
+    prec = qs.QS_FP64 if precision == "fp64" else qs.QS_FP32
+    g = _run_gpu(qs, inst, n, out_every=n // 4, precision=prec)
+    ln_e, ln_b, mx, st = oracle_run(inst, n, out_every=n // 4, renorm=True)
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    _check_all(g, ln_e, ln_b, mx, tol, "hierarchy " + precision)
+    s = g["solver"]
+    f = s.step(0, snapshots=True)
+    s.sync_check()
+    fe = s.snapshot_view(f["ln_e"]).cpu().numpy()[0, :, 0]
+    fb = s.snapshot_view(f["ln_b"]).cpu().numpy()[0, :, 0]
+    h = L / n_xi
+    assert windowed_log_ratio(fe, fb, h, 2.0) < -0.2
+    assert windowed_log_ratio(fe, fb, h, 20.0) > 0.4

@@ -18,6 +18,7 @@ import os
 import numpy as np
 import pytest
 
+from helpers import windowed_log_ratio
 from exact_refs import (asym_critical, asym_front, front_limit_exact, gamma_cfi,
                         impulse_series, impulse_series_long, rk4_growth_factor, xi_transition)
 
@@ -324,3 +325,27 @@ def test_impulse_with_longitudinal_term(oracle, species, gamma, k):
     # second order (error components of the xi and tau discretizations may partly cancel on
     # the coarsest grid, hence the wide upper bound)
     assert 3.4 < errs[0] / errs[1] < 8.0 and 3.4 < errs[1] / errs[2] < 8.0, errs
+
+
+# ------------------------------------------------------------------------- field hierarchy
+@pytest.mark.parametrize("n_xi", [256, 512])
+def test_field_hierarchy_behind_the_front(oracle, n_xi):
+    """Sec. III.C, Fig. 2 (the 2D PIC run: pair beam, n_b = 0.02 per species, gamma = 2e4,
+    k_y ~ 3): at Gamma_CFI tau = 5.63 the magnetic field dominates at xi = 2 (spatiotemporal
+    CFI near the front) and the electric field at xi = 20 (spatiotemporal OTSI behind it).
+    The model seeded by a front impulse reproduces both, with the field energies averaged
+    over one plasma wavelength (the oscillatory OTSI response has nodes in E and B at
+    different places), at two resolutions."""
+    sp, gam, k = [E + (0.02,), P + (0.02,)], 2e4, 3.0
+    G = gamma_cfi(sp, gam, k)
+    L = 40.0
+    beam = oracle.Beam(sp, gam, n_xi, L / n_xi)
+    st = oracle.seed(beam, [k], oracle.SEED_FRONT_IMPULSE, 1e-6)
+    tau, n = 5.63 / G, n_xi // 2
+    oracle.run(beam, [k], tau / n, n, st, renorm=True, want_fields=False, want_max=False)
+    f = oracle.mode_fields(beam, k, st)
+    h = L / n_xi
+    assert windowed_log_ratio(f["ln_e"], f["ln_b"], h, 2.0) < -0.2      # |B| dominates
+    assert windowed_log_ratio(f["ln_e"], f["ln_b"], h, 20.0) > 0.4      # |E| dominates
+    # the magnetic front region is about xi_tr = 2 Gamma tau / sqrt(27) long
+    assert 2.0 < xi_transition(G, tau) < 2.4
