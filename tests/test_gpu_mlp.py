@@ -47,6 +47,30 @@ def test_forward_matches_oracle(qs, n):
     assert np.median(err / scale) <= 1e-5, float(np.median(err / scale))
 
 
+def test_forward_beyond_one_launch(qs):
+    """2^25 + 77 queries: two launches of the persistent inference kernel (2^25 queries per
+    launch) and a ragged last tile; sampled rows at both ends and across the launch boundary
+    against the oracle."""
+    import torch
+    P = _as_f32(_params(11))
+    n = (1 << 25) + 77
+    g = torch.Generator(device="cuda").manual_seed(12)
+    X = (torch.rand((n, 5), device="cuda", generator=g) * 3.0 - 1.5).contiguous()
+    net = qs.MLP(max_batch=128)
+    net.set_params(qs.pack_params(P))
+    y = net.forward(X)
+    torch.cuda.synchronize()
+    rows = np.concatenate([np.arange(300), np.arange((1 << 25) - 300, (1 << 25) + 77),
+                           np.random.default_rng(13).choice(n, 1000, replace=False)])
+    xs = X[torch.as_tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
+    ys = y[torch.as_tensor(rows, device="cuda")].cpu().numpy().astype(np.float64)
+    ref, cache = M.forward(P, xs, rounding="bf16")
+    scale = _row_scale(P, cache)
+    err = np.abs(ys - ref)
+    assert np.all(err <= 2.0 ** -8 * scale), float(np.max(err / scale))
+    assert np.median(err / scale) <= 1e-5
+
+
 def test_gradients_match_oracle(qs):
     import torch
     P = _as_f32(_params(3))
