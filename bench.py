@@ -258,6 +258,20 @@ def bench_surrogate(args):
     frac = float(used.float().mean().item())
     qps = n_q / sur_s
     tf = 1.58e6 * qps / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the FP64 oracle network (numpy) on a sample of the same queries, features included
+        import oracle.growth as OG
+        import oracle.mlp as OM
+        P = qs.unpack_params(net.get_params())
+        P = [(np.asarray(W, np.float64), np.asarray(b, np.float64)) for W, b in P]
+        qh = q[:20000].cpu().numpy().astype(np.float64)
+        t = time.perf_counter()
+        OM.forward(P, OG.features(qh))
+        dt = time.perf_counter() - t
+        cpu = {"value": len(qh) / dt, "unit": "queries/s", "cores": torch.get_num_threads(), "kind": "oracle",
+               "sample": "%d of the same queries through the FP64 oracle network (numpy, features included); "
+                         "%.1f s wall" % (len(qh), dt)}
     _line(METRIC, qps, "queries/s", args.epochs, 0, sur_s / (n_q // chunk) * 1e3, "bf16",
           {"workload": "growth-map queries uniform over log n_b in [-3, -1], log gamma in [1, 4], k in "
                        "[0.05, 4], xi in [0, 200], tau in [0, tau_f]; network 5-512x4-1 trained on the "
@@ -267,7 +281,7 @@ def bench_surrogate(args):
            "traffic": None, "kernel": "fused network forward (one persistent kernel, activations in LDS; "
                                       "3 bf16 512x512 layers on the matrix cores, fp32 first/last "
                                       "layers), 1.58 MFLOP per query"},
-          None,
+          cpu,
           surrogate_s_per_query=sur_s / n_q, solver_s_per_query=sol_s,
           speedup_vs_solver=sol_s / (sur_s / n_q),
           auto_tol=1e-2, auto_fraction_to_solver=frac, auto_s_per_query=auto_s)
