@@ -1,0 +1,196 @@
+// Envelope-approximation (SVEA) variant of the spectral path (include/qs_svea.h, Sec. III.B):
+// d_tau n = m, d_tau m = a * integral_0^xi n, one lane per transverse mode, all tau-steps of
+// a call in one launch (modes are independent), the four Runge-Kutta stages of a step in one
+// causal sweep down the cells with FP64 running integrals, loads a ring of kAhead cells
+// ahead, and an exact power-of-two rescale of a mode whose largest component leaves
+// [2^-100, 2^100] (applied to the next step's loads, like the full model's sweep).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "../../include/qs_svea.h"
+#include "qs_internal.h"
+
+namespace {
+
+constexpr int kAhead = 4;     // cells of loads in flight per lane
+constexpr int kRange = 100;   // rescale when the largest component leaves [2^-kRange, 2^kRange]
+
+struct cplx {
+    double x, y;
+};
+__device__ __forceinline__ cplx operator+(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cplx operator*(double s, cplx a) { return {s * a.x, s * a.y}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ double cmaxabs(cplx a) { return fmax(fabs(a.x), fabs(a.y)); }
+
+__global__ void __launch_bounds__(256) svea_seed(int64_t n_modes, int64_t total, double2 *__restrict__ n,
+                                                 double2 *__restrict__ m, int32_t *__restrict__ l2s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    n[i] = make_double2(0.0, 0.0);
+    m[i] = make_double2(1.0, 0.0);
+    if (i < n_modes) l2s[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, double h, const double2 *__restrict__ a_,
+                                                 double dt, int n_steps, double2 *__restrict__ nn,
+                                                 double2 *__restrict__ mm, int32_t *__restrict__ l2s) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_modes) return;
+    const cplx a = {a_[k].x, a_[k].y};
+    const double hh = 0.5 * h, d2 = 0.5 * dt, d6 = dt / 6.0;
+    const int last = n_xi - 1;
+    double scale = 1.0;   // pending power of two, applied to this step's loads
+    int l2 = l2s[k];
+    for (int s = 0; s < n_steps; ++s) {
+        cplx S1 = {0, 0}, S2 = {0, 0}, S3 = {0, 0}, S4 = {0, 0};   // h sum_{i<j} of each stage's n
+        double big = 0.0;
+        double2 rn[kAhead], rm[kAhead];
+#pragma unroll
+        for (int d = 0; d < kAhead; ++d) {
+            const int64_t o = (int64_t)min(d, last) * n_modes + k;
+            rn[d] = nn[o];
+            rm[d] = mm[o];
+        }
+        auto cell = [&](int j, double2 ln, double2 lm) {
+            const cplx n0 = {scale * ln.x, scale * ln.y}, m0 = {scale * lm.x, scale * lm.y};
+            // stage 1
+            const cplx k1n = m0, k1m = cmul(a, S1 + hh * n0);
+            S1 = S1 + h * n0;
+            // stage 2
+            const cplx n2 = n0 + d2 * k1n, m2 = m0 + d2 * k1m;
+            const cplx k2n = m2, k2m = cmul(a, S2 + hh * n2);
+            S2 = S2 + h * n2;
+            // stage 3
+            const cplx n3 = n0 + d2 * k2n, m3 = m0 + d2 * k2m;
+            const cplx k3n = m3, k3m = cmul(a, S3 + hh * n3);
+            S3 = S3 + h * n3;
+            // stage 4
+            const cplx n4 = n0 + dt * k3n, m4 = m0 + dt * k3m;
+            const cplx k4n = m4, k4m = cmul(a, S4 + hh * n4);
+            S4 = S4 + h * n4;
+            const cplx n1 = n0 + d6 * (k1n + 2.0 * k2n + 2.0 * k3n + k4n);
+            const cplx m1 = m0 + d6 * (k1m + 2.0 * k2m + 2.0 * k3m + k4m);
+            const int64_t o = (int64_t)j * n_modes + k;
+            nn[o] = make_double2(n1.x, n1.y);
+            mm[o] = make_double2(m1.x, m1.y);
+            big = fmax(big, fmax(cmaxabs(n1), cmaxabs(m1)));
+        };
+        int jb = 0;
+        for (; jb + kAhead <= n_xi; jb += kAhead) {
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const double2 ln = rn[u], lm = rm[u];
+                const int64_t o = (int64_t)min(jb + u + kAhead, last) * n_modes + k;   // the end reloads the last cell
+                rn[u] = nn[o];
+                rm[u] = mm[o];
+                cell(jb + u, ln, lm);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            if (jb + u < n_xi) cell(jb + u, rn[u], rm[u]);
+        // power-of-two rescale of the next step's loads (exact)
+        scale = 1.0;
+        if (big > 0.0 && (big > 0x1p100 || big < 0x1p-100)) {
+            const int e = ilogb(big);
+            scale = ldexp(1.0, -e);
+            l2 += e;
+        }
+    }
+    // a pending scale is applied in place before returning, so the stored state is exact
+    if (scale != 1.0) {
+        for (int j = 0; j < n_xi; ++j) {
+            const int64_t o = (int64_t)j * n_modes + k;
+            const double2 x = nn[o], y = mm[o];
+            nn[o] = make_double2(scale * x.x, scale * x.y);
+            mm[o] = make_double2(scale * y.x, scale * y.y);
+        }
+    }
+    l2s[k] = l2;
+}
+
+__global__ void __launch_bounds__(256) svea_ln(int64_t n_modes, int64_t total, const double2 *__restrict__ n,
+                                               const int32_t *__restrict__ l2s, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const double2 v = n[i];
+    const double ln2 = 0.69314718055994531;
+    out[i] = log(hypot(v.x, v.y)) + (double)(l2s[i % n_modes] - 1) * ln2;
+}
+
+qs_status sfail(qs_status st, const std::string &m) {
+    qs::set_last_error(m);
+    return st;
+}
+
+unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+qs_status check(int64_t n_modes, int32_t n_xi) {
+    if (n_modes < 1 || n_xi < 1) return sfail(QS_ERR_ARG, "n_modes and n_xi must be >= 1");
+    if ((n_modes * (int64_t)n_xi + 255) / 256 > (int64_t)0x7fffffff) return sfail(QS_ERR_ARG, "state too large");
+    return QS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_svea_coefficients(int32_t n_species, const double *q, const double *m, const double *nb_over_np,
+                               double gamma_b, int64_t n_modes, const double *k, double *a) {
+    if (n_species < 1 || !q || !m || !nb_over_np || !(gamma_b >= 1.0) || n_modes < 0 || (n_modes > 0 && (!k || !a)))
+        return sfail(QS_ERR_ARG, "species arrays, gamma_b >= 1, k and a are required");
+    double w2 = 0.0;
+    for (int s = 0; s < n_species; ++s) {
+        if (!(m[s] > 0.0)) return sfail(QS_ERR_ARG, "species masses must be > 0");
+        w2 += q[s] * q[s] * nb_over_np[s] / (m[s] * gamma_b);
+    }
+    for (int64_t i = 0; i < n_modes; ++i) {
+        a[2 * i] = 0.0;
+        a[2 * i + 1] = 0.5 * w2 * k[i] * k[i] / (1.0 + k[i] * k[i]);
+    }
+    return QS_OK;
+}
+
+qs_status qs_svea_seed_impulse(int64_t n_modes, int32_t n_xi, double *n, double *m, int32_t *log2_scale,
+                               void *hip_stream) {
+    qs_status st = check(n_modes, n_xi);
+    if (st != QS_OK) return st;
+    if (!n || !m || !log2_scale) return sfail(QS_ERR_ARG, "n, m and log2_scale are required");
+    const int64_t total = n_modes * (int64_t)n_xi;
+    hipLaunchKernelGGL(svea_seed, dim3(blocks_of(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n_modes,
+                       total, reinterpret_cast<double2 *>(n), reinterpret_cast<double2 *>(m), log2_scale);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QS_OK : sfail(QS_ERR_HIP, std::string("svea seed: ") + hipGetErrorString(e));
+}
+
+qs_status qs_svea_step(int64_t n_modes, int32_t n_xi, double h, const double *a, double d_tau, int32_t n_steps,
+                       double *n, double *m, int32_t *log2_scale, void *hip_stream) {
+    qs_status st = check(n_modes, n_xi);
+    if (st != QS_OK) return st;
+    if (!a || !n || !m || !log2_scale) return sfail(QS_ERR_ARG, "a, n, m and log2_scale are required");
+    if (!(h > 0.0) || !std::isfinite(h) || !std::isfinite(d_tau) || n_steps < 0)
+        return sfail(QS_ERR_ARG, "h > 0, finite d_tau and n_steps >= 0 are required");
+    if (n_steps == 0) return QS_OK;
+    hipLaunchKernelGGL(svea_step, dim3(blocks_of(n_modes)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n_modes,
+                       (int)n_xi, h, reinterpret_cast<const double2 *>(a), d_tau, (int)n_steps,
+                       reinterpret_cast<double2 *>(n), reinterpret_cast<double2 *>(m), log2_scale);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QS_OK : sfail(QS_ERR_HIP, std::string("svea step: ") + hipGetErrorString(e));
+}
+
+qs_status qs_svea_ln_envelope(int64_t n_modes, int32_t n_xi, const double *n, const int32_t *log2_scale,
+                              double *ln_abs, void *hip_stream) {
+    qs_status st = check(n_modes, n_xi);
+    if (st != QS_OK) return st;
+    if (!n || !log2_scale || !ln_abs) return sfail(QS_ERR_ARG, "n, log2_scale and ln_abs are required");
+    const int64_t total = n_modes * (int64_t)n_xi;
+    hipLaunchKernelGGL(svea_ln, dim3(blocks_of(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n_modes,
+                       total, reinterpret_cast<const double2 *>(n), log2_scale, ln_abs);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QS_OK : sfail(QS_ERR_HIP, std::string("svea envelope: ") + hipGetErrorString(e));
+}
+
+}  // extern "C"

@@ -90,7 +90,8 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_mlp_train_step", "qs_mlp_free", "qs_growth_targets", "qs_growth_sample",
            "qs_growth_features", "qs_growth_calibrate", "qs_growth_map",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
-           "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint"]
+           "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
+           "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope"]
 
 
 def lib():
@@ -177,6 +178,15 @@ def lib():
     L.qs_load_checkpoint.argtypes = [vp, vp, ctypes.c_size_t]
     L.qs_debug_splitmix64.restype = ctypes.c_uint64
     L.qs_debug_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.qs_svea_coefficients.restype = ctypes.c_int
+    L.qs_svea_coefficients.argtypes = [ctypes.c_int32, _D, _D, _D, ctypes.c_double, ctypes.c_int64, _D, _D]
+    L.qs_svea_seed_impulse.restype = ctypes.c_int
+    L.qs_svea_seed_impulse.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
+    L.qs_svea_step.restype = ctypes.c_int
+    L.qs_svea_step.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_double, vp, ctypes.c_double, ctypes.c_int32,
+                               vp, vp, vp, vp]
+    L.qs_svea_ln_envelope.restype = ctypes.c_int
+    L.qs_svea_ln_envelope.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -630,3 +640,58 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def svea_coefficients(species, gamma, k):
+    """(i/2) Gamma_CFI(k)^2 per wavenumber (include/qs_svea.h), as a complex numpy array."""
+    q = np.ascontiguousarray([sp[0] for sp in species], np.float64)
+    m = np.ascontiguousarray([sp[1] for sp in species], np.float64)
+    nb = np.ascontiguousarray([sp[2] for sp in species], np.float64)
+    k = np.ascontiguousarray(k, np.float64).ravel()
+    a = np.empty(2 * len(k), np.float64)
+    _check(lib().qs_svea_coefficients(len(q), _dp(q), _dp(m), _dp(nb), float(gamma), len(k), _dp(k), _dp(a)))
+    return a[0::2] + 1j * a[1::2]
+
+
+class SVEASolver:
+    """The envelope-approximation variant (include/qs_svea.h) for one beam and a list of
+    wavenumbers: FP64 state n, m [n_xi][n_modes] (complex) in torch device memory, seeded by the
+    front impulse."""
+
+    def __init__(self, species, gamma, k, length, n_xi, d_tau, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        self.k = np.ascontiguousarray(k, np.float64).ravel()
+        self.n_modes, self.n_xi = len(self.k), int(n_xi)
+        self.h = float(length) / self.n_xi
+        self.d_tau = float(d_tau)
+        a = svea_coefficients(species, gamma, self.k)
+        self.a = torch.as_tensor(np.stack([a.real, a.imag], 1), device="cuda").contiguous()
+        self.n = torch.empty((self.n_xi, self.n_modes, 2), dtype=torch.float64, device="cuda")
+        self.m = torch.empty_like(self.n)
+        self.log2 = torch.empty(self.n_modes, dtype=torch.int32, device="cuda")
+        self.seed_impulse()
+
+    def _s(self):
+        return _stream_ptr(self.stream)
+
+    def seed_impulse(self):
+        _check(lib().qs_svea_seed_impulse(self.n_modes, self.n_xi, _vp(self.n), _vp(self.m), _vp(self.log2), self._s()))
+
+    def step(self, n_steps):
+        _check(lib().qs_svea_step(self.n_modes, self.n_xi, self.h, _vp(self.a), self.d_tau, int(n_steps), _vp(self.n),
+                                  _vp(self.m), _vp(self.log2), self._s()))
+
+    def ln_envelope(self, out=None):
+        out = self.torch.empty((self.n_xi, self.n_modes), dtype=self.torch.float64, device="cuda") if out is None else out
+        _check(lib().qs_svea_ln_envelope(self.n_modes, self.n_xi, _vp(self.n), _vp(self.log2), _vp(out), self._s()))
+        return out
+
+    def state(self):
+        """(n, m) as complex numpy arrays [n_xi][n_modes] including the power-of-two scale."""
+        self.torch.cuda.synchronize()
+        sc = np.ldexp(1.0, self.log2.cpu().numpy().astype(np.int64))
+        n = self.n.cpu().numpy()
+        m = self.m.cpu().numpy()
+        return (n[..., 0] + 1j * n[..., 1]) * sc[None, :], (m[..., 0] + 1j * m[..., 1]) * sc[None, :]

@@ -135,3 +135,25 @@ def impulse_series_long(tau, xi, G, beta, dps=40, tol=1e-30):
             if j > 4000:
                 raise RuntimeError("impulse series did not converge")
         return float(total)
+
+
+def svea_series(a, tau, xi, dps=50):
+    """Exact impulse response of the envelope equation d_tau^2 d_xi n = a n + delta(xi)
+    delta(tau) (Sec. III.B after the envelope approximation): Laplace-transforming in tau and
+    xi gives 1/(s^2 p - a), whose inverse is n = sum_j (a xi)^j tau^(2j+1) / (j! (2j+1)!)
+    (n = tau at the front).  Summed in mpmath: for imaginary a the terms rotate in phase and
+    cancel to many digits."""
+    with mp.workdps(dps):
+        z = mp.mpc(a) * mp.mpf(xi) * mp.mpf(tau) ** 2
+        term = mp.mpc(tau)
+        total = mp.mpc(0)
+        j = 0
+        while True:
+            total += term
+            j += 1
+            term = term * z / (j * (2 * j) * (2 * j + 1))
+            if j > 8 and abs(term) < mp.mpf(10) ** (-dps + 5) * abs(total):
+                break
+            if j > 200000:
+                raise RuntimeError("series did not converge")
+        return complex(total)
