@@ -202,6 +202,52 @@ def bench_finite_width(args):
            "tflops": flops, "valu_frac": flops / 157.3, "gpu_ms_per_step": step_s * 1e3}, cpu)
 
 
+def bench_svea(args):
+    """The envelope-approximation variant on the 3D spectral mode set (205,859 modes of the
+    512^2 grid within |k| <= 6, 4096 cells over L = 100, n_b = 0.01, gamma = 1000, d_tau = 10),
+    front-impulse seed, FP64: one library call of K steps (one launch)."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import inputs, qs
+    K = 20 if args.steps == 2000 else args.steps
+    d = inputs.spectral3d()
+    k = np.hypot(d["kx"], d["ky"])
+    sv = qs.SVEASolver(d["species"], d["gamma"], k, d["length"], d["n_xi"], d["d_tau"])
+    sv.step(2)
+    sv.seed_impulse()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(sv.stream)
+    sv.step(K)
+    e1.record(sv.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cells = len(k) * d["n_xi"]
+    launch = e0.elapsed_time(e1) * 1e-3
+    achieved = 64.0 * cells * K / launch / 1e9
+    ln = sv.ln_envelope()
+    torch.cuda.synchronize()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import svea as OS
+        sel = np.linspace(0, len(k) - 1, 256).astype(np.int64)
+        a = OS.svea_coefficient(d["species"], d["gamma"], k[sel])
+        t = time.perf_counter()
+        OS.run(a, d["n_xi"], d["length"] / d["n_xi"], d["d_tau"], 4, out_every=10 ** 9)
+        dt = time.perf_counter() - t
+        cpu = {"value": len(sel) * d["n_xi"] * 4 / dt, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+               "kind": "oracle", "sample": "256 modes spread over the mode list x 4096 cells x 4 steps, FP64 numpy; "
+                                           "%.1f s wall" % dt}
+    _line(METRIC, cells * K / wall, "cell-updates/s", K, 2, wall / K * 1e3, "f64",
+          {"workload": "envelope-approximation variant, 205,859 modes (512^2 grid, |k| <= 6) x 4096 cells, L = 100, "
+                       "n_b/n_p = 0.01, gamma_b = 1000, d_tau = 10, front impulse", "cells_per_step": cells,
+           "max_ln_envelope": float(ln.max().item())},
+          {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": None, "kernel": "svea_step (one lane per mode, all K steps in one launch)",
+           "algorithmic_bytes_per_launch": 64.0 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
+
+
 def bench_surrogate(args):
     """Growth-map queries: the network trained on the batched uniform-seed sweep against the
     solver, with the held-out error table that routes queries."""
@@ -296,11 +342,12 @@ def main():
     ap.add_argument("--snapshot-every", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate"],
+    ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate", "svea"],
                     default="spectral3d",
                     help="spectral3d (default, the headline line); batched: 256-instance sweep in "
                          "one persistent launch; finite_width: 256^2 transverse grid x 8192 cells; "
-                         "surrogate: growth-map queries, network against solver")
+                         "surrogate: growth-map queries, network against solver; svea: the envelope-"
+                         "approximation variant on the 3D mode set")
     ap.add_argument("--epochs", type=int, default=40, help="surrogate training epochs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (x3) and exit: "
@@ -330,7 +377,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "spectral3d":
         {"batched": bench_batched, "finite_width": bench_finite_width,
-         "surrogate": bench_surrogate}[args.workload](args)
+         "surrogate": bench_surrogate, "svea": bench_svea}[args.workload](args)
         return
     inst = inputs.spectral3d()
     prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64

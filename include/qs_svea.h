@@ -19,8 +19,10 @@
  * state * 2^log2_scale.
  *
  * Layouts (all device memory, caller-owned): n and m are complex FP64, interleaved
- * (re, im), [n_xi][n_modes] with the mode fastest; a is complex FP64 [n_modes];
- * log2_scale is int32 [n_modes].  Calls are ordered on hip_stream (NULL = null stream) and
+ * (re, im), in blocks of 64 modes: the value of (cell j, mode k) is element
+ * ((k / 64) n_xi + j) 64 + k % 64, so a buffer holds ceil(n_modes / 64) 64 n_xi complex
+ * values (padding entries are written by the seed and otherwise ignored); a is complex FP64
+ * [n_modes]; log2_scale is int32 [n_modes].  Calls are ordered on hip_stream (NULL = null stream) and
  * do not synchronize.  Errors: QS_ERR_ARG (sizes, NULL pointers; nothing is launched),
  * QS_ERR_HIP (launch failure); qs_last_error() has the text.
  */

@@ -1,8 +1,9 @@
 // Envelope-approximation (SVEA) variant of the spectral path (include/qs_svea.h, Sec. III.B):
 // d_tau n = m, d_tau m = a * integral_0^xi n, one lane per transverse mode, all tau-steps of
-// a call in one launch (modes are independent), the four Runge-Kutta stages of a step in one
-// causal sweep down the cells with FP64 running integrals, loads a ring of kAhead cells
-// ahead, and an exact power-of-two rescale of a mode whose largest component leaves
+// a call in one launch (modes are independent; each 64-mode block's cells contiguous, so a
+// wave streams through one region), the four Runge-Kutta stages of a step in one
+// causal sweep down the cells with FP64 running integrals, loads kAhead cells ahead in a
+// register ring, and an exact power-of-two rescale of a mode whose largest component leaves
 // [2^-100, 2^100] (applied to the next step's loads, like the full model's sweep).
 #include <hip/hip_runtime.h>
 
@@ -25,6 +26,7 @@ __device__ __forceinline__ cplx operator*(double s, cplx a) { return {s * a.x, s
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ double cmaxabs(cplx a) { return fmax(fabs(a.x), fabs(a.y)); }
 
+// state element (cell j, mode k) of the blocked layout: ((k / 64) n_xi + j) 64 + k % 64
 __global__ void __launch_bounds__(256) svea_seed(int64_t n_modes, int64_t total, double2 *__restrict__ n,
                                                  double2 *__restrict__ m, int32_t *__restrict__ l2s) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -40,6 +42,7 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_modes) return;
     const cplx a = {a_[k].x, a_[k].y};
+    const int64_t base = (k / 64) * (int64_t)n_xi * 64 + (k % 64);   // cell j at base + 64 j
     const double hh = 0.5 * h, d2 = 0.5 * dt, d6 = dt / 6.0;
     const int last = n_xi - 1;
     double scale = 1.0;   // pending power of two, applied to this step's loads
@@ -47,10 +50,13 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
     for (int s = 0; s < n_steps; ++s) {
         cplx S1 = {0, 0}, S2 = {0, 0}, S3 = {0, 0}, S4 = {0, 0};   // h sum_{i<j} of each stage's n
         double big = 0.0;
-        double2 rn[kAhead], rm[kAhead];
+        // ring of kAhead + 1 slots: cell j sits in slot j % (kAhead + 1), loaded kAhead cells
+        // early into the slot the previous cell has just freed (no copies at the loop edge)
+        constexpr int R = kAhead + 1;
+        double2 rn[R], rm[R];
 #pragma unroll
         for (int d = 0; d < kAhead; ++d) {
-            const int64_t o = (int64_t)min(d, last) * n_modes + k;
+            const int64_t o = base + 64 * (int64_t)min(d, last);
             rn[d] = nn[o];
             rm[d] = mm[o];
         }
@@ -73,24 +79,24 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
             S4 = S4 + h * n4;
             const cplx n1 = n0 + d6 * (k1n + 2.0 * k2n + 2.0 * k3n + k4n);
             const cplx m1 = m0 + d6 * (k1m + 2.0 * k2m + 2.0 * k3m + k4m);
-            const int64_t o = (int64_t)j * n_modes + k;
+            const int64_t o = base + 64 * (int64_t)j;
             nn[o] = make_double2(n1.x, n1.y);
             mm[o] = make_double2(m1.x, m1.y);
             big = fmax(big, fmax(cmaxabs(n1), cmaxabs(m1)));
         };
         int jb = 0;
-        for (; jb + kAhead <= n_xi; jb += kAhead) {
+        for (; jb + R <= n_xi; jb += R) {
 #pragma unroll
-            for (int u = 0; u < kAhead; ++u) {
-                const double2 ln = rn[u], lm = rm[u];
-                const int64_t o = (int64_t)min(jb + u + kAhead, last) * n_modes + k;   // the end reloads the last cell
-                rn[u] = nn[o];
-                rm[u] = mm[o];
-                cell(jb + u, ln, lm);
+            for (int u = 0; u < R; ++u) {
+                const int64_t o = base + 64 * (int64_t)min(jb + u + kAhead, last);   // the end reloads the last cell
+                rn[(u + kAhead) % R] = nn[o];
+                rm[(u + kAhead) % R] = mm[o];
+                __builtin_amdgcn_sched_barrier(0);   // keep the loads kAhead cells ahead of their use
+                cell(jb + u, rn[u], rm[u]);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kAhead; ++u)
+        for (int u = 0; u < R; ++u)
             if (jb + u < n_xi) cell(jb + u, rn[u], rm[u]);
         // power-of-two rescale of the next step's loads (exact)
         scale = 1.0;
@@ -103,7 +109,7 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
     // a pending scale is applied in place before returning, so the stored state is exact
     if (scale != 1.0) {
         for (int j = 0; j < n_xi; ++j) {
-            const int64_t o = (int64_t)j * n_modes + k;
+            const int64_t o = base + 64 * (int64_t)j;
             const double2 x = nn[o], y = mm[o];
             nn[o] = make_double2(scale * x.x, scale * x.y);
             mm[o] = make_double2(scale * y.x, scale * y.y);
@@ -112,13 +118,15 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
     l2s[k] = l2;
 }
 
-__global__ void __launch_bounds__(256) svea_ln(int64_t n_modes, int64_t total, const double2 *__restrict__ n,
+// ln |N| into [cell][mode] (mode fastest) from the blocked state
+__global__ void __launch_bounds__(256) svea_ln(int64_t n_modes, int n_xi, const double2 *__restrict__ n,
                                                const int32_t *__restrict__ l2s, double *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const double2 v = n[i];
+    if (i >= n_modes * (int64_t)n_xi) return;
+    const int64_t j = i / n_modes, k = i % n_modes;
+    const double2 v = n[((k / 64) * n_xi + j) * 64 + k % 64];
     const double ln2 = 0.69314718055994531;
-    out[i] = log(hypot(v.x, v.y)) + (double)(l2s[i % n_modes] - 1) * ln2;
+    out[i] = log(hypot(v.x, v.y)) + (double)(l2s[k] - 1) * ln2;
 }
 
 qs_status sfail(qs_status st, const std::string &m) {
@@ -128,9 +136,11 @@ qs_status sfail(qs_status st, const std::string &m) {
 
 unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+int64_t padded(int64_t n_modes) { return (n_modes + 63) / 64 * 64; }
+
 qs_status check(int64_t n_modes, int32_t n_xi) {
     if (n_modes < 1 || n_xi < 1) return sfail(QS_ERR_ARG, "n_modes and n_xi must be >= 1");
-    if ((n_modes * (int64_t)n_xi + 255) / 256 > (int64_t)0x7fffffff) return sfail(QS_ERR_ARG, "state too large");
+    if ((padded(n_modes) * (int64_t)n_xi + 255) / 256 > (int64_t)0x7fffffff) return sfail(QS_ERR_ARG, "state too large");
     return QS_OK;
 }
 
@@ -159,7 +169,7 @@ qs_status qs_svea_seed_impulse(int64_t n_modes, int32_t n_xi, double *n, double 
     qs_status st = check(n_modes, n_xi);
     if (st != QS_OK) return st;
     if (!n || !m || !log2_scale) return sfail(QS_ERR_ARG, "n, m and log2_scale are required");
-    const int64_t total = n_modes * (int64_t)n_xi;
+    const int64_t total = padded(n_modes) * (int64_t)n_xi;
     hipLaunchKernelGGL(svea_seed, dim3(blocks_of(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n_modes,
                        total, reinterpret_cast<double2 *>(n), reinterpret_cast<double2 *>(m), log2_scale);
     const hipError_t e = hipGetLastError();
@@ -188,7 +198,7 @@ qs_status qs_svea_ln_envelope(int64_t n_modes, int32_t n_xi, const double *n, co
     if (!n || !log2_scale || !ln_abs) return sfail(QS_ERR_ARG, "n, log2_scale and ln_abs are required");
     const int64_t total = n_modes * (int64_t)n_xi;
     hipLaunchKernelGGL(svea_ln, dim3(blocks_of(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n_modes,
-                       total, reinterpret_cast<const double2 *>(n), log2_scale, ln_abs);
+                       (int)n_xi, reinterpret_cast<const double2 *>(n), log2_scale, ln_abs);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? QS_OK : sfail(QS_ERR_HIP, std::string("svea envelope: ") + hipGetErrorString(e));
 }

@@ -655,8 +655,8 @@ def svea_coefficients(species, gamma, k):
 
 class SVEASolver:
     """The envelope-approximation variant (include/qs_svea.h) for one beam and a list of
-    wavenumbers: FP64 state n, m [n_xi][n_modes] (complex) in torch device memory, seeded by the
-    front impulse."""
+    wavenumbers: FP64 state n, m (complex, blocks of 64 modes) in torch device memory, seeded by
+    the front impulse; state() returns them as [n_xi][n_modes]."""
 
     def __init__(self, species, gamma, k, length, n_xi, d_tau, stream=None):
         import torch
@@ -668,7 +668,8 @@ class SVEASolver:
         self.d_tau = float(d_tau)
         a = svea_coefficients(species, gamma, self.k)
         self.a = torch.as_tensor(np.stack([a.real, a.imag], 1), device="cuda").contiguous()
-        self.n = torch.empty((self.n_xi, self.n_modes, 2), dtype=torch.float64, device="cuda")
+        self.n_blocks = (self.n_modes + 63) // 64
+        self.n = torch.empty((self.n_blocks, self.n_xi, 64, 2), dtype=torch.float64, device="cuda")
         self.m = torch.empty_like(self.n)
         self.log2 = torch.empty(self.n_modes, dtype=torch.int32, device="cuda")
         self.seed_impulse()
@@ -692,6 +693,8 @@ class SVEASolver:
         """(n, m) as complex numpy arrays [n_xi][n_modes] including the power-of-two scale."""
         self.torch.cuda.synchronize()
         sc = np.ldexp(1.0, self.log2.cpu().numpy().astype(np.int64))
-        n = self.n.cpu().numpy()
-        m = self.m.cpu().numpy()
-        return (n[..., 0] + 1j * n[..., 1]) * sc[None, :], (m[..., 0] + 1j * m[..., 1]) * sc[None, :]
+        def unblock(t):
+            a = t.cpu().numpy()                                   # [block][cell][lane][2]
+            a = a.transpose(1, 0, 2, 3).reshape(self.n_xi, self.n_blocks * 64, 2)[:, :self.n_modes]
+            return a[..., 0] + 1j * a[..., 1]
+        return unblock(self.n) * sc[None, :], unblock(self.m) * sc[None, :]
