@@ -80,7 +80,8 @@ enum {
 enum {
     QS_FLAG_DROP_LONGITUDINAL = 1, /* drop the gamma^-2 d_xi^2 term: Eq. CFI_st_master */
     QS_FLAG_NO_RESTORING = 2,      /* plasma operator d_xi^2 only: Eq. CFI_st_master_front */
-    QS_FLAG_STEADY_INFLOW = 4      /* plasma ahead of the front equals cell 0 (uniform test) */
+    QS_FLAG_STEADY_INFLOW = 4,     /* plasma ahead of the front equals cell 0 (uniform test) */
+    QS_FLAG_FPERP_SNAPSHOTS = 8    /* output option: snapshots' ln_e holds ln|F_perp| (below) */
 };
 
 /*
@@ -118,7 +119,13 @@ enum {
  *                                 centroid_offset in x plus uniform noise (u as for NOISE with
  *                                 index (j ny + iy) nx + ix); NOISE is seed_amp (2u - 1) f g,
  *                                 UNIFORM seed_amp f g.
- *   flags                       : QS_FLAG_* test hooks (0 for the physical model).
+ *   flags                       : QS_FLAG_* model test hooks (0 for the physical model) and
+ *                                 the output option QS_FLAG_FPERP_SNAPSHOTS (spectral
+ *                                 geometry only): snapshot ln_e then receives
+ *                                 ln|F_perp| = ln(k kappa |n_p|) (+ the log-scale), the
+ *                                 transverse force E_perp - B_perp = i k Psi on a beam particle
+ *                                 (Sec. III.D, the quantity of Figs. 3 and 4); ln_b and the
+ *                                 per-step max ln A are unchanged.
  */
 typedef struct qs_params {
     int32_t n_species;

@@ -177,6 +177,7 @@ qs_status validate_one(const qs_params &p, int i) {
             return fail(QS_ERR_ARG, at + "nx * ny * n_xi must be at most 2^31");
         if (p.precision != QS_FP32) return fail(QS_ERR_UNSUPPORTED, at + "the transverse grid runs in FP32 only");
         if (p.flags & QS_FLAG_STEADY_INFLOW) return fail(QS_ERR_UNSUPPORTED, at + "STEADY_INFLOW is spectral only");
+        if (p.flags & QS_FLAG_FPERP_SNAPSHOTS) return fail(QS_ERR_UNSUPPORTED, at + "FPERP_SNAPSHOTS is spectral only");
     } else {
         if (p.n_modes < 1 || p.n_modes > (int64_t(1) << 26)) return fail(QS_ERR_ARG, at + "n_modes must be in [1, 2^26]");
         if (!p.kx) return fail(QS_ERR_ARG, at + "kx is required");
@@ -213,7 +214,7 @@ qs_status validate_one(const qs_params &p, int i) {
             if (k2 == 0.0) return fail(QS_ERR_ARG, at + "FRONT_IMPULSE seed needs k != 0 for every mode");
         }
     }
-    if (p.flags & ~(QS_FLAG_DROP_LONGITUDINAL | QS_FLAG_NO_RESTORING | QS_FLAG_STEADY_INFLOW))
+    if (p.flags & ~(QS_FLAG_DROP_LONGITUDINAL | QS_FLAG_NO_RESTORING | QS_FLAG_STEADY_INFLOW | QS_FLAG_FPERP_SNAPSHOTS))
         return fail(QS_ERR_ARG, at + "unknown flag bits");
     return QS_OK;
 }

@@ -388,11 +388,19 @@ march_kernel(StepArgs a) {
                     }
                     const TC a2 = e2 + b2;
                     a2max[t] = a2 > a2max[t] ? a2 : a2max[t];
-                    if (SNAP && writer && mloc[t] < I.n_modes) {
-                        const double sh = (double)L[t] * 0.69314718055994530942;
-                        const int64_t o = a.snap_base + I.snap_off + (int64_t)j * I.n_modes + mloc[t];
-                        static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(e2) + sh);
-                        static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
+                    if (SNAP) {
+                        // snapshot option: |F_perp|^2 = k^2 kappa^2 |n_p|^2 in place of |E|^2
+                        TC s2 = e2;
+                        if (I.flags & QS_FLAG_FPERP_SNAPSHOTS) {
+                            if (NC >= 2) s2 = k2kap2[t] * (ncf0[2 * t] * ncf0[2 * t] + ncf0[2 * t + 1] * ncf0[2 * t + 1]);
+                            else s2 = pair_sum(k2kap2[0] * ncf0[0] * ncf0[0]);
+                        }
+                        if (writer && mloc[t] < I.n_modes) {
+                            const double sh = (double)L[t] * 0.69314718055994530942;
+                            const int64_t o = a.snap_base + I.snap_off + (int64_t)j * I.n_modes + mloc[t];
+                            static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(s2) + sh);
+                            static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
+                        }
                     }
                 }
             }

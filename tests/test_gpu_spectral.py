@@ -278,3 +278,60 @@ def test_field_hierarchy_behind_the_front_gpu(qs, precision):
     h = L / n_xi
     assert windowed_log_ratio(fe, fb, h, 2.0) < -0.2
     assert windowed_log_ratio(fe, fb, h, 20.0) > 0.4
+
+
+def _fig3_inst(n_xi=512):
+    from paper_2607_24234_amd import inputs
+    L = 30.0
+    return _slab(n_xi=n_xi, length=L, profile_table=inputs.gaussian_profile(n_xi, L, 15.0, 3.5),
+                 kx=np.array([5.0]), species=[(-1.0, 1.0, 0.03), (1.0, 1.0, 0.03)], gamma=2000.0, d_tau=5.0,
+                 seed_kind=0, seed_amp=1e-6, rng_seed=0)
+
+
+@pytest.mark.parametrize("precision,nc", [("fp64", 1), ("fp32", 1), ("fp32", 2)])
+def test_fperp_snapshots_gaussian_beam(qs, precision, nc):
+    """The Sec. III.D Gaussian beam (pair beam, peak n_b = 0.03 per species, gamma = 2000,
+    sigma = 3.5 centred at xi = 15, k = 5) with a synthetic noise seed up to Gamma_CFI tau =
+    6.4, snapshots of the transverse force F_perp = i k kappa n_p (QS_FLAG_FPERP_SNAPSHOTS)
+    against the oracle's n_p, and the two behaviours the paper reports: steady growth near
+    the beam centre at about the peak Gamma_CFI (5.4e-3; filaments, CFI), and a response
+    modulated at the plasma wavelength behind it (OTSI)."""
+    import oracle as O
+    from helpers import oracle_beam
+    inst = _fig3_inst()
+    inst["flags"] = qs.FLAG_FPERP_SNAPSHOTS
+    n, every = 240, 8
+    prec = qs.QS_FP64 if precision == "fp64" else qs.QS_FP32
+    s = qs.Solver([inst], precision=prec, columns_per_lane=nc)
+    out = s.step(n, out_every=every, snapshots=True)
+    s.sync_check()
+    lnf = s.snapshot_view(out["ln_e"]).cpu().numpy()[:, :, 0]
+    st = s.get_state()[0]
+    ref_inst = dict(inst, flags=0)
+    beam = oracle_beam(ref_inst)
+    ost = O.seed(beam, [5.0], O.SEED_NOISE, 1e-6, rng_seed=0, n_modes_total=1)
+    kap = 1.0 / 26.0
+    ref = []
+    for t in range(0, n, every):
+        ref.append(np.log(5.0 * kap * np.abs(O.mode_fields(beam, 5.0, ost)["np"])))
+        O.run(beam, [5.0], 5.0, every, ost, want_fields=False, want_max=False)
+    ref = np.array(ref)[:, :, None]
+    ln_compare(lnf[:, :, None], ref, FP64_TOL if precision == "fp64" else FP32_TOL, what="F_perp " + precision)
+    # steady growth at the centre over the last third, at 0.8 .. 1.05 of the peak rate
+    G = math.sqrt(2 * 0.03 / 2000.0 * 25.0 / 26.0)
+    h = 30.0 / 512
+    j15 = int(15.0 / h)
+    f15 = lnf[:, j15]
+    third = len(f15) * 2 // 3
+    assert np.all(np.diff(f15[third:]) > 0)
+    rate = (f15[-1] - f15[third]) / ((len(f15) - 1 - third) * every * 5.0) / G
+    assert 0.8 < rate < 1.05, rate
+    # phase of rho along xi: flat through the centre, winding at ~1 rad per unit xi behind it
+    xi = (np.arange(512) + 0.5) * h
+    ph = np.unwrap(np.angle(st["rho"][0]))
+
+    def slope(a, b):
+        m = (xi >= a) & (xi <= b)
+        return abs(np.polyfit(xi[m], ph[m], 1)[0])
+    assert slope(12.0, 15.0) < 0.6
+    assert 0.8 < slope(24.0, 28.0) < 1.2
