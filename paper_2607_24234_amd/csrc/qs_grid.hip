@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) grid_march(GridArgs a, const float *__res
         v = vn;
         const int64_t o = (int64_t)j * a.P + p;
         np_c[o] = (float)nc;
-        v_f[o] = (float)vn;
+        if (v_f) v_f[o] = (float)vn;   // the field pass needs only n_p and the centre derivative
         if (v_c) v_c[o] = (float)vc;
     };
     const int last = a.n_xi - 1;
@@ -821,7 +821,7 @@ hipError_t fields(GridCtx *c, float *ln_e, float *ln_b, uint32_t *key, hipStream
     const GridArgs &a = c->a;
     const int R = std::min(kRows, a.ny);
     const bool r256 = is256(a);
-    hipLaunchKernelGGL(grid_march, dim3(nblk(a.P)), dim3(256), 0, s, a, c->U[0], c->np_c, c->v_f, c->v_c);
+    hipLaunchKernelGGL(grid_march, dim3(nblk(a.P)), dim3(256), 0, s, a, c->U[0], c->np_c, (float *)nullptr, c->v_c);
     if (r256)
         hipLaunchKernelGGL(grid_rows_fwd256<1>, dim3(16, a.n_xi), dim3(256), 0, s, a, c->np_c, c->U[0], c->v_c,
                            (const float *)nullptr, c->Z1, c->Z2);
