@@ -47,6 +47,25 @@ def read_traffic(precision_name, steps_per_launch):
         return None
 
 
+def read_workload_traffic(workload, amount):
+    """Calibrated HBM bytes (FETCH_SIZE + WRITE_SIZE against a plain copy) of one launch, or of
+    one tau-step for the finite-width pass sequence, from the rocprofv3 counter summary -- only
+    if the counters were taken on the current source of the kernels (else None)."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        e = json.load(open(p))[workload]
+        src = os.path.join(ROOT, e["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != e["source_sha256_16"]:
+            return None
+        return float(e[amount])
+    except Exception:
+        return None
+
+
+def _scaled(v, f):
+    return None if v is None else v * f
+
+
 def cpu_baseline(inst, seconds=15.0):
     """The FP64 oracle timed on the host cores on a bounded sample of the same workload:
     modes spread evenly over the mode list, all 4096 cells, a fixed number of tau-steps;
@@ -136,7 +155,7 @@ def bench_batched(args):
                        "gamma in [10, 1e4], L in [5, 200], 128..8192 cells, 200 steps, noise seed 1e-6",
            "cells_per_step": cells, "plan": s2.plan()},
           {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+           "frac": achieved / HBM_PEAK_GBS, "traffic": read_workload_traffic("batched", "bytes_per_launch"),
            "kernel": "march_kernel (persistent, xi-segmented), one launch = 200 steps of all instances",
            "algorithmic_bytes_per_launch": 48 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
 
@@ -145,8 +164,8 @@ GRID_FLOPS_PER_CELL = 1330.0   # four 2D FFTs per slice per stage (5 N log2 N ea
 # HBM bytes per cell-update of the 256 x 256 pass structure: per stage the march (4 read,
 # 8 written), the row transform (16 + 16), the column pass (16 + 16) and the inverse rows with
 # the update (36 read, 16 written) = 128 B, four stages, plus the per-step field pass (march
-# 4 + 12, rows 12 + 16, columns 16 + 24, inverse rows 24) = 108 B
-GRID_BYTES_PER_CELL = 4 * 128.0 + 108.0
+# 4 + 8, rows 12 + 16, columns 16 + 24, inverse rows 24) = 104 B
+GRID_BYTES_PER_CELL = 4 * 128.0 + 104.0
 
 
 def bench_finite_width(args):
@@ -195,7 +214,7 @@ def bench_finite_width(args):
                        "+ 1e-6 noise", "cells_per_step": cells,
            "max_ln_a_last": float(out["max_ln_a"][-1].item())},
           {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+           "frac": achieved / HBM_PEAK_GBS, "traffic": read_workload_traffic("finite_width", "bytes_per_step"),
            "kernel": "one tau-step of launches (4 stage evaluations: march, row FFT, column FFT + spectral "
                      "operators, inverse row FFT + update; plus the field pass for the per-step maximum)",
            "bytes_per_cell_update": GRID_BYTES_PER_CELL, "algorithmic_flops_per_cell": GRID_FLOPS_PER_CELL,
@@ -244,7 +263,8 @@ def bench_svea(args):
                        "n_b/n_p = 0.01, gamma_b = 1000, d_tau = 10, front impulse", "cells_per_step": cells,
            "max_ln_envelope": float(ln.max().item())},
           {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-           "traffic": None, "kernel": "svea_step (one lane per mode, all K steps in one launch)",
+           "traffic": _scaled(read_workload_traffic("svea", "bytes_per_launch"), K / 20.0),
+           "kernel": "svea_step (one lane per mode, all K steps in one launch)",
            "algorithmic_bytes_per_launch": 64.0 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
 
 

@@ -328,6 +328,29 @@ __global__ void __launch_bounds__(256) grid_cols_o3(GridArgs a, const float2 *__
 // ----------------------------------------------------------------------------- rows^-1
 __device__ __forceinline__ uint32_t fkey_pos(float x) { return __builtin_bit_cast(uint32_t, x); }
 
+// The box maximum of a field pass is folded with atomicMax over non-negative float keys
+// (they order as unsigned ints).  Hundreds of thousands of atomics on one address per pass
+// queue up in one L2 channel and stall the traffic behind them, so each workgroup first
+// reduces its own maximum and the workgroups spread over kKeySlots keys per step, kept
+// key_stride entries apart; grid_max_finish folds the slots.
+constexpr int kKeySlots = 32;
+
+__device__ __forceinline__ float nan_max(float a, float b) { return (b > a || !(b <= b)) ? b : a; }
+
+// workgroup maximum of amax (every thread of the block calls it), one atomic per block
+__device__ __forceinline__ void block_max_to_key(float amax, uint32_t *key, int key_stride) {
+    __shared__ float red[4];
+    for (int off = 32; off >= 1; off >>= 1) amax = nan_max(amax, __shfl_xor(amax, off));
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wv] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) amax = nan_max(amax, red[w]);
+        const int slot = (int)((blockIdx.x + blockIdx.y) & (kKeySlots - 1));
+        atomicMax(key + (int64_t)slot * key_stride, fkey_pos(amax));
+    }
+}
+
 // mode 0: rates and the stage update.  W_in: the stage input (its j_par for the face
 // difference); U: the step's start state; W_out = U + c A W_in, or (final) U += dtau A W_in.
 // mode 1: fields: snapshot ln|E|, ln|B| and the box maximum of |E|^2 + |B|^2.
@@ -340,7 +363,8 @@ struct RowInvArgs {
     float coef;
     int final_update;
     float *ln_e, *ln_b;        // snapshot (mode 1) or null
-    uint32_t *max_key;         // one entry (mode 1) or null
+    uint32_t *max_key;         // the step's first key slot (mode 1) or null
+    int key_stride;            // entries between two slots of one step
     uint32_t *err;             // non-finite flag (final update)
 };
 
@@ -400,14 +424,7 @@ __global__ void __launch_bounds__(256) grid_rows_inv(GridArgs a, RowInvArgs r) {
             amax = (a2 > amax || !(a2 <= a2)) ? a2 : amax;
         }
     }
-    if (r.mode == 1 && r.max_key) {
-        // wave maximum, then one atomic per wave (non-negative floats order as unsigned ints)
-        for (int off = 32; off >= 1; off >>= 1) {
-            const float other = __shfl_xor(amax, off);
-            amax = (other > amax || !(other <= other)) ? other : amax;
-        }
-        if ((threadIdx.x & 63) == 0) atomicMax(r.max_key, fkey_pos(amax));
-    }
+    if (r.mode == 1 && r.max_key) block_max_to_key(amax, r.max_key, r.key_stride);
 }
 
 // ----------------------------------------------------------------------------- 256-point passes
@@ -695,18 +712,16 @@ __global__ void __launch_bounds__(256) grid_rows_inv256(GridArgs a, RowInvArgs r
             amax = (a2 > amax || !(a2 <= a2)) ? a2 : amax;
         }
     }
-    if (NTR == 3 && r.max_key) {
-        for (int off = 32; off >= 1; off >>= 1) {
-            const float other = __shfl_xor(amax, off);
-            amax = (other > amax || !(other <= other)) ? other : amax;
-        }
-        if (lane == 0) atomicMax(r.max_key, fkey_pos(amax));
-    }
+    if (NTR == 3 && r.max_key) block_max_to_key(amax, r.max_key, r.key_stride);
 }
 
-__global__ void grid_max_finish(uint32_t *keys, float *out, int n) {
+// out[i] = ln sqrt of the largest key over the kKeySlots slots of step i
+__global__ void grid_max_finish(const uint32_t *keys, int key_stride, float *out, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = 0.5f * logf(__builtin_bit_cast(float, keys[i]));
+    if (i >= n) return;
+    uint32_t m = 0u;
+    for (int sl = 0; sl < kKeySlots; ++sl) m = max(m, keys[(int64_t)sl * key_stride + i]);
+    out[i] = 0.5f * logf(__builtin_bit_cast(float, m));
 }
 
 __global__ void __launch_bounds__(256) grid_zero_u32(uint32_t *p, int n) {
@@ -772,7 +787,7 @@ size_t grid_bytes(int64_t T, int64_t P, int n_xi, int nx, int ny, size_t *offs) 
     offs[k++] = take((size_t)nx * 8);                                    // twx
     offs[k++] = take((size_t)ny * 8);                                    // twy
     offs[k++] = take(16);                                                // err
-    offs[k++] = take(4096 * 4);                                          // keys (per-step maxima)
+    offs[k++] = take((size_t)kKeySlots * 4096 * 4);                      // keys [slot][step] (per-step maxima)
     return o;
 }
 
@@ -845,6 +860,7 @@ hipError_t fields(GridCtx *c, float *ln_e, float *ln_b, uint32_t *key, hipStream
     r.ln_e = ln_e;
     r.ln_b = ln_b;
     r.max_key = key;
+    r.key_stride = c->max_keys;
     if (r256) hipLaunchKernelGGL(grid_rows_inv256<3>, dim3(16, a.n_xi), dim3(256), 0, s, a, r);
     else hipLaunchKernelGGL(grid_rows_inv, dim3(a.ny / R, a.n_xi), dim3(256), lds_rows(a, 3), s, a, r);
     return hipGetLastError();
@@ -994,7 +1010,9 @@ qs_status grid_step(GridCtx *c, int32_t n_steps, int32_t out_every, void *ln_e, 
     }
     for (int s0 = 0; s0 < n_steps && e == hipSuccess; s0 += c->max_keys) {
         const int cnt = std::min(c->max_keys, n_steps - s0);
-        if (max_ln_a) hipLaunchKernelGGL(grid_zero_u32, dim3(nblk(cnt)), dim3(256), 0, s, c->keys, cnt);
+        if (max_ln_a)
+            hipLaunchKernelGGL(grid_zero_u32, dim3(nblk(kKeySlots * c->max_keys)), dim3(256), 0, s, c->keys,
+                               kKeySlots * c->max_keys);
         for (int i = 0; i < cnt && e == hipSuccess; ++i) {
             const int st = s0 + i;
             const bool snap = ln_e && (st % out_every == 0);
@@ -1010,7 +1028,7 @@ qs_status grid_step(GridCtx *c, int32_t n_steps, int32_t out_every, void *ln_e, 
             if (e == hipSuccess) e = apply(c, c->Wa, c->U, dt, true, s);
         }
         if (e == hipSuccess && max_ln_a) {
-            hipLaunchKernelGGL(grid_max_finish, dim3(nblk(cnt)), dim3(256), 0, s, c->keys,
+            hipLaunchKernelGGL(grid_max_finish, dim3(nblk(cnt)), dim3(256), 0, s, c->keys, c->max_keys,
                                static_cast<float *>(max_ln_a) + s0, cnt);
             e = hipGetLastError();
         }
