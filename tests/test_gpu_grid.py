@@ -106,6 +106,38 @@ def test_grid_larger_matches_oracle(qs):
     assert np.max(np.abs(st["rho"] - ost.rho)) <= TOL * sc
 
 
+def test_grid_max_ln_a_across_key_chunks(qs):
+    """4100 steps in one call: the per-step maxima run past the library's 4096-step block
+    of maximum keys (cleared and folded once per block) and must still follow the oracle."""
+    d = _inst(nx=4, ny=2, n_xi=8, length=2.0, seed_kind=3, seed_amp=1e-6, d_tau=0.05)
+    n = 4100
+    s = qs.GridSolver(d)
+    out = s.step(n, max_ln_a=True)
+    s.sync_check()
+    G = _oracle_grid(d)
+    ost = O.grid_seed(G, 3, d["seed_amp"], offset=d["centroid_offset"], sigma_r=d["sigma_r"], rng_seed=d["rng_seed"])
+    _, _, mx = O.grid_run(G, d["d_tau"], n, ost, want_fields=False)
+    err = np.abs(out["max_ln_a"].cpu().numpy() - mx)
+    assert np.max(err) <= TOL, "step %d: %.3e" % (int(np.argmax(err)), np.max(err))
+
+
+def test_grid_max_keys_cleared_between_calls(qs):
+    """A call after one on a 1e3 times larger state reports its own box maxima: every key
+    slot of the earlier call is cleared (the system is linear, so the expected values are the
+    oracle's maxima of the unscaled run, shifted by ln 1e-3)."""
+    d = _inst(seed_kind=3, seed_amp=1e-6)
+    s = qs.GridSolver(d)
+    s.step(3, max_ln_a=True)
+    st = s.get_state()
+    s.set_state({k: v * 1e-3 for k, v in st.items()})
+    out = s.step(3, max_ln_a=True)
+    s.sync_check()
+    G = _oracle_grid(d)
+    ost = O.grid_seed(G, 3, d["seed_amp"], offset=d["centroid_offset"], sigma_r=d["sigma_r"], rng_seed=d["rng_seed"])
+    _, _, mx = O.grid_run(G, d["d_tau"], 6, ost, want_fields=False)
+    assert np.max(np.abs(out["max_ln_a"].cpu().numpy() - (mx[3:] + math.log(1e-3)))) <= TOL
+
+
 def _compare_ln_large(gpu, ref, what):
     """On a 256 x 256 slice the float32 transforms leave an absolute error of a few
     eps log2(65536) ~ 1e-6 of the slice maximum at every point (the error of a float32 FFT is
