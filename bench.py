@@ -268,6 +268,67 @@ def bench_svea(args):
            "algorithmic_bytes_per_launch": 64.0 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
 
 
+def bench_regime(args):
+    """The E/B regime diagnostic on a snapshot of the 3D run: the spectral solver (FP32, the
+    3D workload) run 500 steps, its ln|E|, ln|B| snapshot (205,859 modes x 4096 cells), and the
+    map with the one-skin-depth window (40 cells either side), K calls timed."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import inputs, qs
+    K = 20 if args.steps == 2000 else args.steps
+    inst = inputs.spectral3d()
+    s = qs.Solver([inst], precision=qs.QS_FP32)
+    s.step(500)
+    f = s.step(0, snapshots=True)
+    s.sync_check()
+    te = s.snapshot_view(f["ln_e"])[0]
+    tb = s.snapshot_view(f["ln_b"])[0]
+    n_xi, n_modes = te.shape
+    w = qs.half_window_cells(1.0, inst["length"] / n_xi)
+    R = torch.empty_like(te)
+    F = torch.empty(n_modes, dtype=torch.int32, device="cuda")
+    L = qs.lib()
+    stream = torch.cuda.current_stream()
+    sp = qs._stream_ptr(stream)
+
+    def call():
+        qs._check(L.qs_regime_map(qs._vp(te), qs._vp(tb), n_modes, n_xi, w, qs.QS_FP32, qs._vp(R), qs._vp(F), sp))
+
+    for _ in range(2):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(K):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch = e0.elapsed_time(e1) * 1e-3 / K
+    cells = n_modes * n_xi
+    achieved = 12.0 * cells / launch / 1e9
+    fr = F.cpu().numpy()
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import regime as RG
+        cols = torch.as_tensor(np.linspace(0, n_modes - 1, 512).astype(np.int64), device="cuda")
+        es = te[:, cols].cpu().numpy().astype(np.float64)
+        bs = tb[:, cols].cpu().numpy().astype(np.float64)
+        t = time.perf_counter()
+        RG.first_e_cell(RG.log_ratio_map(es, bs, w))
+        dt = time.perf_counter() - t
+        cpu = {"value": 512 * n_xi / dt, "unit": "map cells/s", "cores": torch.get_num_threads(), "kind": "oracle",
+               "sample": "512 modes spread over the mode list x 4096 cells, FP64 numpy; %.1f s wall" % dt}
+    _line(METRIC, cells * K / wall, "map cells/s", K, 2, wall / K * 1e3, "f32",
+          {"workload": "E/B regime map of one ln|E|, ln|B| snapshot of the 3D run after 500 steps: 205,859 modes "
+                       "x 4096 cells, window of 2 x 40 + 1 cells (one skin depth either side)",
+           "cells": cells, "half_window_cells": w, "modes_with_electric_region": int((fr >= 0).sum())},
+          {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": None, "kernel": "regime_map<float> (one lane per mode, tiles of 16 outputs, no subtraction)",
+           "algorithmic_bytes_per_launch": 12.0 * cells, "avg_launch_ms": launch * 1e3}, cpu)
+
+
 def bench_surrogate(args):
     """Growth-map queries: the network trained on the batched uniform-seed sweep against the
     solver, with the held-out error table that routes queries."""
@@ -362,12 +423,13 @@ def main():
     ap.add_argument("--snapshot-every", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate", "svea"],
+    ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate", "svea", "regime"],
                     default="spectral3d",
                     help="spectral3d (default, the headline line); batched: 256-instance sweep in "
                          "one persistent launch; finite_width: 256^2 transverse grid x 8192 cells; "
                          "surrogate: growth-map queries, network against solver; svea: the envelope-"
-                         "approximation variant on the 3D mode set")
+                         "approximation variant on the 3D mode set; regime: the E/B regime map of a "
+                         "3D snapshot")
     ap.add_argument("--epochs", type=int, default=40, help="surrogate training epochs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (x3) and exit: "
@@ -397,7 +459,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "spectral3d":
         {"batched": bench_batched, "finite_width": bench_finite_width,
-         "surrogate": bench_surrogate, "svea": bench_svea}[args.workload](args)
+         "surrogate": bench_surrogate, "svea": bench_svea, "regime": bench_regime}[args.workload](args)
         return
     inst = inputs.spectral3d()
     prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64

@@ -1,0 +1,555 @@
+// E/B regime diagnostic over field snapshots (include/qs_regime.h; Sec. III.B and III.C):
+// per (cell, mode) the ratio of the electric to the magnetic field energy summed over a
+// window of 2w + 1 cells, and per mode the first electrically dominated cell.
+//
+// Windows are summed kTile outputs at a time.  With the span s[i] = cell j0 - w + i of
+// outputs j0 + r (r < kTile), the window of output r is s[r .. r + 2w]; when 2w + 1 >= kTile
+// it splits into a suffix of the head s[0 .. kTile-1], the middle s[kTile .. 2w] common to
+// all kTile outputs, and a prefix of the tail s[2w+1 ..], so each output costs a few adds
+// and nothing is ever subtracted (a running sum that drops the cell leaving the window loses
+// the small terms of a field spanning many decades along xi).  Each field's terms are
+// exp(2 (ln - m)) with m that field's largest value over a span around the outputs; an
+// output whose sum falls below Tiny (its window far below m) is summed again over its own
+// window, and a field with no finite value in the span gives -inf (NaN where a value is
+// NaN) without that.  Narrow windows (2w + 1 < kTile) are summed directly.  Three forms:
+// FP32 windows of 8..64 cells stream each 64-mode block down xi through an LDS ring
+// (regime_stream); other windows that fit stage 64-mode tiles in LDS (regime_tile); the
+// rest walk global memory one lane per mode (regime_map).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <string>
+
+#include "../../include/qs_regime.h"
+#include "qs_internal.h"
+
+namespace {
+
+constexpr int kTile = 16;
+
+template <typename T>
+struct Tiny;
+template <>
+struct Tiny<float> {
+    static constexpr float v = 1e-25f;   // FP32 terms below ~1e-38 vanish: < 1e-11 of such a sum
+};
+template <>
+struct Tiny<double> {
+    static constexpr double v = 1e-250;
+};
+
+// FP32 uses the hardware base-2 exponential and logarithm (about 1 ulp each; an argument
+// 2 (ln - m) of magnitude up to ~60 carries a relative rounding of ~1e-6 into a term, far
+// inside the FP32 bar of R); FP64 the library's correctly rounded-to-1-ulp exp and log
+__device__ __forceinline__ float ex(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ double ex(double x) { return exp(x); }
+__device__ __forceinline__ float lg(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ __forceinline__ double lg(double x) { return log(x); }
+
+// 1/2 ln sum_{i=lo..hi} e^{2 v_i} over one window, relative to the window's own largest value:
+// NaN if the window holds a NaN, -inf if every value is -inf
+template <typename T>
+__device__ __attribute__((noinline)) T window_log_energy(const T *__restrict__ v, int64_t stride, int lo, int hi) {
+    T top = -INFINITY;
+    bool nan = false;
+    for (int i = lo; i <= hi; ++i) {
+        const T x = v[(int64_t)i * stride];
+        nan |= x != x;
+        top = fmax(top, x);
+    }
+    if (nan) return (T)NAN;
+    if (top == -INFINITY) return -INFINITY;
+    T s = 0;
+    for (int i = lo; i <= hi; ++i) s += ex(T(2) * (v[(int64_t)i * stride] - top));
+    return top + T(0.5) * lg(s);
+}
+
+// Outputs j = ja .. jb-1 (all valid: w <= j < n - w) of one mode.  E, B address that mode's
+// column with E[(c - cell0) * st] = cell c (global memory, or a staged tile in LDS); R (may be
+// null) is the column of the global output, rst apart; first = the first j with R_j > 0 here
+// (-1 if none).
+// Terms exp(2 (ln - m)) are taken against r = ref(m): m itself, or 0 when m = -inf (no
+// finite value in the span: the terms are then 0, or NaN for a NaN).  A window's 1/2 ln of its
+// energy from its term sum: -inf (or NaN) when m = -inf; m + 1/2 ln(sum) while the sum stays
+// above Tiny; else, or when m = +inf, summed again over the window's own values in G.
+template <typename T>
+__device__ __forceinline__ T ref(T m) { return m == -INFINITY ? T(0) : m; }
+
+template <typename T>
+__device__ __forceinline__ T window_L(T m, T sum, const T *G, int64_t gst, int lo, int hi) {
+    if (m == -INFINITY) return sum != sum ? (T)NAN : -INFINITY;
+    if (m < INFINITY && !(sum < Tiny<T>::v)) return m + T(0.5) * lg(sum);
+    return window_log_energy(G, gst, lo, hi);
+}
+
+template <typename T>
+__device__ __forceinline__ void run_outputs(const T *E, const T *B, int64_t st, int cell0, int ja, int jb, int w,
+                                            T *__restrict__ R, int64_t rst, int &first) {
+    first = -1;
+    auto emit = [&](int j, T le, T lb) {
+        const T r = le - lb;
+        if (R) R[(int64_t)j * rst] = r;
+        if (first < 0 && r > T(0)) first = j;
+    };
+    if (2 * w + 1 < kTile) {
+        for (int j = ja; j < jb; ++j)
+            emit(j, window_log_energy(E, st, j - w - cell0, j + w - cell0),
+                 window_log_energy(B, st, j - w - cell0, j + w - cell0));
+        return;
+    }
+    for (int j0 = ja; j0 < jb; j0 += kTile) {
+        const int c = min(kTile, jb - j0);
+        const T *Es = E + (int64_t)(j0 - w - cell0) * st, *Bs = B + (int64_t)(j0 - w - cell0) * st;   // s[0]
+        const int len = 2 * w + c;                                                                     // span cells
+        T mE = -INFINITY, mB = -INFINITY;
+#pragma unroll 8
+        for (int i = 0; i < len; ++i) {
+            mE = fmax(mE, Es[(int64_t)i * st]);
+            mB = fmax(mB, Bs[(int64_t)i * st]);
+        }
+        const T rE = ref(mE), rB = ref(mB);
+        // head suffix sums, middle sum, then the outputs with the tail prefix
+        T hE[kTile], hB[kTile];
+#pragma unroll
+        for (int r = 0; r < kTile; ++r) {
+            hE[r] = ex(T(2) * (Es[(int64_t)r * st] - rE));
+            hB[r] = ex(T(2) * (Bs[(int64_t)r * st] - rB));
+        }
+#pragma unroll
+        for (int r = kTile - 2; r >= 0; --r) {
+            hE[r] += hE[r + 1];
+            hB[r] += hB[r + 1];
+        }
+        T sE = 0, sB = 0;
+#pragma unroll 8
+        for (int i = kTile; i <= 2 * w; ++i) {
+            sE += ex(T(2) * (Es[(int64_t)i * st] - rE));
+            sB += ex(T(2) * (Bs[(int64_t)i * st] - rB));
+        }
+        T pE = 0, pB = 0;
+#pragma unroll
+        for (int r = 0; r < kTile; ++r) {
+            if (r < c) {
+                const int j = j0 + r;
+                const T se = hE[r] + sE + pE, sb = hB[r] + sB + pB;
+                emit(j, window_L(mE, se, E, st, j - w - cell0, j + w - cell0),
+                     window_L(mB, sb, B, st, j - w - cell0, j + w - cell0));
+                if (r + 1 < c) {
+                    pE += ex(T(2) * (Es[(int64_t)(2 * w + 1 + r) * st] - rE));
+                    pB += ex(T(2) * (Bs[(int64_t)(2 * w + 1 + r) * st] - rB));
+                }
+            }
+        }
+    }
+}
+
+// General form: one lane per mode walks its whole column in global memory (any window).
+template <typename T>
+__global__ void __launch_bounds__(256) regime_map(const T *__restrict__ ln_e, const T *__restrict__ ln_b, int64_t n_modes,
+                                                  int n, int w, T *__restrict__ out, int32_t *__restrict__ first_out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_modes) return;
+    const int64_t st = n_modes;
+    T *R = out ? out + k : nullptr;
+    // cells whose window would leave [0, n)
+    const int jbeg = w < n ? w : n, jend = n - w > jbeg ? n - w : jbeg;   // valid outputs: [jbeg, jend)
+    if (R) {
+        for (int j = 0; j < jbeg; ++j) R[(int64_t)j * st] = (T)NAN;
+        for (int j = jend; j < n; ++j) R[(int64_t)j * st] = (T)NAN;
+    }
+    int first;
+    run_outputs(ln_e + k, ln_b + k, st, 0, jbeg, jend, w, R, st, first);
+    if (first_out) first_out[k] = first;
+}
+
+// Window sums for outputs ja .. jb-1 from terms already in LDS: X[(c - cell0) * 64] holds
+// exp(2 (ln_c - m)) for one field of one mode (m its largest value over the staged span), so
+// each output costs a few adds: the head suffix, the middle common to kTile outputs and the
+// tail prefix (nothing subtracted).  Windows whose sum falls below Tiny (far below m), and
+// every window when m is not finite, are summed again from the raw column G (global memory,
+// G[c * gst] = ln of cell c).  L[r] = 1/2 ln sum |F|^2 of output ja + r (r < kTile).
+template <typename T>
+__device__ __forceinline__ void window_energies(const T *X, int cell0, int ja, int c, int w, T m, const T *G,
+                                                int64_t gst, T (&L)[kTile]) {
+    const T *Xs = X + (ja - w - cell0) * 64;   // s[0]
+    if (2 * w + 1 < kTile) {
+#pragma unroll
+        for (int r = 0; r < kTile; ++r) {
+            if (r < c) {
+                T sum = 0;
+                for (int i = 0; i <= 2 * w; ++i) sum += Xs[(r + i) * 64];
+                L[r] = window_L(m, sum, G, gst, ja + r - w, ja + r + w);
+            }
+        }
+        return;
+    }
+    T h[kTile];
+#pragma unroll
+    for (int r = 0; r < kTile; ++r) h[r] = Xs[r * 64];
+#pragma unroll
+    for (int r = kTile - 2; r >= 0; --r) h[r] += h[r + 1];
+    T mid = 0;
+#pragma unroll 8
+    for (int i = kTile; i <= 2 * w; ++i) mid += Xs[i * 64];
+    T pre = 0;
+#pragma unroll
+    for (int r = 0; r < kTile; ++r) {
+        if (r < c) {
+            const T sum = h[r] + mid + pre;
+            L[r] = window_L(m, sum, G, gst, ja + r - w, ja + r + w);
+            if (r + 1 < c) pre += Xs[(2 * w + 1 + r) * 64];
+        }
+    }
+}
+
+// Staged form: a workgroup takes 64 modes and `to` consecutive outputs.  Its 256 threads copy
+// the span of those outputs (to + 2w cells of both fields, one 64-mode row per wave and
+// load) into LDS once, find each mode's largest value of each field over the span, and turn
+// every staged value into its term exp(2 (ln - m)) in place; wave v then sums the windows of
+// quarter v of the tile from LDS (lane = mode, rows read without bank conflicts).  Each cell
+// is read from memory (to + 2w) / to times and exponentiated as often, instead of once per
+// window.  The first electrically dominated cell combines over the tile's waves, then over
+// tiles with atomicMin (first_out starts at INT32_MAX; regime_first_finish maps what is left
+// to -1).
+template <typename T>
+__global__ void __launch_bounds__(256) regime_tile(const T *__restrict__ ln_e, const T *__restrict__ ln_b, int64_t n_modes,
+                                                   int n, int w, int to, T *__restrict__ out, int32_t *__restrict__ first_out) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ int fw[4][64];
+    __shared__ T pm[2][4][64];
+    T *sE = reinterpret_cast<T *>(smem);
+    T *sB = sE + (size_t)(to + 2 * w) * 64;
+    const int jbeg = w, jend = n - w;   // the host launches this form only when jend > jbeg
+    const int o0 = jbeg + (int)blockIdx.y * to, o1 = min(o0 + to, jend);
+    const int rows = (o1 - o0) + 2 * w, c0 = o0 - w;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = k < n_modes;
+    const int64_t kk = live ? k : 0;
+    constexpr int U = 40;  // rows in flight per wave before their LDS stores
+    T mE = -INFINITY, mB = -INFINITY;
+    for (int r0 = wv; r0 < rows; r0 += 4 * U) {
+        T ve[U], vb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = min(r0 + 4 * u, rows - 1);
+            const int64_t g = (int64_t)(c0 + r) * n_modes + kk;
+            ve[u] = ln_e[g];
+            vb[u] = ln_b[g];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = r0 + 4 * u;
+            if (r < rows) {
+                sE[r * 64 + lane] = ve[u];
+                sB[r * 64 + lane] = vb[u];
+                mE = fmax(mE, ve[u]);
+                mB = fmax(mB, vb[u]);
+            }
+        }
+    }
+    pm[0][wv][lane] = mE;
+    pm[1][wv][lane] = mB;
+    __syncthreads();
+    mE = fmax(fmax(pm[0][0][lane], pm[0][1][lane]), fmax(pm[0][2][lane], pm[0][3][lane]));
+    mB = fmax(fmax(pm[1][0][lane], pm[1][1][lane]), fmax(pm[1][2][lane], pm[1][3][lane]));
+    // each wave turns the rows it staged into terms (its own writes: no barrier needed before)
+    const T rE = ref(mE), rB = ref(mB);
+    for (int r = wv; r < rows; r += 4) {
+        sE[r * 64 + lane] = ex(T(2) * (sE[r * 64 + lane] - rE));
+        sB[r * 64 + lane] = ex(T(2) * (sB[r * 64 + lane] - rB));
+    }
+    __syncthreads();
+    const int q = (o1 - o0 + 3) / 4;
+    const int ja = o0 + wv * q, jb = min(ja + q, o1);
+    T *R = out && live ? out + k : nullptr;
+    int first = -1;
+    if (live) {
+        for (int j0 = ja; j0 < jb; j0 += kTile) {
+            const int c = min(kTile, jb - j0);
+            T le[kTile], lb[kTile];
+            window_energies(sE + lane, c0, j0, c, w, mE, ln_e + k, n_modes, le);
+            window_energies(sB + lane, c0, j0, c, w, mB, ln_b + k, n_modes, lb);
+#pragma unroll
+            for (int r = 0; r < kTile; ++r) {
+                if (r < c) {
+                    const T v = le[r] - lb[r];
+                    if (R) R[(int64_t)(j0 + r) * n_modes] = v;
+                    if (first < 0 && v > T(0)) first = j0 + r;
+                }
+            }
+        }
+    }
+    if (R) {
+        if (blockIdx.y == 0)
+            for (int j = wv; j < jbeg; j += 4) R[(int64_t)j * n_modes] = (T)NAN;
+        if (blockIdx.y == gridDim.y - 1)
+            for (int j = jend + wv; j < n; j += 4) R[(int64_t)j * n_modes] = (T)NAN;
+    }
+    fw[wv][lane] = first < 0 ? INT32_MAX : first;
+    __syncthreads();
+    if (wv == 0 && live && first_out) {
+        const int f = min(min(fw[0][lane], fw[1][lane]), min(fw[2][lane], fw[3][lane]));
+        if (f != INT32_MAX) atomicMin(first_out + k, f);
+    }
+}
+
+// Streaming form (FP32, kTile <= 2w + 1, 2w + kChunk <= kRing): a workgroup of eight waves
+// takes 64 modes and walks its share of the outputs in chunks of kChunk = 128 (16 per wave),
+// with the raw ln values of both fields in an LDS ring of kRing = 256 rows (cell c in row
+// (c - first staged cell) mod 256).  Per chunk the waves find each mode's largest value of
+// each field over the chunk's span, then sum their windows from the ring (terms, head /
+// middle / tail sums); meanwhile the rows of the next chunk are in flight into registers,
+// and they replace the rows the next chunk no longer needs once the chunk is done.  Every
+// cell is read from memory once (plus a 2w halo where a mode block's outputs are split
+// between workgroups).
+constexpr int kChunk = 128;
+constexpr int kRing = 256;
+
+template <typename T>
+__device__ __forceinline__ void ring_outputs(const T *E, const T *B, int base, int ja, int jb, int w, T mE, T mB,
+                                             const T *GE, const T *GB, int64_t gst, T *__restrict__ R, int &first) {
+    constexpr int mask = kRing - 1;
+    auto at = [&](const T *X, int c) { return X[((c - base) & mask) * 64]; };
+    const T rE = ref(mE), rB = ref(mB);
+    for (int j0 = ja; j0 < jb; j0 += kTile) {
+        const int c = min(kTile, jb - j0);
+        const int s0 = j0 - w;   // cell of s[0]
+        T hE[kTile], hB[kTile];
+#pragma unroll
+        for (int r = 0; r < kTile; ++r) {
+            hE[r] = ex(T(2) * (at(E, s0 + r) - rE));
+            hB[r] = ex(T(2) * (at(B, s0 + r) - rB));
+        }
+#pragma unroll
+        for (int r = kTile - 2; r >= 0; --r) {
+            hE[r] += hE[r + 1];
+            hB[r] += hB[r + 1];
+        }
+        T sE = 0, sB = 0;
+#pragma unroll 8
+        for (int i = kTile; i <= 2 * w; ++i) {
+            sE += ex(T(2) * (at(E, s0 + i) - rE));
+            sB += ex(T(2) * (at(B, s0 + i) - rB));
+        }
+        T pE = 0, pB = 0;
+#pragma unroll
+        for (int r = 0; r < kTile; ++r) {
+            if (r < c) {
+                const int j = j0 + r;
+                const T se = hE[r] + sE + pE, sb = hB[r] + sB + pB;
+                const T v = window_L(mE, se, GE, gst, j - w, j + w) - window_L(mB, sb, GB, gst, j - w, j + w);
+                if (R) R[(int64_t)j * gst] = v;
+                if (first < 0 && v > T(0)) first = j;
+                if (r + 1 < c) {
+                    pE += ex(T(2) * (at(E, s0 + 2 * w + 1 + r) - rE));
+                    pB += ex(T(2) * (at(B, s0 + 2 * w + 1 + r) - rB));
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) regime_stream(const T *__restrict__ ln_e, const T *__restrict__ ln_b,
+                                                     int64_t n_modes, int n, int w, int chunks_per_group,
+                                                     T *__restrict__ out, int32_t *__restrict__ first_out) {
+    __shared__ T ring[2][kRing * 64];
+    __shared__ int fw[8][64];
+    __shared__ T pm[2][8][64];
+    const int jbeg = w, jend = n - w;   // the host launches this form only when jend > jbeg and 2w + kChunk <= kRing
+    const int n_chunks = (jend - jbeg + kChunk - 1) / kChunk;
+    const int ca = (int)blockIdx.y * chunks_per_group, cb = min(ca + chunks_per_group, n_chunks);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = k < n_modes;
+    const int64_t kk = live ? k : 0;
+    const T *GE = ln_e + kk, *GB = ln_b + kk;
+    T *R = out && live ? out + k : nullptr;
+    if (R) {
+        if (blockIdx.y == 0)
+            for (int j = wv; j < jbeg; j += 8) R[(int64_t)j * n_modes] = (T)NAN;
+        if (blockIdx.y == gridDim.y - 1)
+            for (int j = jend + wv; j < n; j += 8) R[(int64_t)j * n_modes] = (T)NAN;
+    }
+    int first = -1;
+    if (ca < cb) {   // uniform over the workgroup
+        const int base = jbeg + ca * kChunk - w;   // cell staged in ring row 0
+        // the first chunk's span: cells [base, min(first outputs end, jend) + w)
+        {
+            const int rows = min(kChunk, jend - (jbeg + ca * kChunk)) + 2 * w;
+            constexpr int U = 16;
+            for (int r0 = wv; r0 < rows; r0 += 8 * U) {
+                T ve[U], vb[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int r = min(r0 + 8 * u, rows - 1);
+                    ve[u] = GE[(int64_t)(base + r) * n_modes];
+                    vb[u] = GB[(int64_t)(base + r) * n_modes];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int r = r0 + 8 * u;
+                    if (r < rows) {
+                        ring[0][r * 64 + lane] = ve[u];
+                        ring[1][r * 64 + lane] = vb[u];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int ch = ca; ch < cb; ++ch) {
+            const int o0 = jbeg + ch * kChunk, o1 = min(o0 + kChunk, jend);
+            // rows of the next chunk: cells [o1 + w, o1 + w + nn), loaded now, stored after this chunk
+            const int nn = ch + 1 < cb ? min(o1 + kChunk, jend) - o1 : 0;
+            constexpr int P = kChunk / 8;
+            T pe[P], pb[P];
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int r = min(wv + 8 * u, max(nn - 1, 0));
+                const int64_t g = (int64_t)(nn > 0 ? o1 + w + r : base) * n_modes;
+                pe[u] = GE[g];
+                pb[u] = GB[g];
+            }
+            // the chunk span's largest value of each field, per mode (rows split over the waves)
+            {
+                T a = -INFINITY, b = -INFINITY;
+                for (int c = o0 - w + wv; c < o1 + w; c += 8) {
+                    const int row = (c - base) & (kRing - 1);
+                    a = fmax(a, ring[0][row * 64 + lane]);
+                    b = fmax(b, ring[1][row * 64 + lane]);
+                }
+                pm[0][wv][lane] = a;
+                pm[1][wv][lane] = b;
+            }
+            __syncthreads();
+            T mE = pm[0][0][lane], mB = pm[1][0][lane];
+#pragma unroll
+            for (int v = 1; v < 8; ++v) {
+                mE = fmax(mE, pm[0][v][lane]);
+                mB = fmax(mB, pm[1][v][lane]);
+            }
+            const int ja = o0 + kTile * wv, jb = min(ja + kTile, o1);
+            if (live && ja < jb) {
+                int f = -1;
+                ring_outputs(ring[0] + lane, ring[1] + lane, base, ja, jb, w, mE, mB, GE, GB, n_modes, R, f);
+                if (first < 0) first = f;
+            }
+            __syncthreads();   // the chunk's windows are summed: its first rows may be replaced
+#pragma unroll
+            for (int u = 0; u < P; ++u) {
+                const int r = wv + 8 * u;
+                if (r < nn) {
+                    const int slot = (o1 + w + r - base) & (kRing - 1);
+                    ring[0][slot * 64 + lane] = pe[u];
+                    ring[1][slot * 64 + lane] = pb[u];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    fw[wv][lane] = first < 0 ? INT32_MAX : first;
+    __syncthreads();
+    if (wv == 0 && live && first_out) {
+        int f = fw[0][lane];
+#pragma unroll
+        for (int v = 1; v < 8; ++v) f = min(f, fw[v][lane]);
+        if (f != INT32_MAX) atomicMin(first_out + k, f);
+    }
+}
+
+__global__ void __launch_bounds__(256) regime_first_fill(int32_t *__restrict__ f, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = INT32_MAX;
+}
+
+__global__ void __launch_bounds__(256) regime_first_finish(int32_t *__restrict__ f, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && f[i] == INT32_MAX) f[i] = -1;
+}
+
+// Tile length of the staged form for a window of w cells, and its LDS bytes: the longest
+// tile (at least 64 outputs) whose span fits 74 KiB (two workgroups per compute unit), else
+// 152 KiB (one); 0 if neither fits (the general form runs instead).
+template <typename T>
+int tile_outputs(int w, int n_valid, size_t *lds) {
+    const size_t row = 64 * 2 * sizeof(T);
+    for (const size_t lim : {(size_t)74 * 1024, (size_t)152 * 1024}) {
+        const int64_t rmax = (int64_t)(lim / row);
+        if (rmax >= 2 * (int64_t)w + 64) {
+            // whole sub-tiles of kTile outputs for each of the four waves
+            const int to = (int)std::min<int64_t>((rmax - 2 * (int64_t)w) / (4 * kTile) * (4 * kTile), n_valid);
+            *lds = (size_t)(to + 2 * w) * row;
+            return to;
+        }
+    }
+    return 0;
+}
+
+template <typename T>
+hipError_t launch(const T *e, const T *b, int64_t n_modes, int n, int w, T *R, int32_t *F, hipStream_t s) {
+    const int n_valid = n - 2 * w;
+    const int64_t mblocks = (n_modes + 63) / 64;
+    // (windows narrower than a sub-tile, 2w + 1 < kTile, take the tile form's direct sums)
+    if constexpr (sizeof(T) == 4) if (n_valid > 0 && 2 * w + 1 >= kTile && 2 * w + kChunk <= kRing && mblocks <= 0x7fffffff) {
+        // split the chunks of a mode block over workgroups until there are ~2048 of them
+        const int n_chunks = (n_valid + kChunk - 1) / kChunk;
+        const int64_t want = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (2048 + mblocks - 1) / mblocks));
+        const int cpg = (int)((n_chunks + want - 1) / want);
+        const int groups = (n_chunks + cpg - 1) / cpg;
+        const dim3 g1((unsigned)((n_modes + 255) / 256));
+        if (F) hipLaunchKernelGGL(regime_first_fill, g1, dim3(256), 0, s, F, n_modes);
+        hipLaunchKernelGGL(regime_stream<T>, dim3((unsigned)mblocks, (unsigned)groups), dim3(512), 0, s, e, b, n_modes, n,
+                           w, cpg, R, F);
+        if (F) hipLaunchKernelGGL(regime_first_finish, g1, dim3(256), 0, s, F, n_modes);
+        return hipGetLastError();
+    }
+    size_t lds = 0;
+    const int to = n_valid > 0 ? tile_outputs<T>(w, n_valid, &lds) : 0;
+    const int64_t tiles = to > 0 ? (n_valid + to - 1) / to : 0;
+    if (to == 0 || tiles > 65535 || mblocks > 0x7fffffff) {
+        hipLaunchKernelGGL(regime_map<T>, dim3((unsigned)((n_modes + 255) / 256)), dim3(256), 0, s, e, b, n_modes, n, w,
+                           R, F);
+        return hipGetLastError();
+    }
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(&regime_tile<T>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    const dim3 g1((unsigned)((n_modes + 255) / 256));
+    if (F) hipLaunchKernelGGL(regime_first_fill, g1, dim3(256), 0, s, F, n_modes);
+    hipLaunchKernelGGL(regime_tile<T>, dim3((unsigned)mblocks, (unsigned)tiles), dim3(256), lds, s, e, b, n_modes, n, w, to,
+                       R, F);
+    if (F) hipLaunchKernelGGL(regime_first_finish, g1, dim3(256), 0, s, F, n_modes);
+    return hipGetLastError();
+}
+
+qs_status rfail(qs_status s, const std::string &m) {
+    qs::set_last_error(m);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_regime_map(const void *ln_e, const void *ln_b, int64_t n_modes, int32_t n_xi, int32_t half_window,
+                        int32_t precision, void *log_ratio, int32_t *first_e_cell, void *hip_stream) {
+    if (n_modes < 1 || n_xi < 1 || half_window < 0) return rfail(QS_ERR_ARG, "n_modes >= 1, n_xi >= 1, half_window >= 0");
+    if (precision != QS_FP32 && precision != QS_FP64) return rfail(QS_ERR_ARG, "precision must be QS_FP32 or QS_FP64");
+    if (!ln_e || !ln_b) return rfail(QS_ERR_ARG, "ln_e and ln_b are required");
+    if (!log_ratio && !first_e_cell) return rfail(QS_ERR_ARG, "at least one of log_ratio and first_e_cell is required");
+    if ((n_modes + 255) / 256 > 0x7fffffff) return rfail(QS_ERR_ARG, "too many modes");
+    const int w = (int)std::min<int64_t>(half_window, n_xi);   // a longer window leaves no valid cell either way
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const hipError_t e =
+        precision == QS_FP32
+            ? launch(static_cast<const float *>(ln_e), static_cast<const float *>(ln_b), n_modes, (int)n_xi, w,
+                     static_cast<float *>(log_ratio), first_e_cell, s)
+            : launch(static_cast<const double *>(ln_e), static_cast<const double *>(ln_b), n_modes, (int)n_xi, w,
+                     static_cast<double *>(log_ratio), first_e_cell, s);
+    return e == hipSuccess ? QS_OK : rfail(QS_ERR_HIP, std::string("regime map: ") + hipGetErrorString(e));
+}
+
+}  // extern "C"

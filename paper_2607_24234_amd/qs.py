@@ -7,6 +7,7 @@ loaded, importing this module's ``lib()`` raises -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -91,7 +92,8 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_growth_features", "qs_growth_calibrate", "qs_growth_map",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
-           "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope"]
+           "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope",
+           "qs_regime_map"]
 
 
 def lib():
@@ -187,6 +189,8 @@ def lib():
                                vp, vp, vp, vp]
     L.qs_svea_ln_envelope.restype = ctypes.c_int
     L.qs_svea_ln_envelope.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
+    L.qs_regime_map.restype = ctypes.c_int
+    L.qs_regime_map.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     _lib = L
     return L
 
@@ -651,6 +655,35 @@ def svea_coefficients(species, gamma, k):
     a = np.empty(2 * len(k), np.float64)
     _check(lib().qs_svea_coefficients(len(q), _dp(q), _dp(m), _dp(nb), float(gamma), len(k), _dp(k), _dp(a)))
     return a[0::2] + 1j * a[1::2]
+
+
+def half_window_cells(half_width, h):
+    """Cells within half_width of a cell centre on either side: floor(half_width / h), with a
+    relative allowance of 1e-9 for a ratio that is an integer up to rounding."""
+    return int(math.floor(half_width / h * (1.0 + 1e-9)))
+
+
+def regime_map(ln_e, ln_b, half_window, log_ratio=True, first_e_cell=True, stream=None):
+    """E/B regime diagnostic (include/qs_regime.h) of one snapshot pair: ln_e, ln_b are torch
+    device tensors [n_xi][n_modes] (float32 or float64, contiguous), half_window the window's
+    half width in cells.  Returns (R [n_xi][n_modes] of the same type or None, first
+    electrically dominated cell int32 [n_modes] or None)."""
+    import torch
+    if ln_e.shape != ln_b.shape or ln_e.dtype != ln_b.dtype or ln_e.dim() != 2:
+        raise ValueError("ln_e and ln_b must be [n_xi][n_modes] tensors of one type")
+    if not (ln_e.is_contiguous() and ln_b.is_contiguous()):
+        raise ValueError("ln_e and ln_b must be contiguous")
+    prec = {torch.float32: QS_FP32, torch.float64: QS_FP64}.get(ln_e.dtype)
+    if prec is None:
+        raise ValueError("ln_e and ln_b must be float32 or float64")
+    n_xi, n_modes = ln_e.shape
+    R = torch.empty_like(ln_e) if log_ratio else None
+    F = torch.empty(n_modes, dtype=torch.int32, device=ln_e.device) if first_e_cell else None
+    s = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().qs_regime_map(_vp(ln_e), _vp(ln_b), n_modes, n_xi, int(half_window), prec,
+                               _vp(R) if R is not None else None, _vp(F) if F is not None else None,
+                               _stream_ptr(s)))
+    return R, F
 
 
 class SVEASolver:

@@ -139,6 +139,22 @@ def test_null_arguments():
     assert L.qs_init(None, 1, None, None, 0, None) == qs.QS_ERR_ARG
 
 
+def test_regime_map_arguments_rejected_on_host():
+    """qs_regime_map checks its arguments before any device work (host pointers stand in for
+    device ones: nothing is launched on these paths)."""
+    import ctypes
+    qs, L = _lib()
+    buf = (ctypes.c_double * 16)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.qs_regime_map(p, p, 0, 4, 1, qs.QS_FP64, p, None, None) == qs.QS_ERR_ARG       # no modes
+    assert L.qs_regime_map(p, p, 4, 0, 1, qs.QS_FP64, p, None, None) == qs.QS_ERR_ARG       # no cells
+    assert L.qs_regime_map(p, p, 4, 4, -1, qs.QS_FP64, p, None, None) == qs.QS_ERR_ARG      # negative window
+    assert L.qs_regime_map(p, p, 4, 4, 1, 9, p, None, None) == qs.QS_ERR_ARG                # precision
+    assert L.qs_regime_map(None, p, 4, 4, 1, qs.QS_FP32, p, None, None) == qs.QS_ERR_ARG    # input
+    assert L.qs_regime_map(p, p, 4, 4, 1, qs.QS_FP32, None, None, None) == qs.QS_ERR_ARG    # no output
+    assert b"log_ratio" in L.qs_last_error()
+
+
 def test_device_generator_equals_oracle_generator(oracle):
     qs, L = _lib()
     for seed in (0, 1, 0xDEADBEEF, 2**64 - 1):
