@@ -296,70 +296,118 @@ __global__ void __launch_bounds__(256) regime_tile(const T *__restrict__ ln_e, c
     }
 }
 
-// Streaming form (FP32, kTile <= 2w + 1, 2w + kChunk <= kRing): a workgroup of eight waves
-// takes 64 modes and walks its share of the outputs in chunks of kChunk = 128 (16 per wave),
-// with the raw ln values of both fields in an LDS ring of kRing = 256 rows (cell c in row
-// (c - first staged cell) mod 256).  Per chunk the waves find each mode's largest value of
-// each field over the chunk's span, then sum their windows from the ring (terms, head /
-// middle / tail sums); meanwhile the rows of the next chunk are in flight into registers,
-// and they replace the rows the next chunk no longer needs once the chunk is done.  Every
+// Streaming form (FP32, kTile <= 2w + 1, 2w + kChunk <= kSpan): a workgroup of 16 waves takes
+// 64 modes and walks its share of the outputs in chunks of kChunk = 128 (8 per wave).  LDS
+// holds the raw ln values of both fields over the current chunk's span, row i = cell
+// o0 - w + i (o0 the chunk's first output), so every access is a fixed offset from the
+// wave's first row.  Per chunk: each mode's largest value of each field over the span
+// (from the values the threads staged, exchanged through LDS), the terms of each 8-row
+// block summed once, then each wave's windows (head and tail term by term, the middle from
+// block sums).  Meanwhile the rows of the next chunk are in flight into registers; once the
+// chunk is done the last 2w rows move to the front and the new rows follow them.  Every
 // cell is read from memory once (plus a 2w halo where a mode block's outputs are split
 // between workgroups).
 constexpr int kChunk = 128;
-constexpr int kRing = 256;
+constexpr int kSpan = 256;
+constexpr int kWaves = 16;               // waves per streaming workgroup
+constexpr int kSub = kChunk / kWaves;    // outputs (and block rows) per wave and chunk
 
-template <typename T>
-__device__ __forceinline__ void ring_outputs(const T *E, const T *B, int base, int ja, int jb, int w, T mE, T mB,
-                                             const T *GE, const T *GB, int64_t gst, T *__restrict__ R, int &first) {
-    constexpr int mask = kRing - 1;
-    auto at = [&](const T *X, int c) { return X[((c - base) & mask) * 64]; };
+// Outputs ja .. ja+c-1 (c <= TS) of one wave against the chunk's references mE, mB.  E, B
+// point at the wave's first span row (s[0] = cell ja - w), rows 64 apart; bE, bB at the
+// block sums of that row's block (block TS rows, 64 apart), so the middle s[TS .. 2w] is
+// q = (2w + 1 - TS) / TS whole blocks plus a remainder; head and tail terms one by one.
+template <int TS, typename T>
+__device__ __forceinline__ void span_outputs(const T *E, const T *B, const T *bE, const T *bB, int ja, int c, int w,
+                                             T mE, T mB, const T *GE, const T *GB, int64_t gst, T *__restrict__ R,
+                                             int &first) {
     const T rE = ref(mE), rB = ref(mB);
-    for (int j0 = ja; j0 < jb; j0 += kTile) {
-        const int c = min(kTile, jb - j0);
-        const int s0 = j0 - w;   // cell of s[0]
-        T hE[kTile], hB[kTile];
+    T hE[TS], hB[TS];
 #pragma unroll
-        for (int r = 0; r < kTile; ++r) {
-            hE[r] = ex(T(2) * (at(E, s0 + r) - rE));
-            hB[r] = ex(T(2) * (at(B, s0 + r) - rB));
-        }
+    for (int r = 0; r < TS; ++r) {
+        hE[r] = ex(T(2) * (E[r * 64] - rE));
+        hB[r] = ex(T(2) * (B[r * 64] - rB));
+    }
 #pragma unroll
-        for (int r = kTile - 2; r >= 0; --r) {
-            hE[r] += hE[r + 1];
-            hB[r] += hB[r + 1];
-        }
-        T sE = 0, sB = 0;
-#pragma unroll 8
-        for (int i = kTile; i <= 2 * w; ++i) {
-            sE += ex(T(2) * (at(E, s0 + i) - rE));
-            sB += ex(T(2) * (at(B, s0 + i) - rB));
-        }
-        T pE = 0, pB = 0;
+    for (int r = TS - 2; r >= 0; --r) {
+        hE[r] += hE[r + 1];
+        hB[r] += hB[r + 1];
+    }
+    const int q = (2 * w + 1 - TS) / TS;
+    T sE = 0, sB = 0;
+    for (int b = 1; b <= q; ++b) {
+        sE += bE[b * 64];
+        sB += bB[b * 64];
+    }
+    for (int i = TS * (q + 1); i <= 2 * w; ++i) {
+        sE += ex(T(2) * (E[i * 64] - rE));
+        sB += ex(T(2) * (B[i * 64] - rB));
+    }
+    const T *Et = E + (2 * w + 1) * 64, *Bt = B + (2 * w + 1) * 64;   // the tail
+    // the quick form of window_L; outputs that need their own window's sum are marked and
+    // done after the loop (written out there: the kernel makes no calls)
+    auto quick = [&](T m, T sum, bool &again) -> T {
+        if (m == -INFINITY) return sum != sum ? (T)NAN : -INFINITY;
+        if (m < INFINITY && !(sum < Tiny<T>::v)) return m + T(0.5) * lg(sum);
+        again = true;
+        return T(0);
+    };
+    unsigned again = 0, pos = 0;   // bit r: output r redone below / R > 0
+    T pE = 0, pB = 0;
 #pragma unroll
-        for (int r = 0; r < kTile; ++r) {
-            if (r < c) {
-                const int j = j0 + r;
-                const T se = hE[r] + sE + pE, sb = hB[r] + sB + pB;
-                const T v = window_L(mE, se, GE, gst, j - w, j + w) - window_L(mB, sb, GB, gst, j - w, j + w);
-                if (R) R[(int64_t)j * gst] = v;
-                if (first < 0 && v > T(0)) first = j;
-                if (r + 1 < c) {
-                    pE += ex(T(2) * (at(E, s0 + 2 * w + 1 + r) - rE));
-                    pB += ex(T(2) * (at(B, s0 + 2 * w + 1 + r) - rB));
-                }
+    for (int r = 0; r < TS; ++r) {
+        if (r < c) {
+            bool a = false;
+            const T v = quick(mE, hE[r] + sE + pE, a) - quick(mB, hB[r] + sB + pB, a);
+            if (!a) {
+                if (R) R[(int64_t)(ja + r) * gst] = v;
+                pos |= (unsigned)(v > T(0)) << r;
+            } else {
+                again |= 1u << r;
+            }
+            if (r + 1 < c) {
+                pE += ex(T(2) * (Et[r * 64] - rE));
+                pB += ex(T(2) * (Bt[r * 64] - rB));
             }
         }
     }
+    if (again) {
+        // rare: 1/2 ln sum over the output's own window from global memory, against that
+        // window's own largest value (as window_log_energy)
+        auto own = [&](const T *G, int lo, int hi) -> T {
+            T top = -INFINITY;
+            bool nan = false;
+            for (int i = lo; i <= hi; ++i) {
+                const T x = G[(int64_t)i * gst];
+                nan |= x != x;
+                top = fmax(top, x);
+            }
+            if (nan) return (T)NAN;
+            if (top == -INFINITY) return -INFINITY;
+            T sum = 0;
+            for (int i = lo; i <= hi; ++i) sum += ex(T(2) * (G[(int64_t)i * gst] - top));
+            return top + T(0.5) * lg(sum);
+        };
+        for (int r = 0; r < c; ++r) {
+            if ((again >> r) & 1u) {
+                const int j = ja + r;
+                const T v = own(GE, j - w, j + w) - own(GB, j - w, j + w);
+                if (R) R[(int64_t)j * gst] = v;
+                pos |= (unsigned)(v > T(0)) << r;
+            }
+        }
+    }
+    if (first < 0 && pos) first = ja + __builtin_ctz(pos);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512) regime_stream(const T *__restrict__ ln_e, const T *__restrict__ ln_b,
-                                                     int64_t n_modes, int n, int w, int chunks_per_group,
-                                                     T *__restrict__ out, int32_t *__restrict__ first_out) {
-    __shared__ T ring[2][kRing * 64];
-    __shared__ int fw[8][64];
-    __shared__ T pm[2][8][64];
-    const int jbeg = w, jend = n - w;   // the host launches this form only when jend > jbeg and 2w + kChunk <= kRing
+__global__ void __launch_bounds__(64 * kWaves) regime_stream(const T *__restrict__ ln_e, const T *__restrict__ ln_b,
+                                                             int64_t n_modes, int n, int w, int chunks_per_group,
+                                                             T *__restrict__ out, int32_t *__restrict__ first_out) {
+    __shared__ T span[2][kSpan * 64];
+    __shared__ int fw[kWaves][64];
+    __shared__ T pm[2][kWaves][64];
+    __shared__ T bsum[2][kSpan / kSub][64];
+    const int jbeg = w, jend = n - w;   // the host launches this form only when jend > jbeg and 2w + kChunk <= kSpan
     const int n_chunks = (jend - jbeg + kChunk - 1) / kChunk;
     const int ca = (int)blockIdx.y * chunks_per_group, cb = min(ca + chunks_per_group, n_chunks);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -368,86 +416,128 @@ __global__ void __launch_bounds__(512) regime_stream(const T *__restrict__ ln_e,
     const int64_t kk = live ? k : 0;
     const T *GE = ln_e + kk, *GB = ln_b + kk;
     T *R = out && live ? out + k : nullptr;
+    T *sE = span[0] + lane, *sB = span[1] + lane;
     if (R) {
         if (blockIdx.y == 0)
-            for (int j = wv; j < jbeg; j += 8) R[(int64_t)j * n_modes] = (T)NAN;
+            for (int j = wv; j < jbeg; j += kWaves) R[(int64_t)j * n_modes] = (T)NAN;
         if (blockIdx.y == gridDim.y - 1)
-            for (int j = jend + wv; j < n; j += 8) R[(int64_t)j * n_modes] = (T)NAN;
+            for (int j = jend + wv; j < n; j += kWaves) R[(int64_t)j * n_modes] = (T)NAN;
     }
     int first = -1;
     if (ca < cb) {   // uniform over the workgroup
-        const int base = jbeg + ca * kChunk - w;   // cell staged in ring row 0
-        // the first chunk's span: cells [base, min(first outputs end, jend) + w)
+        // the first chunk's span: cells [o0 - w, min(o0 + kChunk, jend) + w) into rows 0 ..
         {
+            const int c0 = jbeg + ca * kChunk - w;
             const int rows = min(kChunk, jend - (jbeg + ca * kChunk)) + 2 * w;
-            constexpr int U = 16;
-            for (int r0 = wv; r0 < rows; r0 += 8 * U) {
+            T a = -INFINITY, bb = -INFINITY;
+            constexpr int U = kSpan / kWaves / 2;   // two rounds of loads in flight
+            for (int r0 = wv; r0 < rows; r0 += kWaves * U) {
                 T ve[U], vb[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int r = min(r0 + 8 * u, rows - 1);
-                    ve[u] = GE[(int64_t)(base + r) * n_modes];
-                    vb[u] = GB[(int64_t)(base + r) * n_modes];
+                    const int r = min(r0 + kWaves * u, rows - 1);
+                    ve[u] = GE[(int64_t)(c0 + r) * n_modes];
+                    vb[u] = GB[(int64_t)(c0 + r) * n_modes];
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int r = r0 + 8 * u;
+                    const int r = r0 + kWaves * u;
                     if (r < rows) {
-                        ring[0][r * 64 + lane] = ve[u];
-                        ring[1][r * 64 + lane] = vb[u];
+                        sE[r * 64] = ve[u];
+                        sB[r * 64] = vb[u];
+                        a = fmax(a, ve[u]);
+                        bb = fmax(bb, vb[u]);
                     }
                 }
             }
+            pm[0][wv][lane] = a;
+            pm[1][wv][lane] = bb;
         }
         __syncthreads();
         for (int ch = ca; ch < cb; ++ch) {
             const int o0 = jbeg + ch * kChunk, o1 = min(o0 + kChunk, jend);
-            // rows of the next chunk: cells [o1 + w, o1 + w + nn), loaded now, stored after this chunk
+            // rows of the next chunk: cells [o1 + w, o1 + w + nn), in flight during this chunk
             const int nn = ch + 1 < cb ? min(o1 + kChunk, jend) - o1 : 0;
-            constexpr int P = kChunk / 8;
+            constexpr int P = kChunk / kWaves;
             T pe[P], pb[P];
 #pragma unroll
             for (int u = 0; u < P; ++u) {
-                const int r = min(wv + 8 * u, max(nn - 1, 0));
-                const int64_t g = (int64_t)(nn > 0 ? o1 + w + r : base) * n_modes;
+                const int r = min(wv + kWaves * u, max(nn - 1, 0));
+                const int64_t g = (int64_t)(nn > 0 ? o1 + w + r : o0) * n_modes;
                 pe[u] = GE[g];
                 pb[u] = GB[g];
             }
-            // the chunk span's largest value of each field, per mode (rows split over the waves)
-            {
-                T a = -INFINITY, b = -INFINITY;
-                for (int c = o0 - w + wv; c < o1 + w; c += 8) {
-                    const int row = (c - base) & (kRing - 1);
-                    a = fmax(a, ring[0][row * 64 + lane]);
-                    b = fmax(b, ring[1][row * 64 + lane]);
-                }
-                pm[0][wv][lane] = a;
-                pm[1][wv][lane] = b;
-            }
-            __syncthreads();
             T mE = pm[0][0][lane], mB = pm[1][0][lane];
 #pragma unroll
-            for (int v = 1; v < 8; ++v) {
+            for (int v = 1; v < kWaves; ++v) {
                 mE = fmax(mE, pm[0][v][lane]);
                 mB = fmax(mB, pm[1][v][lane]);
             }
-            const int ja = o0 + kTile * wv, jb = min(ja + kTile, o1);
-            if (live && ja < jb) {
-                int f = -1;
-                ring_outputs(ring[0] + lane, ring[1] + lane, base, ja, jb, w, mE, mB, GE, GB, n_modes, R, f);
-                if (first < 0) first = f;
-            }
-            __syncthreads();   // the chunk's windows are summed: its first rows may be replaced
+            // sums of the terms over kSub-row blocks of the span (each term once)
+            {
+                const T rE = ref(mE), rB = ref(mB);
+                const int len = (o1 - o0) + 2 * w, nblk = (len + kSub - 1) / kSub;
+                for (int b = wv; b < nblk; b += kWaves) {
+                    T a = 0, bb = 0;
 #pragma unroll
-            for (int u = 0; u < P; ++u) {
-                const int r = wv + 8 * u;
-                if (r < nn) {
-                    const int slot = (o1 + w + r - base) & (kRing - 1);
-                    ring[0][slot * 64 + lane] = pe[u];
-                    ring[1][slot * 64 + lane] = pb[u];
+                    for (int i = 0; i < kSub; ++i) {
+                        const int rr = b * kSub + i;
+                        if (rr < len) {
+                            a += ex(T(2) * (sE[rr * 64] - rE));
+                            bb += ex(T(2) * (sB[rr * 64] - rB));
+                        }
+                    }
+                    bsum[0][b][lane] = a;
+                    bsum[1][b][lane] = bb;
                 }
             }
             __syncthreads();
+            const int ja = o0 + kSub * wv, c = min(kSub, o1 - ja);
+            if (live && c > 0) {
+                int f = -1;
+                span_outputs<kSub>(sE + kSub * wv * 64, sB + kSub * wv * 64, &bsum[0][wv][lane], &bsum[1][wv][lane], ja,
+                                   c, w, mE, mB, GE, GB, n_modes, R, f);
+                if (first < 0) first = f;
+            }
+            __syncthreads();   // the chunk's windows are summed
+            if (nn > 0) {      // uniform; then o1 - o0 = kChunk
+                // the last 2w rows move to the front, the new rows follow; the next span's maxima
+                constexpr int H = kChunk / kWaves;   // 2w <= kChunk rows of halo
+                T he[H], hb[H];
+                T a = -INFINITY, bb = -INFINITY;
+#pragma unroll
+                for (int u = 0; u < H; ++u) {
+                    const int r = wv + kWaves * u;
+                    if (r < 2 * w) {
+                        he[u] = sE[(kChunk + r) * 64];
+                        hb[u] = sB[(kChunk + r) * 64];
+                        a = fmax(a, he[u]);
+                        bb = fmax(bb, hb[u]);
+                    }
+                }
+                __syncthreads();   // every halo row is read before any is overwritten
+#pragma unroll
+                for (int u = 0; u < H; ++u) {
+                    const int r = wv + kWaves * u;
+                    if (r < 2 * w) {
+                        sE[r * 64] = he[u];
+                        sB[r * 64] = hb[u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < P; ++u) {
+                    const int r = wv + kWaves * u;
+                    if (r < nn) {
+                        sE[(2 * w + r) * 64] = pe[u];
+                        sB[(2 * w + r) * 64] = pb[u];
+                        a = fmax(a, pe[u]);
+                        bb = fmax(bb, pb[u]);
+                    }
+                }
+                pm[0][wv][lane] = a;
+                pm[1][wv][lane] = bb;
+                __syncthreads();
+            }
         }
     }
     fw[wv][lane] = first < 0 ? INT32_MAX : first;
@@ -455,7 +545,7 @@ __global__ void __launch_bounds__(512) regime_stream(const T *__restrict__ ln_e,
     if (wv == 0 && live && first_out) {
         int f = fw[0][lane];
 #pragma unroll
-        for (int v = 1; v < 8; ++v) f = min(f, fw[v][lane]);
+        for (int v = 1; v < kWaves; ++v) f = min(f, fw[v][lane]);
         if (f != INT32_MAX) atomicMin(first_out + k, f);
     }
 }
@@ -493,7 +583,7 @@ hipError_t launch(const T *e, const T *b, int64_t n_modes, int n, int w, T *R, i
     const int n_valid = n - 2 * w;
     const int64_t mblocks = (n_modes + 63) / 64;
     // (windows narrower than a sub-tile, 2w + 1 < kTile, take the tile form's direct sums)
-    if constexpr (sizeof(T) == 4) if (n_valid > 0 && 2 * w + 1 >= kTile && 2 * w + kChunk <= kRing && mblocks <= 0x7fffffff) {
+    if constexpr (sizeof(T) == 4) if (n_valid > 0 && 2 * w + 1 >= kTile && 2 * w + kChunk <= kSpan && mblocks <= 0x7fffffff) {
         // split the chunks of a mode block over workgroups until there are ~2048 of them
         const int n_chunks = (n_valid + kChunk - 1) / kChunk;
         const int64_t want = std::max<int64_t>(1, std::min<int64_t>(n_chunks, (2048 + mblocks - 1) / mblocks));
@@ -501,7 +591,7 @@ hipError_t launch(const T *e, const T *b, int64_t n_modes, int n, int w, T *R, i
         const int groups = (n_chunks + cpg - 1) / cpg;
         const dim3 g1((unsigned)((n_modes + 255) / 256));
         if (F) hipLaunchKernelGGL(regime_first_fill, g1, dim3(256), 0, s, F, n_modes);
-        hipLaunchKernelGGL(regime_stream<T>, dim3((unsigned)mblocks, (unsigned)groups), dim3(512), 0, s, e, b, n_modes, n,
+        hipLaunchKernelGGL(regime_stream<T>, dim3((unsigned)mblocks, (unsigned)groups), dim3(64 * kWaves), 0, s, e, b, n_modes, n,
                            w, cpg, R, F);
         if (F) hipLaunchKernelGGL(regime_first_finish, g1, dim3(256), 0, s, F, n_modes);
         return hipGetLastError();
