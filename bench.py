@@ -325,8 +325,9 @@ def bench_regime(args):
                        "x 4096 cells, window of 2 x 40 + 1 cells (one skin depth either side)",
            "cells": cells, "half_window_cells": w, "modes_with_electric_region": int((fr >= 0).sum())},
           {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-           "traffic": None, "kernel": "regime_stream<float> (a 64-mode block per workgroup walks xi through an LDS "
-                                      "ring; head/middle/tail window sums, no subtraction)",
+           "traffic": read_workload_traffic("regime", "bytes_per_launch"),
+           "kernel": "regime_stream<float> (a 64-mode block per 16-wave workgroup walks xi through LDS; "
+                     "head/middle/tail window sums, no subtraction)",
            "algorithmic_bytes_per_launch": 12.0 * cells, "avg_launch_ms": launch * 1e3}, cpu)
 
 

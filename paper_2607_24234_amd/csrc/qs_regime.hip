@@ -411,7 +411,13 @@ __global__ void __launch_bounds__(64 * kWaves) regime_stream(const T *__restrict
     const int n_chunks = (jend - jbeg + kChunk - 1) / kChunk;
     const int ca = (int)blockIdx.y * chunks_per_group, cb = min(ca + chunks_per_group, n_chunks);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+    // Workgroups are dealt to the eight XCDs in turn; XCD x takes a contiguous range of mode
+    // blocks, so the blocks that run side by side on one XCD are neighbours in memory and
+    // share, in that XCD's L2, the cache lines their rows straddle (a row of n_modes values
+    // is in general not line-aligned).
+    const unsigned nb = gridDim.x, q8 = nb / 8, r8 = nb % 8, x8 = blockIdx.x % 8;
+    const unsigned mb = x8 * q8 + min(x8, r8) + blockIdx.x / 8;
+    const int64_t k = (int64_t)mb * 64 + lane;
     const bool live = k < n_modes;
     const int64_t kk = live ? k : 0;
     const T *GE = ln_e + kk, *GB = ln_b + kk;
