@@ -386,6 +386,27 @@ def bench_surrogate(args):
     log("auto %.4f s per query" % auto_s)
     frac = float(used.float().mean().item())
     qps = n_q / sur_s
+    # dense maps: G at every (xi cell, tau step) of every instance-mode from one solver run
+    # (32 instances of the sweep, snapshots every step, the growth-target pass over all of them)
+    sub = S.sweep_instances(seed=0)[:32]
+    n_st = 200
+    sd = qs.Solver(sub, precision=qs.QS_FP32)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    od = sd.step(n_st, out_every=1, snapshots=True)
+    fd = sd.step(0, snapshots=True)
+    le = torch.cat([od["ln_e"], fd["ln_e"]])
+    lb = torch.cat([od["ln_b"], fd["ln_b"]])
+    del od, fd
+    Gd = torch.empty_like(le)
+    qs.growth_targets(qs.GrowthInstances(sub), le, lb, Gd, stream=sd.stream)
+    torch.cuda.synchronize()
+    dense_s = time.perf_counter() - t
+    dense_vals = Gd.numel()
+    sd.sync_check()
+    del le, lb, Gd
+    sd.close()
+    log("dense maps: %d values in %.3f s" % (dense_vals, dense_s))
     tf = 1.58e6 * qps / 1e12
     cpu = None
     if not args.no_cpu_baseline:
@@ -413,6 +434,7 @@ def bench_surrogate(args):
           cpu,
           surrogate_s_per_query=sur_s / n_q, solver_s_per_query=sol_s,
           speedup_vs_solver=sol_s / (sur_s / n_q),
+          dense_map_values_per_s=dense_vals / dense_s, dense_map_solver_over_surrogate=dense_vals / dense_s / qps,
           auto_tol=1e-2, auto_fraction_to_solver=frac, auto_s_per_query=auto_s)
 
 
