@@ -26,8 +26,9 @@
  *   n_modes >= 1, n_xi >= 1, half_window >= 0 (a window longer than the cells leaves no valid j)
  *   log_ratio     : [n_xi][n_modes] of the same type, or NULL
  *   first_e_cell  : int32 [n_modes], or NULL (at least one of the two outputs is required)
- * Ordered on hip_stream (NULL = null stream): one map kernel, with a fill before it and a
- * finish after it when first_e_cell is given; no synchronization, no allocation.  Calls
+ * Ordered on hip_stream (NULL = null stream): one map kernel, with (for the staged forms,
+ * when first_e_cell is given) a fill before it and a finish after it; no synchronization,
+ * no allocation.  Calls
  * that write the same outputs concurrently on different streams race.
  * Errors: QS_ERR_ARG (sizes, precision, NULL inputs, both outputs NULL; nothing is launched),
  * QS_ERR_HIP (launch failure); qs_last_error() has the text.
