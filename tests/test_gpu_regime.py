@@ -100,6 +100,20 @@ def test_windows_far_below_the_span_maximum(qs, precision):
     _compare(qs, e, b, w, precision)
 
 
+@pytest.mark.parametrize("slope", [-0.3, 0.3, -0.05])
+def test_steep_fields_across_chunks(qs, slope):
+    """Fields falling (or rising) by 0.3 or 0.05 nepers per cell, with noise: across the
+    streaming form's 128-output chunks the span maximum moves by up to ~40 nepers, so the
+    windows far below a chunk's reference (summed again from memory) and the chunk-to-chunk
+    hand-over of the halo rows are both exercised; FP32 against the oracle."""
+    n_xi, n_modes, w = 1000, 70, 40
+    rng = np.random.default_rng(int(abs(slope) * 100) + (slope > 0))
+    j = np.arange(n_xi)[:, None]
+    e = slope * j + rng.normal(0, 0.3, (n_xi, n_modes)) + rng.uniform(-5, 5, n_modes)
+    b = slope * j + rng.normal(0, 0.3, (n_xi, n_modes)) + rng.uniform(-5, 5, n_modes)
+    _compare(qs, e, b, w, "fp32")
+
+
 def test_outputs_optional_and_argument_errors(qs):
     import torch
     e, b = _fields(64, 10, seed=3)
