@@ -2,19 +2,19 @@
 // per (cell, mode) the ratio of the electric to the magnetic field energy summed over a
 // window of 2w + 1 cells, and per mode the first electrically dominated cell.
 //
-// Windows are summed kTile outputs at a time.  With the span s[i] = cell j0 - w + i of
-// outputs j0 + r (r < kTile), the window of output r is s[r .. r + 2w]; when 2w + 1 >= kTile
-// it splits into a suffix of the head s[0 .. kTile-1], the middle s[kTile .. 2w] common to
-// all kTile outputs, and a prefix of the tail s[2w+1 ..], so each output costs a few adds
-// and nothing is ever subtracted (a running sum that drops the cell leaving the window loses
-// the small terms of a field spanning many decades along xi).  Each field's terms are
+// Windows are summed a sub-tile of T consecutive outputs at a time.  With the span
+// s[i] = cell j0 - w + i of outputs j0 + r (r < T), the window of output r is s[r .. r + 2w];
+// when 2w + 1 >= T it splits into a suffix of the head s[0 .. T-1], the middle s[T .. 2w]
+// common to all T outputs, and a prefix of the tail s[2w+1 ..], so each output costs a few
+// adds and nothing is ever subtracted (a running sum that drops the cell leaving the window
+// loses the small terms of a field spanning many decades along xi).  Each field's terms are
 // exp(2 (ln - m)) with m that field's largest value over a span around the outputs; an
 // output whose sum falls below Tiny (its window far below m) is summed again over its own
 // window, and a field with no finite value in the span gives -inf (NaN where a value is
 // NaN) without that.  Narrow windows (2w + 1 < kTile) are summed directly.  Three forms:
-// FP32 windows of 8..64 cells stream each 64-mode block down xi through an LDS ring
-// (regime_stream); other windows that fit stage 64-mode tiles in LDS (regime_tile); the
-// rest walk global memory one lane per mode (regime_map).
+// FP32 windows of 8..64 cells stream each 64-mode block down xi through LDS, the middles
+// from 8-row block sums (regime_stream); other windows that fit stage 64-mode tiles in LDS
+// (regime_tile); the rest walk global memory one lane per mode (regime_map).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -66,10 +66,6 @@ __device__ __attribute__((noinline)) T window_log_energy(const T *__restrict__ v
     return top + T(0.5) * lg(s);
 }
 
-// Outputs j = ja .. jb-1 (all valid: w <= j < n - w) of one mode.  E, B address that mode's
-// column with E[(c - cell0) * st] = cell c (global memory, or a staged tile in LDS); R (may be
-// null) is the column of the global output, rst apart; first = the first j with R_j > 0 here
-// (-1 if none).
 // Terms exp(2 (ln - m)) are taken against r = ref(m): m itself, or 0 when m = -inf (no
 // finite value in the span: the terms are then 0, or NaN for a NaN).  A window's 1/2 ln of its
 // energy from its term sum: -inf (or NaN) when m = -inf; m + 1/2 ln(sum) while the sum stays
@@ -84,6 +80,10 @@ __device__ __forceinline__ T window_L(T m, T sum, const T *G, int64_t gst, int l
     return window_log_energy(G, gst, lo, hi);
 }
 
+// Outputs j = ja .. jb-1 (all valid: w <= j < n - w) of one mode, read from global memory.
+// E, B address that mode's column with E[(c - cell0) * st] = cell c; R (may be null) is the
+// column of the output, rst apart; first = the first j with R_j > 0 here (-1 if none).  Per
+// kTile outputs the span maximum, the terms, and the head / middle / tail sums.
 template <typename T>
 __device__ __forceinline__ void run_outputs(const T *E, const T *B, int64_t st, int cell0, int ja, int jb, int w,
                                             T *__restrict__ R, int64_t rst, int &first) {
