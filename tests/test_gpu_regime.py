@@ -220,6 +220,15 @@ def test_regime_chunks_split_over_workgroups(qs):
     _check_sampled(qs, e, b, 40, 128)
 
 
+@pytest.mark.parametrize("n_modes,n_xi", [(64, 70000), (6400, 20000)])
+def test_regime_long_columns(qs, n_modes, n_xi):
+    """Long columns (70,000 and 20,000 cells, FP32, w = 40): one 64-mode block whose 547 chunks
+    go to 547 workgroups, and 100 blocks whose 156 chunks go 8 at a time to 20 workgroups
+    each; 64 modes against the oracle."""
+    e, b = _sampled_device_fields(n_modes, n_xi, seed=n_xi)
+    _check_sampled(qs, e, b, 40, min(n_modes, 64))
+
+
 def test_regime_full_size_sampled(qs):
     """The 3D workload's snapshot size, 205,859 modes x 4096 cells in FP32, random-walk fields
     made on the device; the window of the 3D run's cell width (one skin depth = 40 cells); 96
