@@ -505,12 +505,12 @@ __global__ void __launch_bounds__(64 * kWaves) regime_stream(const T *__restrict
                                    c, w, mE, mB, GE, GB, n_modes, R, f);
                 if (first < 0) first = f;
             }
-            __syncthreads();   // the chunk's windows are summed
-            if (nn > 0) {      // uniform; then o1 - o0 = kChunk
-                // the last 2w rows move to the front, the new rows follow; the next span's maxima
-                constexpr int H = kChunk / kWaves;   // 2w <= kChunk rows of halo
-                T he[H], hb[H];
-                T a = -INFINITY, bb = -INFINITY;
+            // the last 2w rows move to the front and the new rows follow: this thread's halo
+            // rows into registers now (nothing writes the span before the barrier below)
+            constexpr int H = kChunk / kWaves;   // 2w <= kChunk rows of halo
+            T he[H], hb[H];
+            T a = -INFINITY, bb = -INFINITY;
+            if (nn > 0) {
 #pragma unroll
                 for (int u = 0; u < H; ++u) {
                     const int r = wv + kWaves * u;
@@ -521,7 +521,9 @@ __global__ void __launch_bounds__(64 * kWaves) regime_stream(const T *__restrict
                         bb = fmax(bb, hb[u]);
                     }
                 }
-                __syncthreads();   // every halo row is read before any is overwritten
+            }
+            __syncthreads();   // the chunk's windows are summed and every halo row is read
+            if (nn > 0) {      // uniform; then o1 - o0 = kChunk
 #pragma unroll
                 for (int u = 0; u < H; ++u) {
                     const int r = wv + kWaves * u;
