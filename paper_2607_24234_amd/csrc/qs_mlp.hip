@@ -326,34 +326,83 @@ __global__ void __launch_bounds__(256) gemm_nt(GemmArgs g) {
     }
 }
 
-// out[i] = sum_{s < S} part[s * stride + i * step] (fixed order)
+// Reductions of per-tile partials.  Every sum runs in a fixed order (gradients are
+// deterministic), with all of a thread's loads issued before its adds.
+
+// out[i] = sum_{s < S} part[s * stride + i * step], S <= 16: one thread per output, the S terms
+// added in order
 __global__ void __launch_bounds__(256) reduce_parts(const float *__restrict__ part, int S, int64_t stride,
                                                     int64_t count, int64_t step, float *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = k < S ? part[(int64_t)k * stride + i * step] : 0.f;
     float s = 0.f;
-    for (int k = 0; k < S; ++k) s += part[(int64_t)k * stride + i * step];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (k < S) s += v[k];
     out[i] = s;
 }
 
-// first-layer partials [tiles][o][6] -> dW1 [o][5], db1 [o]
-__global__ void __launch_bounds__(256) reduce_l1(const float *__restrict__ part, int tiles, float *__restrict__ G) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= D * (DIN + 1)) return;
-    const int o = i / (DIN + 1), c = i % (DIN + 1);
-    float s = 0.f;
-    for (int k = 0; k < tiles; ++k) s += part[((int64_t)k * D + o) * (DIN + 1) + c];
-    if (c < DIN) G[OFF_W1 + (int64_t)o * DIN + c] = s;
-    else G[OFF_B1 + o] = s;
+// sum over 64 lanes, each lane's value in a fixed butterfly order; lane 0's result is used
+__device__ __forceinline__ float wave_sum(float s) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    return s;
 }
 
-// sum over blocks of the (loss, dy) partial pairs -> db5 (device) ; loss is read by the host
-__global__ void reduce_db5(const float *__restrict__ lossp, int blocks, float *__restrict__ G, float *__restrict__ loss_out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out[o] = sum_{s < S} part[s * stride + o * step] for many partials: one wave per output,
+// lane l adding s = l, l + 64, ... in order, then the wave's fixed butterfly
+__global__ void __launch_bounds__(256) reduce_parts_wide(const float *__restrict__ part, int S, int64_t stride,
+                                                         int64_t count, int64_t step, float *__restrict__ out) {
+    const int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (o >= count) return;   // whole waves
+    float s = 0.f;
+    for (int k = lane; k < S; k += 64) s += part[(int64_t)k * stride + o * step];
+    s = wave_sum(s);
+    if (lane == 0) out[o] = s;
+}
+
+// first-layer partials [tiles][o][6] -> dW1 [o][5], db1 [o]: one wave per (o, c)
+__global__ void __launch_bounds__(256) reduce_l1(const float *__restrict__ part, int tiles, float *__restrict__ G) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= D * (DIN + 1)) return;   // whole waves
+    const int o = i / (DIN + 1), c = i % (DIN + 1);
+    float s = 0.f;
+    for (int k = lane; k < tiles; k += 64) s += part[((int64_t)k * D + o) * (DIN + 1) + c];
+    s = wave_sum(s);
+    if (lane == 0) {
+        if (c < DIN) G[OFF_W1 + (int64_t)o * DIN + c] = s;
+        else G[OFF_B1 + o] = s;
+    }
+}
+
+// sum over blocks of the (loss, dy) partial pairs -> db5 (device); the loss is read by the host.
+// One workgroup: thread t adds blocks t, t + 256, ... in order, then a fixed tree over the
+// four waves.
+__global__ void __launch_bounds__(256) reduce_db5(const float *__restrict__ lossp, int blocks, float *__restrict__ G,
+                                                  float *__restrict__ loss_out) {
+    __shared__ float red[2][4];
     float sl = 0.f, sd = 0.f;
-    for (int b = 0; b < blocks; ++b) { sl += lossp[2 * b]; sd += lossp[2 * b + 1]; }
-    G[OFF_B5] = sd;
-    loss_out[0] = sl;
+    for (int b = threadIdx.x; b < blocks; b += 256) {
+        sl += lossp[2 * b];
+        sd += lossp[2 * b + 1];
+    }
+    sl = wave_sum(sl);
+    sd = wave_sum(sd);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wv] = sl;
+        red[1][wv] = sd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        G[OFF_B5] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        loss_out[0] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    }
 }
 
 // ----------------------------------------------------------------------------- optimizer
@@ -869,11 +918,11 @@ qs_status qs_mlp_grads(qs_mlp *c, const float *x, const float *t, int32_t batch,
     // last layer
     hipLaunchKernelGGL(l5_bwd, dim3(D / 64, (unsigned)tiles), dim3(256), 0, s, c->dy, c->P, c->z[3], c->h[3],
                        c->dzb[0], c->dzT[0], ldT, c->colpart, c->w5part);
-    hipLaunchKernelGGL(reduce_parts, dim3(2), dim3(256), 0, s, c->colpart, (int)tiles, (int64_t)D, (int64_t)D,
+    hipLaunchKernelGGL(reduce_parts_wide, dim3(D / 4), dim3(256), 0, s, c->colpart, (int)tiles, (int64_t)D, (int64_t)D,
                        (int64_t)1, c->G + OFF_B4);
-    hipLaunchKernelGGL(reduce_parts, dim3(2), dim3(256), 0, s, c->w5part, (int)tiles, (int64_t)D, (int64_t)D,
+    hipLaunchKernelGGL(reduce_parts_wide, dim3(D / 4), dim3(256), 0, s, c->w5part, (int)tiles, (int64_t)D, (int64_t)D,
                        (int64_t)1, c->G + OFF_W5);
-    hipLaunchKernelGGL(reduce_db5, dim3(1), dim3(64), 0, s, c->lossp, (int)(B / 4), c->G, c->loss);
+    hipLaunchKernelGGL(reduce_db5, dim3(1), dim3(256), 0, s, c->lossp, (int)(B / 4), c->G, c->loss);
     // layers 4, 3, 2: weight gradient (split over rows), then the input gradient
     // row splits of the weight gradients: at most 16, >= 512 rows each, dividing B/16
     int splits = (int)std::max<int64_t>(1, std::min<int64_t>(16, B / 512));
@@ -903,13 +952,13 @@ qs_status qs_mlp_grads(qs_mlp *c, const float *x, const float *t, int32_t batch,
         }
         gemm_launch(EPI_BWD, d, 1, s);
         if (l > 0)
-            hipLaunchKernelGGL(reduce_parts, dim3(2), dim3(256), 0, s, c->colpart, (int)tiles, (int64_t)D, (int64_t)D,
-                               (int64_t)1, c->G + off_b(l - 1));
+            hipLaunchKernelGGL(reduce_parts_wide, dim3(D / 4), dim3(256), 0, s, c->colpart, (int)tiles, (int64_t)D,
+                               (int64_t)D, (int64_t)1, c->G + off_b(l - 1));
         cur ^= 1;
     }
     // first layer
     hipLaunchKernelGGL(l1_wgrad, dim3(D / 64, (unsigned)tiles), dim3(256), 0, s, c->dz1, x, c->l1part);
-    hipLaunchKernelGGL(reduce_l1, dim3((D * (DIN + 1) + 255) / 256), dim3(256), 0, s, c->l1part, (int)tiles, c->G);
+    hipLaunchKernelGGL(reduce_l1, dim3((D * (DIN + 1) + 3) / 4), dim3(256), 0, s, c->l1part, (int)tiles, c->G);
     MLP_HIP(hipGetLastError(), "gradient kernels");
     if (loss) {
         float l = 0.f;
