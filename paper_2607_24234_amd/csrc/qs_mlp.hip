@@ -447,16 +447,24 @@ __global__ void __launch_bounds__(256) pack_weights(const float *__restrict__ P,
 
 // ----------------------------------------------------------------------------- fused inference
 // One persistent kernel runs the whole network on tiles of 64 queries; only x and y touch
-// memory outside the workgroup.  The tile's activations stay in LDS as bfloat16
+// memory outside the workgroup.  A tile's activations stay in LDS as bfloat16
 // [64 queries][512 features] with a row pitch of 520 elements (the 32 rows of a fragment
-// read then fall on distinct banks).  Wave w of the four computes output features
+// read then fall on distinct banks).  Wave w of a group of four computes output features
 // 128 w .. 128 w + 127 of each layer for all 64 queries as the transposed product
 // z^T = W h^T: the weights are the A operand, read from L2 in fragment order (Wp), the
 // activations the B operand, read from LDS.  The first layer is a float32 matrix-core
 // product with the bias as a sixth input of value 1; the last layer is a float32 dot
 // product per query, summed over the four waves in a fixed order.  GELU takes Phi from a
-// table of cubic Hermite pieces (phi_table below).  Two workgroups share a compute unit, so
-// one's activation work overlaps the other's matrix products.
+// table of cubic Hermite pieces (phi_table below).
+//
+// A workgroup holds two such groups, each with a tile of its own, on one compute unit.  A
+// tile's work is a chain of seven items separated by workgroup barriers: the first layer
+// and its GELU; the products of each 512 x 512 layer, each but the last followed by its
+// GELU into the tile; the last GELU with the dot product.  Group 1 runs one item behind
+// group 0, so between two barriers one group's waves issue matrix products while the
+// other's (on the same SIMDs) do GELU work.  What bounds the kernel is then the weight
+// stream of the product items: each tile reads all 1.5 MB of W2..W4 from L2, about 64 bytes
+// per clock per compute unit at the matrix-core rate, which is the order of what L2 delivers.
 constexpr int FT = 64;              // queries per tile
 constexpr int ALD = D + 8;          // LDS row pitch of the activation tile (bfloat16 elements)
 constexpr int KS = D / 16;          // k-steps of a 512-long product
@@ -502,15 +510,22 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 __device__ __forceinline__ float bf_lo(uint32_t p) { return __builtin_bit_cast(float, p << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t p) { return __builtin_bit_cast(float, p & 0xFFFF0000u); }
 
-__global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
-    __shared__ __attribute__((aligned(16))) bf16_t act[FT * ALD];
+__global__ void __launch_bounds__(512, 1) mlp_infer(InferArgs a) {
+    __shared__ __attribute__((aligned(16))) bf16_t act[2][FT * ALD];
     __shared__ f32x4 tab[PHI_N];
     __shared__ f32x4 bw[D];              // b2, b3, b4, W5: four rows of 512 floats
-    __shared__ float red[4][FT];
+    __shared__ float red[2][4][FT];
+    __shared__ float w1s[D * (DIN + 1)];     // [feature][W1 row, b1]
+    __shared__ float xs[2][FT * DIN];        // each group's inputs of its coming tile
     const int tid = threadIdx.x, lane = tid & 63, lr = lane & 31, lh = lane >> 5;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int i = tid; i < PHI_N; i += 256) tab[i] = a.phi[i];
-    for (int i = tid; i < D; i += 256) {
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int grp = wid >> 2, w = wid & 3, gt = tid & 255;
+    for (int i = tid; i < PHI_N; i += 512) tab[i] = a.phi[i];
+    for (int i = tid; i < D * (DIN + 1); i += 512) {
+        const int f = i / (DIN + 1), c = i % (DIN + 1);
+        w1s[i] = c < DIN ? a.P[OFF_W1 + (int64_t)f * DIN + c] : a.P[OFF_B1 + f];
+    }
+    for (int i = tid; i < D; i += 512) {
         const int r = i / (D / 4), e = i % (D / 4);
         const float *src = r < 3 ? a.P + off_b(r) : a.P + OFF_W5;
         bw[i] = *reinterpret_cast<const f32x4 *>(src + 4 * e);
@@ -518,38 +533,26 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
     const rsrc_t rx = make_rsrc(a.x, (uint32_t)a.n * DIN * 4);
     const rsrc_t ry = make_rsrc(a.y, (uint32_t)a.n * 4);
     const rsrc_t rw = make_rsrc(a.Wp, 3u * D * D * 2);
-    // first layer (32 x 32 x 2 float32 products, k = inputs 0..4 and the bias): lane holds
-    // W1[32 (4 w + fb) + lane%32][2 s + lane/32], the sixth column being b1
-    float w1[4][3];
-#pragma unroll
-    for (int fb = 0; fb < 4; ++fb)
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const int f = 32 * (4 * w + fb) + lr, c = 2 * s + lh;
-            w1[fb][s] = c < DIN ? a.P[OFF_W1 + (int64_t)f * DIN + c] : a.P[OFF_B1 + f];
-        }
     const int tiles = (a.n + FT - 1) / FT;
-    // inputs of tile t for the B operand: query 32 qb + lane%32, input 2 s + lane/32 (the
-    // sixth input is 1).  The whole byte offset is in the per-lane operand, which the
-    // descriptor's range check covers: queries past n read 0.  Tiles past the last are not read.
-    auto load_x = [&](int t, float (&xb)[2][3]) {
-        if (t >= tiles) return;
-        const int voff = t * FT * DIN * 4 + (lr * DIN + lh) * 4;
-#pragma unroll
-        for (int qb = 0; qb < 2; ++qb)
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const float v = __builtin_bit_cast(
-                    float, __builtin_amdgcn_raw_buffer_load_b32(rx, voff + (32 * qb * DIN + 2 * s) * 4, 0, 0));
-                xb[qb][s] = (s < 2 || lh == 0) ? v : 1.f;
-            }
+    // group g of workgroup b takes tiles 2 b + g + 2 G k, k = 0, 1, ... (G workgroups); group 0
+    // never has fewer than group 1
+    const int stride = 2 * gridDim.x, t0 = 2 * blockIdx.x + grp;
+    const int mine = t0 < tiles ? (tiles - 1 - t0) / stride + 1 : 0;
+    const int most = 2 * blockIdx.x < tiles ? (tiles - 1 - 2 * (int)blockIdx.x) / stride + 1 : 0;
+    bf16_t *const at = act[grp];
+    // element e of tile t's inputs ([64][5] float32; the group's thread gt takes e = gt and,
+    // below 320, e = gt + 256).  The whole byte offset is in the per-lane operand, which the
+    // descriptor's range check covers: queries past n read 0.
+    auto load_x = [&](int t, int e) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, (t * FT * DIN + e) * 4, 0, 0));
     };
+    constexpr int XE = FT * DIN - 256;   // threads with a second input element
     // bias (or W5) row r for the four consecutive features of accumulator group (fb, j)
     auto brow = [&](int r, int fb, int j) { return bw[r * (D / 4) + (32 * (4 * w + fb) + 8 * j + 4 * lh) / 4]; };
     // GELU of acc as bfloat16 into the activation tile: element 4 j + e of acc[fb][qb] is
     // feature 32 (4 w + fb) + 8 j + 4 (lane/32) + e of query 32 qb + lane%32
     auto store = [&](f32x16 (&acc)[4][2]) {
-        bf16_t *row = act + lr * ALD + 128 * w + 4 * lh;
+        bf16_t *row = at + lr * ALD + 128 * w + 4 * lh;
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
@@ -564,98 +567,134 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
                     __builtin_amdgcn_sched_barrier(0);   // bounds the table reads in flight
                 }
     };
-    float xn[2][3] = {};
-    load_x(blockIdx.x, xn);
-    __syncthreads();
-    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
-        f32x16 acc[4][2];
+    // products of hidden layer l + 2 (l = 0, 1, 2) for this wave's 128 features of the tile
+    auto layer = [&](int l, f32x16 (&acc)[4][2]) {
+        // weight fragment (fb, ks) of this wave: 1 KiB block ((l 16 + 4 w + fb) KS + ks)
+        const int wbase = (l * 16 + 4 * w) * KS * 1024;
+        auto wload = [&](int fb, int ks) {
+            return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rw, lane * 16, wbase + (fb * KS + ks) * 1024, 0));
+        };
+        auto aload = [&](int qb, int ks) {
+            return *reinterpret_cast<const bf16x8 *>(at + (32 * qb + lr) * ALD + 16 * ks + 8 * lh);
+        };
+        // weight fragments in a ring of four k-steps (slot ks % 4), each loaded two k-steps
+        // ahead, activation fragments one k-step ahead (slot ks % 2); the group barriers
+        // keep that order.  The first k-step starts the sums from the bias.
+        bf16x8 A[4][4], B[2][2];
+        auto step = [&](int ks, auto slot, auto first) {
+            constexpr int u = decltype(slot)::value;
+            const int kn = min(ks + 2, KS - 1), kb = min(ks + 1, KS - 1);   // the end reloads the last step
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb)
+            for (int fb = 0; fb < 4; ++fb) A[(u + 2) % 4][fb] = wload(fb, kn);
 #pragma unroll
-            for (int qb = 0; qb < 2; ++qb) {
-                f32x16 z = {};
-#pragma unroll
-                for (int s = 0; s < 3; ++s) z = __builtin_amdgcn_mfma_f32_32x32x2f32(w1[fb][s], xn[qb][s], z, 0, 0, 0);
-                acc[fb][qb] = z;
-            }
-        load_x(t + gridDim.x, xn);   // next tile's inputs, in flight during this tile
-        store(acc);
-        __syncthreads();
-        for (int l = 0; l < 3; ++l) {
-            // weight fragment (fb, ks) of this wave: 1 KiB block ((l 16 + 4 w + fb) KS + ks)
-            const int wbase = (l * 16 + 4 * w) * KS * 1024;
-            auto wload = [&](int fb, int ks) {
-                return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rw, lane * 16, wbase + (fb * KS + ks) * 1024, 0));
-            };
-            auto aload = [&](int qb, int ks) {
-                return *reinterpret_cast<const bf16x8 *>(act + (32 * qb + lr) * ALD + 16 * ks + 8 * lh);
-            };
-            // weight fragments in a ring of four k-steps (slot ks % 4), each loaded two k-steps
-            // ahead, activation fragments one k-step ahead (slot ks % 2); the group barriers
-            // keep that order.  The first k-step starts the sums from the bias.
-            bf16x8 A[4][4], B[2][2];
-            auto step = [&](int ks, auto slot, auto first) {
-                constexpr int u = decltype(slot)::value;
-                const int kn = min(ks + 2, KS - 1), kb = min(ks + 1, KS - 1);   // the end reloads the last step
-#pragma unroll
-                for (int fb = 0; fb < 4; ++fb) A[(u + 2) % 4][fb] = wload(fb, kn);
-#pragma unroll
-                for (int qb = 0; qb < 2; ++qb) B[(u + 1) % 2][qb] = aload(qb, kb);
-#pragma unroll
-                for (int fb = 0; fb < 4; ++fb) {
-                    if constexpr (decltype(first)::value) {
-                        f32x16 bias;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const f32x4 b = brow(l, fb, j);
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) bias[4 * j + e] = b[e];
-                        }
-#pragma unroll
-                        for (int qb = 0; qb < 2; ++qb)
-                            acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], bias, 0, 0, 0);
-                    } else {
-#pragma unroll
-                        for (int qb = 0; qb < 2; ++qb)
-                            acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], acc[fb][qb], 0, 0, 0);
-                    }
-                }
-                if constexpr (!decltype(first)::value) {
-                    __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);   // 4 global (buffer) reads
-                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // 2 LDS reads
-                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // 8 matrix products
-                }
-            };
-            using I0 = std::integral_constant<int, 0>;
-            using I1 = std::integral_constant<int, 1>;
-            using I2 = std::integral_constant<int, 2>;
-            using I3 = std::integral_constant<int, 3>;
-            using T = std::true_type;
-            using F = std::false_type;
+            for (int qb = 0; qb < 2; ++qb) B[(u + 1) % 2][qb] = aload(qb, kb);
 #pragma unroll
             for (int fb = 0; fb < 4; ++fb) {
-                A[0][fb] = wload(fb, 0);
-                A[1][fb] = wload(fb, 1);
+                if constexpr (decltype(first)::value) {
+                    f32x16 bias;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const f32x4 b = brow(l, fb, j);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) bias[4 * j + e] = b[e];
+                    }
+#pragma unroll
+                    for (int qb = 0; qb < 2; ++qb)
+                        acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], bias, 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int qb = 0; qb < 2; ++qb)
+                        acc[fb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[u][fb], B[u % 2][qb], acc[fb][qb], 0, 0, 0);
+                }
             }
-            B[0][0] = aload(0, 0);
-            B[0][1] = aload(1, 0);
-            step(0, I0{}, T{});
+            if constexpr (!decltype(first)::value) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);   // 4 global (buffer) reads
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // 2 LDS reads
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);   // 8 matrix products
+            }
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        using T = std::true_type;
+        using F = std::false_type;
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) {
+            A[0][fb] = wload(fb, 0);
+            A[1][fb] = wload(fb, 1);
+        }
+        B[0][0] = aload(0, 0);
+        B[0][1] = aload(1, 0);
+        step(0, I0{}, T{});
 #pragma nounroll
-            for (int kk = 1; kk < KS - 3; kk += 4) {   // k-steps 1 .. 28
-                step(kk, I1{}, F{});
-                step(kk + 1, I2{}, F{});
-                step(kk + 2, I3{}, F{});
-                step(kk + 3, I0{}, F{});
+        for (int kk = 1; kk < KS - 3; kk += 4) {   // k-steps 1 .. 28
+            step(kk, I1{}, F{});
+            step(kk + 1, I2{}, F{});
+            step(kk + 2, I3{}, F{});
+            step(kk + 3, I0{}, F{});
+        }
+        step(KS - 3, I1{}, F{});
+        step(KS - 2, I2{}, F{});
+        step(KS - 1, I3{}, F{});
+    };
+    if (mine > 0) {
+        xs[grp][gt] = load_x(t0, gt);
+        if (gt < XE) xs[grp][gt + 256] = load_x(t0, gt + 256);
+    }
+    // output of the group's tile t: the four waves' partial sums in a fixed order, plus b5
+    auto put_y = [&](int t) {
+        if (gt < FT) {
+            const float v = (((red[grp][0][gt] + red[grp][1][gt]) + red[grp][2][gt]) + red[grp][3][gt]) + a.P[OFF_B5];
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ry, (t * FT + gt) * 4, 0, 0);
+        }
+    };
+    f32x16 acc[4][2];
+    __syncthreads();
+    // Every item below ends at a workgroup barrier.  Group 1 passes one barrier first, so it
+    // runs one item behind group 0; both pass 7 most + 1 barriers.
+    if (grp == 1) __syncthreads();
+    for (int k = 0; k < most; ++k) {
+        const bool live = k < mine;
+        const int t = t0 + k * stride;
+        if (k >= 1 && k - 1 < mine) put_y(t - stride);   // the previous tile's partial sums are in
+        if (live) {
+            // first layer (32 x 32 x 2 float32 products, k = inputs 0..4 and the bias): lane
+            // holds W1[32 (4 w + fb) + lane%32][2 s + lane/32] (the sixth column is b1) and
+            // input 2 s + lane/32 of query 32 qb + lane%32 (the sixth input is 1)
+            float w1[4][3], xb[2][3];
+#pragma unroll
+            for (int s3 = 0; s3 < 3; ++s3) {
+#pragma unroll
+                for (int fb = 0; fb < 4; ++fb) w1[fb][s3] = w1s[(32 * (4 * w + fb) + lr) * (DIN + 1) + 2 * s3 + lh];
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb)
+                    xb[qb][s3] = (s3 < 2 || lh == 0) ? xs[grp][(32 * qb + lr) * DIN + 2 * s3 + lh] : 1.f;
             }
-            step(KS - 3, I1{}, F{});
-            step(KS - 2, I2{}, F{});
-            step(KS - 1, I3{}, F{});
-            if (l < 2) {
-                __syncthreads();     // every wave has read this layer's input
+#pragma unroll
+            for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) {
+                    f32x16 z = {};
+#pragma unroll
+                    for (int s3 = 0; s3 < 3; ++s3) z = __builtin_amdgcn_mfma_f32_32x32x2f32(w1[fb][s3], xb[qb][s3], z, 0, 0, 0);
+                    acc[fb][qb] = z;
+                }
+            store(acc);
+        }
+        __syncthreads();
+        for (int l = 0; l < 3; ++l) {
+            if (live) layer(l, acc);
+            __syncthreads();
+            if (live && l < 2) {
                 store(acc);
-                __syncthreads();
-            } else {
-                // last layer: y = W5 . bf16(GELU(z4)) + b5
+            } else if (live) {
+                // last layer: this wave's part of y = W5 . bf16(GELU(z4)); meanwhile the next
+                // tile's inputs come into the group's input buffer
+                const int tn = t + stride;
+                const bool more = tn < tiles;
+                const float xv0 = more ? load_x(tn, gt) : 0.f;
+                const float xv1 = more && gt < XE ? load_x(tn, gt + 256) : 0.f;
 #pragma unroll
                 for (int qb = 0; qb < 2; ++qb) {
                     float sum = 0.f;
@@ -670,16 +709,18 @@ __global__ void __launch_bounds__(256, 2) mlp_infer(InferArgs a) {
                             __builtin_amdgcn_sched_barrier(0);
                         }
                     sum += __shfl_xor(sum, 32);
-                    if (lh == 0) red[w][32 * qb + lr] = sum;
+                    if (lh == 0) red[grp][w][32 * qb + lr] = sum;
                 }
-                __syncthreads();     // also: every wave has read the last layer's input
-                if (tid < FT) {
-                    const float v = (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) + a.P[OFF_B5];
-                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ry, (t * FT + tid) * 4, 0, 0);
+                if (more) {
+                    xs[grp][gt] = xv0;
+                    if (gt < XE) xs[grp][gt + 256] = xv1;
                 }
             }
+            __syncthreads();
         }
     }
+    if (grp == 0) __syncthreads();
+    if (most >= 1 && most - 1 < mine) put_y(t0 + (most - 1) * stride);
 }
 
 }  // namespace
@@ -898,10 +939,10 @@ qs_status qs_mlp_forward(qs_mlp *c, const float *x, int64_t n, float *y) {
     for (int64_t r0 = 0; r0 < n; r0 += kInferChunk) {
         const int32_t m = (int32_t)std::min<int64_t>(kInferChunk, n - r0);
         const int64_t tiles = (m + FT - 1) / FT;
-        const unsigned grid = (unsigned)std::min<int64_t>(tiles, 2 * (int64_t)std::max(c->cus, 1));
+        const unsigned grid = (unsigned)std::min<int64_t>((tiles + 1) / 2, std::max(c->cus, 1));
         InferArgs a{x + r0 * DIN, m, c->P, reinterpret_cast<const bf16x8 *>(c->Wp),
                     reinterpret_cast<const f32x4 *>(c->phi), y + r0};
-        hipLaunchKernelGGL(mlp_infer, dim3(grid), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(mlp_infer, dim3(grid), dim3(512), 0, c->stream, a);
     }
     MLP_HIP(hipGetLastError(), "forward kernel");
     return QS_OK;
