@@ -63,7 +63,7 @@ typedef enum {
     QS_ERR_ALLOC = -2,       /* device or host allocation failed, or workspace too small */
     QS_ERR_HIP = -3,         /* a HIP runtime call failed; the message names it */
     QS_ERR_NUMERIC = -4,     /* a non-finite value was found when renormalizing */
-    QS_ERR_UNSUPPORTED = -5, /* valid request that this build does not implement */
+    QS_ERR_UNSUPPORTED = -5, /* valid request that the library does not implement */
     QS_ERR_STATE = -6        /* the context is in a state that does not allow the call */
 } qs_status;
 
