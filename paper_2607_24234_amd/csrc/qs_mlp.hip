@@ -3,9 +3,11 @@
 //
 // The three 512 x 512 layers and their backward products are one kernel, gemm_nt:
 // C[M][N] = A[M][K] B[N][K]^T with bfloat16 operands (both K-contiguous) on the matrix cores
-// (v_mfma_f32_32x32x16_bf16, float32 accumulation), 128 x 128 tiles per workgroup of four
-// waves, each wave 64 x 64 (2 x 2 MFMA tiles), operands read as 16-byte fragments.  The
-// three uses differ only in operands and epilogue:
+// (v_mfma_f32_32x32x16_bf16, float32 accumulation), 128 x 128 tiles per workgroup of eight
+// waves (two per SIMD), each wave 64 x 32 (2 x 1 MFMA tiles).  The workgroup stages its 128 rows of A and
+// of B through LDS in chunks of 64 reduction indices (double buffered; eight threads read
+// each row's 128 contiguous bytes) and the waves read their fragments there.  The three
+// uses differ only in operands and epilogue:
 //   forward      z = h W^T + b             A = h [rows][in],      B = W [out][in]
 //   input grad   dh = dz W                 A = dz [rows][out],    B = W^T [in][out]
 //   weight grad  dW = dz^T h (split over rows) A = dz^T [out][rows], B = h^T [in][rows]
@@ -53,6 +55,7 @@ static_assert(off_w(2) == OFF_W4 && off_b(2) == OFF_B4, "layer spacing");
 using bf16_t = uint16_t;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 
 // float32 -> bfloat16, round to nearest, ties to even (NaN kept quiet)
@@ -219,7 +222,7 @@ struct GemmArgs {
     int64_t lda;
     const bf16_t *B;
     int64_t ldb;
-    int64_t k_len;        // reduction length per split (multiple of 16)
+    int64_t k_len;        // reduction length per split (multiple of 64)
     int64_t M, N;         // C extent (multiples of 128)
     // EPI_FWD
     const float *bias;    // [N]
@@ -241,46 +244,80 @@ __device__ __forceinline__ bf16x8 frag(const bf16_t *p) {
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
 }
 
+constexpr int KC = 64;         // reduction chunk staged through LDS
+constexpr int SLD = KC + 8;    // LDS row pitch of a staged chunk (bfloat16 elements)
+constexpr int NJ = 1;          // 32-column MFMA tiles per wave
+
 template <int EPI>
-__global__ void __launch_bounds__(256) gemm_nt(GemmArgs g) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int wm = wv >> 1, wn = wv & 1;
+__global__ void __launch_bounds__(512) gemm_nt(GemmArgs g) {
+    // the workgroup's 128 rows of A and of B for one chunk of 64 reduction indices, double
+    // buffered; the 8-element pad puts the rows a fragment read touches on distinct banks
+    __shared__ __attribute__((aligned(16))) bf16_t sa[2][128 * SLD];
+    __shared__ __attribute__((aligned(16))) bf16_t sb[2][128 * SLD];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv >> 2, wn = wv & 3;
     const int64_t m0 = (int64_t)blockIdx.y * 128 + 64 * wm;
-    const int64_t n0 = (int64_t)blockIdx.x * 128 + 64 * wn;
+    const int64_t n0 = (int64_t)blockIdx.x * 128 + 32 * NJ * wn;
     const int64_t kb = (int64_t)blockIdx.z * g.k_len;
+    // staging: thread t moves 16 bytes of rows t/8 + 64 i (i < 2) at chunk columns 8 (t%8),
+    // so eight threads read one row's 128 contiguous bytes
+    const int sr = tid >> 3, sc = 8 * (tid & 7);
+    const bf16_t *ga = g.A + ((int64_t)blockIdx.y * 128 + sr) * g.lda + kb + sc;
+    const bf16_t *gb = g.B + ((int64_t)blockIdx.x * 128 + sr) * g.ldb + kb + sc;
+    u32x4 stA[2], stB[2];
+    auto fetch = [&](int64_t k) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            stA[i] = *reinterpret_cast<const u32x4 *>(ga + 64 * i * g.lda + k);
+            stB[i] = *reinterpret_cast<const u32x4 *>(gb + 64 * i * g.ldb + k);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            *reinterpret_cast<u32x4 *>(&sa[buf][(sr + 64 * i) * SLD + sc]) = stA[i];
+            *reinterpret_cast<u32x4 *>(&sb[buf][(sr + 64 * i) * SLD + sc]) = stB[i];
+        }
+    };
+    // fragments: lane reads 8 reduction indices 16 s + 8 (lane/32) .. of row lane%32 (+ 32)
     const int lr = lane & 31, lk = 8 * (lane >> 5);
-    const bf16_t *pa0 = g.A + (m0 + lr) * g.lda + kb + lk;
-    const bf16_t *pa1 = pa0 + 32 * g.lda;
-    const bf16_t *pb0 = g.B + (n0 + lr) * g.ldb + kb + lk;
-    const bf16_t *pb1 = pb0 + 32 * g.ldb;
-    f32x16 acc[2][2];
+    f32x16 acc[2][NJ];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-    bf16x8 a0 = frag(pa0), a1 = frag(pa1), b0 = frag(pb0), b1 = frag(pb1);
-    for (int64_t k = 16; k < g.k_len; k += 16) {
-        const bf16x8 na0 = frag(pa0 + k), na1 = frag(pa1 + k), nb0 = frag(pb0 + k), nb1 = frag(pb1 + k);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
-        a0 = na0; a1 = na1; b0 = nb0; b1 = nb1;
+    const int chunks = (int)(g.k_len / KC);
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int c = 0; c < chunks; ++c) {
+        const int cur = c & 1;
+        if (c + 1 < chunks) fetch((int64_t)(c + 1) * KC);   // in flight during this chunk's products
+        const bf16_t *pa = &sa[cur][(64 * wm + lr) * SLD + lk];
+        const bf16_t *pb = &sb[cur][(32 * NJ * wn + lr) * SLD + lk];
+#pragma unroll
+        for (int s = 0; s < KC / 16; ++s) {
+            const bf16x8 a0 = frag(pa + 16 * s), a1 = frag(pa + 32 * SLD + 16 * s);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const bf16x8 b = frag(pb + 32 * j * SLD + 16 * s);
+                acc[0][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][j], 0, 0, 0);
+            }
+        }
+        if (c + 1 < chunks) put(cur ^ 1);   // that buffer's last readers passed the previous barrier
+        __syncthreads();
     }
-    acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
 
     // result element r of lane: row 8(r/4) + 4(lane/32) + r%4, column lane%32 of each tile
     const int rb = 4 * (lane >> 5);
-    float csum[2] = {0.f, 0.f};
+    float csum[NJ] = {};
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NJ; ++j) {
             const int64_t n = n0 + 32 * j + lr;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -319,7 +356,7 @@ __global__ void __launch_bounds__(256) gemm_nt(GemmArgs g) {
     if (EPI == EPI_BWD && g.colpart) {
         // this wave's 64 rows: lanes l and l + 32 hold the two halves of each column
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NJ; ++j) {
             const float s = csum[j] + __shfl_xor(csum[j], 32);
             if (lane < 32) g.colpart[((m0 >> 6)) * g.N + n0 + 32 * j + lr] = s;
         }
@@ -789,7 +826,7 @@ size_t mlp_bytes(int64_t B, std::vector<size_t> *offs) {
 }
 
 void gemm_launch(int epi, const GemmArgs &a, int splits, hipStream_t s) {
-    dim3 grid((unsigned)(a.N / 128), (unsigned)(a.M / 128), (unsigned)splits), block(256);
+    dim3 grid((unsigned)(a.N / 128), (unsigned)(a.M / 128), (unsigned)splits), block(512);
     if (epi == EPI_FWD) hipLaunchKernelGGL(gemm_nt<EPI_FWD>, grid, block, 0, s, a);
     else if (epi == EPI_BWD) hipLaunchKernelGGL(gemm_nt<EPI_BWD>, grid, block, 0, s, a);
     else hipLaunchKernelGGL(gemm_nt<EPI_PART>, grid, block, 0, s, a);
@@ -965,9 +1002,10 @@ qs_status qs_mlp_grads(qs_mlp *c, const float *x, const float *t, int32_t batch,
                        (int64_t)1, c->G + OFF_W5);
     hipLaunchKernelGGL(reduce_db5, dim3(1), dim3(256), 0, s, c->lossp, (int)(B / 4), c->G, c->loss);
     // layers 4, 3, 2: weight gradient (split over rows), then the input gradient
-    // row splits of the weight gradients: at most 16, >= 512 rows each, dividing B/16
+    // row splits of the weight gradients: at most 16, >= 512 rows each, dividing B/64 (each
+    // split's rows are whole reduction chunks)
     int splits = (int)std::max<int64_t>(1, std::min<int64_t>(16, B / 512));
-    while ((B / 16) % splits != 0) --splits;
+    while ((B / 64) % splits != 0) --splits;
     int cur = 0;
     for (int l = 2; l >= 0; --l) {
         GemmArgs w{};
