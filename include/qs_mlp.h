@@ -59,6 +59,8 @@ qs_status qs_mlp_get_params(qs_mlp *net, float *host_params);
  * Inference: y[i] = network(x[i]) for i < n (n >= 0, any size, independent of max_batch).
  * x: device float32 [n][5]; y: device float32 [n].  One persistent kernel per 2^25 queries
  * keeps every activation on chip; it uses no buffer of the network besides its parameters.
+ * The first call after the parameters change (qs_mlp_set_params, qs_mlp_adamw) first
+ * repacks the inference copy of W2..W4 (one small kernel on the same stream).
  */
 qs_status qs_mlp_forward(qs_mlp *net, const float *x, int64_t n, float *y);
 

@@ -772,6 +772,7 @@ struct qs_mlp {
     float *P, *G, *Mo, *Vo;
     bf16_t *Wb, *WTb;       // [3][D][D]
     bf16_t *Wp;             // [3][D][D] in fragment order (inference)
+    bool wp_stale = true;   // Wp lags P: repacked by the next forward call
     float *phi;             // [PHI_N][4] GELU table
     int cus = 0;            // compute units of the device
     float *z[4];            // [B][D]
@@ -855,11 +856,12 @@ void forward_train(qs_mlp *c, const float *x, int64_t rows, const float *t, floa
                        c->dy, c->lossp);
 }
 
-// bfloat16 copies of W2..W4 for training (row-major and transposed) and inference (packed)
+// bfloat16 copies of W2..W4 for training (row-major and transposed); the packed inference
+// copy follows at the next forward call (training steps do not read it)
 void convert(qs_mlp *c) {
     const dim3 grid((unsigned)((3 * D * D + 255) / 256)), block(256);
     hipLaunchKernelGGL(convert_weights, grid, block, 0, c->stream, c->P, c->Wb, c->WTb);
-    hipLaunchKernelGGL(pack_weights, grid, block, 0, c->stream, c->P, c->Wp);
+    c->wp_stale = true;
 }
 
 // Cubic Hermite pieces of Phi (standard normal distribution function) on [-6, 6], 16 per
@@ -973,6 +975,11 @@ qs_status qs_mlp_forward(qs_mlp *c, const float *x, int64_t n, float *y) {
     if (n > 0 && (!x || !y)) return mfail(QS_ERR_ARG, "x and y are required");
     MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
     if (n == 0) return QS_OK;
+    if (c->wp_stale) {
+        hipLaunchKernelGGL(pack_weights, dim3((unsigned)((3 * D * D + 255) / 256)), dim3(256), 0, c->stream, c->P, c->Wp);
+        MLP_HIP(hipGetLastError(), "pack weights");
+        c->wp_stale = false;
+    }
     for (int64_t r0 = 0; r0 < n; r0 += kInferChunk) {
         const int32_t m = (int32_t)std::min<int64_t>(kInferChunk, n - r0);
         const int64_t tiles = (m + FT - 1) / FT;
