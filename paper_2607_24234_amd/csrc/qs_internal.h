@@ -78,9 +78,19 @@ struct SeedArgs {
 
 // launchers (qs_spectral.hip)
 constexpr int kMaxSegments = 16;  // most waves per workgroup of the march kernel
-// waves per workgroup of the march kernel: 16 for FP32 with one column per lane, else 8
-// (the register budget of the larger column counts and of FP64 allows half the waves)
-inline int march_wg_waves(int precision, int nc) { return precision == QS_FP32 && nc == 1 ? 16 : 8; }
+// Tau-steps the FP32 one-column stepping kernels advance per sweep over the state (1 or 2).
+// With 2 the second step follows the first through every cell: its stage inputs at cell j
+// need the first step's results at cells <= j only, which are in registers by then, so the
+// state is read and written once per two steps.
+#ifndef QS_STEPS_PER_SWEEP
+#define QS_STEPS_PER_SWEEP 2
+#endif
+// waves per workgroup of the march kernel: for FP32 with one column per lane 16 (12 when a
+// sweep takes two steps, whose carries need up to 170 registers), else 8 (the register
+// budget of the larger column counts and of FP64 allows half the waves)
+inline int march_wg_waves(int precision, int nc) {
+    return precision == QS_FP32 && nc == 1 ? (QS_STEPS_PER_SWEEP == 2 ? 12 : 16) : 8;
+}
 hipError_t launch_march(int precision, int nc, bool restoring, bool fields, bool flat, int n_wg,
                         int wg_waves, bool segmented, const StepArgs &a, hipStream_t s);
 size_t march_lds_bytes(int precision, int nc, int wg_waves, bool segmented);

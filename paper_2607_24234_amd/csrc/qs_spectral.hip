@@ -205,20 +205,21 @@ __device__ __forceinline__ void atomic_max_key(double *dst, double v) {
 // crossing a boundary are rescaled exactly by the difference of the two exponents.
 //
 // LDS layout (dynamic): int ready[16], taken[16], abort, 3 pad; then per boundary w (0..S-2)
-// the payload double Y[4][NC][64], V[4][NC][64];  TC PP[4][NC][64];  int32 LL[MPL][64].
+// the payload: per step of a sweep (slot s) double Y[4][NC][64], V[4][NC][64], TC PP[4][NC][64];
+// then int32 LL[MPL][64].  The flags count sweeps.
 constexpr int kMaxSeg = 16;
 constexpr int kFlagInts = 2 * kMaxSeg + 4;
+constexpr int kSweepSlots = QS_STEPS_PER_SWEEP;
 
 template <typename TC, int NC>
 struct Payload {
     static constexpr int MPL = NC >= 2 ? NC / 2 : 1;
-    static constexpr int BYTES = kWave * (8 * NC * 8 + 4 * NC * (int)sizeof(TC) + MPL * 4);
-    __device__ static double *Y(char *p) { return reinterpret_cast<double *>(p); }
-    __device__ static double *V(char *p) { return reinterpret_cast<double *>(p) + 4 * NC * kWave; }
-    __device__ static TC *PP(char *p) { return reinterpret_cast<TC *>(p + 8 * NC * kWave * 8); }
-    __device__ static int32_t *LL(char *p) {
-        return reinterpret_cast<int32_t *>(p + 8 * NC * kWave * 8 + 4 * NC * kWave * (int)sizeof(TC));
-    }
+    static constexpr int SLOT = kWave * (8 * NC * 8 + 4 * NC * (int)sizeof(TC));
+    static constexpr int BYTES = kSweepSlots * SLOT + kWave * MPL * 4;
+    __device__ static double *Y(char *p, int s) { return reinterpret_cast<double *>(p + s * SLOT); }
+    __device__ static double *V(char *p, int s) { return reinterpret_cast<double *>(p + s * SLOT) + 4 * NC * kWave; }
+    __device__ static TC *PP(char *p, int s) { return reinterpret_cast<TC *>(p + s * SLOT + 8 * NC * kWave * 8); }
+    __device__ static int32_t *LL(char *p) { return reinterpret_cast<int32_t *>(p + kSweepSlots * SLOT); }
 };
 
 // Wait until *flag >= target (LDS, same workgroup).  Gives up (false) when another wave of
@@ -238,8 +239,8 @@ __device__ __forceinline__ bool wait_flag(int *flag, int target, int *abort, uin
 }
 
 template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, bool SNAP, bool FLAT>
-__global__ void __launch_bounds__(sizeof(TS) == 4 && NC == 1 ? 1024 : 512)
-__attribute__((amdgpu_waves_per_eu(NC == 1 && !SNAP ? (sizeof(TS) == 8 ? 4 : 5) : 1)))
+__global__ void __launch_bounds__(sizeof(TS) == 4 && NC == 1 ? (kSweepSlots == 2 ? 768 : 1024) : 512)
+__attribute__((amdgpu_waves_per_eu(NC == 1 && !SNAP ? (sizeof(TS) == 8 ? 4 : (kSweepSlots == 2 ? 3 : 5)) : 1)))
 march_kernel(StepArgs a) {
     using CL = Cols<NC>;
     using PL = Payload<TC, NC>;
@@ -312,26 +313,33 @@ march_kernel(StepArgs a) {
         }
     };
 
-    double y[4][NC], v[4][NC];  // oscillator carries per stage: n_p and d_xi n_p at the front face
-    TC pp[4][NC];               // stage inputs of P' at the front face of the current cell
-    TC scale[MPL], rmax[MPL], a2max[MPL];
+    // steps one sweep can take: two for the FP32 stepping kernels with one column per lane,
+    // where the second step's carries still fit the register budget; one otherwise
+    constexpr int NS = (!SNAP && NC == 1 && sizeof(TS) == 4) ? kSweepSlots : 1;
+    double y[NS][4][NC], v[NS][4][NC];  // per step of the sweep and stage: n_p and d_xi n_p at the front face
+    TC pp[NS][4][NC];                   // stage inputs of P' at the front face of the current cell
+    TC scale[MPL], rmax[MPL], a2max[NS][MPL];
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
 
-    // One segment pass of one tau-step: all four stages per cell, the fields of the state at
-    // tau_n (stage-1 values) and the update.
-    auto pass = [&](const bool init_steady) __attribute__((always_inline)) {
-        auto cell = [&](const int j, const TS (&x)[XW], auto first) __attribute__((always_inline)) {
+    // One segment pass of a sweep of K tau-steps: per cell, all four stages of each step, the
+    // fields of the state at the step's start (stage-1 values) and the update.
+    auto pass = [&](const bool init_steady, auto steps) __attribute__((always_inline)) {
+        constexpr int K = decltype(steps)::value;
+        // step `slot` of the sweep at cell j from its stage-1 values u (TC, pending power of
+        // two applied) and Omega at the centre and the rear face: fields, and the updated
+        // values un rounded to the storage type
+        auto step_cell = [&](const int j, const TC (&u)[3][NC], const TC Oc, const TC Of, TS (&un)[3][NC],
+                             auto first, auto slot) __attribute__((always_inline)) {
             constexpr bool FIRST = decltype(first)::value;
-            const bool last = (j == N - 1);
-            const TC Oc = FLAT ? om0 : (TC)x[ROW];
-            const TC Of = last ? (TC)0 : (FLAT ? om0 : (TC)x[ROW + 1]);
-            TC r0[NC], P0[NC], T0[NC], cTO[NC], cPO[NC];
+            constexpr int sl = decltype(slot)::value;
+            const TC(&r0)[NC] = u[0];
+            const TC(&P0)[NC] = u[1];
+            const TC(&T0)[NC] = u[2];
+            TC cTO[NC], cPO[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const int t = NC >= 2 ? c / 2 : 0;
-                // stored values times the pending exact power of two (1 when none)
-                r0[c] = (TC)x[0 * NC + c] * scale[t];
-                P0[c] = (TC)x[1 * NC + c] * scale[t];
-                T0[c] = (TC)x[2 * NC + c] * scale[t];
                 cTO[c] = cT[t] * Oc;
                 cPO[c] = cP[t] * Of;
             }
@@ -346,25 +354,26 @@ march_kernel(StepArgs a) {
                     const TC Pm = (m == 0) ? P0[c] : P0[c] + cm * dP[c];
                     const TC Tm = (m == 0) ? T0[c] : T0[c] + cm * dT[c];
                     const double rd = (double)rm;
-                    if (FIRST && init_steady) { y[m][c] = rd; v[m][c] = 0.0; }
+                    double &ym = y[sl][m][c], &vm = v[sl][m][c];
+                    if (FIRST && init_steady) { ym = rd; vm = 0.0; }
                     double nc, yn, vn, vc;
                     if (RESTORING) {
-                        const double u = y[m][c] - rd;
-                        nc = rd + C2 * u + S2 * v[m][c];
-                        yn = rd + C1 * u + S1 * v[m][c];
-                        vn = C1 * v[m][c] - S1 * u;
-                        if (FIELDS && m == 0) vc = C2 * v[m][c] - S2 * u;
+                        const double uu = ym - rd;
+                        nc = rd + C2 * uu + S2 * vm;
+                        yn = rd + C1 * uu + S1 * vm;
+                        vn = C1 * vm - S1 * uu;
+                        if (FIELDS && m == 0) vc = C2 * vm - S2 * uu;
                     } else {
-                        nc = y[m][c] + 0.5 * h * v[m][c] + 0.125 * h * h * rd;
-                        yn = y[m][c] + h * v[m][c] + 0.5 * h * h * rd;
-                        vn = v[m][c] + h * rd;
-                        if (FIELDS && m == 0) vc = v[m][c] + 0.5 * h * rd;
+                        nc = ym + 0.5 * h * vm + 0.125 * h * h * rd;
+                        yn = ym + h * vm + 0.5 * h * h * rd;
+                        vn = vm + h * rd;
+                        if (FIELDS && m == 0) vc = vm + 0.5 * h * rd;
                     }
-                    y[m][c] = yn;
-                    v[m][c] = vn;
+                    ym = yn;
+                    vm = vn;
                     if (FIELDS && m == 0) { ncf0[c] = (TC)nc; vcf0[c] = (TC)vc; }
-                    dr[c] = (Pm - pp[m][c]) + Tm;
-                    pp[m][c] = Pm;
+                    dr[c] = (Pm - pp[sl][m][c]) + Tm;
+                    pp[sl][m][c] = Pm;
                     dT[c] = cTO[c] * (TC)nc;
                     dP[c] = cPO[c] * (TC)vn;
                 }
@@ -387,7 +396,7 @@ march_kernel(StepArgs a) {
                         b2 = pair_sum(k2kap2[0] * r0[0] * r0[0]);
                     }
                     const TC a2 = e2 + b2;
-                    a2max[t] = a2 > a2max[t] ? a2 : a2max[t];
+                    a2max[sl][t] = a2 > a2max[sl][t] ? a2 : a2max[sl][t];
                     if (SNAP) {
                         // snapshot option: |F_perp|^2 = k^2 kappa^2 |n_p|^2 in place of |E|^2
                         TC s2 = e2;
@@ -404,15 +413,43 @@ march_kernel(StepArgs a) {
                     }
                 }
             }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                un[0][c] = (TS)(r0[c] + dt * dr[c]);
+                un[1][c] = (TS)(P0[c] + dt * dP[c]);
+                un[2][c] = (TS)(T0[c] + dt * dT[c]);
+            }
+        };
+        auto cell = [&](const int j, const TS (&x)[XW], auto first) __attribute__((always_inline)) {
+            const bool last = (j == N - 1);
+            const TC Oc = FLAT ? om0 : (TC)x[ROW];
+            const TC Of = last ? (TC)0 : (FLAT ? om0 : (TC)x[ROW + 1]);
+            TC u[3][NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int t = NC >= 2 ? c / 2 : 0;
+                // stored values times the pending exact power of two (1 when none)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) u[r][c] = (TC)x[r * NC + c] * scale[t];
+            }
+            TS un[3][NC];
+            step_cell(j, u, Oc, Of, un, first, I0{});
+            if constexpr (K == 2) {
+                // the second step of the sweep starts from the first one's stored values
+                TC u2[3][NC];
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) u2[r][c] = (TC)un[r][c];
+                step_cell(j, u2, Oc, Of, un, first, std::integral_constant<int, NS - 1>{});
+            }
             if (a.update) {
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const int t = NC >= 2 ? c / 2 : 0;
-                    const TS rn = (TS)(r0[c] + dt * dr[c]);
-                    bstore(rn, rs, voff, (j * ROW + 0 * NC + c) * RB);
-                    bstore((TS)(P0[c] + dt * dP[c]), rs, voff, (j * ROW + 1 * NC + c) * RB);
-                    bstore((TS)(T0[c] + dt * dT[c]), rs, voff, (j * ROW + 2 * NC + c) * RB);
-                    const TC ar = (TC)fabs((TC)rn);
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) bstore(un[r][c], rs, voff, (j * ROW + r * NC + c) * RB);
+                    const TC ar = (TC)fabs((TC)un[0][c]);
                     rmax[t] = (ar > rmax[t] || !(ar <= ar)) ? ar : rmax[t];  // NaN sticks
                 }
             }
@@ -425,7 +462,8 @@ march_kernel(StepArgs a) {
         // the descriptor (0 returned, unused).
         using first_t = std::integral_constant<bool, true>;
         using rest_t = std::integral_constant<bool, false>;
-        constexpr int D = QS_PREFETCH;
+        // a two-step sweep computes twice per cell loaded: two cells in flight suffice
+        constexpr int D = (K == 2 && QS_PREFETCH > 2) ? 2 : QS_PREFETCH;
         TS xs[D + 1][XW];
 #pragma unroll
         for (int d = 0; d <= D; ++d) ldx(c0 + d, xs[d]);
@@ -446,8 +484,11 @@ march_kernel(StepArgs a) {
     };
 
     constexpr int R = RenormRange<TS>::R;
-    for (int n = 0; n < a.n_steps; ++n) {
-        // apply the pending renormalization of each (mode, segment): this step's loads are
+    int sweeps = 0;   // sweeps done; the hand-off flags count these
+    for (int n = 0; n < a.n_steps; ++sweeps) {
+        // steps of this sweep: two while at least two remain (stepping kernels only)
+        const int k = (NS == 2 && a.update && n + 1 < a.n_steps) ? 2 : 1;
+        // apply the pending renormalization of each (mode, segment): this sweep's loads are
         // multiplied by 2^-e; a fields-only launch (no update) reads the stored values with
         // their current exponent
 #pragma unroll
@@ -458,52 +499,68 @@ march_kernel(StepArgs a) {
                 scale[t] = (TC)ldexp(1.0, -ep[t]);
             }
             rmax[t] = (TC)0;
-            a2max[t] = (TC)0;
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) a2max[sl][t] = (TC)0;
         }
         // carries at the segment's front face: zero at the beam front, else from wave-1
         if (wave == 0) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int sl = 0; sl < NS; ++sl)
 #pragma unroll
-                for (int c = 0; c < NC; ++c) { y[m][c] = 0.0; v[m][c] = 0.0; pp[m][c] = (TC)0; }
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) { y[sl][m][c] = 0.0; v[sl][m][c] = 0.0; pp[sl][m][c] = (TC)0; }
         } else {
-            if (!wait_flag(&ready[slot - 1], n + 1, abort, a.wait_ticks)) { a.err[1] = 1u; return; }
+            if (!wait_flag(&ready[slot - 1], sweeps + 1, abort, a.wait_ticks)) { a.err[1] = 1u; return; }
             char *pl = payload + (slot - 1) * PL::BYTES;
 #pragma unroll
             for (int t = 0; t < MPL; ++t) {
                 const int lp = PL::LL(pl)[t * kWave + lane];
                 const double f = ldexp(1.0, lp - L[t]);  // predecessor units -> ours (exact)
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
+                for (int sl = 0; sl < NS; ++sl) {
+                    if (sl >= k) break;
 #pragma unroll
-                    for (int p = 0; p < (NC >= 2 ? 2 : 1); ++p) {
-                        const int c = NC >= 2 ? 2 * t + p : 0;
-                        y[m][c] = PL::Y(pl)[(m * NC + c) * kWave + lane] * f;
-                        v[m][c] = PL::V(pl)[(m * NC + c) * kWave + lane] * f;
-                        pp[m][c] = PL::PP(pl)[(m * NC + c) * kWave + lane] * (TC)f;
-                    }
+                    for (int m = 0; m < 4; ++m)
+#pragma unroll
+                        for (int p = 0; p < (NC >= 2 ? 2 : 1); ++p) {
+                            const int c = NC >= 2 ? 2 * t + p : 0;
+                            y[sl][m][c] = PL::Y(pl, sl)[(m * NC + c) * kWave + lane] * f;
+                            v[sl][m][c] = PL::V(pl, sl)[(m * NC + c) * kWave + lane] * f;
+                            pp[sl][m][c] = PL::PP(pl, sl)[(m * NC + c) * kWave + lane] * (TC)f;
+                        }
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane == 0) __hip_atomic_store(&taken[slot - 1], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lane == 0) __hip_atomic_store(&taken[slot - 1], sweeps + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        pass(wave == 0 && steady);
+        if constexpr (NS == 2) {
+            if (k == 2) pass(wave == 0 && steady, std::integral_constant<int, 2>{});
+            else pass(wave == 0 && steady, std::integral_constant<int, 1>{});
+        } else {
+            pass(wave == 0 && steady, std::integral_constant<int, 1>{});
+        }
 
         // hand the carries at this segment's rear face to the next segment
         if (has_next) {
-            if (!wait_flag(&taken[slot], n, abort, a.wait_ticks)) { a.err[1] = 1u; return; }
+            if (!wait_flag(&taken[slot], sweeps, abort, a.wait_ticks)) { a.err[1] = 1u; return; }
             char *pl = payload + slot * PL::BYTES;
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int sl = 0; sl < NS; ++sl) {
+                if (sl >= k) break;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    PL::Y(pl)[(m * NC + c) * kWave + lane] = y[m][c];
-                    PL::V(pl)[(m * NC + c) * kWave + lane] = v[m][c];
-                    PL::PP(pl)[(m * NC + c) * kWave + lane] = pp[m][c];
-                }
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        PL::Y(pl, sl)[(m * NC + c) * kWave + lane] = y[sl][m][c];
+                        PL::V(pl, sl)[(m * NC + c) * kWave + lane] = v[sl][m][c];
+                        PL::PP(pl, sl)[(m * NC + c) * kWave + lane] = pp[sl][m][c];
+                    }
+            }
 #pragma unroll
             for (int t = 0; t < MPL; ++t) PL::LL(pl)[t * kWave + lane] = L[t];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane == 0) __hip_atomic_store(&ready[slot], n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lane == 0) __hip_atomic_store(&ready[slot], sweeps + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
 
 #pragma unroll
@@ -511,10 +568,14 @@ march_kernel(StepArgs a) {
             if (NC == 1) rmax[t] = pair_max(rmax[t]);
             if (FIELDS && a.max_ln_a && writer && mloc[t] < I.n_modes) {
                 const double sh = (double)L[t] * 0.69314718055994530942;
-                const TS val = (TS)(0.5 * (double)log(a2max[t]) + sh);
-                TS *dst = static_cast<TS *>(a.max_ln_a) + a.max_base + (int64_t)n * a.total_modes + I.mode0 + mloc[t];
-                if (a.keyed) atomic_max_key(dst, val);
-                else *dst = val;
+#pragma unroll
+                for (int sl = 0; sl < NS; ++sl) {
+                    if (sl >= k) break;
+                    const TS val = (TS)(0.5 * (double)log(a2max[sl][t]) + sh);
+                    TS *dst = static_cast<TS *>(a.max_ln_a) + a.max_base + (int64_t)(n + sl) * a.total_modes + I.mode0 + mloc[t];
+                    if (a.keyed) atomic_max_key(dst, val);
+                    else *dst = val;
+                }
             }
             int e = 0;
             if (a.update) {
@@ -527,6 +588,7 @@ march_kernel(StepArgs a) {
             }
             ep[t] = e;
         }
+        n += k;
     }
     if (a.update) {
 #pragma unroll
