@@ -156,7 +156,7 @@ def bench_batched(args):
            "cells_per_step": cells, "plan": s2.plan()},
           {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": read_workload_traffic("batched", "bytes_per_launch"),
-           "kernel": "march_kernel (persistent, xi-segmented), one launch = 200 steps of all instances",
+           "kernel": "march_kernel (persistent, xi-segmented), one launch = 200 steps of all instances, two per sweep",
            "algorithmic_bytes_per_launch": 48 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
 
 
@@ -578,7 +578,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "kernel": "march_kernel (fields, no snapshot): one persistent launch = "
-                               "the tau-steps between two snapshots, all modes",
+                               "the tau-steps between two snapshots, all modes, two steps per sweep",
                      "steps_per_launch": steps_per_launch,
                      "algorithmic_bytes_per_launch": bpc * cells * steps_per_launch,
                      "avg_launch_ms": avg_launch * 1e3,

@@ -17,7 +17,8 @@
 // stage-m input at cell j needs only stage m-1 rates at cell j, which need stage m-2's
 // march up to the rear face of cell j (causality in xi).  Each lane therefore carries four
 // oscillator states (n_p, d_xi n_p) per column in FP64 and reads and writes the state of
-// each cell exactly once per tau-step.
+// each cell once per sweep; the FP32 one-column stepping kernels take two tau-steps per
+// sweep (QS_STEPS_PER_SWEEP).
 #include <type_traits>
 
 #include "qs_internal.h"
