@@ -1,21 +1,29 @@
 // Envelope-approximation (SVEA) variant of the spectral path (include/qs_svea.h, Sec. III.B):
 // d_tau n = m, d_tau m = a * integral_0^xi n, one lane per transverse mode, all tau-steps of
 // a call in one launch (modes are independent; each 64-mode block's cells contiguous, so a
-// wave streams through one region), the four Runge-Kutta stages of a step in one
+// wave streams through one region), the four Runge-Kutta stages of two steps in one
 // causal sweep down the cells with FP64 running integrals, loads kAhead cells ahead in a
 // register ring, and an exact power-of-two rescale of a mode whose largest component leaves
-// [2^-100, 2^100] (applied to the next step's loads, like the full model's sweep).
+// [2^-100, 2^100] (applied to the next sweep's loads, like the full model's sweep).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <string>
+#include <type_traits>
 
 #include "../../include/qs_svea.h"
 #include "qs_internal.h"
 
 namespace {
 
-constexpr int kAhead = 4;     // cells of loads in flight per lane
+constexpr int kAhead = 3;     // cells of loads in flight per lane
+// tau-steps advanced per sweep over the state (1 to 4): step q + 1 at cell j starts from step
+// q's values at cell j, so the state is read and written once per sweep
+#ifndef QS_SVEA_STEPS_PER_SWEEP
+#define QS_SVEA_STEPS_PER_SWEEP 4
+#endif
+constexpr int kSweep = QS_SVEA_STEPS_PER_SWEEP;
+static_assert(kSweep >= 1 && kSweep <= 4, "steps per sweep");
 constexpr int kRange = 100;   // rescale when the largest component leaves [2^-kRange, 2^kRange]
 
 struct cplx {
@@ -45,10 +53,35 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
     const int64_t base = (k / 64) * (int64_t)n_xi * 64 + (k % 64);   // cell j at base + 64 j
     const double hh = 0.5 * h, d2 = 0.5 * dt, d6 = dt / 6.0;
     const int last = n_xi - 1;
-    double scale = 1.0;   // pending power of two, applied to this step's loads
+    double scale = 1.0;   // pending power of two, applied to this sweep's loads
     int l2 = l2s[k];
-    for (int s = 0; s < n_steps; ++s) {
-        cplx S1 = {0, 0}, S2 = {0, 0}, S3 = {0, 0}, S4 = {0, 0};   // h sum_{i<j} of each stage's n
+    // one RK4 step at a cell from its values (n0, m0); S holds h sum_{i<j} of each stage's n
+    // for this step and advances past the cell
+    auto rk4 = [&](const cplx n0, const cplx m0, cplx (&S)[4], cplx &n1, cplx &m1) __attribute__((always_inline)) {
+        // stage 1
+        const cplx k1n = m0, k1m = cmul(a, S[0] + hh * n0);
+        S[0] = S[0] + h * n0;
+        // stage 2
+        const cplx n2 = n0 + d2 * k1n, m2 = m0 + d2 * k1m;
+        const cplx k2n = m2, k2m = cmul(a, S[1] + hh * n2);
+        S[1] = S[1] + h * n2;
+        // stage 3
+        const cplx n3 = n0 + d2 * k2n, m3 = m0 + d2 * k2m;
+        const cplx k3n = m3, k3m = cmul(a, S[2] + hh * n3);
+        S[2] = S[2] + h * n3;
+        // stage 4
+        const cplx n4 = n0 + dt * k3n, m4 = m0 + dt * k3m;
+        const cplx k4n = m4, k4m = cmul(a, S[3] + hh * n4);
+        S[3] = S[3] + h * n4;
+        n1 = n0 + d6 * (k1n + 2.0 * k2n + 2.0 * k3n + k4n);
+        m1 = m0 + d6 * (k1m + 2.0 * k2m + 2.0 * k3m + k4m);
+    };
+    // One sweep down the cells advancing K tau-steps: step 2 at cell j starts from step 1's
+    // results at cell j (its inputs there need only cells <= j), so the state is read and
+    // written once per sweep.
+    auto sweep = [&](auto kk) __attribute__((always_inline)) {
+        constexpr int K = decltype(kk)::value;
+        cplx S[K][4] = {};
         double big = 0.0;
         // ring of kAhead + 1 slots: cell j sits in slot j % (kAhead + 1), loaded kAhead cells
         // early into the slot the previous cell has just freed (no copies at the loop edge)
@@ -60,29 +93,19 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
             rn[d] = nn[o];
             rm[d] = mm[o];
         }
-        auto cell = [&](int j, double2 ln, double2 lm) {
-            const cplx n0 = {scale * ln.x, scale * ln.y}, m0 = {scale * lm.x, scale * lm.y};
-            // stage 1
-            const cplx k1n = m0, k1m = cmul(a, S1 + hh * n0);
-            S1 = S1 + h * n0;
-            // stage 2
-            const cplx n2 = n0 + d2 * k1n, m2 = m0 + d2 * k1m;
-            const cplx k2n = m2, k2m = cmul(a, S2 + hh * n2);
-            S2 = S2 + h * n2;
-            // stage 3
-            const cplx n3 = n0 + d2 * k2n, m3 = m0 + d2 * k2m;
-            const cplx k3n = m3, k3m = cmul(a, S3 + hh * n3);
-            S3 = S3 + h * n3;
-            // stage 4
-            const cplx n4 = n0 + dt * k3n, m4 = m0 + dt * k3m;
-            const cplx k4n = m4, k4m = cmul(a, S4 + hh * n4);
-            S4 = S4 + h * n4;
-            const cplx n1 = n0 + d6 * (k1n + 2.0 * k2n + 2.0 * k3n + k4n);
-            const cplx m1 = m0 + d6 * (k1m + 2.0 * k2m + 2.0 * k3m + k4m);
+        auto cell = [&](int j, double2 ln, double2 lm) __attribute__((always_inline)) {
+            cplx n = {scale * ln.x, scale * ln.y}, m = {scale * lm.x, scale * lm.y};
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                cplx n1, m1;
+                rk4(n, m, S[q], n1, m1);
+                n = n1;
+                m = m1;
+            }
             const int64_t o = base + 64 * (int64_t)j;
-            nn[o] = make_double2(n1.x, n1.y);
-            mm[o] = make_double2(m1.x, m1.y);
-            big = fmax(big, fmax(cmaxabs(n1), cmaxabs(m1)));
+            nn[o] = make_double2(n.x, n.y);
+            mm[o] = make_double2(m.x, m.y);
+            big = fmax(big, fmax(cmaxabs(n), cmaxabs(m)));
         };
         int jb = 0;
         for (; jb + R <= n_xi; jb += R) {
@@ -98,12 +121,25 @@ __global__ void __launch_bounds__(256) svea_step(int64_t n_modes, int n_xi, doub
 #pragma unroll
         for (int u = 0; u < R; ++u)
             if (jb + u < n_xi) cell(jb + u, rn[u], rm[u]);
-        // power-of-two rescale of the next step's loads (exact)
+        // power-of-two rescale of the next sweep's loads (exact), from this sweep's stored values
         scale = 1.0;
         if (big > 0.0 && (big > 0x1p100 || big < 0x1p-100)) {
             const int e = ilogb(big);
             scale = ldexp(1.0, -e);
             l2 += e;
+        }
+    };
+    for (int s = 0; s < n_steps;) {
+        const int left = n_steps - s;
+        if (left >= kSweep) {
+            sweep(std::integral_constant<int, kSweep>{});
+            s += kSweep;
+        } else {
+            // the last steps of the call: one sweep of the rest
+            if (kSweep > 3 && left == 3) sweep(std::integral_constant<int, (kSweep > 3 ? 3 : 1)>{});
+            else if (kSweep > 2 && left == 2) sweep(std::integral_constant<int, (kSweep > 2 ? 2 : 1)>{});
+            else sweep(std::integral_constant<int, 1>{});
+            s += left;
         }
     }
     // a pending scale is applied in place before returning, so the stored state is exact

@@ -40,6 +40,20 @@ def test_matches_oracle(qs, n_xi, n_modes):
     _compare(gn, gm, on, om)
 
 
+def test_calls_of_every_remainder(qs):
+    """Calls of 1, 2, 3 and 5 steps (a sweep advances up to four steps at once, so each call
+    ends with a shorter sweep of its remainder) against one oracle run of all 11 steps."""
+    sp, gam = [E + (0.02,)], 200.0
+    k = np.linspace(0.2, 3.0, 65)
+    L, n_xi, dt = 10.0, 77, 3.0
+    s = qs.SVEASolver(sp, gam, k, L, n_xi, dt)
+    for c in (1, 2, 3, 5):
+        s.step(c)
+    gn, gm = s.state()
+    _, on, om = S.run(S.svea_coefficient(sp, gam, k), n_xi, L / n_xi, dt, 11, out_every=10 ** 9)
+    _compare(gn, gm, on, om)
+
+
 def test_envelope_against_exact_series(qs):
     """N = (i/2) n: |N| on the GPU against the exact impulse response at 256 cells."""
     G = 0.02
