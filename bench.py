@@ -62,6 +62,19 @@ def read_workload_traffic(workload, amount):
         return None
 
 
+def launch_plan(args, insts, precision, steps_per_call):
+    """The march's launch plan: the library's autotuner (qs_tune: candidate column counts and
+    segment lengths timed on the device for calls of this length) or its built-in heuristic."""
+    from paper_2607_24234_amd import qs
+    if args.plan == "auto":
+        return {}, "heuristic"
+    t = time.perf_counter()
+    tuned = qs.tune(insts, precision=precision, steps_per_call=max(1, int(steps_per_call)))
+    print("[plan] autotuner: %s (%.1f s)" % (tuned, time.perf_counter() - t), file=sys.stderr, flush=True)
+    return ({"columns_per_lane": tuned["columns_per_lane"], "segment_cells": tuned["segment_cells"]},
+            "autotuner (qs_tune, calls of %d steps)" % steps_per_call)
+
+
 def _scaled(v, f):
     return None if v is None else v * f
 
@@ -115,12 +128,13 @@ def bench_batched(args):
     from paper_2607_24234_amd import inputs, qs
     insts = inputs.batched()
     K = insts[0]["n_steps"]
-    s = qs.Solver(insts, precision=qs.QS_FP32)
+    plan, plan_src = launch_plan(args, insts, qs.QS_FP32, K)
+    s = qs.Solver(insts, precision=qs.QS_FP32, **plan)
     buf = torch.empty((K, s.total_modes), dtype=torch.float32, device="cuda")
     L = qs.lib()
     qs._check(L.qs_step_tau(s.ctx, 5, 1, None, None, buf.data_ptr()))
     torch.cuda.synchronize()
-    s2 = qs.Solver(insts, precision=qs.QS_FP32)       # timed from the initial state
+    s2 = qs.Solver(insts, precision=qs.QS_FP32, **plan)       # timed from the initial state
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -153,7 +167,7 @@ def bench_batched(args):
     _line(METRIC, cells * K / wall, "cell-updates/s", K, 0, wall / K * 1e3, "f32",
           {"workload": "batched sweep: 256 instances x 128 modes, log-uniform n_b in [1e-3, 1e-1], "
                        "gamma in [10, 1e4], L in [5, 200], 128..8192 cells, 200 steps, noise seed 1e-6",
-           "cells_per_step": cells, "plan": s2.plan()},
+           "cells_per_step": cells, "plan": dict(s2.plan(), source=plan_src)},
           {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": read_workload_traffic("batched", "bytes_per_launch"),
            "kernel": "march_kernel (persistent, xi-segmented), one launch = 200 steps of all instances, two per sweep",
@@ -446,6 +460,9 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--snapshot-every", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan", choices=["tuned", "auto"], default="tuned",
+                    help="march launch plan of the spectral and batched workloads: the autotuner's "
+                         "(timed candidates, a few seconds) or the built-in heuristic")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate", "svea", "regime"],
                     default="spectral3d",
@@ -487,7 +504,8 @@ def main():
         return
     inst = inputs.spectral3d()
     prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64
-    solver = qs.Solver([inst], precision=prec)
+    plan, plan_src = launch_plan(args, [inst], prec, args.snapshot_every - 1 if args.snapshot_every > 1 else args.steps)
+    solver = qs.Solver([inst], precision=prec, **plan)
     n_modes, n_xi = solver.total_modes, inst["n_xi"]
     dtype = solver.dtype
     K, W = args.steps, args.warmup
@@ -573,7 +591,7 @@ def main():
                    "state": args.precision, "oscillator_carry": "f64",
                    "outputs": "per-step max ln A per mode; ln|E|,ln|B| snapshots every %d steps" % args.snapshot_every,
                    "growth_nepers_over_run": growth,
-                   "plan": plan},
+                   "plan": dict(plan, source=plan_src)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
