@@ -78,7 +78,7 @@ struct SeedArgs {
 
 // launchers (qs_spectral.hip)
 constexpr int kMaxSegments = 16;  // most waves per workgroup of the march kernel
-// Tau-steps the FP32 one-column stepping kernels advance per sweep over the state (1 or 2).
+// Tau-steps the one-column stepping kernels advance per sweep over the state (1 or 2).
 // With 2 the second step follows the first through every cell: its stage inputs at cell j
 // need the first step's results at cells <= j only, which are in registers by then, so the
 // state is read and written once per two steps.
@@ -87,7 +87,8 @@ constexpr int kMaxSegments = 16;  // most waves per workgroup of the march kerne
 #endif
 // waves per workgroup of the march kernel: for FP32 with one column per lane 16 (12 when a
 // sweep takes two steps, whose carries need up to 170 registers), else 8 (the register
-// budget of the larger column counts and of FP64 allows half the waves)
+// budget of the larger column counts and of FP64 allows half the waves; a two-step FP64
+// sweep needs up to 228)
 inline int march_wg_waves(int precision, int nc) {
     return precision == QS_FP32 && nc == 1 ? (QS_STEPS_PER_SWEEP == 2 ? 12 : 16) : 8;
 }

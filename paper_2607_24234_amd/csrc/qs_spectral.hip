@@ -17,8 +17,8 @@
 // stage-m input at cell j needs only stage m-1 rates at cell j, which need stage m-2's
 // march up to the rear face of cell j (causality in xi).  Each lane therefore carries four
 // oscillator states (n_p, d_xi n_p) per column in FP64 and reads and writes the state of
-// each cell once per sweep; the FP32 one-column stepping kernels take two tau-steps per
-// sweep (QS_STEPS_PER_SWEEP).
+// each cell once per sweep; the one-column stepping kernels take two tau-steps per sweep
+// (QS_STEPS_PER_SWEEP).
 #include <type_traits>
 
 #include "qs_internal.h"
@@ -241,7 +241,7 @@ __device__ __forceinline__ bool wait_flag(int *flag, int target, int *abort, uin
 
 template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, bool SNAP, bool FLAT>
 __global__ void __launch_bounds__(sizeof(TS) == 4 && NC == 1 ? (kSweepSlots == 2 ? 768 : 1024) : 512)
-__attribute__((amdgpu_waves_per_eu(NC == 1 && !SNAP ? (sizeof(TS) == 8 ? 4 : (kSweepSlots == 2 ? 3 : 5)) : 1)))
+__attribute__((amdgpu_waves_per_eu(NC == 1 && !SNAP ? (sizeof(TS) == 8 ? (kSweepSlots == 2 ? 2 : 4) : (kSweepSlots == 2 ? 3 : 5)) : 1)))
 march_kernel(StepArgs a) {
     using CL = Cols<NC>;
     using PL = Payload<TC, NC>;
@@ -314,9 +314,9 @@ march_kernel(StepArgs a) {
         }
     };
 
-    // steps one sweep can take: two for the FP32 stepping kernels with one column per lane,
-    // where the second step's carries still fit the register budget; one otherwise
-    constexpr int NS = (!SNAP && NC == 1 && sizeof(TS) == 4) ? kSweepSlots : 1;
+    // steps one sweep can take: two for the stepping kernels with one column per lane, where
+    // the second step's carries still fit the register budget; one otherwise
+    constexpr int NS = (!SNAP && NC == 1) ? kSweepSlots : 1;
     double y[NS][4][NC], v[NS][4][NC];  // per step of the sweep and stage: n_p and d_xi n_p at the front face
     TC pp[NS][4][NC];                   // stage inputs of P' at the front face of the current cell
     TC scale[MPL], rmax[MPL], a2max[NS][MPL];
