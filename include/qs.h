@@ -291,8 +291,8 @@ qs_status qs_load_checkpoint(qs_ctx *ctx, const void *src, size_t bytes);
  * steps that output the per-step maxima.  Candidates: columns_per_lane 1 and 2, each with
  * 1, 2, 3, 4, 6, 8, 12 or 16 xi-segments (as many as the workgroup holds) and the automatic
  * plan.  Each is initialized on a scratch workspace that qs_tune allocates (hipMalloc) and
- * frees before returning, and timed: directly for steps_per_call <= 40, else as calls of 8
- * and 40 steps fitted to a + b n (a segmented plan pays a pipeline fill once per call) and
+ * frees before returning, and timed: directly for steps_per_call <= 96, else as calls of 16
+ * and 96 steps fitted to a + b n (a segmented plan pays a pipeline fill once per call) and
  * evaluated at n = steps_per_call.  With QS_TUNE_VERBOSE set, each candidate's time is
  * printed to stderr.  If
  * the environment variable QS_TUNE_CACHE names a file, a result for the same parameters

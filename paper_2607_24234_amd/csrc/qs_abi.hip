@@ -1001,8 +1001,10 @@ qs_status qs_tune(const qs_params *params, int32_t n_instances, int32_t steps_pe
     size_t ws_bytes = 0;
     for (const Cand &c : cands) ws_bytes = std::max(ws_bytes, c.pl.total);
     // a call of n steps costs a + b n (a: launch and, for segmented plans, the pipeline
-    // fill); measured directly for short calls, else fitted from calls of 8 and 40 steps
-    const int T1 = 8, T2 = 40;
+    // fill); measured directly for short calls, else fitted from calls of 16 and 96 steps
+    // (long enough that the candidates of one run are ranked reliably: with two steps per
+    // sweep a call of 96 steps is 48 sweeps)
+    const int T1 = 16, T2 = 96;
     const bool direct = steps_per_call <= T2;
     const int T = direct ? steps_per_call : T2;
     const size_t out_bytes = (size_t)T * base.total_modes * base.ts;
