@@ -100,6 +100,32 @@ qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64
 qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float *q, int64_t n,
                         int32_t mode, float *out, uint8_t *used_solver, void *hip_stream);
 
+/* Largest query count of one qs_growth_map_noalloc call (its scratch holds their features). */
+#define QS_GROWTH_NOALLOC_MAX 262144
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc): qs_growth_map's network answers without any
+ * allocation, synchronization or solver call.  For each of the n queries (device q [n][5]):
+ *   out[i]          : the network's answer, bitwise equal to qs_growth_map in
+ *                     QS_GROWTH_SURROGATE mode on the same network and queries;
+ *   needs_solver[i] : 1 where QS_GROWTH_AUTO would send the query to the solver (outside the
+ *                     box, no held-out estimate in its bin, or the estimate above tol, or
+ *                     table == NULL), else 0; such answers are not to be trusted at tol and
+ *                     the caller may pass those queries to qs_growth_map afterwards.
+ * 0 <= n <= QS_GROWTH_NOALLOC_MAX (QS_ERR_ARG beyond, with nothing launched).  out, needs_solver:
+ * device arrays of n elements; table: device [QS_GROWTH_BINS] or NULL.
+ * Work is queued on the network's stream (qs_mlp_create), with no host synchronization.
+ * The query features are staged in a fixed 5 MiB device array of the library (one per
+ * device, held until the process ends, resolved on the first call on that device): calls
+ * that overlap on one device, on any streams, race on it and must be serialized by the
+ * caller.  The call after a parameter change also repacks the network's inference weights
+ * (qs_mlp_forward), which is a kernel launch, not an allocation.
+ * Errors: QS_ERR_ARG, QS_ERR_HIP (qs_last_error has the text).
+ */
+qs_status qs_growth_map_noalloc(qs_mlp *net, const float *table, float tol, const float *q, int64_t n, float *out,
+                                uint8_t *needs_solver);
+
 #ifdef __cplusplus
 }
 #endif

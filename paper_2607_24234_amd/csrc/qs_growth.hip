@@ -7,12 +7,18 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "../../include/qs_growth.h"
 #include "qs_internal.h"
+
+// Scratch of the allocation-free query entry point: the features of at most
+// QS_GROWTH_NOALLOC_MAX queries (5 MiB).  Each device holds its own copy, from the library's
+// load until the process ends; every call on a device shares it.
+static __device__ __align__(256) float scratch[(size_t)QS_GROWTH_NOALLOC_MAX * 5];
 
 namespace {
 
@@ -211,6 +217,26 @@ __global__ void __launch_bounds__(256) scatter_kernel(const int64_t *__restrict_
 }
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (null: not yet resolved)
+
+// Device address of this device's scratch copy, resolved once per device with that device
+// current.  The host-side name `scratch` is not a device address and is never passed on.
+qs_status scratch_for_device(int dev, float **out) {
+    if (dev < 0 || dev >= kMaxDevices) return gfail(QS_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return gfail(QS_ERR_HIP, std::string("resolving the query scratch: ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return QS_OK;
+}
 
 qs_status check_insts(const qs_growth_instance *inst, int32_t n_inst) {
     if (!inst || n_inst < 1) return gfail(QS_ERR_ARG, "at least one instance is required");
@@ -496,6 +522,29 @@ qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64
     (void)hipFree(cnt);
     if (st != QS_OK) return st;
     if (e != hipSuccess) return gfail(QS_ERR_HIP, std::string("calibration: ") + hipGetErrorString(e));
+    return QS_OK;
+}
+
+qs_status qs_growth_map_noalloc(qs_mlp *net, const float *table, float tol, const float *q, int64_t n, float *out,
+                                uint8_t *needs_solver) {
+    if (!net) return gfail(QS_ERR_ARG, "the network is required");
+    if (n < 0 || (n > 0 && (!q || !out || !needs_solver))) return gfail(QS_ERR_ARG, "q, out and needs_solver are required");
+    if (n > QS_GROWTH_NOALLOC_MAX)
+        return gfail(QS_ERR_ARG, "n = " + std::to_string(n) + " queries exceed the scratch of this entry point (at most " +
+                                     std::to_string((long long)QS_GROWTH_NOALLOC_MAX) + " per call)");
+    const int dev = qs::mlp_device(net);
+    G_HIP(hipSetDevice(dev), "hipSetDevice");
+    if (n == 0) return QS_OK;
+    float *x = nullptr;
+    qs_status st = scratch_for_device(dev, &x);
+    if (st != QS_OK) return st;
+    hipStream_t s = qs::mlp_stream(net);
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, x);
+    G_HIP(hipGetLastError(), "features kernel");
+    st = qs_mlp_forward(net, x, n, out);
+    if (st != QS_OK) return st;
+    hipLaunchKernelGGL(route_kernel, dim3(blocks_for(n)), dim3(256), 0, s, x, n, table, tol, needs_solver);
+    G_HIP(hipGetLastError(), "routing kernel");
     return QS_OK;
 }
 

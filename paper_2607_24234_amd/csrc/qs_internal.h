@@ -121,8 +121,9 @@ qs_status grid_set_state(GridCtx *c, const double *rho, const double *jpar, cons
 // text returned by qs_last_error on this thread
 void set_last_error(const std::string &msg);
 
-// stream a surrogate network was created with (qs_mlp.hip)
+// stream and device a surrogate network was created with (qs_mlp.hip)
 hipStream_t mlp_stream(const qs_mlp *net);
+int mlp_device(const qs_mlp *net);
 
 // host helper mirroring the device SplitMix64 (exported for the generator tests)
 uint64_t splitmix64_host(uint64_t seed, uint64_t i);

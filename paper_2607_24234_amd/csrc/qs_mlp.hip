@@ -888,6 +888,7 @@ std::vector<float> phi_table() {
 
 namespace qs {
 hipStream_t mlp_stream(const qs_mlp *net) { return net->stream; }
+int mlp_device(const qs_mlp *net) { return net->device; }
 }  // namespace qs
 
 extern "C" {

@@ -89,7 +89,7 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_step_tau", "qs_grid_get_state", "qs_grid_set_state", "qs_mlp_param_count", "qs_mlp_create", "qs_mlp_set_params", "qs_mlp_get_params",
            "qs_mlp_forward", "qs_mlp_grads", "qs_mlp_get_grads", "qs_mlp_set_grads", "qs_mlp_adamw",
            "qs_mlp_train_step", "qs_mlp_free", "qs_growth_targets", "qs_growth_sample",
-           "qs_growth_features", "qs_growth_calibrate", "qs_growth_map",
+           "qs_growth_features", "qs_growth_calibrate", "qs_growth_map", "qs_growth_map_noalloc",
            "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
            "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope",
@@ -157,6 +157,8 @@ def lib():
     L.qs_growth_calibrate.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     L.qs_growth_map.restype = ctypes.c_int
     L.qs_growth_map.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int64, ctypes.c_int32, vp, vp, vp]
+    L.qs_growth_map_noalloc.restype = ctypes.c_int
+    L.qs_growth_map_noalloc.argtypes = [vp, vp, ctypes.c_float, vp, ctypes.c_int64, vp, vp]
     for name in ("qs_grid_get_state", "qs_grid_set_state"):
         getattr(L, name).restype = ctypes.c_int
         getattr(L, name).argtypes = [vp, _D, _D, _D, _D]
@@ -398,6 +400,16 @@ def growth_calibrate(net, X, T, table):
 def growth_map(net, table, tol, q, mode, out, used_solver=None, stream=None):
     _check(lib().qs_growth_map(net.h if net is not None else None, _vp(table), float(tol), _vp(q), int(q.shape[0]),
                                int(mode), _vp(out), _vp(used_solver), _stream_ptr(stream)))
+
+
+GROWTH_NOALLOC_MAX = 262144  # mirrored from include/qs_growth.h
+
+
+def growth_map_noalloc(net, table, tol, q, out, needs_solver):
+    """Network answers and routing flags with no allocation (qs_growth_map_noalloc), queued
+    on the network's stream."""
+    _check(lib().qs_growth_map_noalloc(net.h, _vp(table), float(tol), _vp(q), int(q.shape[0]), _vp(out),
+                                       _vp(needs_solver)))
 
 
 class GridSolver:
