@@ -8,9 +8,11 @@ marshals numpy arrays through ctypes and builds the C file with gcc when needed.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
+import tempfile
 
 import numpy as np
 
@@ -54,33 +56,65 @@ class _Beam(ctypes.Structure):
 
 _lib = None
 
+# mistakes the C source can plant (ORC_PLANT_<name>), for checking that the pins catch them
+PLANTS = ("EPERP_SIGN", "BPERP_NP", "NONFLUX", "LONG_SIGN", "FACE_INDEX", "TRANS_SIGN")
+
+
+def build_variant(plant: str, outdir: str | None = None) -> str:
+    """Compile a copy of the oracle with one planted mistake (ORC_PLANT_<plant>) into its own
+    shared library and return its path; the normal library is untouched."""
+    if plant not in PLANTS:
+        raise ValueError("unknown plant %r" % plant)
+    outdir = outdir or tempfile.mkdtemp(prefix="orc_plant_")
+    out = os.path.join(outdir, "liborc_%s.so" % plant.lower())
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-DORC_PLANT_" + plant,
+                           "-o", out, _SRC, _SRC_GRID, "-lm"])
+    return out
+
+
+@contextlib.contextmanager
+def use_library(path: str):
+    """Run the oracle's functions on another build of it (e.g. build_variant) inside the block."""
+    global _lib
+    saved = _lib
+    _lib = _declare(ctypes.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
+
 
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
-        D = ctypes.POINTER(ctypes.c_double)
-        B = ctypes.POINTER(_Beam)
-        _lib.orc_splitmix64.restype = ctypes.c_uint64
-        _lib.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
-        _lib.orc_u53.restype = ctypes.c_double
-        _lib.orc_u53.argtypes = [ctypes.c_uint64]
-        _lib.orc_run_modes.restype = ctypes.c_int
-        _lib.orc_run_modes.argtypes = [B, ctypes.c_int, D, ctypes.c_double, ctypes.c_int,
-                                       ctypes.c_int, D, D, D, D, ctypes.c_int, D, D, D,
-                                       ctypes.c_int]
-        _lib.orc_mode_fields.restype = ctypes.c_int
-        _lib.orc_mode_fields.argtypes = [B, ctypes.c_double, D, D, D, ctypes.c_double,
-                                         D, D, D, D, D]
-        _lib.orc_march_io.restype = ctypes.c_int
-        _lib.orc_march_io.argtypes = [B, D, D, D, D]
-        _lib.orc_collapse.restype = ctypes.c_int
-        _lib.orc_collapse.argtypes = [B, D, D, D, D, D, D]
-        _lib.orc_seed_mode.restype = ctypes.c_int
-        _lib.orc_seed_mode.argtypes = [B, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
-                                       ctypes.c_uint64, D, D, D]
+        _lib = _declare(ctypes.CDLL(build()))
     return _lib
+
+
+def _declare(L):
+    """Declare the C signatures on a loaded oracle library."""
+    D = ctypes.POINTER(ctypes.c_double)
+    B = ctypes.POINTER(_Beam)
+    L.orc_splitmix64.restype = ctypes.c_uint64
+    L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.orc_u53.restype = ctypes.c_double
+    L.orc_u53.argtypes = [ctypes.c_uint64]
+    L.orc_run_modes.restype = ctypes.c_int
+    L.orc_run_modes.argtypes = [B, ctypes.c_int, D, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_int, D, D, D, D, ctypes.c_int, D, D, D,
+                                ctypes.c_int]
+    L.orc_mode_fields.restype = ctypes.c_int
+    L.orc_mode_fields.argtypes = [B, ctypes.c_double, D, D, D, ctypes.c_double,
+                                  D, D, D, D, D]
+    L.orc_march_io.restype = ctypes.c_int
+    L.orc_march_io.argtypes = [B, D, D, D, D]
+    L.orc_collapse.restype = ctypes.c_int
+    L.orc_collapse.argtypes = [B, D, D, D, D, D, D]
+    L.orc_seed_mode.restype = ctypes.c_int
+    L.orc_seed_mode.argtypes = [B, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                ctypes.c_uint64, D, D, D]
+    return L
 
 
 def _dp(a):

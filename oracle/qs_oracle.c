@@ -36,6 +36,10 @@
  *   so that E_perp - B_perp = i k Psi, the transverse force of Sec. III.D.
  *
  * Everything is double / double complex; no blocking, fusion or reordering.
+ *
+ * Mutation hooks: the ORC_PLANT_* macros below each plant one deliberate mistake (a sign
+ * or index slip, a dropped term).  They are never defined in the oracle's normal build;
+ * the pin tests compile variants with one of them defined and check that a pin fails.
  */
 #include <complex.h>
 #include <math.h>
@@ -168,14 +172,29 @@ static void rates(const orc_beam *b, double k, const orc_state *x, orc_state *dx
             /* longitudinal flux n0 u on the two faces of cell j (zero on the outer faces) */
             double complex f_rear = 0.0, f_front = 0.0;
             if (!(b->flags & ORC_DROP_LONGITUDINAL)) {
+#ifdef ORC_PLANT_NONFLUX /* mutation: n0 taken at the cell centre on both faces */
+                if (j < N - 1) f_rear = n0_centre(b, s, j) * x->pz[s * N + j] / g3;
+                if (j > 0) f_front = n0_centre(b, s, j) * x->pz[s * N + j - 1] / g3;
+#else
                 if (j < N - 1) f_rear = n0_face(b, s, j) * x->pz[s * N + j] / g3;
                 if (j > 0) f_front = n0_face(b, s, j - 1) * x->pz[s * N + j - 1] / g3;
+#endif
             }
             double complex psi = kap * w->np_c[j];
             dx->n[s * N + j] = (f_rear - f_front) / h - I * k * n0_centre(b, s, j) * x->pt[s * N + j] / g;
+#ifdef ORC_PLANT_TRANS_SIGN /* mutation: sign of the transverse force */
+            dx->pt[s * N + j] = -qm * I * k * psi;
+#else
             dx->pt[s * N + j] = qm * I * k * psi;
+#endif
             if (j < N - 1 && !(b->flags & ORC_DROP_LONGITUDINAL))
+#if defined(ORC_PLANT_LONG_SIGN) /* mutation: sign of the longitudinal force */
+                dx->pz[s * N + j] = qm * kap * w->dnp_f[j];
+#elif defined(ORC_PLANT_FACE_INDEX) /* mutation: the next face's plasma gradient */
+                dx->pz[s * N + j] = -qm * kap * w->dnp_f[j + 1];
+#else
                 dx->pz[s * N + j] = -qm * kap * w->dnp_f[j];
+#endif
             else
                 dx->pz[s * N + j] = 0.0;
         }
@@ -223,8 +242,16 @@ static void fields(const orc_beam *b, double k, const orc_state *x, orc_work *w,
     const double shift = log2_scale * log(2.0);
     for (int j = 0; j < N; ++j) {
         double complex epar = -kap * w->dnp_c[j];
+#ifdef ORC_PLANT_EPERP_SIGN /* mutation: sign inside rho - n_p */
+        double complex eperp = -I * k * kap * (w->rho[j] + w->np_c[j]);
+#else
         double complex eperp = -I * k * kap * (w->rho[j] - w->np_c[j]);
+#endif
+#ifdef ORC_PLANT_BPERP_NP /* mutation: n_p in place of rho */
+        double complex bperp = -I * k * kap * w->np_c[j];
+#else
         double complex bperp = -I * k * kap * w->rho[j];
+#endif
         double e2 = creal(epar * conj(epar)) + creal(eperp * conj(eperp));
         double b2 = creal(bperp * conj(bperp));
         if (ln_e) ln_e[j] = 0.5 * log(e2) + shift;

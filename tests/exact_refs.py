@@ -157,3 +157,75 @@ def svea_series(a, tau, xi, dps=50):
             if j > 200000:
                 raise RuntimeError("series did not converge")
         return complex(total)
+
+
+def charge_impulse_series(tau, xi, G, beta, dps=40, tol=1e-30):
+    """Exact response of one Fourier mode of Eq. full_master_eq to an initial charge impulse
+    rho(xi, 0) = delta(xi) with no initial current (Sec. II; at k = 0 the longitudinal master
+    equation of Sec. IV.A, whose envelope obeys Eq. TSI_QSA).  The Laplace transform in tau
+    is s times that of impulse_series_long (a charge present at tau = 0 instead of created
+    there), so n is the tau-derivative of that series, taken term by term with
+    d/dtau [tau^nu J_nu(b tau)] = b tau^nu J_(nu-1)(b tau):
+        n = sum_j xi^(j+1) j_j(xi)/(2^j j!) (G^2+beta^2)^j sqrt(pi)/j! b (2b)^-(j+1/2)
+            tau^(j+1/2) J_(j-1/2)(b tau).
+    At tau = 0 it reduces to the free plasma response sin(xi)."""
+    if xi <= 0:
+        return 0.0
+    if beta <= 0:
+        raise ValueError("beta must be positive")
+    with mp.workdps(dps):
+        G, b, tau, xi = mp.mpf(G), mp.mpf(beta), mp.mpf(tau), mp.mpf(xi)
+        a2 = G * G + b * b
+        half = mp.mpf(1) / 2
+        total = mp.mpf(0)
+        big = mp.mpf(0)
+        j = 0
+        while True:
+            sj = mp.sqrt(mp.pi / (2 * xi)) * mp.besselj(j + half, xi)
+            dl = mp.sqrt(mp.pi) / mp.factorial(j) * b * (2 * b) ** (-(j + half)) * tau ** (j + half) * \
+                mp.besselj(j - half, b * tau)
+            term = xi ** (j + 1) * sj / (2 ** j * mp.factorial(j)) * a2 ** j * dl
+            total += term
+            big = max(big, abs(term))
+            if j > 4 and abs(term) < tol * max(big, mp.mpf(1e-300)) and j > xi and j > b * tau:
+                break
+            j += 1
+            if j > 4000:
+                raise RuntimeError("series did not converge")
+        return float(total)
+
+
+def asym_rear_saddle(tau, xi, G):
+    """Rear asymptote with the exponent taken to the order Appendix B carries in its saddle
+    value: tau h_+(alpha_s5^+) = i G tau (C - (3/2) e^(i pi/3) C^(1/3) + e^(-i pi/3)/(8 C^(1/3))),
+    C = xi/(G tau).  The third term, (sqrt(3) + i)/16 (G tau)^(4/3) xi^(-1/3) in the exponent,
+    is dropped in Eqs. OTSI_ST / np_large_C; it is not small unless (G tau)^4 << xi, and
+    restoring it brings the asymptote onto the exact response at C >> C_cr.  Prefactor as in
+    Eq. np_large_C; returns the real value 2 Re{...}."""
+    C = xi / (G * tau)
+    pref = 1.0 / (4 * G) * math.sqrt(2.0 / (3 * math.pi * xi))
+    corr = 1 + 1.0 / (6 * C ** (2.0 / 3.0)) * complex(0.25, math.sqrt(3) / 2)
+    ph = 1j * xi + 0.75 * complex(math.sqrt(3), -1) * (G * tau) ** (2.0 / 3.0) * xi ** (1.0 / 3.0) \
+        + complex(math.sqrt(3), 1) / 16.0 * (G * tau) ** (4.0 / 3.0) * xi ** (-1.0 / 3.0) - 1j * math.pi / 4
+    return pref * 2 * (corr * np.exp(ph)).real
+
+
+def tsi_envelope_series(beta, xi, tau, dps=60):
+    """Envelope equation of Sec. IV.A (Eq. TSI_QSA, d_tau^2 d_xi n = a n with
+    a = (8i/3^(3/2)) Gamma_TSI^3 = i beta^2/2) for a charge present at tau = 0: the e^(-i xi)
+    part of the full response at s >> beta gives n = sum_j (a xi)^j tau^(2j)/(j! (2j)!).
+    Returns ln|n| (summed in mpmath; the terms rotate in phase and cancel to many digits)."""
+    with mp.workdps(dps):
+        w = mp.mpc(0, 1) * mp.mpf(beta) ** 2 / 2 * mp.mpf(xi) * mp.mpf(tau) ** 2
+        total = mp.mpc(0)
+        term = mp.mpc(1)
+        j = 0
+        while True:
+            total += term
+            j += 1
+            term = term * w / (j * (2 * j) * (2 * j - 1))
+            if j > 8 and abs(term) < mp.mpf(10) ** (-dps + 5) * abs(total):
+                break
+            if j > 200000:
+                raise RuntimeError("series did not converge")
+        return float(mp.log(abs(total)))
