@@ -209,7 +209,11 @@ qs_status qs_init(const qs_params *params, int32_t n_instances, void *hip_stream
                   void *workspace, size_t workspace_bytes, qs_ctx **out);
 
 /* As qs_init, with an explicit execution plan (NULL = automatic).  QS_ERR_ARG for an invalid
- * plan.  The plan changes only the schedule: results are identical for every plan. */
+ * plan.  The plan changes only the schedule and the association of the arithmetic: in FP64
+ * the results of different plans agree to rounding (~1e-15 relative); in FP32 the stored
+ * state is rounded after a different number of operations per segment, so plans differ by
+ * FP32 rounding, a few 1e-7 relative per step (at most 2e-6 in ln A over the tests' runs).
+ * For one plan the results are bitwise reproducible. */
 qs_status qs_init_ex(const qs_params *params, int32_t n_instances, const qs_plan *plan,
                      void *hip_stream, void *workspace, size_t workspace_bytes, qs_ctx **out);
 
@@ -239,10 +243,33 @@ qs_status qs_step_tau(qs_ctx *ctx, int32_t n_steps, int32_t out_every, void *out
                       void *out_ln_b, void *out_max_ln_a);
 
 /*
- * Synchronize the context's stream and report whether any renormalization since the last
- * call met a non-finite value (QS_ERR_NUMERIC; the message names the step and mode).
+ * Synchronize the context's stream and report any failure of the launches since the last
+ * call:
+ *   QS_ERR_NUMERIC : a renormalization met a non-finite value; the message names the first
+ *                    one found: the instance, its mode index (as given in qs_params) and the
+ *                    tau-step after which the state was non-finite;
+ *   QS_ERR_HIP     : a xi-segment hand-off wait of the march kernel gave up (a device that
+ *                    stalled a workgroup beyond the wait budget); that launch's results are
+ *                    invalid.
+ * After either failure, if the rollback copy is enabled (qs_set_rollback) and holds a state,
+ * the state, scales and step count are restored to it -- the state at the start of the last
+ * qs_step_tau call (or graph replay) that began with no failure pending, i.e. the last good
+ * tau -- and the message names that step; the context is usable again.  Otherwise the
+ * context is marked invalid: qs_step_tau and qs_graph_launch return QS_ERR_STATE until
+ * qs_set_state, qs_grid_set_state or qs_load_checkpoint replaces the state (qs_get_state
+ * still reads it).  The failure is reported once.
  */
 qs_status qs_sync_check(qs_ctx *ctx);
+
+/*
+ * Rollback copy (spectral contexts): with enable != 0 the library allocates a device copy
+ * of the state and its scales (the size of a checkpoint, qs_checkpoint_size) and every
+ * stepping call first refreshes it, on the context's stream, unless a failure is pending; a
+ * failure reported by qs_sync_check then restores it (above).  The copy costs one device
+ * read and write of the state per qs_step_tau call.  enable == 0 frees it.
+ * Errors: QS_ERR_ARG, QS_ERR_UNSUPPORTED (transverse-grid context), QS_ERR_ALLOC.
+ */
+qs_status qs_set_rollback(qs_ctx *ctx, int32_t enable);
 
 /*
  * Number of tau-steps taken since qs_init (host).  Returns -1 for a NULL context.
@@ -337,6 +364,14 @@ qs_status qs_grid_set_state(qs_ctx *ctx, const double *rho, const double *j_par,
 
 /* Release the context and anything the library allocated for it.  NULL is ignored. */
 void qs_free(qs_ctx *ctx);
+
+/*
+ * Test hook: the wall-clock budget of each xi-segment hand-off wait of this context's march
+ * launches, in seconds (-1: the default, 2 s plus 20 us per segment cell).  A small budget
+ * makes the waits give up -- every wave of the launch still exits -- so that the stall path
+ * of qs_sync_check can be exercised.  Errors: QS_ERR_ARG.
+ */
+qs_status qs_debug_set_wait_budget(qs_ctx *ctx, double seconds);
 
 /*
  * Diagnostics: output number i (0-based) of the SplitMix64 stream started at `seed`, as the

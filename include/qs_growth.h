@@ -15,7 +15,9 @@
  * the plasma-period ripple of the response).  The solver answer uses the discretization of
  * the batched sweep: an instance of length L (the largest xi of its group of queries) with
  * N = round(128 + 8064 (L - 5)/195) cells (N = max(1, round(128 L/5)) below L = 5),
- * d_tau = tau_f/200, FP32 state; tau is rounded to whole steps.
+ * d_tau = tau_f/200, FP32 state; tau is rounded to whole steps (a tau beyond tau_f takes
+ * more than 200 steps).  A query sent to the solver must have finite values, gamma > 1,
+ * k >= 0, xi >= 0 and 0 <= tau <= 1e4 tau_f (QS_ERR_ARG otherwise, naming the query).
  *
  * Network inputs (features) of a query:
  *   x = ( log10 n_b + 2, (log10 gamma - 2.5)/1.5, (k - 2.025)/1.975, xi/100 - 1,

@@ -74,6 +74,9 @@ struct Plan {
         off_iidx, off_err, off_wtab, total;
 };
 
+// 32-bit words of the error region: see StepArgs::err
+constexpr int kErrWords = 8;
+
 int device_cus() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -374,7 +377,7 @@ qs_status make_plan(const qs_params *params, int32_t n, const qs_plan *plan, Pla
     pl.off_inst = o; o = align_up(o + (size_t)n * sizeof(InstDev));
     pl.off_blk = o; o = align_up(o + (size_t)blocks * sizeof(int32_t));
     pl.off_iidx = o; o = align_up(o + (size_t)n * sizeof(int32_t));
-    pl.off_err = o; o = align_up(o + sizeof(uint32_t) * 4);
+    pl.off_err = o; o = align_up(o + sizeof(uint32_t) * kErrWords);
     pl.off_wtab = o; o = align_up(o + pl.wave_table.size() * sizeof(int2));
     pl.total = o;
     return QS_OK;
@@ -390,14 +393,40 @@ struct qs_ctx {
     GridCtx *grid = nullptr;   // finite-width context (then pl is unused)
     int device = 0;
     double wall_clock_hz = 1e8;  // rate of the device's constant wall clock
+    double wait_seconds = -1.0;  // test hook: hand-off wait budget (< 0: the default)
     hipStream_t stream = nullptr;
     char *ws = nullptr;
     bool owns_ws = false;
     int64_t steps_done = 0;
+    // the state holds invalid results (a reported failure with no rollback copy); stepping is
+    // refused until qs_set_state or qs_load_checkpoint replaces it
+    bool poisoned = false;
+    std::string poison_why;
+    // rollback guard (qs_set_rollback): state, scales, then an int64 step count (-1: empty)
+    char *guard = nullptr;
+    size_t guard_bytes = 0;
     char *at(size_t off) const { return ws + off; }
 };
 
 namespace {
+
+// the three state regions and their copies in the rollback guard
+GuardArgs guard_args(qs_ctx *c) {
+    const Plan &pl = c->pl;
+    const size_t sb = (size_t)pl.state_elems * pl.ts, nb = (size_t)pl.n_scale * sizeof(int32_t);
+    GuardArgs g{};
+    const size_t off[3] = {pl.off_state, pl.off_log2s, pl.off_epend};
+    const size_t gof[3] = {0, sb, sb + nb};
+    const size_t len[3] = {sb, nb, nb};
+    for (int r = 0; r < 3; ++r) {
+        g.src[r] = reinterpret_cast<const uint4 *>(c->at(off[r]));
+        g.dst[r] = reinterpret_cast<uint4 *>(c->guard + gof[r]);
+        g.n16[r] = (int64_t)(len[r] / 16);
+    }
+    g.err = reinterpret_cast<const uint32_t *>(c->at(pl.off_err));
+    g.meta = reinterpret_cast<int64_t *>(c->guard + c->guard_bytes - sizeof(int64_t));
+    return g;
+}
 
 qs_status upload_tables(qs_ctx *c, const qs_params *params) {
     const Plan &pl = c->pl;
@@ -453,7 +482,7 @@ qs_status upload_tables(qs_ctx *c, const qs_params *params) {
                           hipMemcpyHostToDevice, c->stream), "copy instance index");
     QS_HIP(hipMemcpyAsync(c->at(pl.off_wtab), pl.wave_table.data(), pl.wave_table.size() * sizeof(int2),
                           hipMemcpyHostToDevice, c->stream), "copy wave table");
-    QS_HIP(hipMemsetAsync(c->at(pl.off_err), 0, sizeof(uint32_t) * 4, c->stream), "clear error flag");
+    QS_HIP(hipMemsetAsync(c->at(pl.off_err), 0, sizeof(uint32_t) * kErrWords, c->stream), "clear error flag");
     // the host vectors die here: make the copies complete first
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
     return QS_OK;
@@ -608,6 +637,9 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     const bool snaps = out_ln_e != nullptr;
     if (snaps && out_every < 1) return fail(QS_ERR_ARG, "out_every must be >= 1");
     if (n_steps == 0 && !snaps) return QS_OK;
+    if (c->poisoned && n_steps > 0)
+        return fail(QS_ERR_STATE, "the context's state is invalid (" + c->poison_why +
+                                      "); replace it with qs_set_state or qs_load_checkpoint");
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     if (c->grid) {
         std::string msg;
@@ -630,7 +662,8 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     a.wave_table = reinterpret_cast<const int2 *>(c->at(pl.off_wtab));
     // a segment waits for its predecessor to finish one step of its own cells: allow 2 s
     // plus 20 us per cell before the wait reports a stall
-    a.wait_ticks = (uint64_t)(c->wall_clock_hz * (2.0 + 20e-6 * pl.max_seg_len));
+    a.wait_ticks = (uint64_t)(c->wall_clock_hz * (c->wait_seconds >= 0.0 ? c->wait_seconds
+                                                                         : 2.0 + 20e-6 * pl.max_seg_len));
     const bool restoring = !(pl.inst[0].flags & QS_FLAG_NO_RESTORING);
     bool flat = true;
     for (const InstDev &d : pl.inst) flat = flat && (d.flags & kFlatProfile);
@@ -646,6 +679,7 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
         QS_HIP(launch(true), "march kernel");
         return QS_OK;
     }
+    if (c->guard) QS_HIP(launch_guard_copy(guard_args(c), c->stream), "rollback copy");
     // segments of one mode combine their per-step maxima with order-independent atomics
     const bool keyed = out_max_ln_a != nullptr && pl.max_seg > 1;
     if (keyed)
@@ -668,6 +702,7 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
         a.max_base = (int64_t)s0 * pl.total_modes;
         a.n_steps = s1 - s0;
         QS_HIP(launch(snap || out_max_ln_a != nullptr), "march kernel");
+        QS_HIP(launch_advance_steps(a.err, s1 - s0, c->stream), "step counter");
         c->steps_done += s1 - s0;
         s0 = s1;
     }
@@ -682,23 +717,94 @@ qs_status qs_sync_check(qs_ctx *c) {
     if (c->grid) {
         std::string msg;
         qs_status st = grid_sync_check(c->grid, c->stream, &msg);
-        return st == QS_OK ? QS_OK : fail(st, msg + " after step " + std::to_string(c->steps_done));
+        if (st == QS_OK) return QS_OK;
+        c->poisoned = true;
+        c->poison_why = msg;
+        return fail(st, msg + " after step " + std::to_string(c->steps_done) +
+                            "; the state is invalid until replaced (qs_grid_set_state)");
     }
     QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
-    uint32_t flag = 0;
-    QS_HIP(hipMemcpy(&flag, c->at(c->pl.off_err), sizeof(flag), hipMemcpyDeviceToHost), "read error flag");
-    uint32_t stall = 0;
-    QS_HIP(hipMemcpy(&stall, c->at(c->pl.off_err) + sizeof(uint32_t), sizeof(stall), hipMemcpyDeviceToHost), "read error flag");
-    if (stall) {
-        QS_HIP(hipMemset(c->at(c->pl.off_err) + sizeof(uint32_t), 0, sizeof(uint32_t)), "clear error flag");
-        return fail(QS_ERR_HIP, "a xi-segment hand-off wait gave up (results of the last launch are invalid)");
+    const Plan &pl = c->pl;
+    uint32_t err[kErrWords];
+    QS_HIP(hipMemcpy(err, c->at(pl.off_err), sizeof(err), hipMemcpyDeviceToHost), "read error flags");
+    if (!err[0] && !err[1]) return QS_OK;
+    qs_status st;
+    std::string msg;
+    if (err[1]) {
+        st = QS_ERR_HIP;
+        msg = "a xi-segment hand-off wait gave up (the results of that launch are invalid)";
+    } else {
+        st = QS_ERR_NUMERIC;
+        uint64_t key;
+        std::memcpy(&key, err + 2, sizeof(key));
+        key = ~key;
+        const int64_t step = (int64_t)(key >> 32);
+        const int64_t pm = (int64_t)(key & 0xffffffffu);
+        msg = "non-finite state at renormalization";
+        const int lm = 32 * pl.nc;  // padded modes per block
+        for (size_t i = 0; i < pl.inst.size(); ++i) {
+            const InstDev &d = pl.inst[i];
+            if (pm >= d.pmode0 && pm < d.pmode0 + (int64_t)d.n_blocks * lm) {
+                msg += " in instance " + std::to_string(i) + ", mode " + std::to_string(pm - d.pmode0);
+                break;
+            }
+        }
+        msg += ", after tau-step " + std::to_string(step);
     }
-    if (flag) {
-        QS_HIP(hipMemset(c->at(c->pl.off_err), 0, sizeof(uint32_t)), "clear error flag");
-        return fail(QS_ERR_NUMERIC, "non-finite state at renormalization (padded mode " +
-                                        std::to_string(flag - 1) + ") after step " +
-                                        std::to_string(c->steps_done));
+    // clear the flags, the first-failure key and nothing else (the step counter stays)
+    QS_HIP(hipMemset(c->at(pl.off_err), 0, 4 * sizeof(uint32_t)), "clear error flags");
+    int64_t good = -1;
+    if (c->guard)
+        QS_HIP(hipMemcpy(&good, c->guard + c->guard_bytes - sizeof(int64_t), sizeof(good), hipMemcpyDeviceToHost),
+               "read rollback step");
+    if (good >= 0) {
+        const size_t sb = (size_t)pl.state_elems * pl.ts, nb = (size_t)pl.n_scale * sizeof(int32_t);
+        QS_HIP(hipMemcpy(c->at(pl.off_state), c->guard, sb, hipMemcpyDeviceToDevice), "restore state");
+        QS_HIP(hipMemcpy(c->at(pl.off_log2s), c->guard + sb, nb, hipMemcpyDeviceToDevice), "restore scales");
+        QS_HIP(hipMemcpy(c->at(pl.off_epend), c->guard + sb + nb, nb, hipMemcpyDeviceToDevice), "restore scales");
+        QS_HIP(hipMemcpy(c->at(pl.off_err) + 4 * sizeof(uint32_t), &good, sizeof(good), hipMemcpyHostToDevice),
+               "restore step counter");
+        c->steps_done = good;
+        return fail(st, msg + "; the state was rolled back to tau-step " + std::to_string(good));
     }
+    c->poisoned = true;
+    c->poison_why = msg;
+    return fail(st, msg + "; the state is invalid until replaced (qs_set_state or qs_load_checkpoint)");
+}
+
+qs_status qs_set_rollback(qs_ctx *c, int32_t enable) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "transverse-grid contexts have no rollback copy");
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    if (!enable) {
+        if (c->guard) {
+            QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+            (void)hipFree(c->guard);
+            c->guard = nullptr;
+            c->guard_bytes = 0;
+        }
+        return QS_OK;
+    }
+    if (c->guard) return QS_OK;
+    const Plan &pl = c->pl;
+    const size_t bytes = (size_t)pl.state_elems * pl.ts + 2 * (size_t)pl.n_scale * sizeof(int32_t) + sizeof(int64_t);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(QS_ERR_ALLOC, "hipMalloc of the rollback copy failed");
+    }
+    const int64_t empty = -1;
+    hipError_t e = hipMemcpy(static_cast<char *>(p) + bytes - sizeof(int64_t), &empty, sizeof(empty), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(p); return hip_fail(e, "initialize the rollback copy"); }
+    c->guard = static_cast<char *>(p);
+    c->guard_bytes = bytes;
+    return QS_OK;
+}
+
+qs_status qs_debug_set_wait_budget(qs_ctx *c, double seconds) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (!(seconds >= 0.0) && seconds != -1.0) return fail(QS_ERR_ARG, "seconds must be >= 0, or -1 for the default");
+    c->wait_seconds = seconds;
     return QS_OK;
 }
 
@@ -805,6 +911,7 @@ qs_status qs_set_state(qs_ctx *c, const double *rho, const double *j_par, const 
     QS_HIP(hipMemcpy(c->at(pl.off_state), raw.data(), raw.size(), hipMemcpyHostToDevice), "copy state");
     QS_HIP(hipMemcpy(c->at(pl.off_log2s), l2.data(), l2.size() * 4, hipMemcpyHostToDevice), "copy scales");
     QS_HIP(hipMemcpy(c->at(pl.off_epend), ep.data(), ep.size() * 4, hipMemcpyHostToDevice), "copy scales");
+    c->poisoned = false;
     return QS_OK;
 }
 
@@ -875,7 +982,10 @@ qs_status qs_load_checkpoint(qs_ctx *c, const void *src, size_t bytes) {
     QS_HIP(hipMemcpy(c->at(pl.off_log2s), o, pl.n_scale * 4, hipMemcpyHostToDevice), "copy scales");
     o += pl.n_scale * 4;
     QS_HIP(hipMemcpy(c->at(pl.off_epend), o, pl.n_scale * 4, hipMemcpyHostToDevice), "copy scales");
+    QS_HIP(hipMemcpy(c->at(pl.off_err) + 4 * sizeof(uint32_t), &hd.steps_done, sizeof(int64_t), hipMemcpyHostToDevice),
+           "set step counter");
     c->steps_done = hd.steps_done;
+    c->poisoned = false;
     return QS_OK;
 }
 
@@ -887,11 +997,10 @@ void qs_free(qs_ctx *c) {
         delete c;
         return;
     }
-    if (c->owns_ws && c->ws) {
-        (void)hipSetDevice(c->device);
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->ws);
-    }
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->guard) (void)hipFree(c->guard);
+    if (c->owns_ws && c->ws) (void)hipFree(c->ws);
     delete c;
 }
 
@@ -1080,7 +1189,9 @@ qs_status qs_grid_set_state(qs_ctx *c, const double *rho, const double *j_par, c
     QS_HIP(hipSetDevice(c->device), "hipSetDevice");
     std::string msg;
     qs_status st = grid_set_state(c->grid, rho, j_par, j_x, j_y, c->stream, &msg);
-    return st == QS_OK ? QS_OK : fail(st, msg);
+    if (st != QS_OK) return fail(st, msg);
+    c->poisoned = false;
+    return QS_OK;
 }
 
 // ----------------------------------------------------------------------------- graphs
@@ -1130,6 +1241,9 @@ qs_status qs_graph_create(qs_ctx *c, int32_t n_steps, int32_t out_every, void *o
 
 qs_status qs_graph_launch(qs_graph *g) {
     if (!g) return fail(QS_ERR_ARG, "graph is NULL");
+    if (g->ctx->poisoned)
+        return fail(QS_ERR_STATE, "the context's state is invalid (" + g->ctx->poison_why +
+                                      "); replace it with qs_set_state or qs_load_checkpoint");
     QS_HIP(hipSetDevice(g->ctx->device), "hipSetDevice");
     QS_HIP(hipGraphLaunch(g->exec, g->ctx->stream), "graph launch");
     g->ctx->steps_done += g->n_steps;

@@ -305,7 +305,7 @@ qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> 
                        const std::vector<Group> &groups, size_t g0, size_t g1, hipStream_t s,
                        std::vector<float> *vals) {
     const double S = 1e-6;
-    const int n_steps_max = 200;
+    const int n_steps_max = 200;  // steps of tau_f
     const size_t ng = g1 - g0;
     std::vector<qs_params> params(ng);
     std::vector<double> qv(1, -1.0), mv(1, 1.0);
@@ -351,7 +351,7 @@ qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> 
         for (int64_t p : groups[g0 + i].members) {
             gof[p] = (int)i;
             const float *q = &hq[5 * (size_t)sel[p]];
-            const int stp = (int)std::lround(std::min(std::max((double)q[4] / params[i].d_tau, 0.0), (double)n_steps_max));
+            const int stp = (int)std::lround((double)q[4] / params[i].d_tau);  // tau >= 0 (checked)
             order.push_back({stp, p});
         }
     std::sort(order.begin(), order.end());
@@ -392,6 +392,19 @@ qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> 
 
 qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t> &sel, hipStream_t s,
                         std::vector<float> *vals) {
+    // the solver needs a physical beam and a point on or behind its front at tau >= 0; the
+    // step count follows tau (tau_f/200 per step), so tau beyond tau_f marches further
+    for (int64_t p : sel) {
+        const float *q = &hq[5 * (size_t)p];
+        bool ok = true;
+        for (int d = 0; d < 5; ++d) ok = ok && std::isfinite(q[d]);
+        ok = ok && q[1] > 0.0f && q[2] >= 0.0f && q[3] >= 0.0f && q[4] >= 0.0f;
+        if (ok) ok = (double)q[4] / (tau_final(std::exp((double)q[0]), std::exp((double)q[1])) / 200.0) < 2.0e6;
+        if (!ok)
+            return gfail(QS_ERR_ARG, "query " + std::to_string(p) +
+                                         " cannot go to the solver: it needs finite values, gamma > 1, k >= 0, "
+                                         "xi >= 0 and 0 <= tau <= 1e4 tau_f");
+    }
     std::map<std::pair<uint32_t, uint32_t>, int> gid;
     std::vector<Group> groups;
     for (size_t p = 0; p < sel.size(); ++p) {

@@ -59,7 +59,20 @@ struct StepArgs {
     uint64_t wait_ticks;      // wall-clock ticks a segment hand-off wait allows before giving up
     const int2 *wave_table;   // per (workgroup, wave slot): (global block, segment) or (-1, -1)
     uint32_t *err;            // [0]: 1 + padded mode after a non-finite renormalization;
-                              // [1]: 1 if a segment hand-off wait gave up
+                              // [1]: 1 if a segment hand-off wait gave up;
+                              // [2..3]: uint64 ~(step << 32 | padded mode) of the first
+                              //         non-finite value (largest complement = first step);
+                              // [4..5]: int64 tau-steps done (the device's step counter)
+};
+
+// Device copy of the state and scales, taken at the start of a stepping call when no error
+// is pending (the rollback guard); meta[0] receives the step count of the copy.
+struct GuardArgs {
+    const uint4 *src[3];
+    uint4 *dst[3];
+    int64_t n16[3];           // 16-byte words per region
+    const uint32_t *err;
+    int64_t *meta;
 };
 
 struct SeedArgs {
@@ -100,6 +113,8 @@ size_t march_lds_bytes(int precision, int nc, int wg_waves, bool segmented);
 int march_wgs_per_cu(int precision, int nc, bool restoring, bool flat, int wg_waves, bool segmented);
 hipError_t allow_march_lds(int precision, int nc, size_t bytes);
 hipError_t launch_key_fill(int precision, void *p, int64_t n, hipStream_t s);
+hipError_t launch_advance_steps(uint32_t *err, int32_t n, hipStream_t s);
+hipError_t launch_guard_copy(const GuardArgs &g, hipStream_t s);
 hipError_t launch_key_decode(int precision, void *p, int64_t n, hipStream_t s);
 hipError_t launch_seed(int precision, int nc, int n_blocks, int max_n_xi, const SeedArgs &a,
                        hipStream_t s);

@@ -582,7 +582,15 @@ march_kernel(StepArgs a) {
             if (a.update) {
                 const double mx = (double)rmax[t];
                 if (!isfinite(mx)) {
-                    if (writer) a.err[0] = 1u + (uint32_t)(I.pmode0 + mloc[t]);
+                    if (writer) {
+                        const uint32_t pm = (uint32_t)(I.pmode0 + mloc[t]);
+                        a.err[0] = 1u + pm;
+                        // the step after which the stored state is non-finite; the first
+                        // (lowest step, then mode) wins through a max of complements
+                        const int64_t step = *reinterpret_cast<const int64_t *>(a.err + 4) + n + k;
+                        atomicMax(reinterpret_cast<unsigned long long *>(a.err + 2),
+                                  ~(((unsigned long long)step << 32) | pm));
+                    }
                 } else if (mx > 0.0 && (mx > ldexp(1.0, R) || mx < ldexp(1.0, -R))) {
                     (void)frexp(mx, &e);
                 }
@@ -724,6 +732,33 @@ hipError_t allow_march_lds(int precision, int nc, size_t bytes) {
 #undef QS_ALLOW_ALL
 #undef QS_ALLOW
     return e;
+}
+
+// The device's step counter advances after each stepping launch (a kernel node, so that
+// replays of a captured step sequence count their steps too).
+__global__ void advance_steps(uint32_t *err, int32_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *reinterpret_cast<int64_t *>(err + 4) += n;
+}
+
+// Rollback guard: copy the state regions unless an error is pending (then the guard keeps
+// the last good copy); the first thread records the step count of the copy.
+__global__ void __launch_bounds__(256) guard_copy(GuardArgs g) {
+    if (g.err[0] != 0u || g.err[1] != 0u) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = 0; r < 3; ++r)
+        for (int64_t i = t0; i < g.n16[r]; i += stride) g.dst[r][i] = g.src[r][i];
+    if (t0 == 0) g.meta[0] = *reinterpret_cast<const int64_t *>(g.err + 4);
+}
+
+hipError_t launch_advance_steps(uint32_t *err, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(advance_steps, dim3(1), dim3(64), 0, s, err, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_guard_copy(const GuardArgs &g, hipStream_t s) {
+    hipLaunchKernelGGL(guard_copy, dim3(2048), dim3(256), 0, s, g);
+    return hipGetLastError();
 }
 
 hipError_t launch_key_fill(int precision, void *p, int64_t n, hipStream_t s) {

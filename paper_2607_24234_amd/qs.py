@@ -90,7 +90,7 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_mlp_forward", "qs_mlp_grads", "qs_mlp_get_grads", "qs_mlp_set_grads", "qs_mlp_adamw",
            "qs_mlp_train_step", "qs_mlp_free", "qs_growth_targets", "qs_growth_sample",
            "qs_growth_features", "qs_growth_calibrate", "qs_growth_map", "qs_growth_map_noalloc",
-           "qs_sync_check", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
+           "qs_sync_check", "qs_set_rollback", "qs_debug_set_wait_budget", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
            "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope",
            "qs_regime_map"]
@@ -166,6 +166,10 @@ def lib():
     L.qs_step_tau.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     L.qs_sync_check.restype = ctypes.c_int
     L.qs_sync_check.argtypes = [vp]
+    L.qs_set_rollback.restype = ctypes.c_int
+    L.qs_set_rollback.argtypes = [vp, ctypes.c_int32]
+    L.qs_debug_set_wait_budget.restype = ctypes.c_int
+    L.qs_debug_set_wait_budget.argtypes = [vp, ctypes.c_double]
     L.qs_steps_done.restype = ctypes.c_int64
     L.qs_steps_done.argtypes = [vp]
     L.qs_get_state.restype = ctypes.c_int
@@ -601,6 +605,14 @@ class Solver:
 
     def sync_check(self):
         _check(lib().qs_sync_check(self.ctx))
+
+    def set_rollback(self, enable=True):
+        """Keep a device copy of the last good state for qs_sync_check to restore."""
+        _check(lib().qs_set_rollback(self.ctx, 1 if enable else 0))
+
+    def debug_wait_budget(self, seconds):
+        """Test hook: the hand-off wait budget of the march launches (-1 = default)."""
+        _check(lib().qs_debug_set_wait_budget(self.ctx, float(seconds)))
 
     @property
     def steps_done(self):

@@ -160,3 +160,11 @@ def test_device_generator_equals_oracle_generator(oracle):
     for seed in (0, 1, 0xDEADBEEF, 2**64 - 1):
         for i in (0, 1, 2, 12345, 2**40 + 7):
             assert L.qs_debug_splitmix64(seed, i) == oracle.splitmix64(seed, i)
+
+
+def test_failure_handling_entry_points_reject_null_context():
+    """qs_set_rollback and the wait-budget hook check their context on the host."""
+    qs, L = _lib()
+    assert L.qs_set_rollback(None, 1) == qs.QS_ERR_ARG
+    assert L.qs_debug_set_wait_budget(None, 0.0) == qs.QS_ERR_ARG
+    assert L.qs_sync_check(None) == qs.QS_ERR_ARG

@@ -164,7 +164,7 @@ def _oracle_solver_answers(q):
         dt = 10 * math.sqrt(g / nb) / 200
         inst = dict(species=[inputs.ELECTRON + (nb,)], gamma=g, length=L, n_xi=N, kx=ks, ky=None, d_tau=dt,
                     seed_kind=1, seed_amp=1e-6, rng_seed=0)
-        steps = [int(round(min(max(float(np.float32(q[i, 4])) / dt, 0), 200))) for i in idx]
+        steps = [int(round(float(np.float32(q[i, 4])) / dt)) for i in idx]
         ln_e, ln_b, _, _ = oracle_run(inst, max(steps) + 1, out_every=1)
         h = L / N
         for i, s in zip(idx, steps):
@@ -227,3 +227,28 @@ def test_growth_map_surrogate_and_auto(qs):
     out2 = torch.empty(n, dtype=torch.float32, device="cuda")
     qs.growth_map(net, table, 1e-2, torch.as_tensor(q2, device="cuda"), qs.GROWTH_AUTO, out2, used2)
     assert np.all(used2.cpu().numpy() == 1)
+
+
+def test_growth_map_solver_beyond_final_time(qs):
+    """A query at tau = 1.5 tau_f is marched for 300 steps of tau_f/200 (not clamped to
+    tau_f), matching the oracle; a negative tau is refused."""
+    import torch
+    nb, g = 0.0113, 137.0
+    tf = 10 * math.sqrt(g / nb)
+    q = np.array([[math.log(nb), math.log(g), 2.0, 3.3, 1.5 * tf],
+                  [math.log(nb), math.log(g), 0.5, 1.2, 0.7 * tf]], np.float32)
+    out = torch.empty(len(q), dtype=torch.float32, device="cuda")
+    qs.growth_map(None, None, 0.0, torch.as_tensor(q, device="cuda"), qs.GROWTH_SOLVER, out)
+    ref = _oracle_solver_answers(q)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= 1e-4
+    # the answer at 1.5 tau_f is not the one at tau_f
+    q2 = q.copy()
+    q2[0, 4] = tf
+    out2 = torch.empty(len(q), dtype=torch.float32, device="cuda")
+    qs.growth_map(None, None, 0.0, torch.as_tensor(q2, device="cuda"), qs.GROWTH_SOLVER, out2)
+    assert out.cpu().numpy()[0] - out2.cpu().numpy()[0] > 1.0
+    bad = q.copy()
+    bad[1, 4] = -1.0
+    with pytest.raises(qs.QSError) as e:
+        qs.growth_map(None, None, 0.0, torch.as_tensor(bad, device="cuda"), qs.GROWTH_SOLVER, out)
+    assert e.value.status == qs.QS_ERR_ARG and "query 1" in str(e.value)
