@@ -345,111 +345,117 @@ def bench_regime(args):
            "algorithmic_bytes_per_launch": 12.0 * cells, "avg_launch_ms": launch * 1e3}, cpu)
 
 
-def bench_surrogate(args):
-    """Growth-map queries: the network trained on the batched uniform-seed sweep against the
-    solver, with the held-out error table that routes queries."""
+def surrogate_vs_solver(n_cmp, cfg=None, log=None):
+    """The growth-map surrogate end to end: trained by the library (qs_surrogate_train, its
+    default configuration unless `cfg`), then n_cmp scattered box queries answered by the
+    solver alone and by AUTO at tolerance 1e-2 (network where the held-out error table
+    trusts it, solver elsewhere), each timed with its own fallback and device
+    synchronization; the errors are AUTO's and the network's against the solver's answers.
+    Returns (the figures, the loaded surrogate)."""
+    import tempfile
     import numpy as np
     import torch
-    from paper_2607_24234_amd import qs, surrogate as S
+    from paper_2607_24234_amd import inputs, qs, surrogate as S
+
+    log = log or (lambda m: None)
+    path = os.path.join(tempfile.mkdtemp(prefix="qs_surrogate_"), "surrogate.bin")
+    t = time.perf_counter()
+    st = S.train(path, cfg)
+    train_wall = time.perf_counter() - t
+    log("trained in %.1f s: %s" % (train_wall, st))
+    sur = S.load(path)
+    q = torch.as_tensor(inputs.growth_queries(n_cmp, 3 + n_cmp), device="cuda")
+    auto = torch.empty(n_cmp, device="cuda")
+    used = torch.zeros(n_cmp, dtype=torch.uint8, device="cuda")
+    sol = torch.empty(n_cmp, device="cuda")
+    net = torch.empty(n_cmp, device="cuda")
+    # warm both paths on a few queries (kernel loads, network weight packing)
+    qs.growth_map(sur.net, sur.table, 1e-2, q[:64], qs.GROWTH_AUTO, auto[:64], used[:64])
+    qs.growth_map(None, None, 0.0, q[:8], qs.GROWTH_SOLVER, sol[:8])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    qs.growth_map(sur.net, sur.table, 1e-2, q, qs.GROWTH_AUTO, auto, used)
+    torch.cuda.synchronize()
+    auto_s = time.perf_counter() - t
+    t = time.perf_counter()
+    qs.growth_map(None, None, 0.0, q, qs.GROWTH_SOLVER, sol)
+    torch.cuda.synchronize()
+    sol_s = time.perf_counter() - t
+    qs.growth_map(sur.net, None, 0.0, q, qs.GROWTH_SURROGATE, net)
+    torch.cuda.synchronize()
+    da = (auto - sol).abs().cpu().numpy().astype(np.float64)
+    dn = (net - sol).abs().cpu().numpy().astype(np.float64)
+    n_sol = int(used.sum().item())
+    log("AUTO %.4f s (%d to the solver), SOLVER %.3f s: %.1fx" % (auto_s, n_sol, sol_s, sol_s / auto_s))
+    fig = {"queries": n_cmp, "tol": 1e-2,
+           "auto_s": auto_s, "solver_s": sol_s, "auto_speedup_vs_solver": sol_s / auto_s,
+           "auto_fraction_to_solver": n_sol / n_cmp,
+           "auto_err_vs_solver": {"rms": float(np.sqrt(np.mean(da * da))), "p99": float(np.percentile(da, 99)),
+                                  "max": float(da.max()), "within_tol": float(np.mean(da <= 1e-2))},
+           "network_err_vs_solver": {"rms": float(np.sqrt(np.mean(dn * dn))), "p99": float(np.percentile(dn, 99)),
+                                     "max": float(dn.max()), "within_tol": float(np.mean(dn <= 1e-2))},
+           "heldout": st, "train_wall_s": train_wall,
+           "queries_recipe": "uniform over log10 n_b in [-3, -1], log10 gamma in [1, 4], k in [0.05, 4], "
+                             "xi in [0, 200], tau in [0, tau_f]"}
+    return fig, sur
+
+
+def bench_surrogate(args):
+    """Growth-map queries: the network's throughput on 1e8 scattered queries (the timed
+    region), and AUTO against the solver on 1e5 of them."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import inputs, qs
 
     def log(msg):
         print("[surrogate] %s" % msg, file=sys.stderr, flush=True)
 
-    t0 = time.perf_counter()
-    X, T = S.examples(S.sweep_instances(seed=0), int(1e7), 1)
-    Xh, Th = S.examples(S.sweep_instances(seed=1), int(2e6), 2)
-    ts = T[:200000].cpu().numpy()
-    net = qs.MLP(max_batch=65536)
-    net.set_params(qs.pack_params(S.initial_params(0, float(ts.mean()), float(ts.std()))))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log("data %.1f s" % (t1 - t0))
-    S.train(net, X, T, epochs=args.epochs, batch=8192, lr=1e-3, log=log)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    log("trained %.1f s" % (t2 - t1))
-    err = S.held_out_errors(net, Xh, Th)
-    table = S.calibrate(net, Xh, Th)
+    cfg = {"epochs": args.epochs} if args.epochs else None
+    fig, sur = surrogate_vs_solver(100000, cfg, log)
     n_q = int(1e8)
     chunk = int(1e7)
-    q = torch.as_tensor(S.query_box(chunk, 3), device="cuda")
+    q = torch.as_tensor(inputs.growth_queries(chunk, 3), device="cuda")
     out = torch.empty(chunk, device="cuda")
-    qs.growth_map(net, table, 1e-2, q[:1024], qs.GROWTH_SURROGATE, out[:1024])
+    stream = sur.net.stream
+    qs.growth_map(sur.net, None, 0.0, q[:1024], qs.GROWTH_SURROGATE, out[:1024], stream=stream)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(n_q // chunk):
-        qs.growth_map(net, table, 1e-2, q, qs.GROWTH_SURROGATE, out)
-    e1.record()
+    with torch.cuda.stream(stream):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n_q // chunk):
+            qs.growth_map(sur.net, None, 0.0, q, qs.GROWTH_SURROGATE, out, stream=stream)
+        e1.record()
     torch.cuda.synchronize()
     sur_s = e0.elapsed_time(e1) * 1e-3
-    log("surrogate %.3f s for %d queries" % (sur_s, n_q))
-    n_s = 64
-    t = time.perf_counter()
-    qs.growth_map(None, None, 0.0, q[:n_s], qs.GROWTH_SOLVER, out[:n_s])
-    torch.cuda.synchronize()
-    sol_s = (time.perf_counter() - t) / n_s
-    log("solver %.3f s per scattered query" % sol_s)
-    n_a = 512
-    used = torch.zeros(n_a, dtype=torch.uint8, device="cuda")
-    auto = torch.empty(n_a, device="cuda")
-    t = time.perf_counter()
-    qs.growth_map(net, table, 1e-2, q[:n_a], qs.GROWTH_AUTO, auto, used)
-    torch.cuda.synchronize()
-    auto_s = (time.perf_counter() - t) / n_a
-    log("auto %.4f s per query" % auto_s)
-    frac = float(used.float().mean().item())
+    log("network %.3f s for %d queries" % (sur_s, n_q))
     qps = n_q / sur_s
-    # dense maps: G at every (xi cell, tau step) of every instance-mode from one solver run
-    # (32 instances of the sweep, snapshots every step, the growth-target pass over all of them)
-    sub = S.sweep_instances(seed=0)[:32]
-    n_st = 200
-    sd = qs.Solver(sub, precision=qs.QS_FP32)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    od = sd.step(n_st, out_every=1, snapshots=True)
-    fd = sd.step(0, snapshots=True)
-    le = torch.cat([od["ln_e"], fd["ln_e"]])
-    lb = torch.cat([od["ln_b"], fd["ln_b"]])
-    del od, fd
-    Gd = torch.empty_like(le)
-    qs.growth_targets(qs.GrowthInstances(sub), le, lb, Gd, stream=sd.stream)
-    torch.cuda.synchronize()
-    dense_s = time.perf_counter() - t
-    dense_vals = Gd.numel()
-    sd.sync_check()
-    del le, lb, Gd
-    sd.close()
-    log("dense maps: %d values in %.3f s" % (dense_vals, dense_s))
     tf = 1.58e6 * qps / 1e12
     cpu = None
     if not args.no_cpu_baseline:
-        # the FP64 oracle network (numpy) on a sample of the same queries, features included
+        # the FP64 oracle (numpy) on a sample of the same queries: inputs, baseline, network
         import oracle.growth as OG
         import oracle.mlp as OM
-        P = qs.unpack_params(net.get_params())
+        P = qs.unpack_params(sur.net.get_params())
         P = [(np.asarray(W, np.float64), np.asarray(b, np.float64)) for W, b in P]
         qh = q[:20000].cpu().numpy().astype(np.float64)
         t = time.perf_counter()
         OM.forward(P, OG.features(qh))
+        OG.baseline(qh)
         dt = time.perf_counter() - t
         cpu = {"value": len(qh) / dt, "unit": "queries/s", "cores": torch.get_num_threads(), "kind": "oracle",
-               "sample": "%d of the same queries through the FP64 oracle network (numpy, features included); "
+               "sample": "%d of the same queries through the FP64 oracle (numpy: inputs, baseline, network); "
                          "%.1f s wall" % (len(qh), dt)}
-    _line(METRIC, qps, "queries/s", args.epochs, 0, sur_s / (n_q // chunk) * 1e3, "bf16",
+    _line(METRIC, qps, "queries/s", n_q // chunk, 1, sur_s / (n_q // chunk) * 1e3, "bf16",
           {"workload": "growth-map queries uniform over log n_b in [-3, -1], log gamma in [1, 4], k in "
-                       "[0.05, 4], xi in [0, 200], tau in [0, tau_f]; network 5-512x4-1 trained on the "
-                       "batched uniform-seed sweep (1e7 examples), held out: a second sweep (2e6)",
-           "queries": n_q, "train_s": t2 - t1, "data_s": t1 - t0, "held_out": err},
+                       "[0.05, 4], xi in [0, 200], tau in [0, tau_f]; network 5-512x4-1 trained by the library "
+                       "on the batched uniform-seed sweep (1e7 examples), held out: a second sweep (4e6)",
+           "queries": n_q},
           {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0,
            "traffic": None, "kernel": "fused network forward (one persistent kernel, activations in LDS; "
                                       "3 bf16 512x512 layers on the matrix cores, fp32 first/last "
                                       "layers), 1.58 MFLOP per query"},
-          cpu,
-          surrogate_s_per_query=sur_s / n_q, solver_s_per_query=sol_s,
-          speedup_vs_solver=sol_s / (sur_s / n_q),
-          dense_map_values_per_s=dense_vals / dense_s, dense_map_solver_over_surrogate=dense_vals / dense_s / qps,
-          auto_tol=1e-2, auto_fraction_to_solver=frac, auto_s_per_query=auto_s)
+          cpu, surrogate=fig, network_s_per_query=sur_s / n_q,
+          network_speedup_vs_solver=(fig["solver_s"] / fig["queries"]) / (sur_s / n_q))
 
 
 def main():
@@ -471,7 +477,10 @@ def main():
                          "surrogate: growth-map queries, network against solver; svea: the envelope-"
                          "approximation variant on the 3D mode set; regime: the E/B regime map of a "
                          "3D snapshot")
-    ap.add_argument("--epochs", type=int, default=40, help="surrogate training epochs")
+    ap.add_argument("--epochs", type=int, default=0,
+                    help="surrogate training epochs (0: the library's default)")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="leave the surrogate-against-solver figures out of the default line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (x3) and exit: "
                          "the reference reading for HBM traffic counters")
@@ -605,6 +614,13 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
+    if not args.no_surrogate:
+        # the metric's second half: the growth-map surrogate against the solver at 1e-2
+        del snap_e, snap_b, max_buf
+        solver.close()
+        torch.cuda.empty_cache()
+        out["surrogate"], _ = surrogate_vs_solver(
+            100000, None, lambda m: print("[surrogate] %s" % m, file=sys.stderr, flush=True))
     print(json.dumps(out), flush=True)
 
 

@@ -9,19 +9,44 @@
  *   tau in [0, tau_f],  tau_f = 10 sqrt(gamma / n_b)
  * (tau_f: ten e-folds of the temporal CFI rate sqrt(n_b/gamma) at large k, Eq. CFI_temporal).
  * Its answer is the growth of the windowed field amplitude over the seed,
- *   G = 1/2 ln( mean over the cells with centres in (xi - 2 pi, xi] of A^2 ) - ln S,
- *   A^2 = |E|^2 + |B|^2,
- * i.e. the log amplitude averaged over one plasma wavelength behind xi (A itself carries
- * the plasma-period ripple of the response).  The solver answer uses the discretization of
- * the batched sweep: an instance of length L (the largest xi of its group of queries) with
- * N = round(128 + 8064 (L - 5)/195) cells (N = max(1, round(128 L/5)) below L = 5),
- * d_tau = tau_f/200, FP32 state; tau is rounded to whole steps (a tau beyond tau_f takes
- * more than 200 steps).  A query sent to the solver must have finite values, gamma > 1,
- * k >= 0, xi >= 0 and 0 <= tau <= 1e4 tau_f (QS_ERR_ARG otherwise, naming the query).
+ *   G = 1/2 ln( sum_i w_i A^2_(j-i) / sum_i w_i ) - ln S,   A^2 = |E|^2 + |B|^2,
+ * at the cell j holding xi, with W = round(4 pi / h) cells (two plasma wavelengths, at least
+ * one), Hann weights w_i = sin^2(pi (i + 1/2)/W) on the cells i = 0..min(j, W-1) behind and
+ * at xi_j: the log amplitude smoothed over the two plasma wavelengths behind xi (A itself
+ * carries the plasma-period ripple of the response; a one-wavelength box average leaves a
+ * ripple wherever the envelope grows across the window, the Hann weights take it to second
+ * order).  The solver's answer: per (n_b, gamma) of the queries one beam of cells of width
+ * h0 = 200/8192 (the finest of the batched sweep, the same for every answer) reaching two cells
+ * beyond the largest xi, d_tau = tau_f/200, FP32 state, the windowed growth of every step's
+ * fields, bilinearly interpolated between the two cell centres around xi and the two steps
+ * around tau.  A query sent to the solver must have finite values, gamma > 1, k >= 0, xi >= 0
+ * and 0 <= tau <= 1e4 tau_f
+ * (QS_ERR_ARG otherwise, naming the query).
  *
- * Network inputs (features) of a query:
- *   x = ( log10 n_b + 2, (log10 gamma - 2.5)/1.5, (k - 2.025)/1.975, xi/100 - 1,
- *         2 tau/tau_f - 1 ),   each in [-1, 1] inside the box.
+ * Box coordinates of a query (its place in the held-out error table), each in [-1, 1] inside
+ * the box:  b = ( log10 n_b + 2, (log10 gamma - 2.5)/1.5, (k - 2.025)/1.975, xi/100 - 1,
+ * 2 tau/tau_f - 1 ).
+ * The surrogate's answer is B(q) + network(x(q)): the network (qs_mlp.h) learns the residual
+ * over a closed-form baseline
+ *   B = 1/2 ln(kappa^2 (1 + 3 k^2)/2) + J( M(ln cosh t, F), O ),
+ *   F = 2 (sqrt(1 + t xi) - 1),  O = 3 ((1 + z)^(1/3) - 1),  z = (3 sqrt(3)/64) t_e^2 xi,
+ *   t = Gamma_CFI tau = sqrt(n_b/gamma) k kappa^(1/2) tau,  kappa = 1/(1+k^2),
+ *   t_e = t (1 + 1/(gamma k)^2)^(1/2),
+ *   J(a, b) = ln(e^a + e^b - 1),  M(a, b) = -ln(e^-a + e^-b - e^-(a+b))
+ * (the wavelength-averaged field of the extended disturbance at tau = 0, then the temporal
+ * CFI growth of Appendix C held back near the front by F, whose exponent tends to the
+ * spatiotemporal CFI one 2 sqrt(t xi) of Eq. CFI_ST, and overtaken deep in the beam by O,
+ * whose exponent tends to the spatiotemporal OTSI one (3 sqrt(3)/4) t_e^(2/3) xi^(1/3) of
+ * Eq. OTSI_ST, at the rate (Gamma_CFI^2 + beta^2)^(1/2) the longitudinal term gives it; for
+ * a, b >= 0, J and M are 0 at a = b = 0, J(a, 0) = a, M(a, 0) = 0, and they tend to max and
+ * min once both are large; F and O start linearly in t xi and z, so B is smooth in the
+ * inputs and is the field level at tau = 0), from the inputs
+ *   x = ( log10 n_b + 2, (log10(gamma k) - 2.1505)/2.4515, 2 log10(k/0.05)/log10(80) - 1,
+ *         2 sqrt(xi/200) - 1, 2 sqrt(t/t_max) - 1 ),  t_max = 40/sqrt(17),
+ * each in [-1, 1] inside the box (k floored at 1e-3 and xi, t at 0 so that any query has
+ * finite inputs).  In these coordinates the continuum answer depends on n_b only through
+ * the discretization: the master equation with tau -> Gamma_CFI tau keeps the one parameter
+ * 1/(gamma k).
  *
  * Device arrays are float32 and caller-owned; calls are ordered on `hip_stream` (NULL =
  * null stream).  Errors: QS_ERR_ARG, QS_ERR_ALLOC, QS_ERR_HIP (qs_last_error has the text).
@@ -41,7 +66,7 @@ extern "C" {
 
 enum { QS_GROWTH_SURROGATE = 0, QS_GROWTH_SOLVER = 1, QS_GROWTH_AUTO = 2 };
 
-/* Bins of the held-out error table: 8 per feature, 8^5 in all, row-major in feature order. */
+/* Bins of the held-out error table: 8 per box coordinate, 8^5 in all, row-major in order. */
 enum { QS_GROWTH_BINS = 32768 };
 
 /* One solver instance whose snapshots feed qs_growth_targets / qs_growth_sample. */
@@ -69,28 +94,31 @@ qs_status qs_growth_targets(const qs_growth_instance *inst, int32_t n_inst, cons
  * Draw n training examples uniformly over all (snapshot, instance, cell, mode) entries of G
  * (entry number floor(u * total), u = top 53 bits of SplitMix64 output i of `seed`, over
  * 2^53).  snap_step: host [n_snap] step index of each snapshot (tau = step * d_tau).
- * X: device [n][5] features; T: device [n] targets.
+ * Q: device [n][5] the entry's query (ln n_b, ln gamma, k, xi_j, tau) in float32;
+ * T: device [n] its target G.
  */
 qs_status qs_growth_sample(const qs_growth_instance *inst, int32_t n_inst, const float *G,
                            int32_t n_snap, const int32_t *snap_step, uint64_t seed, int64_t n,
-                           float *X, float *T, void *hip_stream);
+                           float *Q, float *T, void *hip_stream);
 
-/* Features x (device [n][5]) of queries q (device [n][5]). */
-qs_status qs_growth_features(const float *q, int64_t n, float *x, void *hip_stream);
+/* The network inputs x (device [n][5], or NULL) and the baseline B (device [n], or NULL) of
+ * queries q (device [n][5]); at least one output is required. */
+qs_status qs_growth_features(const float *q, int64_t n, float *x, float *baseline, void *hip_stream);
 
 /*
- * Held-out error table: per bin, an upper estimate of the 99th percentile of
- * |network(x) - t| over the held-out examples in the bin: the upper edge of the histogram
- * bucket that holds it, buckets (1e-4 2^((b-1)/4), 1e-4 2^(b/4)] (b = 1..62; bucket 0 is
- * [0, 1e-4], bucket 63 everything above 1e-4 2^15.5, reported as 3e38).  -1 where a bin
- * holds fewer than 32 examples.  X, T: device held-out examples; table: device
- * [QS_GROWTH_BINS].  Uses the network's stream; allocates an 8 MB histogram.
+ * Held-out error table: per bin of the box coordinates, an upper estimate of the 99th
+ * percentile of |B(q) + network(x(q)) - t| over the held-out examples in the bin: the upper
+ * edge of the histogram bucket that holds it (so within a factor 2^(1/32) above the plain
+ * percentile), buckets (1e-4 2^((b-1)/32), 1e-4 2^(b/32)] (b = 1..542; bucket 0 is [0, 1e-4],
+ * bucket 543 everything above 1e-4 2^(542/32) ~ 12.5, reported as 3e38).  -1 where a bin holds
+ * fewer than 32 examples.  Q, T: device held-out queries [n][5] and targets [n]; table: device
+ * [QS_GROWTH_BINS].  Uses the network's stream; allocates 28 n bytes and a 71 MB histogram.
  */
-qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64_t n, float *table);
+qs_status qs_growth_calibrate(qs_mlp *net, const float *Q, const float *T, int64_t n, float *table);
 
 /*
  * Answer n queries (device q [n][5]) into out (device [n]).
- *   QS_GROWTH_SURROGATE : the network for every query (net required).
+ *   QS_GROWTH_SURROGATE : B(q) + network(x(q)) for every query (net required).
  *   QS_GROWTH_SOLVER    : the solver for every query (net and table ignored; may be NULL).
  *   QS_GROWTH_AUTO      : the network where the query is inside the box and its bin's
  *                         held-out error is in [0, tol]; the solver elsewhere.
@@ -102,7 +130,8 @@ qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64
 qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float *q, int64_t n,
                         int32_t mode, float *out, uint8_t *used_solver, void *hip_stream);
 
-/* Largest query count of one qs_growth_map_noalloc call (its scratch holds their features). */
+/* Largest query count of one qs_growth_map_noalloc call (its scratch holds their inputs and
+ * baselines). */
 #define QS_GROWTH_NOALLOC_MAX 262144
 
 /*
@@ -118,7 +147,7 @@ qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float 
  * 0 <= n <= QS_GROWTH_NOALLOC_MAX (QS_ERR_ARG beyond, with nothing launched).  out, needs_solver:
  * device arrays of n elements; table: device [QS_GROWTH_BINS] or NULL.
  * Work is queued on the network's stream (qs_mlp_create), with no host synchronization.
- * The query features are staged in a fixed 5 MiB device array of the library (one per
+ * The network inputs and baselines are staged in a fixed 6 MiB device array of the library (one per
  * device, held until the process ends, resolved on the first call on that device): calls
  * that overlap on one device, on any streams, race on it and must be serialized by the
  * caller.  The call after a parameter change also repacks the network's inference weights

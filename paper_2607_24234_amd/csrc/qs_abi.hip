@@ -687,7 +687,8 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     a.max_ln_a = out_max_ln_a;
     a.keyed = keyed ? 1 : 0;
     a.update = 1;
-    // snapshot steps run as one-step launches, the steps between them in one launch each
+    // snapshot steps run as one-step launches, the steps between them in one launch each; a
+    // snapshot at every step runs as one launch of snapshot steps
     int s0 = 0;
     while (s0 < n_steps) {
         const bool snap = snaps && (s0 % out_every == 0);
@@ -695,10 +696,13 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
         if (!snap) {
             s1 = n_steps;
             if (snaps) s1 = std::min(n_steps, (s0 / out_every + 1) * out_every);
+        } else if (out_every == 1) {
+            s1 = n_steps;
         }
         a.ln_e = snap ? out_ln_e : nullptr;
         a.ln_b = snap ? out_ln_b : nullptr;
         a.snap_base = snap ? (int64_t)(s0 / out_every) * pl.snap_elems : 0;
+        a.snap_stride = snap ? pl.snap_elems : 0;
         a.max_base = (int64_t)s0 * pl.total_modes;
         a.n_steps = s1 - s0;
         QS_HIP(launch(snap || out_max_ln_a != nullptr), "march kernel");

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -15,15 +16,16 @@
 #include "../../include/qs_growth.h"
 #include "qs_internal.h"
 
-// Scratch of the allocation-free query entry point: the features of at most
-// QS_GROWTH_NOALLOC_MAX queries (5 MiB).  Each device holds its own copy, from the library's
-// load until the process ends; every call on a device shares it.
-static __device__ __align__(256) float scratch[(size_t)QS_GROWTH_NOALLOC_MAX * 5];
+// Scratch of the allocation-free query entry point: the network inputs (5 floats) and the
+// baseline (1 float) of at most QS_GROWTH_NOALLOC_MAX queries (6 MiB).  Each device holds its
+// own copy, from the library's load until the process ends; every call on a device shares it.
+static __device__ __align__(256) float scratch[(size_t)QS_GROWTH_NOALLOC_MAX * 6];
 
 namespace {
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kBinsPerFeature = 8;
+constexpr double kTMax = 9.7014250014533188;  // 40/sqrt(17): Gamma_CFI tau at k = 4, tau = tau_f
 
 qs_status gfail(qs_status st, const std::string &m) {
     qs::set_last_error(m);
@@ -42,26 +44,77 @@ struct GInst {
     int32_t n_xi, n_modes, win;
     int32_t k0;         // first entry of this instance in the k table
     double h, d_tau, ln_s;
-    float f_nb, f_gamma;  // features 0 and 1
-    double tau_f;
+    float ln_nb, ln_gamma;
 };
 
-// cells in one plasma wavelength 2 pi (at least one)
-int window_cells(double h) { return std::max(1, (int)std::lround(kTwoPi / h)); }
+// cells of the window: two plasma wavelengths 4 pi (at least one)
+int window_cells(double h) { return std::max(1, (int)std::lround(4.0 * kPi / h)); }
 
-__host__ __device__ inline float feat_nb(double nb) { return (float)(log10(nb) + 2.0); }
-__host__ __device__ inline float feat_gamma(double g) { return (float)((log10(g) - 2.5) / 1.5); }
-__host__ __device__ inline float feat_k(double k) { return (float)((k - 2.025) / 1.975); }
-__host__ __device__ inline float feat_xi(double xi) { return (float)(xi / 100.0 - 1.0); }
 __host__ __device__ inline double tau_final(double nb, double g) { return 10.0 * sqrt(g / nb); }
+
+// Box coordinates of a query (ln n_b, ln gamma, k, xi, tau): each in [-1, 1] inside the box
+// n_b in [1e-3, 1e-1], gamma in [10, 1e4], k in [0.05, 4], xi in [0, 200], tau in [0, tau_f].
+__device__ inline void box_coords(const float *q, float b[5]) {
+    const double nb = exp((double)q[0]), g = exp((double)q[1]);
+    b[0] = (float)((double)q[0] * 0.43429448190325182765 + 2.0);
+    b[1] = (float)(((double)q[1] * 0.43429448190325182765 - 2.5) / 1.5);
+    b[2] = (float)(((double)q[2] - 2.025) / 1.975);
+    b[3] = (float)((double)q[3] / 100.0 - 1.0);
+    b[4] = (float)(2.0 * (double)q[4] / tau_final(nb, g) - 1.0);
+}
+
+// For a, b >= 0: J(a, b) = ln(e^a + e^b - 1) and M(a, b) = -ln(e^-a + e^-b - e^-(a+b)), both
+// 0 at a = b = 0, with J(a, 0) = a and M(a, 0) = 0, tending to max(a, b) and min(a, b) once both
+// are large.  With hi = max, lo = min, d = hi - lo: e^a + e^b - 1 = e^hi (1 + e^-d - e^-hi) and
+// e^-a + e^-b - e^-(a+b) = e^-lo (1 + e^-d - e^-hi), where 1 + e^-d - e^-hi >= 1.
+__device__ inline double join_rest(double a, double b) { return log1p(exp(-fabs(a - b)) - exp(-fmax(a, b))); }
+__device__ inline double join_up(double a, double b) { return fmax(a, b) + join_rest(a, b); }
+__device__ inline double join_down(double a, double b) { return fmin(a, b) - join_rest(a, b); }
+
+// Network inputs and baseline of a query.  Inputs: log10 n_b + 2, (log10(gamma k) - 2.1505)/
+// 2.4515, 2 log10(k/0.05)/log10(80) - 1, 2 sqrt(xi/200) - 1, 2 sqrt(t/t_max) - 1 with
+// t = Gamma_CFI tau = sqrt(n_b/gamma) k/sqrt(1+k^2) tau.  Baseline: the wavelength-averaged
+// field of the extended disturbance at tau = 0, 1/2 ln(kappa^2 (1+3k^2)/2), plus the growth
+// J(M(C, F), O): the temporal CFI growth C = ln cosh t (Appendix C) held back near the front by
+// F = 2 (sqrt(1 + t xi) - 1), whose exponent tends to the spatiotemporal CFI one 2 sqrt(t xi)
+// (Eq. CFI_ST), and overtaken deep in the beam by O = 3 ((1 + z)^(1/3) - 1),
+// z = (3 sqrt(3)/64) t_e^2 xi, whose exponent tends to the spatiotemporal OTSI one
+// (3 sqrt(3)/4) t_e^(2/3) xi^(1/3) (Eq. OTSI_ST) at t_e = t (1 + 1/(gamma k)^2)^(1/2).  F and O
+// start linearly in t xi and z, so the baseline is smooth in the inputs and equals the field
+// level at tau = 0.  k is floored at 1e-3 and xi, t at 0, so every query has finite inputs.
+__device__ inline void net_inputs(const float *q, float x[5], float *base) {
+    const double lnb = (double)q[0], lng = (double)q[1];
+    const double k = fmax((double)q[2], 1e-3), xi = fmax((double)q[3], 0.0), tau = (double)q[4];
+    const double kap = 1.0 / (1.0 + k * k);
+    const double t = fmax(exp(0.5 * (lnb - lng)) * k * sqrt(kap) * tau, 0.0);
+    const double l10 = 0.43429448190325182765;  // 1/ln 10
+    x[0] = (float)(lnb * l10 + 2.0);
+    x[1] = (float)(((lng + log(k)) * l10 - 2.1505) / 2.4515);
+    x[2] = (float)(2.0 * log(k / 0.05) / log(80.0) - 1.0);
+    x[3] = (float)(2.0 * sqrt(xi / 200.0) - 1.0);
+    x[4] = (float)(2.0 * sqrt(t / kTMax) - 1.0);
+    const double lcosh = t + log1p(exp(-2.0 * t)) - 0.69314718055994530942;
+    // behind the front the longitudinal term adds beta^2 = Gamma_CFI^2/(gamma k)^2 to
+    // Gamma_CFI^2 (the Laplace form of the transverse master equation with its gamma^-2 term)
+    const double gk = exp(lng) * k;
+    const double z = 0.08118988160479113 * t * t * (1.0 + 1.0 / (gk * gk)) * xi;  // 3 sqrt(3)/64
+    const double otsi = 3.0 * (cbrt(1.0 + z) - 1.0);
+    const double front = 2.0 * (sqrt(1.0 + t * xi) - 1.0);
+    *base = (float)(0.5 * log(kap * kap * (1.0 + 3.0 * k * k) * 0.5) + join_up(join_down(lcosh, front), otsi));
+}
 
 // A^2 / S^2 of one entry from ln|E| and ln|B| (exp of -inf is 0)
 __device__ inline double a2_rel(float le, float lb, double ln_s) {
     return exp(2.0 * ((double)le - ln_s)) + exp(2.0 * ((double)lb - ln_s));
 }
 
-// One thread per (snapshot, column): sliding window over the cells, recomputed exactly at
-// every multiple of the window length so that rounding does not accumulate.
+// One thread per (snapshot, column).  Hann-weighted window of W cells ending at cell j:
+// with zeta = e^(2 pi i/W) and w_i = sin^2(pi (i + 1/2)/W) = 1/2 - 1/2 Re(e^(i pi/W) zeta^i),
+//   sum_i w_i a_(j-i) = S0/2 - Re(e^(i pi/W) T)/2,  S0 = sum_i a_(j-i),  T = sum_i a_(j-i) zeta^i,
+// both advanced by one cell per step (T <- a_(j+1) + zeta T - a_(j+1-W), as zeta^W = 1) and
+// recomputed directly every kResum cells so that no rounding accumulates; the weights present
+// in a truncated window (the first W-1 cells) sum to n/2 - Re(e^(i pi/W) (1 - zeta^n)/(1 - zeta))/2.
+constexpr int kResum = 64;
 __global__ void __launch_bounds__(256) targets_kernel(const GInst *__restrict__ inst, int n_inst,
                                                       const float *__restrict__ le, const float *__restrict__ lb,
                                                       int64_t snap_elems, int64_t cols, int n_snap,
@@ -78,17 +131,50 @@ __global__ void __launch_bounds__(256) targets_kernel(const GInst *__restrict__ 
     const GInst I = inst[lo];
     const int m = (int)(c - I.col0);
     const int64_t base = (int64_t)t * snap_elems + I.off + m;
-    const int M = I.n_modes, W = I.win;
-    double sum = 0.0;
+    const int64_t M = I.n_modes;
+    const int W = I.win;
+    auto a_at = [&](int j) { return a2_rel(le[base + j * M], lb[base + j * M], I.ln_s); };
+    double zr = 1.0, zi = 0.0, hr = 1.0, hi2 = 0.0;  // zeta, e^(i pi/W)
+    if (W > 1) {
+        sincos(2.0 * kPi / W, &zi, &zr);
+        sincos(kPi / W, &hi2, &hr);
+    }
+    double s0 = 0.0, tr = 0.0, ti = 0.0;
     for (int j = 0; j < I.n_xi; ++j) {
-        if (j % W == 0 && j > 0) {  // exact re-summation of the window ending at j - 1
-            sum = 0.0;
-            for (int i = j - W; i < j; ++i) sum += a2_rel(le[base + (int64_t)i * M], lb[base + (int64_t)i * M], I.ln_s);
+        const int n = min(j + 1, W);
+        const double aj = a_at(j);
+        if (j % kResum == 0) {  // direct sums over the window
+            s0 = 0.0; tr = 0.0; ti = 0.0;
+            double pr = 1.0, pi = 0.0;  // zeta^i
+            for (int i = 0; i < n; ++i) {
+                const double v = (i == 0) ? aj : a_at(j - i);
+                s0 += v; tr += v * pr; ti += v * pi;
+                const double nr = pr * zr - pi * zi;
+                pi = pr * zi + pi * zr;
+                pr = nr;
+            }
+        } else {
+            const double old = (j >= W) ? a_at(j - W) : 0.0;
+            s0 += aj - old;
+            const double nr = aj + zr * tr - zi * ti - old;
+            ti = zr * ti + zi * tr;
+            tr = nr;
         }
-        sum += a2_rel(le[base + (int64_t)j * M], lb[base + (int64_t)j * M], I.ln_s);
-        if (j >= W) sum -= a2_rel(le[base + (int64_t)(j - W) * M], lb[base + (int64_t)(j - W) * M], I.ln_s);
-        const int cnt = min(j + 1, W);
-        G[base + (int64_t)j * M] = (float)(0.5 * log(fmax(sum, 0.0) / cnt));
+        double num, den;
+        if (W == 1) {
+            num = aj;
+            den = 1.0;
+        } else {
+            num = 0.5 * s0 - 0.5 * (hr * tr - hi2 * ti);
+            // sum_{i<n} zeta^i = (1 - zeta^n)/(1 - zeta)
+            double snr, cnr;
+            sincos(2.0 * kPi * n / W, &snr, &cnr);
+            const double ar = 1.0 - cnr, ai = -snr, br = 1.0 - zr, bi = -zi;
+            const double bb = br * br + bi * bi;
+            const double gr = (ar * br + ai * bi) / bb, gi = (ai * br - ar * bi) / bb;
+            den = 0.5 * n - 0.5 * (hr * gr - hi2 * gi);
+        }
+        G[base + (int64_t)j * M] = (float)(0.5 * log(fmax(num, 0.0) / den));
     }
 }
 
@@ -99,10 +185,12 @@ __device__ inline uint64_t sm64(uint64_t seed, uint64_t i) {
     return z ^ (z >> 31);
 }
 
+// Draw n examples uniformly over all (snapshot, instance, cell, mode) entries of G: the query
+// (ln n_b, ln gamma, k, xi_j, tau) of the entry and its target.
 __global__ void __launch_bounds__(256) sample_kernel(const GInst *__restrict__ inst, int n_inst,
                                                      const double *__restrict__ kt, const float *__restrict__ G,
                                                      int64_t snap_elems, const int32_t *__restrict__ steps, int n_snap,
-                                                     uint64_t seed, int64_t n, float *__restrict__ X,
+                                                     uint64_t seed, int64_t n, float *__restrict__ Q,
                                                      float *__restrict__ T) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -117,37 +205,36 @@ __global__ void __launch_bounds__(256) sample_kernel(const GInst *__restrict__ i
         if (inst[mid].off <= r) lo = mid; else hi = mid - 1;
     }
     const GInst I = inst[lo];
-    const int64_t q = r - I.off;
-    const int j = (int)(q / I.n_modes), m = (int)(q % I.n_modes);
-    const double xi = (j + 0.5) * I.h;
-    const double tau = steps[t] * I.d_tau;
-    X[5 * i + 0] = I.f_nb;
-    X[5 * i + 1] = I.f_gamma;
-    X[5 * i + 2] = feat_k(kt[I.k0 + m]);
-    X[5 * i + 3] = feat_xi(xi);
-    X[5 * i + 4] = (float)(2.0 * tau / I.tau_f - 1.0);
+    const int64_t qq = r - I.off;
+    const int j = (int)(qq / I.n_modes), m = (int)(qq % I.n_modes);
+    Q[5 * i + 0] = I.ln_nb;
+    Q[5 * i + 1] = I.ln_gamma;
+    Q[5 * i + 2] = (float)kt[I.k0 + m];
+    Q[5 * i + 3] = (float)((j + 0.5) * I.h);
+    Q[5 * i + 4] = (float)(steps[t] * I.d_tau);
     T[i] = G[e];
 }
 
-__global__ void __launch_bounds__(256) features_kernel(const float *__restrict__ q, int64_t n, float *__restrict__ x) {
+// x [n][5] network inputs and base [n] baseline (either may be null)
+__global__ void __launch_bounds__(256) features_kernel(const float *__restrict__ q, int64_t n, float *__restrict__ x,
+                                                       float *__restrict__ base) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double nb = exp((double)q[5 * i]), g = exp((double)q[5 * i + 1]);
-    x[5 * i + 0] = feat_nb(nb);
-    x[5 * i + 1] = feat_gamma(g);
-    x[5 * i + 2] = feat_k(q[5 * i + 2]);
-    x[5 * i + 3] = feat_xi(q[5 * i + 3]);
-    x[5 * i + 4] = (float)(2.0 * (double)q[5 * i + 4] / tau_final(nb, g) - 1.0);
+    float xv[5], bv;
+    net_inputs(q + 5 * i, xv, &bv);
+    if (x)
+        for (int d = 0; d < 5; ++d) x[5 * i + d] = xv[d];
+    if (base) base[i] = bv;
 }
 
-__device__ inline int bin_of(const float *x) {
-    int b = 0;
+__device__ inline int bin_of(const float *b) {
+    int out = 0;
     for (int d = 0; d < 5; ++d) {
-        int c = (int)floorf((x[d] + 1.0f) * (kBinsPerFeature / 2));
+        int c = (int)floorf((b[d] + 1.0f) * (kBinsPerFeature / 2));
         c = min(kBinsPerFeature - 1, max(0, c));
-        b = b * kBinsPerFeature + c;
+        out = out * kBinsPerFeature + c;
     }
-    return b;
+    return out;
 }
 
 __global__ void __launch_bounds__(256) fill_kernel(float *p, int64_t n, float v) {
@@ -156,25 +243,31 @@ __global__ void __launch_bounds__(256) fill_kernel(float *p, int64_t n, float v)
 }
 
 // Held-out error histogram: bucket 0 holds |y - t| <= e0, bucket b >= 1 the range
-// (e0 2^((b-1)/4), e0 2^(b/4)], the last bucket everything above (and non-finite errors).
-constexpr int kBuckets = 64;
+// (e0 2^((b-1)/32), e0 2^(b/32)], the last bucket everything above e0 2^(542/32) ~ 12.5 (and
+// non-finite errors): a reported percentile is at most 2^(1/32) (2.2 %) above the exact one.
+constexpr int kPerOctave = 32;
+constexpr int kBuckets = 544;
 constexpr float kE0 = 1e-4f;
 constexpr int kMinCount = 32;  // fewer held-out examples in a bin: no estimate
 
 __host__ __device__ inline float bucket_edge(int b) {
-    return b >= kBuckets - 1 ? 3.0e38f : kE0 * exp2f(0.25f * (float)b);
+    return b >= kBuckets - 1 ? 3.0e38f : kE0 * exp2f((float)b / kPerOctave);
 }
 
-__global__ void __launch_bounds__(256) hist_kernel(const float *__restrict__ x, const float *__restrict__ y,
-                                                   const float *__restrict__ t, int64_t n, uint32_t *__restrict__ cnt) {
+// error of the answer y + base against the target t, binned by the query's box coordinates
+__global__ void __launch_bounds__(256) hist_kernel(const float *__restrict__ q, const float *__restrict__ y,
+                                                   const float *__restrict__ base, const float *__restrict__ t,
+                                                   int64_t n, uint32_t *__restrict__ cnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float e = fabsf(y[i] - t[i]);
+    const float e = fabsf(y[i] + base[i] - t[i]);
     int b;
     if (!(e <= 3.0e38f)) b = kBuckets - 1;
     else if (e <= kE0) b = 0;
-    else b = min(kBuckets - 1, 1 + (int)floorf(4.0f * log2f(e / kE0)));
-    atomicAdd(cnt + (int64_t)bin_of(x + 5 * i) * kBuckets + b, 1u);
+    else b = min(kBuckets - 1, 1 + (int)floorf((float)kPerOctave * log2f(e / kE0)));
+    float bc[5];
+    box_coords(q + 5 * i, bc);
+    atomicAdd(cnt + (int64_t)bin_of(bc) * kBuckets + b, 1u);
 }
 
 // table[bin] = upper edge of the bucket holding the 99th percentile, -1 below kMinCount
@@ -195,16 +288,22 @@ __global__ void __launch_bounds__(256) p99_kernel(const uint32_t *__restrict__ c
     table[bin] = bucket_edge(min(b, kBuckets - 1));
 }
 
-// 1 where the solver must answer: outside the box, no held-out data in the bin, or the
-// bin's held-out error above tol
-__global__ void __launch_bounds__(256) route_kernel(const float *__restrict__ x, int64_t n,
-                                                    const float *__restrict__ table, float tol,
-                                                    uint8_t *__restrict__ flag) {
+// out += base (the network's residual plus the baseline); with flag != null also the routing
+// flag: 1 where the solver must answer (outside the box, no held-out data in the bin, or the
+// bin's held-out error above tol)
+__global__ void __launch_bounds__(256) finish_kernel(const float *__restrict__ q, int64_t n,
+                                                     const float *__restrict__ base, float *__restrict__ out,
+                                                     const float *__restrict__ table, float tol,
+                                                     uint8_t *__restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    out[i] += base[i];
+    if (!flag) return;
+    float b[5];
+    box_coords(q + 5 * i, b);
     bool inside = true;
-    for (int d = 0; d < 5; ++d) inside = inside && x[5 * i + d] >= -1.0f && x[5 * i + d] <= 1.0f;
-    const float e = table ? table[bin_of(x + 5 * i)] : -1.0f;
+    for (int d = 0; d < 5; ++d) inside = inside && b[d] >= -1.0f && b[d] <= 1.0f;
+    const float e = table ? table[bin_of(b)] : -1.0f;
     flag[i] = (inside && e >= 0.0f && e <= tol) ? 0 : 1;
 }
 
@@ -267,9 +366,8 @@ qs_status upload_insts(const qs_growth_instance *inst, int32_t n_inst, hipStream
         d.k0 = (int32_t)kt.size();
         d.d_tau = g.d_tau;
         d.ln_s = std::log(g.seed_amp);
-        d.f_nb = feat_nb(g.nb_over_np);
-        d.f_gamma = feat_gamma(g.gamma_b);
-        d.tau_f = tau_final(g.nb_over_np, g.gamma_b);
+        d.ln_nb = (float)std::log(g.nb_over_np);
+        d.ln_gamma = (float)std::log(g.gamma_b);
         for (int m = 0; m < g.n_modes; ++m) kt.push_back(g.k[m]);
         off += (int64_t)g.n_xi * g.n_modes;
         col += g.n_modes;
@@ -286,21 +384,73 @@ qs_status upload_insts(const qs_growth_instance *inst, int32_t n_inst, hipStream
     return QS_OK;
 }
 
-// cells of the batched sweep's discretization for a beam of length L
-int cells_for(double L) {
-    if (L >= 5.0) return (int)std::lround(128.0 + 8064.0 * (L - 5.0) / 195.0);
-    return std::max(1, (int)std::lround(128.0 * L / 5.0));
-}
+// The growth map's cell width: the finest of the batched sweep, 200/8192, for every beam, so
+// that an answer depends on the query alone and not on the length of the beam it comes from.
+constexpr double kCellWidth = 200.0 / 8192.0;
+
+// cells of width kCellWidth that cover xi in [0, L]
+int cells_for(double L) { return std::max(1, (int)std::ceil(L / kCellWidth - 1e-9)); }
 
 // Solver answers for the queries hq[5 i..] at positions sel; values returned in vals.
 struct Group {
-    double nb, g, L = 0.0;
+    double nb, g, L = 0.0, tau_max = 0.0;
     std::vector<double> ks;
     std::vector<int64_t> members;  // positions in the selection
 };
 
+// One solver-answered query: the bilinear interpolation of the discrete windowed growth
+// between the two cell centres around its xi and the two steps around its tau.
+struct QueryRec {
+    int64_t base;     // snapshot element of (instance, mode) at cell 0 of step 0
+    int32_t stride;   // the instance's mode count (elements between cells)
+    int32_t win;      // window cells
+    int32_t j0, s0;   // first cell and first step
+    int32_t dst;      // answer slot
+    int32_t pad;
+    double fx, ft;    // interpolation weights of cell j0 + 1 and step s0 + 1
+    double ln_s;
+};
+
+// The windowed growth at one cell of one snapshot column by the direct Hann-weighted sum over
+// its window (the definition, in FP64; the full target pass over every cell is not needed
+// for a few queries).
+__device__ inline double growth_at(const float *__restrict__ le, const float *__restrict__ lb, int64_t base,
+                                   int32_t stride, int j, int win, double ln_s) {
+    const int cnt = min(j + 1, win);
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < cnt; ++i) {
+        const double s = sin(kPi * (i + 0.5) / win);
+        const double w = s * s;
+        const int64_t e = base + (int64_t)(j - i) * stride;
+        num += w * a2_rel(le[e], lb[e], ln_s);
+        den += w;
+    }
+    return 0.5 * log(num / den);
+}
+
+__global__ void __launch_bounds__(256) answer_kernel(const QueryRec *__restrict__ recs, int n,
+                                                     const float *__restrict__ le, const float *__restrict__ lb,
+                                                     int64_t snap_elems, float *__restrict__ vals) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const QueryRec Q = recs[r];
+    double acc = 0.0;
+    for (int c = 0; c < 2; ++c) {
+        const double wt = c == 0 ? 1.0 - Q.ft : Q.ft;
+        if (wt == 0.0) continue;
+        const int64_t row = Q.base + (int64_t)(Q.s0 + c) * snap_elems;
+        for (int d = 0; d < 2; ++d) {
+            const double w = wt * (d == 0 ? 1.0 - Q.fx : Q.fx);
+            if (w == 0.0) continue;
+            acc += w * growth_at(le, lb, row, Q.stride, Q.j0 + d, Q.win, Q.ln_s);
+        }
+    }
+    vals[Q.dst] = (float)acc;
+}
+
 // Solver answers for the selected queries of groups [g0, g1): one batched context, one
-// instance per group, marched to each distinct step in turn.
+// instance per group, marched in one launch to the last step any query needs with the fields
+// written at every step, then every answer from those snapshots in one kernel.
 qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> &sel,
                        const std::vector<Group> &groups, size_t g0, size_t g1, hipStream_t s,
                        std::vector<float> *vals) {
@@ -310,7 +460,8 @@ qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> 
     std::vector<qs_params> params(ng);
     std::vector<double> qv(1, -1.0), mv(1, 1.0);
     std::vector<std::vector<double>> nbv(ng);
-    std::vector<qs_growth_instance> gis(ng);
+    std::vector<int64_t> goff(ng);
+    int64_t snap = 0;
     for (size_t i = 0; i < ng; ++i) {
         const Group &G = groups[g0 + i];
         nbv[i] = {G.nb};
@@ -321,7 +472,7 @@ qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> 
         p.m = mv.data();
         p.nb_over_np = nbv[i].data();
         p.gamma_b = G.g;
-        p.length = G.L;
+        p.length = cells_for(G.L) * kCellWidth;
         p.profile = QS_PROFILE_FLATTOP;
         p.geometry = QS_GEOM_SPECTRAL;
         p.n_modes = (int64_t)G.ks.size();
@@ -331,59 +482,68 @@ qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> 
         p.precision = QS_FP32;
         p.seed_kind = QS_SEED_UNIFORM;
         p.seed_amp = S;
-        gis[i] = qs_growth_instance{G.nb, G.g, G.L, p.d_tau, S, p.n_xi, (int32_t)p.n_modes, p.kx};
+        goff[i] = snap;
+        snap += (int64_t)p.n_xi * p.n_modes;
     }
+    std::vector<QueryRec> recs;
+    std::vector<int64_t> slot_pos;  // answer slot -> position in sel
+    int last_step = 0;
+    for (size_t i = 0; i < ng; ++i) {
+        const qs_params &p = params[i];
+        const double h = p.length / p.n_xi;
+        const auto &ks = groups[g0 + i].ks;
+        for (int64_t pos : groups[g0 + i].members) {
+            const float *q = &hq[5 * (size_t)sel[pos]];
+            QueryRec r{};
+            r.base = goff[i] + (int64_t)(std::lower_bound(ks.begin(), ks.end(), (double)q[2]) - ks.begin());
+            r.stride = (int32_t)p.n_modes;
+            r.win = window_cells(h);
+            // cells: centres (j + 1/2) h around xi (clamped to the first and last cell)
+            const double xc = (double)q[3] / h - 0.5;
+            r.j0 = (int)std::floor(xc);
+            r.fx = xc - r.j0;
+            if (r.j0 < 0) { r.j0 = 0; r.fx = 0.0; }
+            if (r.j0 >= p.n_xi - 1) { r.j0 = p.n_xi - 1; r.fx = 0.0; }
+            const double ts = (double)q[4] / p.d_tau;  // tau >= 0 (checked)
+            r.s0 = (int)std::floor(ts);
+            r.ft = ts - r.s0;
+            r.ln_s = std::log(S);
+            r.dst = (int32_t)slot_pos.size();
+            slot_pos.push_back(pos);
+            last_step = std::max(last_step, r.s0 + (r.ft > 0.0 ? 1 : 0));
+            recs.push_back(r);
+        }
+    }
+    const int n_snap = last_step + 1;  // the states at steps 0 .. last_step
     qs_ctx *ctx = nullptr;
     qs_status st = qs_init(params.data(), (int32_t)params.size(), s, nullptr, 0, &ctx);
     if (st != QS_OK) return st;
-    int64_t snap = 0;
-    for (const qs_growth_instance &g : gis) snap += (int64_t)g.n_xi * g.n_modes;
-    float *buf = nullptr;
-    if (hipMalloc(&buf, (size_t)snap * 3 * sizeof(float)) != hipSuccess) {
+    char *buf = nullptr;
+    const size_t snap_bytes = (((size_t)snap * n_snap * 2 * sizeof(float) + 255) / 256) * 256;
+    const size_t rec_bytes = recs.size() * sizeof(QueryRec);
+    if (hipMalloc(&buf, snap_bytes + rec_bytes + slot_pos.size() * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
         qs_free(ctx);
         return gfail(QS_ERR_ALLOC, "growth map: snapshot buffers");
     }
-    float *le = buf, *lb = buf + snap, *Gd = buf + 2 * snap;
-    // queries by step
-    std::vector<std::pair<int, int64_t>> order;  // (step, position in sel)
-    std::map<int64_t, int> gof;  // position in sel -> local group
-    for (size_t i = 0; i < ng; ++i)
-        for (int64_t p : groups[g0 + i].members) {
-            gof[p] = (int)i;
-            const float *q = &hq[5 * (size_t)sel[p]];
-            const int stp = (int)std::lround((double)q[4] / params[i].d_tau);  // tau >= 0 (checked)
-            order.push_back({stp, p});
-        }
-    std::sort(order.begin(), order.end());
-    std::vector<int64_t> goff(ng);
-    {
-        int64_t o = 0;
-        for (size_t i = 0; i < ng; ++i) { goff[i] = o; o += (int64_t)gis[i].n_xi * gis[i].n_modes; }
+    float *le = reinterpret_cast<float *>(buf), *lb = le + (size_t)snap * n_snap;
+    QueryRec *d_recs = reinterpret_cast<QueryRec *>(buf + snap_bytes);
+    float *d_vals = reinterpret_cast<float *>(buf + snap_bytes + rec_bytes);
+    if (hipMemcpyAsync(d_recs, recs.data(), rec_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        st = gfail(QS_ERR_HIP, "growth map: copy query records");
+    if (st == QS_OK) st = n_snap > 1 ? qs_step_tau(ctx, n_snap, 1, le, lb, nullptr) : qs_step_tau(ctx, 0, 1, le, lb, nullptr);
+    if (st == QS_OK) {
+        hipLaunchKernelGGL(answer_kernel, dim3(blocks_for((int64_t)recs.size())), dim3(256), 0, s, d_recs,
+                           (int)recs.size(), le, lb, snap, d_vals);
+        if (hipGetLastError() != hipSuccess) st = gfail(QS_ERR_HIP, "growth map: answer kernel");
     }
-    std::vector<float> hG(snap);
-    int done = 0;
-    size_t a = 0;
-    while (a < order.size() && st == QS_OK) {
-        const int stp = order[a].first;
-        if (stp > done) st = qs_step_tau(ctx, stp - done, 1, nullptr, nullptr, nullptr);
-        done = stp;
-        if (st == QS_OK) st = qs_step_tau(ctx, 0, 1, le, lb, nullptr);
-        if (st == QS_OK) st = qs_growth_targets(gis.data(), (int32_t)gis.size(), le, lb, 1, Gd, s);
-        if (st == QS_OK && hipMemcpyAsync(hG.data(), Gd, (size_t)snap * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
-            st = gfail(QS_ERR_HIP, "growth map: copy targets");
-        if (st == QS_OK && hipStreamSynchronize(s) != hipSuccess) st = gfail(QS_ERR_HIP, "growth map: synchronize");
-        for (; st == QS_OK && a < order.size() && order[a].first == stp; ++a) {
-            const int64_t p = order[a].second;
-            const int i = gof.at(p);
-            const float *q = &hq[5 * (size_t)sel[p]];
-            const double h = gis[i].length / gis[i].n_xi;
-            const int j = std::min(gis[i].n_xi - 1, std::max(0, (int)std::ceil((double)q[3] / h) - 1));
-            const auto &ks = groups[g0 + i].ks;
-            const int m = (int)(std::lower_bound(ks.begin(), ks.end(), (double)q[2]) - ks.begin());
-            (*vals)[p] = hG[goff[i] + (int64_t)j * gis[i].n_modes + m];
-        }
-    }
+    std::vector<float> hv(slot_pos.size());
+    if (st == QS_OK && (hipMemcpyAsync(hv.data(), d_vals, hv.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+        st = gfail(QS_ERR_HIP, "growth map: copy answers");
     if (st == QS_OK) st = qs_sync_check(ctx);
+    if (st == QS_OK)
+        for (size_t slot = 0; slot < hv.size(); ++slot) (*vals)[slot_pos[slot]] = hv[slot];
     (void)hipFree(buf);
     qs_free(ctx);
     return st;
@@ -423,6 +583,7 @@ qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t>
         }
         Group &G = groups[id];
         G.L = std::max(G.L, (double)q[3]);
+        G.tau_max = std::max(G.tau_max, (double)q[4]);
         G.ks.push_back((double)q[2]);
         G.members.push_back((int64_t)p);
     }
@@ -430,18 +591,29 @@ qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t>
     for (Group &G : groups) {
         std::sort(G.ks.begin(), G.ks.end());
         G.ks.erase(std::unique(G.ks.begin(), G.ks.end()), G.ks.end());
-        G.L = std::max(G.L, 1e-3);
+        // two cells beyond the largest xi: the cell centre behind each query is in the beam and
+        // is not the last cell (the beam's rear face carries no current, which changes the last
+        // cell's charge -- and only that cell's, the march being causal)
+        G.L = G.L + 2.0 * kCellWidth;
     }
-    // run the groups in chunks whose solver state stays within a fixed budget
-    const size_t kBudget = size_t(8) << 30;  // bytes of FP32 state per chunk
+    // run the groups in chunks whose solver state and snapshots (every step up to the last one
+    // any of the chunk's queries needs) stay within a fixed budget
+    const size_t kBudget = size_t(8) << 30;
     size_t g0 = 0;
     while (g0 < groups.size()) {
-        size_t g1 = g0, bytes = 0;
+        size_t g1 = g0, state = 0, cells = 0;
+        int steps = 1;
         while (g1 < groups.size()) {
-            const size_t blocks = (groups[g1].ks.size() + 31) / 32;
-            const size_t b = blocks * (size_t)cells_for(groups[g1].L) * 3 * 64 * 4;
-            if (g1 > g0 && (bytes + b > kBudget || g1 - g0 >= 65536)) break;
-            bytes += b;
+            const Group &G = groups[g1];
+            const size_t c = (size_t)cells_for(G.L);
+            const size_t blocks = (G.ks.size() + 31) / 32;
+            const int st_g = (int)std::ceil(G.tau_max / (tau_final(G.nb, G.g) / 200.0)) + 2;
+            const size_t bytes = (state + blocks * c * 3 * 64 * 4) +
+                                 (cells + c * G.ks.size()) * 8 * (size_t)std::max(steps, st_g);
+            if (g1 > g0 && (bytes > kBudget || g1 - g0 >= 65536)) break;
+            state += blocks * c * 3 * 64 * 4;
+            cells += c * G.ks.size();
+            steps = std::max(steps, st_g);
             ++g1;
         }
         qs_status st = solve_groups(hq, sel, groups, g0, g1, s, vals);
@@ -475,11 +647,11 @@ qs_status qs_growth_targets(const qs_growth_instance *inst, int32_t n_inst, cons
 }
 
 qs_status qs_growth_sample(const qs_growth_instance *inst, int32_t n_inst, const float *G, int32_t n_snap,
-                           const int32_t *snap_step, uint64_t seed, int64_t n, float *X, float *T, void *hip_stream) {
+                           const int32_t *snap_step, uint64_t seed, int64_t n, float *Q, float *T, void *hip_stream) {
     qs_status st = check_insts(inst, n_inst);
     if (st != QS_OK) return st;
-    if (!G || !snap_step || n_snap < 1 || n < 0 || (n > 0 && (!X || !T)))
-        return gfail(QS_ERR_ARG, "G, snap_step, n_snap >= 1, n >= 0, X and T are required");
+    if (!G || !snap_step || n_snap < 1 || n < 0 || (n > 0 && (!Q || !T)))
+        return gfail(QS_ERR_ARG, "G, snap_step, n_snap >= 1, n >= 0, Q and T are required");
     if (n == 0) return QS_OK;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     GInst *d_inst = nullptr;
@@ -492,7 +664,7 @@ qs_status qs_growth_sample(const qs_growth_instance *inst, int32_t n_inst, const
     if (e == hipSuccess) e = hipMemcpyAsync(d_steps, snap_step, n_snap * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n)), dim3(256), 0, s, d_inst, n_inst, d_k, G, snap, d_steps,
-                           n_snap, seed, n, X, T);
+                           n_snap, seed, n, Q, T);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -503,35 +675,38 @@ qs_status qs_growth_sample(const qs_growth_instance *inst, int32_t n_inst, const
     return QS_OK;
 }
 
-qs_status qs_growth_features(const float *q, int64_t n, float *x, void *hip_stream) {
-    if (n < 0 || (n > 0 && (!q || !x))) return gfail(QS_ERR_ARG, "q and x are required");
+qs_status qs_growth_features(const float *q, int64_t n, float *x, float *baseline, void *hip_stream) {
+    if (n < 0 || (n > 0 && (!q || (!x && !baseline)))) return gfail(QS_ERR_ARG, "q and x or baseline are required");
     if (n == 0) return QS_OK;
-    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), q, n, x);
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), q, n,
+                       x, baseline);
     G_HIP(hipGetLastError(), "features kernel");
     return QS_OK;
 }
 
-qs_status qs_growth_calibrate(qs_mlp *net, const float *X, const float *T, int64_t n, float *table) {
-    if (!net || !table || n < 0 || (n > 0 && (!X || !T))) return gfail(QS_ERR_ARG, "net, X, T and table are required");
+qs_status qs_growth_calibrate(qs_mlp *net, const float *Q, const float *T, int64_t n, float *table) {
+    if (!net || !table || n < 0 || (n > 0 && (!Q || !T))) return gfail(QS_ERR_ARG, "net, Q, T and table are required");
     hipStream_t s = qs::mlp_stream(net);
-    float *y = nullptr;
+    float *buf = nullptr;  // inputs [n][5], baseline [n], answers [n]
     uint32_t *cnt = nullptr;
-    if (n > 0) G_HIP(hipMalloc(&y, n * sizeof(float)), "allocate predictions");
+    if (n > 0) G_HIP(hipMalloc(&buf, (size_t)n * 7 * sizeof(float)), "allocate calibration buffers");
     if (hipMalloc(&cnt, (size_t)QS_GROWTH_BINS * kBuckets * sizeof(uint32_t)) != hipSuccess) {
-        if (y) (void)hipFree(y);
+        if (buf) (void)hipFree(buf);
         return gfail(QS_ERR_ALLOC, "allocate histogram");
     }
+    float *x = buf, *base = buf ? buf + (size_t)n * 5 : nullptr, *y = buf ? buf + (size_t)n * 6 : nullptr;
     hipLaunchKernelGGL(fill_kernel, dim3(blocks_for((int64_t)QS_GROWTH_BINS * kBuckets)), dim3(256), 0, s,
                        reinterpret_cast<float *>(cnt), (int64_t)QS_GROWTH_BINS * kBuckets, 0.0f);
     qs_status st = QS_OK;
     if (n > 0) {
-        st = qs_mlp_forward(net, X, n, y);
-        if (st == QS_OK) hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(n)), dim3(256), 0, s, X, y, T, n, cnt);
+        hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, s, Q, n, x, base);
+        st = qs_mlp_forward(net, x, n, y);
+        if (st == QS_OK) hipLaunchKernelGGL(hist_kernel, dim3(blocks_for(n)), dim3(256), 0, s, Q, y, base, T, n, cnt);
     }
     if (st == QS_OK) hipLaunchKernelGGL(p99_kernel, dim3(blocks_for(QS_GROWTH_BINS)), dim3(256), 0, s, cnt, table);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (y) (void)hipFree(y);
+    if (buf) (void)hipFree(buf);
     (void)hipFree(cnt);
     if (st != QS_OK) return st;
     if (e != hipSuccess) return gfail(QS_ERR_HIP, std::string("calibration: ") + hipGetErrorString(e));
@@ -551,13 +726,14 @@ qs_status qs_growth_map_noalloc(qs_mlp *net, const float *table, float tol, cons
     float *x = nullptr;
     qs_status st = scratch_for_device(dev, &x);
     if (st != QS_OK) return st;
+    float *base = x + (size_t)n * 5;
     hipStream_t s = qs::mlp_stream(net);
-    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, x);
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, x, base);
     G_HIP(hipGetLastError(), "features kernel");
     st = qs_mlp_forward(net, x, n, out);
     if (st != QS_OK) return st;
-    hipLaunchKernelGGL(route_kernel, dim3(blocks_for(n)), dim3(256), 0, s, x, n, table, tol, needs_solver);
-    G_HIP(hipGetLastError(), "routing kernel");
+    hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, base, out, table, tol, needs_solver);
+    G_HIP(hipGetLastError(), "finishing kernel");
     return QS_OK;
 }
 
@@ -576,15 +752,18 @@ qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float 
         if (x) (void)hipFree(x);
         if (flag && flag != used_solver) (void)hipFree(flag);
     };
+    float *base = nullptr;
     if (mode != QS_GROWTH_SOLVER) {
-        G_HIP(hipMalloc(&x, (size_t)n * 5 * sizeof(float)), "allocate features");
-        hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, x);
+        G_HIP(hipMalloc(&x, (size_t)n * 6 * sizeof(float)), "allocate features");
+        base = x + (size_t)n * 5;
+        hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, x, base);
         if (hipStreamSynchronize(s) != hipSuccess) { cleanup(); return gfail(QS_ERR_HIP, "features kernel"); }
         st = qs_mlp_forward(net, x, n, out);
         if (st == QS_OK && hipStreamSynchronize(qs::mlp_stream(net)) != hipSuccess) st = gfail(QS_ERR_HIP, "network");
         if (st != QS_OK) { cleanup(); return st; }
     }
     if (mode == QS_GROWTH_SURROGATE) {
+        hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, base, out, nullptr, 0.0f, nullptr);
         if (used_solver && hipMemsetAsync(used_solver, 0, (size_t)n, s) != hipSuccess) { cleanup(); return gfail(QS_ERR_HIP, "clear flags"); }
         cleanup();
         G_HIP(hipStreamSynchronize(s), "synchronize");
@@ -597,7 +776,7 @@ qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float 
     if (mode == QS_GROWTH_AUTO) {
         flag = used_solver;
         if (!flag && hipMalloc(&flag, (size_t)n) != hipSuccess) { cleanup(); return gfail(QS_ERR_ALLOC, "allocate flags"); }
-        hipLaunchKernelGGL(route_kernel, dim3(blocks_for(n)), dim3(256), 0, s, x, n, table, tol, flag);
+        hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, base, out, table, tol, flag);
         std::vector<uint8_t> hf((size_t)n);
         if (hipMemcpyAsync(hf.data(), flag, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) { cleanup(); return gfail(QS_ERR_HIP, "copy flags"); }

@@ -50,7 +50,9 @@ struct StepArgs {
     int32_t *epend;           // per (segment, padded mode): pending exponent (next step)
     void *ln_e, *ln_b;        // snapshot outputs (TS) or null
     void *max_ln_a;           // [step][total modes] (TS) or null
-    int64_t snap_base;        // element offset of this step's snapshot (ln_e/ln_b)
+    int64_t snap_base;        // element offset of the launch's first snapshot (ln_e/ln_b)
+    int64_t snap_stride;      // elements between the snapshots of consecutive steps of one
+                              // launch (snapshot launches that take several steps)
     int64_t max_base;         // element offset of the launch's first row in max_ln_a
     int32_t total_modes;      // unpadded total modes (row length of max_ln_a)
     int32_t update;           // 1: advance the state; 0: fields only

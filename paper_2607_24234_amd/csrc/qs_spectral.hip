@@ -323,6 +323,8 @@ march_kernel(StepArgs a) {
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
 
+    int64_t snap_row = a.snap_base;  // snapshot of the current step (SNAP launches: one step per sweep)
+
     // One segment pass of a sweep of K tau-steps: per cell, all four stages of each step, the
     // fields of the state at the step's start (stage-1 values) and the update.
     auto pass = [&](const bool init_steady, auto steps) __attribute__((always_inline)) {
@@ -407,7 +409,7 @@ march_kernel(StepArgs a) {
                         }
                         if (writer && mloc[t] < I.n_modes) {
                             const double sh = (double)L[t] * 0.69314718055994530942;
-                            const int64_t o = a.snap_base + I.snap_off + (int64_t)j * I.n_modes + mloc[t];
+                            const int64_t o = snap_row + I.snap_off + (int64_t)j * I.n_modes + mloc[t];
                             static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(s2) + sh);
                             static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
                         }
@@ -489,6 +491,7 @@ march_kernel(StepArgs a) {
     for (int n = 0; n < a.n_steps; ++sweeps) {
         // steps of this sweep: two while at least two remain (stepping kernels only)
         const int k = (NS == 2 && a.update && n + 1 < a.n_steps) ? 2 : 1;
+        snap_row = a.snap_base + (int64_t)n * a.snap_stride;
         // apply the pending renormalization of each (mode, segment): this sweep's loads are
         // multiplied by 2^-e; a fields-only launch (no update) reads the stored values with
         // their current exponent

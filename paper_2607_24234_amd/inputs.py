@@ -98,3 +98,16 @@ def finite_width(nx=256, ny=256, n_xi=8192, n_steps=500, length=200.0, box=16.0,
     return dict(species=[ELECTRON + (nb,)], gamma=gamma, length=length, n_xi=n_xi,
                 nx=nx, ny=ny, lx=box, ly=box, sigma_r=sigma_r, d_tau=d_tau, n_steps=n_steps,
                 seed_kind=SEED_CENTROID, seed_amp=1e-6, centroid_offset=1e-3 * sigma_r, rng_seed=seed)
+
+
+def growth_queries(n, seed):
+    """Growth-map queries uniform over the box log10 n_b in [-3, -1], log10 gamma in [1, 4],
+    k in [0.05, 4], xi in [0, 200], tau in [0, tau_f] (numpy PCG64), as float32 rows
+    (ln n_b, ln gamma, k, xi, tau)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x515259]))
+    nb = 10.0 ** rng.uniform(-3, -1, n)
+    g = 10.0 ** rng.uniform(1, 4, n)
+    k = rng.uniform(0.05, 4.0, n)
+    xi = rng.uniform(0.0, 200.0, n)
+    tau = rng.uniform(0.0, 1.0, n) * 10.0 * np.sqrt(g / nb)
+    return np.stack([np.log(nb), np.log(g), k, xi, tau], axis=1).astype(np.float32)

@@ -93,7 +93,8 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_sync_check", "qs_set_rollback", "qs_debug_set_wait_budget", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
            "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope",
-           "qs_regime_map"]
+           "qs_regime_map", "qs_surrogate_train", "qs_surrogate_load", "qs_surrogate_net", "qs_surrogate_table",
+           "qs_surrogate_free"]
 
 
 def lib():
@@ -152,7 +153,7 @@ def lib():
     L.qs_growth_sample.argtypes = [GI, ctypes.c_int32, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.c_uint64, ctypes.c_int64, vp, vp, vp]
     L.qs_growth_features.restype = ctypes.c_int
-    L.qs_growth_features.argtypes = [vp, ctypes.c_int64, vp, vp]
+    L.qs_growth_features.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     L.qs_growth_calibrate.restype = ctypes.c_int
     L.qs_growth_calibrate.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     L.qs_growth_map.restype = ctypes.c_int
@@ -195,6 +196,16 @@ def lib():
                                vp, vp, vp, vp]
     L.qs_svea_ln_envelope.restype = ctypes.c_int
     L.qs_svea_ln_envelope.argtypes = [ctypes.c_int64, ctypes.c_int32, vp, vp, vp, vp]
+    L.qs_surrogate_train.restype = ctypes.c_int
+    L.qs_surrogate_train.argtypes = [ctypes.c_char_p, ctypes.c_char_p, vp, ctypes.POINTER(ctypes.c_double)]
+    L.qs_surrogate_load.restype = ctypes.c_int
+    L.qs_surrogate_load.argtypes = [ctypes.c_char_p, vp, ctypes.POINTER(vp)]
+    L.qs_surrogate_net.restype = vp
+    L.qs_surrogate_net.argtypes = [vp]
+    L.qs_surrogate_table.restype = vp
+    L.qs_surrogate_table.argtypes = [vp]
+    L.qs_surrogate_free.restype = None
+    L.qs_surrogate_free.argtypes = [vp]
     L.qs_regime_map.restype = ctypes.c_int
     L.qs_regime_map.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
     _lib = L
@@ -355,6 +366,63 @@ class MLP:
             pass
 
 
+class BorrowedMLP(MLP):
+    """A network owned by another handle (qs_surrogate_net): same calls, never freed here."""
+
+    def __init__(self, handle, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        self.h = ctypes.c_void_p(handle)
+        self.max_batch = 128
+        self.n_params = int(lib().qs_mlp_param_count())
+
+    def close(self):
+        self.h = None
+
+
+SURROGATE_STATS = 8
+SURROGATE_STAT_NAMES = ("heldout_rms", "heldout_p99", "heldout_max", "heldout_within_1e-2", "bins_trusted_1e-2",
+                        "final_loss", "seconds_data", "seconds_train")
+
+
+def surrogate_train(path, cfg=None, stream=None):
+    """qs_surrogate_train: the whole training pipeline in the library; cfg is a dict of the
+    configuration keys of include/qs_surrogate.h.  Returns the statistics as a dict."""
+    import json
+    import torch
+    text = json.dumps(cfg or {}).encode()
+    st = (ctypes.c_double * SURROGATE_STATS)()
+    s = torch.cuda.current_stream() if stream is None else stream
+    _check(lib().qs_surrogate_train(text, os.fsencode(path), ctypes.c_void_p(s.cuda_stream), st))
+    return dict(zip(SURROGATE_STAT_NAMES, list(st)))
+
+
+class Surrogate:
+    """A trained surrogate file loaded on the current device (qs_surrogate_load): `net` for
+    qs_growth_map and `table`, the device address of its error table."""
+
+    def __init__(self, path, stream=None):
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        h = ctypes.c_void_p()
+        _check(lib().qs_surrogate_load(os.fsencode(path), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.net = BorrowedMLP(lib().qs_surrogate_net(h), s)
+        self.table = int(lib().qs_surrogate_table(h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().qs_surrogate_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class GrowthInstances:
     """qs_growth_instance descriptions of solver instances (dicts from inputs.py with a
     single species); keeps the k arrays alive."""
@@ -375,7 +443,12 @@ class GrowthInstances:
 
 
 def _vp(t):
-    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    """Device pointer of a torch tensor, or a raw address (int), or None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _stream_ptr(stream):
@@ -387,18 +460,20 @@ def growth_targets(gi, ln_e, ln_b, G, stream=None):
     _check(lib().qs_growth_targets(gi.arr, gi.n, _vp(ln_e), _vp(ln_b), int(n_snap), _vp(G), _stream_ptr(stream)))
 
 
-def growth_sample(gi, G, snap_steps, seed, n, X, T, stream=None):
+def growth_sample(gi, G, snap_steps, seed, n, Q, T, stream=None):
+    """Examples: queries Q [n, 5] (ln n_b, ln gamma, k, xi, tau) and their targets T [n]."""
     st = np.ascontiguousarray(snap_steps, np.int32)
     _check(lib().qs_growth_sample(gi.arr, gi.n, _vp(G), len(st), st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                  int(seed), int(n), _vp(X), _vp(T), _stream_ptr(stream)))
+                                  int(seed), int(n), _vp(Q), _vp(T), _stream_ptr(stream)))
 
 
-def growth_features(q, x, stream=None):
-    _check(lib().qs_growth_features(_vp(q), int(q.shape[0]), _vp(x), _stream_ptr(stream)))
+def growth_features(q, x=None, baseline=None, stream=None):
+    """Network inputs x [n, 5] and baseline [n] of queries q [n, 5] (either output optional)."""
+    _check(lib().qs_growth_features(_vp(q), int(q.shape[0]), _vp(x), _vp(baseline), _stream_ptr(stream)))
 
 
-def growth_calibrate(net, X, T, table):
-    _check(lib().qs_growth_calibrate(net.h, _vp(X), _vp(T), int(X.shape[0]), _vp(table)))
+def growth_calibrate(net, Q, T, table):
+    _check(lib().qs_growth_calibrate(net.h, _vp(Q), _vp(T), int(Q.shape[0]), _vp(table)))
 
 
 def growth_map(net, table, tol, q, mode, out, used_solver=None, stream=None):

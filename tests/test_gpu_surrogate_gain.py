@@ -1,76 +1,68 @@
 """What the trained surrogate gains over the method without it -- the solver answering every
-growth-map query -- end to end on the GPU at a reduced size.
+growth-map query -- end to end on the GPU, with the library's default training
+configuration (qs_surrogate_train: the 256-instance uniform-seed sweep, 1e7 examples, the
+network trained by the library's forward, backward and AdamW kernels, the held-out error
+table from a second, independent sweep of 1024 instances).
 
-Training examples come from a 32-instance uniform-seed sweep, held-out examples from a
-second sweep and check examples from a third (solver, growth targets and example draws all
-in the library's kernels); the network is trained by the library's own forward, backward and
-AdamW kernels.  The gain, stated as assertions:
-  - accuracy: after training, the held-out RMS error is below a tenth of what the best
-    constant (the targets' mean) and the untrained network give;
-  - the held-out error table keeps its promise out of sample: of the check sweep's examples
-    in the bins that the table trusts at a tolerance, at least 90 % are within it (the
-    table holds a per-bin 99th percentile);
-  - speed: the network answers scattered box queries more than 100 times faster per query
-    than the solver does.
+The gain, stated as assertions:
+  - accuracy on the held-out sweep: RMS error below 5e-3 and 99th percentile below 1e-2 in
+    ln amplitude, far below what the closed-form baseline alone gives;
+  - the error table trusts nearly the whole box at 1e-2;
+  - on 10^5 scattered queries uniform over the box, AUTO at tolerance 1e-2 sends at most 1 %
+    of them to the solver, agrees with the solver's answers within 1e-2 on at least 99 % of
+    them (99th percentile within 1e-2), and answers them more than 100 times faster than
+    the solver does.  (AUTO's time is the network's plus one solver run for the queries it
+    sends there, whose latency -- tens of milliseconds for 200 tau-steps of a beam up to
+    8192 cells long -- does not shrink with the batch: the batch has to be large enough for
+    the solver's per-query cost to show.)
 """
+import os
 import time
 
 import numpy as np
 import pytest
 
-from oracle import growth as Gr
-
 pytestmark = pytest.mark.gpu
 
 
-def test_trained_network_gain_over_solver(qs):
+def test_trained_network_gain_over_solver(qs, tmp_path):
     import torch
-    from paper_2607_24234_amd import surrogate as S
+    from paper_2607_24234_amd import inputs, surrogate as S
 
-    X, T = S.examples(S.sweep_instances(n_instances=32, seed=10), 1 << 19, 11)
-    Xh, Th = S.examples(S.sweep_instances(n_instances=32, seed=12), 1 << 18, 13)
-    Xc, Tc = S.examples(S.sweep_instances(n_instances=32, seed=14), 1 << 18, 15)
-    t = T.cpu().numpy().astype(np.float64)
-    th = Th.cpu().numpy().astype(np.float64)
-    net = qs.MLP(max_batch=1 << 16)
-    net.set_params(qs.pack_params(S.initial_params(3, float(t.mean()), float(t.std()))))
+    path = os.path.join(str(tmp_path), "surrogate.bin")
+    t = time.perf_counter()
+    st = S.train(path)
+    print("trained in %.1f s: %s" % (time.perf_counter() - t, st), flush=True)
+    assert st["heldout_rms"] < 5e-3 and st["heldout_p99"] < 1e-2
+    assert st["bins_trusted_1e-2"] > 0.99
+    sur = S.load(path)
 
-    rms_const = float(np.sqrt(np.mean((th - t.mean()) ** 2)))
-    rms_init = S.held_out_errors(net, Xh, Th)["rms"]
-    S.train(net, X, T, epochs=12, batch=8192, lr=1e-3)
-    err = S.held_out_errors(net, Xh, Th)
-    print("held-out rms: constant %.4f, untrained %.4f, trained %.4f (p99 %.4f)"
-          % (rms_const, rms_init, err["rms"], err["p99"]))
-    assert err["rms"] < 0.1 * rms_const and err["rms"] < 0.1 * rms_init
-
-    # the error table from the held-out sweep, checked on the third sweep
-    table = S.calibrate(net, Xh, Th).cpu().numpy()
-    known = table[table >= 0]
-    assert known.size > 0
-    tol = float(np.median(known))
-    yc = net.forward(Xc).cpu().numpy().astype(np.float64)
-    ec = np.abs(yc - Tc.cpu().numpy())
-    trusted = (table >= 0) & (table <= tol)
-    inb = trusted[Gr.bin_of(Xc.cpu().numpy())]
-    cover = float(np.mean(ec[inb] <= tol))
-    print("tolerance %.4f: %d of %d bins trusted, %.1f %% of check examples there, %.2f %% of those within"
-          % (tol, int(trusted.sum()), known.size, 100 * inb.mean(), 100 * cover))
-    assert inb.mean() > 0.05 and cover >= 0.9
-
-    # speed on scattered queries from the box
-    q = torch.as_tensor(S.query_box(1 << 20, 16), device="cuda")
-    out = torch.empty(q.shape[0], device="cuda")
-    qs.growth_map(net, None, 0.0, q, qs.GROWTH_SURROGATE, out)
+    m = 100000
+    q = torch.as_tensor(inputs.growth_queries(m, 77), device="cuda")
+    auto = torch.empty(m, device="cuda")
+    used = torch.zeros(m, dtype=torch.uint8, device="cuda")
+    sol = torch.empty(m, device="cuda")
+    base = torch.empty(m, device="cuda")
+    qs.growth_map(sur.net, sur.table, 1e-2, q[:64], qs.GROWTH_AUTO, auto[:64], used[:64])
+    qs.growth_map(None, None, 0.0, q[:8], qs.GROWTH_SOLVER, sol[:8])
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(4):
-        qs.growth_map(net, None, 0.0, q, qs.GROWTH_SURROGATE, out)
+    t = time.perf_counter()
+    qs.growth_map(sur.net, sur.table, 1e-2, q, qs.GROWTH_AUTO, auto, used)
     torch.cuda.synchronize()
-    s_net = (time.perf_counter() - t0) / (4 * q.shape[0])
-    n_s = 16
-    t0 = time.perf_counter()
-    qs.growth_map(None, None, 0.0, q[:n_s], qs.GROWTH_SOLVER, out[:n_s])
+    t_auto = time.perf_counter() - t
+    t = time.perf_counter()
+    qs.growth_map(None, None, 0.0, q, qs.GROWTH_SOLVER, sol)
     torch.cuda.synchronize()
-    s_sol = (time.perf_counter() - t0) / n_s
-    print("per query: network %.3e s, solver %.3e s (%.2e x)" % (s_net, s_sol, s_sol / s_net))
-    assert s_sol > 100.0 * s_net
+    t_sol = time.perf_counter() - t
+    qs.growth_features(q, baseline=base)
+    d = (auto - sol).abs().cpu().numpy().astype(np.float64)
+    db = (base - sol).abs().cpu().numpy().astype(np.float64)
+    frac = float(used.float().mean().item())
+    print("AUTO %.4f s (%.3f %% to the solver), SOLVER %.3f s (%.0fx); |AUTO - SOLVER| rms %.4f p99 %.4f "
+          "max %.4f, within 1e-2 %.4f; baseline alone rms %.3f"
+          % (t_auto, 100 * frac, t_sol, t_sol / t_auto, np.sqrt(np.mean(d * d)), np.percentile(d, 99), d.max(),
+             np.mean(d <= 1e-2), np.sqrt(np.mean(db * db))), flush=True)
+    assert frac <= 0.01
+    assert np.mean(d <= 1e-2) >= 0.99 and np.percentile(d, 99) <= 1e-2
+    assert np.sqrt(np.mean(db * db)) > 10 * np.sqrt(np.mean(d * d))
+    assert t_sol > 100.0 * t_auto
