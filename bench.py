@@ -23,6 +23,19 @@ sys.path.insert(0, ROOT)
 METRIC = ("mode·ξ·τ cell-updates/s at 1 GPU; surrogate vs solver speed at "
           "≤1e-2 log-amp err")
 HBM_PEAK_GBS = 8000.0
+# VALU peak of MI355X without packed FP32 (which this library does not use): 256 CUs x 4 SIMDs
+# x 16 lanes x 2.4 GHz, one wave64 instruction per SIMD every 4 cycles; an FMA counts as two
+# flops, so FP32 and FP64 FMAs both peak at 78.6 TFLOP/s
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4          # wave64 VALU instructions per second
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# the march's arithmetic per cell-update (one mode, one cell, one tau-step; per column of the
+# mode's two real columns): RK4 stage inputs 3 x 3 FMA (18 flops), the exact propagator of each
+# of the 4 stages (difference, 2 FMA for n_p at the centre, 2 for n_p at the face, a product
+# and an FMA for d_xi n_p: 12 flops, 48), d_xi n_p at the centre for the fields (3), the stage
+# derivatives (difference and sum for rho, one product each for the two currents: 4 per
+# stage, 16), the field energies and their sum over the columns (12), the update (3 FMA, 6):
+# 103 flops per column
+FLOP_PER_CELL_UPDATE = 2 * 103
 
 
 def kernel_source_hash():
@@ -43,6 +56,20 @@ def read_traffic(precision_name, steps_per_launch):
         if not e or e.get("kernel_sha256_16") != kernel_source_hash():
             return None
         return float(e["bytes_per_step"]) * steps_per_launch
+    except Exception:
+        return None
+
+
+def read_valu(precision_name):
+    """Wave64 VALU instructions per cell-update of the stepping launch (SQ_INSTS_VALU over
+    the launch's cell-updates) from the rocprofv3 counter summary -- only if the counters
+    were taken on the current kernel source (else None)."""
+    p = os.path.join(ROOT, "profiles", "march_spectral3d_valu.json")
+    try:
+        e = json.load(open(p))[precision_name]
+        if e.get("kernel_sha256_16") != kernel_source_hash():
+            return None
+        return float(e["wave_instructions_per_cell_update"])
     except Exception:
         return None
 
@@ -79,10 +106,28 @@ def _scaled(v, f):
     return None if v is None else v * f
 
 
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
+
+
 def cpu_baseline(inst, seconds=15.0):
     """The FP64 oracle timed on the host cores on a bounded sample of the same workload:
     modes spread evenly over the mode list, all 4096 cells, a fixed number of tau-steps;
-    the mode count is sized from a short probe so that the timed run takes ~`seconds`."""
+    the mode count is sized from a short probe so that each of three timed runs takes about
+    seconds/3, and the median run is reported."""
     import numpy as np
     import oracle as O
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -103,13 +148,18 @@ def cpu_baseline(inst, seconds=15.0):
 
     probe_modes = 2 * threads
     rate = probe_modes * inst["n_xi"] * 2 / timed(probe_modes, 2)
-    n_modes = int(max(threads, min(len(k_all), seconds * rate / (inst["n_xi"] * steps))))
+    n_modes = int(max(threads, min(len(k_all), seconds / 3 * rate / (inst["n_xi"] * steps))))
     n_modes = max(threads, n_modes // threads * threads)
-    dt = timed(n_modes, steps)
+    runs = sorted(timed(n_modes, steps) for _ in range(3))
+    dt = runs[1]
     cells = n_modes * inst["n_xi"] * steps
+    model, avail = host_cpu()
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "cpus_available": avail,
+            "runs_s": runs,
             "sample": "%d modes evenly spread over the 205,859-mode list x %d cells x %d steps "
-                      "(FP64, per-step max ln A output), %.1f s wall" % (n_modes, inst["n_xi"], steps, dt)}
+                      "(FP64, per-step max ln A output); median of 3 runs, %.1f s wall each"
+                      % (n_modes, inst["n_xi"], steps, dt)}
 
 
 def _line(metric, value, unit, K, W, ms, dtype, config, roofline, cpu, **extra):
@@ -146,7 +196,8 @@ def bench_batched(args):
     s2.sync_check()
     cells = sum(len(d["kx"]) * d["n_xi"] for d in insts)
     launch = e0.elapsed_time(e1) * 1e-3
-    achieved = 48 * cells * K / launch / 1e9
+    rate = cells * K / launch
+    flops = FLOP_PER_CELL_UPDATE * rate / 1e12
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -168,10 +219,13 @@ def bench_batched(args):
           {"workload": "batched sweep: 256 instances x 128 modes, log-uniform n_b in [1e-3, 1e-1], "
                        "gamma in [10, 1e4], L in [5, 200], 128..8192 cells, 200 steps, noise seed 1e-6",
            "cells_per_step": cells, "plan": dict(s2.plan(), source=plan_src)},
-          {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved / HBM_PEAK_GBS, "traffic": read_workload_traffic("batched", "bytes_per_launch"),
+          {"bound": "alu", "achieved": flops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": flops / VALU_PEAK_TFLOPS, "traffic": read_workload_traffic("batched", "bytes_per_launch"),
            "kernel": "march_kernel (persistent, xi-segmented), one launch = 200 steps of all instances, two per sweep",
-           "algorithmic_bytes_per_launch": 48 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
+           "algorithmic_flop_per_cell_update": FLOP_PER_CELL_UPDATE,
+           "algorithmic_flop_per_launch": FLOP_PER_CELL_UPDATE * cells * K, "avg_launch_ms": launch * 1e3,
+           "hbm": {"algorithmic_bytes_per_cell_update": 24, "achieved_GBs": 24 * rate / 1e9,
+                   "frac": 24 * rate / 1e9 / HBM_PEAK_GBS}}, cpu)
 
 
 GRID_FLOPS_PER_CELL = 1330.0   # four 2D FFTs per slice per stage (5 N log2 N each) x 4 stages
@@ -258,7 +312,8 @@ def bench_svea(args):
     wall = time.perf_counter() - t0
     cells = len(k) * d["n_xi"]
     launch = e0.elapsed_time(e1) * 1e-3
-    achieved = 64.0 * cells * K / launch / 1e9
+    # the state (n, m complex, FP64: 32 B) is read and written once per sweep of four steps
+    achieved = 16.0 * cells * K / launch / 1e9
     ln = sv.ln_envelope()
     torch.cuda.synchronize()
     cpu = None
@@ -278,8 +333,9 @@ def bench_svea(args):
            "max_ln_envelope": float(ln.max().item())},
           {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
            "traffic": _scaled(read_workload_traffic("svea", "bytes_per_launch"), K / 20.0),
-           "kernel": "svea_step (one lane per mode, all K steps in one launch)",
-           "algorithmic_bytes_per_launch": 64.0 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
+           "kernel": "svea_step (one lane per mode, all K steps in one launch, four steps per sweep)",
+           "algorithmic_bytes_per_cell_update": 16.0,
+           "algorithmic_bytes_per_launch": 16.0 * cells * K, "avg_launch_ms": launch * 1e3}, cpu)
 
 
 def bench_regime(args):
@@ -513,7 +569,7 @@ def main():
         return
     inst = inputs.spectral3d()
     prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64
-    plan, plan_src = launch_plan(args, [inst], prec, args.snapshot_every - 1 if args.snapshot_every > 1 else args.steps)
+    plan, plan_src = launch_plan(args, [inst], prec, min(args.steps, args.snapshot_every) if args.snapshot_every > 0 else args.steps)
     solver = qs.Solver([inst], precision=prec, **plan)
     n_modes, n_xi = solver.total_modes, inst["n_xi"]
     dtype = solver.dtype
@@ -528,23 +584,20 @@ def main():
     stream = solver.stream
     L = qs.lib()
 
-    # The K steps as library calls: each snapshot step alone (it also writes ln|E|, ln|B| of
-    # every cell), the steps between two snapshots as one call (one persistent launch).
+    # The K steps as library calls, one per snapshot interval: the call writes ln|E|, ln|B| of
+    # every cell at its first step and advances `every` steps (one persistent launch; the
+    # stepping kernel writes the snapshot during its first sweep).
     chunks = []
     s = 0
     while s < K:
-        if every > 0 and s % every == 0:
-            chunks.append((s, 1, True))
-            s += 1
-        else:
-            e = min(K, (s // every + 1) * every) if every > 0 else K
-            chunks.append((s, e - s, False))
-            s = e
+        e = min(K, s + every) if every > 0 else K
+        chunks.append((s, e - s, every > 0))
+        s = e
 
     def run_chunk(s0, n, snap):
         pe = snap_e[s0 // every].data_ptr() if snap else None
         pb = snap_b[s0 // every].data_ptr() if snap else None
-        qs._check(L.qs_step_tau(solver.ctx, n, 1, pe, pb, max_buf[s0].data_ptr()))
+        qs._check(L.qs_step_tau(solver.ctx, n, max(n, 1), pe, pb, max_buf[s0].data_ptr()))
 
     if W > 0:
         qs._check(L.qs_step_tau(solver.ctx, W, 1, None, None, max_buf[0].data_ptr()))
@@ -567,17 +620,17 @@ def main():
     dur = [ea.elapsed_time(eb) * 1e-3 for ea, eb in ev]
     cells = n_modes * n_xi
     value = cells * K / wall
-    bpc = 48 if prec == qs.QS_FP32 else 96
-    # dominant kernel: the persistent launches that advance the steps between snapshots
-    runs = [(n, d) for (s0, n, snap), d in zip(chunks, dur) if not snap]
-    if not runs:
-        runs = [(n, d) for (s0, n, snap), d in zip(chunks, dur)]
-    run_steps = sum(n for n, _ in runs)
-    run_time = sum(d for _, d in runs)
-    avg_launch = run_time / len(runs)
-    steps_per_launch = run_steps / len(runs)
-    achieved = bpc * cells * run_steps / run_time / 1e9
+    # dominant kernel: the persistent launch of one snapshot interval (its first step also
+    # writes the snapshot); timed by HIP events on the solver's stream around each call
+    run_steps = sum(n for (s0, n, snap) in chunks)
+    run_time = sum(dur)
+    avg_launch = run_time / len(chunks)
+    steps_per_launch = run_steps / len(chunks)
+    rate = cells * run_steps / run_time          # cell-updates/s inside the launches
+    flops = FLOP_PER_CELL_UPDATE * rate / 1e12   # TFLOP/s of the method's arithmetic
+    bpc = 24 if prec == qs.QS_FP32 else 48       # state bytes per cell-update, two steps per sweep
     traffic = read_traffic(args.precision, steps_per_launch)
+    valu = read_valu(args.precision)
     growth = float((max_buf[K - 1].max() - max_buf[0].max()).item()) if K > 1 else 0.0
     plan = solver.plan()
 
@@ -601,15 +654,22 @@ def main():
                    "outputs": "per-step max ln A per mode; ln|E|,ln|B| snapshots every %d steps" % args.snapshot_every,
                    "growth_nepers_over_run": growth,
                    "plan": dict(plan, source=plan_src)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "alu", "achieved": flops, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / VALU_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": "march_kernel (fields, no snapshot): one persistent launch = "
-                               "the tau-steps between two snapshots, all modes, two steps per sweep",
+                     "kernel": "march_kernel (fields; the interval's first step also writes the snapshot): one "
+                               "persistent launch = one snapshot interval, all modes, two tau-steps per sweep",
+                     "algorithmic_flop_per_cell_update": FLOP_PER_CELL_UPDATE,
                      "steps_per_launch": steps_per_launch,
-                     "algorithmic_bytes_per_launch": bpc * cells * steps_per_launch,
+                     "algorithmic_flop_per_launch": FLOP_PER_CELL_UPDATE * cells * steps_per_launch,
                      "avg_launch_ms": avg_launch * 1e3,
-                     "gpu_ms_per_step": sum(dur) / K * 1e3},
+                     "gpu_ms_per_step": sum(dur) / K * 1e3,
+                     "valu_issue": (None if valu is None else
+                                    {"instructions_per_cell_update": valu,
+                                     "frac_of_issue_peak": valu * rate / VALU_ISSUE_PEAK,
+                                     "source": "rocprofv3 SQ_INSTS_VALU on the same kernel source"}),
+                     "hbm": {"algorithmic_bytes_per_cell_update": bpc,
+                             "achieved_GBs": bpc * rate / 1e9, "frac": bpc * rate / 1e9 / HBM_PEAK_GBS}},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -667,16 +667,16 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     const bool restoring = !(pl.inst[0].flags & QS_FLAG_NO_RESTORING);
     bool flat = true;
     for (const InstDev &d : pl.inst) flat = flat && (d.flags & kFlatProfile);
-    auto launch = [&](bool fields) {
+    auto launch = [&](bool fields, bool snap_first_only) {
         return launch_march(pl.precision, pl.nc, restoring, fields, flat, pl.n_wg, pl.wg_waves, pl.max_seg > 1,
-                            a, c->stream);
+                            snap_first_only, a, c->stream);
     };
     if (n_steps == 0) {
         a.ln_e = out_ln_e;
         a.ln_b = out_ln_b;
         a.update = 0;
         a.n_steps = 1;
-        QS_HIP(launch(true), "march kernel");
+        QS_HIP(launch(true, false), "march kernel");
         return QS_OK;
     }
     if (c->guard) QS_HIP(launch_guard_copy(guard_args(c), c->stream), "rollback copy");
@@ -687,13 +687,16 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     a.max_ln_a = out_max_ln_a;
     a.keyed = keyed ? 1 : 0;
     a.update = 1;
-    // snapshot steps run as one-step launches, the steps between them in one launch each; a
-    // snapshot at every step runs as one launch of snapshot steps
+    // one launch per snapshot interval: with one column per lane the stepping kernel writes
+    // the snapshot of the interval's first step itself, keeping its two-step sweeps; with two
+    // columns per lane the snapshot step runs as a one-step launch and the steps up to the
+    // next snapshot as another; a snapshot at every step runs as one launch of snapshot steps
+    const bool first_form = pl.nc == 1 && out_every > 1;
     int s0 = 0;
     while (s0 < n_steps) {
         const bool snap = snaps && (s0 % out_every == 0);
         int s1 = s0 + 1;
-        if (!snap) {
+        if (!snap || first_form) {
             s1 = n_steps;
             if (snaps) s1 = std::min(n_steps, (s0 / out_every + 1) * out_every);
         } else if (out_every == 1) {
@@ -705,7 +708,7 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
         a.snap_stride = snap ? pl.snap_elems : 0;
         a.max_base = (int64_t)s0 * pl.total_modes;
         a.n_steps = s1 - s0;
-        QS_HIP(launch(snap || out_max_ln_a != nullptr), "march kernel");
+        QS_HIP(launch(snap || out_max_ln_a != nullptr, snap && first_form), "march kernel");
         QS_HIP(launch_advance_steps(a.err, s1 - s0, c->stream), "step counter");
         c->steps_done += s1 - s0;
         s0 = s1;

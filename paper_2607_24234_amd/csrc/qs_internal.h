@@ -107,8 +107,11 @@ constexpr int kMaxSegments = 16;  // most waves per workgroup of the march kerne
 inline int march_wg_waves(int precision, int nc) {
     return precision == QS_FP32 && nc == 1 ? (QS_STEPS_PER_SWEEP == 2 ? 12 : 16) : 8;
 }
+// snap_first_only: with snapshot outputs, write them for the launch's first step only, from
+// the stepping kernel (a launch of several steps keeps its two-step sweeps); otherwise every
+// step of the launch is written, one step per sweep.
 hipError_t launch_march(int precision, int nc, bool restoring, bool fields, bool flat, int n_wg,
-                        int wg_waves, bool segmented, const StepArgs &a, hipStream_t s);
+                        int wg_waves, bool segmented, bool snap_first_only, const StepArgs &a, hipStream_t s);
 size_t march_lds_bytes(int precision, int nc, int wg_waves, bool segmented);
 // resident workgroups per CU of the march kernel for this shape (-1 if the runtime cannot
 // tell, e.g. without a device)

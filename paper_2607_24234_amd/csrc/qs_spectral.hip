@@ -239,9 +239,13 @@ __device__ __forceinline__ bool wait_flag(int *flag, int target, int *abort, uin
     return true;
 }
 
-template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, bool SNAP, bool FLAT>
+// Snapshot forms of the march: none; every step of the launch (one step per sweep); the
+// launch's first step only, inside the stepping kernel (its sweeps keep their step count).
+constexpr int kSnapNone = 0, kSnapEvery = 1, kSnapFirst = 2;
+
+template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, int SNAP, bool FLAT>
 __global__ void __launch_bounds__(sizeof(TS) == 4 && NC == 1 ? (kSweepSlots == 2 ? 768 : 1024) : 512)
-__attribute__((amdgpu_waves_per_eu(NC == 1 && !SNAP ? (sizeof(TS) == 8 ? (kSweepSlots == 2 ? 2 : 4) : (kSweepSlots == 2 ? 3 : 5)) : 1)))
+__attribute__((amdgpu_waves_per_eu(NC == 1 && SNAP != kSnapEvery ? (sizeof(TS) == 8 ? (kSweepSlots == 2 ? 2 : 4) : (kSweepSlots == 2 ? 3 : 5)) : 1)))
 march_kernel(StepArgs a) {
     using CL = Cols<NC>;
     using PL = Payload<TC, NC>;
@@ -316,19 +320,21 @@ march_kernel(StepArgs a) {
 
     // steps one sweep can take: two for the stepping kernels with one column per lane, where
     // the second step's carries still fit the register budget; one otherwise
-    constexpr int NS = (!SNAP && NC == 1) ? kSweepSlots : 1;
+    constexpr int NS = (SNAP != kSnapEvery && NC == 1) ? kSweepSlots : 1;
     double y[NS][4][NC], v[NS][4][NC];  // per step of the sweep and stage: n_p and d_xi n_p at the front face
     TC pp[NS][4][NC];                   // stage inputs of P' at the front face of the current cell
     TC scale[MPL], rmax[MPL], a2max[NS][MPL];
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
 
-    int64_t snap_row = a.snap_base;  // snapshot of the current step (SNAP launches: one step per sweep)
+    int64_t snap_row = a.snap_base;  // snapshot of the current step (kSnapEvery: one step per sweep)
+    bool snap_now = SNAP == kSnapEvery;  // kSnapFirst: the first sweep's first step
 
     // One segment pass of a sweep of K tau-steps: per cell, all four stages of each step, the
     // fields of the state at the step's start (stage-1 values) and the update.
-    auto pass = [&](const bool init_steady, auto steps) __attribute__((always_inline)) {
+    auto pass = [&](const bool init_steady, auto steps, auto scaled) __attribute__((always_inline)) {
         constexpr int K = decltype(steps)::value;
+        constexpr bool SCALED = decltype(scaled)::value;  // a pending power of two in the wave
         // step `slot` of the sweep at cell j from its stage-1 values u (TC, pending power of
         // two applied) and Omega at the centre and the rear face: fields, and the updated
         // values un rounded to the storage type
@@ -386,21 +392,28 @@ march_kernel(StepArgs a) {
                 for (int t = 0; t < MPL; ++t) {
                     // |E_par|^2 = kappa^2 |n_p'|^2, |E_perp|^2 = k^2 kappa^2 |rho - n_p|^2,
                     // |B_perp|^2 = k^2 kappa^2 |rho|^2, summed over the two parts of the mode
-                    TC e2, b2;
+                    const bool snap_here = SNAP == kSnapEvery || (SNAP == kSnapFirst && sl == 0 && snap_now);
+                    TC e2 = (TC)0, b2 = (TC)0, a2;
                     if (NC >= 2) {
                         const int ca = 2 * t, cb = 2 * t + 1;
                         const TC en = vcf0[ca] * vcf0[ca] + vcf0[cb] * vcf0[cb];
                         const TC d0 = r0[ca] - ncf0[ca], d1 = r0[cb] - ncf0[cb];
                         e2 = kap2[t] * en + k2kap2[t] * (d0 * d0 + d1 * d1);
                         b2 = k2kap2[t] * (r0[ca] * r0[ca] + r0[cb] * r0[cb]);
+                        a2 = e2 + b2;
                     } else {
                         const TC d0 = r0[0] - ncf0[0];
-                        e2 = pair_sum(kap2[0] * vcf0[0] * vcf0[0] + k2kap2[0] * d0 * d0);
-                        b2 = pair_sum(k2kap2[0] * r0[0] * r0[0]);
+                        if (snap_here) {
+                            e2 = pair_sum(kap2[0] * vcf0[0] * vcf0[0] + k2kap2[0] * d0 * d0);
+                            b2 = pair_sum(k2kap2[0] * r0[0] * r0[0]);
+                            a2 = e2 + b2;
+                        } else {
+                            // A^2 alone: one sum over the mode's two lanes
+                            a2 = pair_sum(kap2[0] * vcf0[0] * vcf0[0] + k2kap2[0] * (d0 * d0 + r0[0] * r0[0]));
+                        }
                     }
-                    const TC a2 = e2 + b2;
                     a2max[sl][t] = a2 > a2max[sl][t] ? a2 : a2max[sl][t];
-                    if (SNAP) {
+                    if (snap_here) {
                         // snapshot option: |F_perp|^2 = k^2 kappa^2 |n_p|^2 in place of |E|^2
                         TC s2 = e2;
                         if (I.flags & QS_FLAG_FPERP_SNAPSHOTS) {
@@ -433,7 +446,7 @@ march_kernel(StepArgs a) {
                 const int t = NC >= 2 ? c / 2 : 0;
                 // stored values times the pending exact power of two (1 when none)
 #pragma unroll
-                for (int r = 0; r < 3; ++r) u[r][c] = (TC)x[r * NC + c] * scale[t];
+                for (int r = 0; r < 3; ++r) u[r][c] = SCALED ? (TC)x[r * NC + c] * scale[t] : (TC)x[r * NC + c];
             }
             TS un[3][NC];
             step_cell(j, u, Oc, Of, un, first, I0{});
@@ -492,6 +505,7 @@ march_kernel(StepArgs a) {
         // steps of this sweep: two while at least two remain (stepping kernels only)
         const int k = (NS == 2 && a.update && n + 1 < a.n_steps) ? 2 : 1;
         snap_row = a.snap_base + (int64_t)n * a.snap_stride;
+        if (SNAP == kSnapFirst) snap_now = n == 0;
         // apply the pending renormalization of each (mode, segment): this sweep's loads are
         // multiplied by 2^-e; a fields-only launch (no update) reads the stored values with
         // their current exponent
@@ -538,11 +552,24 @@ march_kernel(StepArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) __hip_atomic_store(&taken[slot - 1], sweeps + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        // the loads are multiplied by the pending power of two only in the (rare) sweeps
+        // where a lane of the wave has one
+        bool pend = false;
+#pragma unroll
+        for (int t = 0; t < MPL; ++t) pend = pend || scale[t] != (TC)1;
+        const bool scaled = __any(pend ? 1 : 0) != 0;
+        using S1 = std::true_type;
+        using S0 = std::false_type;
         if constexpr (NS == 2) {
-            if (k == 2) pass(wave == 0 && steady, std::integral_constant<int, 2>{});
-            else pass(wave == 0 && steady, std::integral_constant<int, 1>{});
+            if (k == 2) {
+                if (scaled) pass(wave == 0 && steady, std::integral_constant<int, 2>{}, S1{});
+                else pass(wave == 0 && steady, std::integral_constant<int, 2>{}, S0{});
+            } else {
+                pass(wave == 0 && steady, std::integral_constant<int, 1>{}, S1{});
+            }
         } else {
-            pass(wave == 0 && steady, std::integral_constant<int, 1>{});
+            if (scaled) pass(wave == 0 && steady, std::integral_constant<int, 1>{}, S1{});
+            else pass(wave == 0 && steady, std::integral_constant<int, 1>{}, S0{});
         }
 
         // hand the carries at this segment's rear face to the next segment
@@ -630,26 +657,30 @@ __global__ void __launch_bounds__(256) key_decode(TS *p, int64_t n) {
 }
 
 template <typename TS, typename TC, int NC, bool RESTORING>
-hipError_t launch_march_r(bool fields, bool snap, bool flat, int n_wg, int wg_waves, bool segmented,
+hipError_t launch_march_r(bool fields, int snap, bool flat, int n_wg, int wg_waves, bool segmented,
                           const StepArgs &a, hipStream_t s) {
     dim3 grid(n_wg), block(kWave * wg_waves);
     const size_t lds = march_lds_bytes(sizeof(TS) == 8 ? QS_FP64 : QS_FP32, NC, wg_waves, segmented);
 #define QS_LAUNCH(F, S, FL) hipLaunchKernelGGL((march_kernel<TS, TC, NC, RESTORING, F, S, FL>), grid, block, lds, s, a)
+    // the first-step form exists where sweeps take two steps (one column per lane)
+    if (NC != 1 && snap == kSnapFirst) snap = kSnapEvery;
     if (flat) {
-        if (snap) QS_LAUNCH(true, true, true);
-        else if (fields) QS_LAUNCH(true, false, true);
-        else QS_LAUNCH(false, false, true);
+        if (snap == kSnapEvery) QS_LAUNCH(true, kSnapEvery, true);
+        else if (snap == kSnapFirst) QS_LAUNCH(true, NC == 1 ? kSnapFirst : kSnapEvery, true);
+        else if (fields) QS_LAUNCH(true, kSnapNone, true);
+        else QS_LAUNCH(false, kSnapNone, true);
     } else {
-        if (snap) QS_LAUNCH(true, true, false);
-        else if (fields) QS_LAUNCH(true, false, false);
-        else QS_LAUNCH(false, false, false);
+        if (snap == kSnapEvery) QS_LAUNCH(true, kSnapEvery, false);
+        else if (snap == kSnapFirst) QS_LAUNCH(true, NC == 1 ? kSnapFirst : kSnapEvery, false);
+        else if (fields) QS_LAUNCH(true, kSnapNone, false);
+        else QS_LAUNCH(false, kSnapNone, false);
     }
 #undef QS_LAUNCH
     return hipGetLastError();
 }
 
 template <typename TS, typename TC, int NC>
-hipError_t launch_march_t(bool restoring, bool fields, bool snap, bool flat, int n_wg, int wg_waves,
+hipError_t launch_march_t(bool restoring, bool fields, int snap, bool flat, int n_wg, int wg_waves,
                           bool segmented, const StepArgs &a, hipStream_t s) {
     if (restoring) return launch_march_r<TS, TC, NC, true>(fields, snap, flat, n_wg, wg_waves, segmented, a, s);
     return launch_march_r<TS, TC, NC, false>(fields, snap, flat, n_wg, wg_waves, segmented, a, s);
@@ -674,8 +705,8 @@ size_t march_lds_bytes(int precision, int nc, int wg_waves, bool segmented) {
 }
 
 hipError_t launch_march(int precision, int nc, bool restoring, bool fields, bool flat, int n_wg,
-                        int wg_waves, bool segmented, const StepArgs &a, hipStream_t s) {
-    const bool snap = a.ln_e != nullptr;
+                        int wg_waves, bool segmented, bool snap_first_only, const StepArgs &a, hipStream_t s) {
+    const int snap = a.ln_e == nullptr ? kSnapNone : (snap_first_only ? kSnapFirst : kSnapEvery);
     if (wg_waves < 1 || wg_waves > march_wg_waves(precision, nc)) return hipErrorInvalidConfiguration;
     if (precision == QS_FP64) {
         if (nc == 1) return launch_march_t<double, double, 1>(restoring, fields, snap, flat, n_wg, wg_waves, segmented, a, s);
@@ -690,10 +721,10 @@ int march_wgs_per_cu(int precision, int nc, bool restoring, bool flat, int wg_wa
     const size_t lds = march_lds_bytes(precision, nc, wg_waves, segmented);
     const void *f = nullptr;
 #define QS_PICK(TS, TC, NCc)                                                                          \
-    f = restoring ? (flat ? reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, true, true, false, true>)   \
-                          : reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, true, true, false, false>)) \
-                  : (flat ? reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, false, true, false, true>)  \
-                          : reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, false, true, false, false>));
+    f = restoring ? (flat ? reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, true, true, kSnapNone, true>)   \
+                          : reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, true, true, kSnapNone, false>)) \
+                  : (flat ? reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, false, true, kSnapNone, true>)  \
+                          : reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, false, true, kSnapNone, false>));
     if (precision == QS_FP64) {
         if (nc == 1) { QS_PICK(double, double, 1) } else { QS_PICK(double, double, 2) }
     } else {
@@ -719,20 +750,23 @@ hipError_t allow_march_lds(int precision, int nc, size_t bytes) {
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&march_kernel<TS, TC, NCc, R, F, S, FL>), \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
     if (e != hipSuccess) return e;
-#define QS_ALLOW_ALL(TS, TC, NCc) \
-    QS_ALLOW(TS, TC, NCc, true, true, true, true) QS_ALLOW(TS, TC, NCc, true, true, false, true) \
-    QS_ALLOW(TS, TC, NCc, true, false, false, true) QS_ALLOW(TS, TC, NCc, true, true, true, false) \
-    QS_ALLOW(TS, TC, NCc, true, true, false, false) QS_ALLOW(TS, TC, NCc, true, false, false, false) \
-    QS_ALLOW(TS, TC, NCc, false, true, true, true) QS_ALLOW(TS, TC, NCc, false, true, false, true) \
-    QS_ALLOW(TS, TC, NCc, false, false, false, true) QS_ALLOW(TS, TC, NCc, false, true, true, false) \
-    QS_ALLOW(TS, TC, NCc, false, true, false, false) QS_ALLOW(TS, TC, NCc, false, false, false, false)
+#define QS_ALLOW_R(TS, TC, NCc, R) \
+    QS_ALLOW(TS, TC, NCc, R, true, kSnapEvery, true) QS_ALLOW(TS, TC, NCc, R, true, kSnapNone, true) \
+    QS_ALLOW(TS, TC, NCc, R, false, kSnapNone, true) QS_ALLOW(TS, TC, NCc, R, true, kSnapEvery, false) \
+    QS_ALLOW(TS, TC, NCc, R, true, kSnapNone, false) QS_ALLOW(TS, TC, NCc, R, false, kSnapNone, false)
+#define QS_ALLOW_ALL(TS, TC, NCc) QS_ALLOW_R(TS, TC, NCc, true) QS_ALLOW_R(TS, TC, NCc, false)
+#define QS_ALLOW_FIRST(TS, TC) \
+    QS_ALLOW(TS, TC, 1, true, true, kSnapFirst, true) QS_ALLOW(TS, TC, 1, true, true, kSnapFirst, false) \
+    QS_ALLOW(TS, TC, 1, false, true, kSnapFirst, true) QS_ALLOW(TS, TC, 1, false, true, kSnapFirst, false)
     hipError_t e = hipSuccess;
     if (precision == QS_FP64) {
-        if (nc == 1) { QS_ALLOW_ALL(double, double, 1) } else { QS_ALLOW_ALL(double, double, 2) }
+        if (nc == 1) { QS_ALLOW_ALL(double, double, 1) QS_ALLOW_FIRST(double, double) } else { QS_ALLOW_ALL(double, double, 2) }
     } else {
-        if (nc == 1) { QS_ALLOW_ALL(float, float, 1) } else { QS_ALLOW_ALL(float, float, 2) }
+        if (nc == 1) { QS_ALLOW_ALL(float, float, 1) QS_ALLOW_FIRST(float, float) } else { QS_ALLOW_ALL(float, float, 2) }
     }
+#undef QS_ALLOW_FIRST
 #undef QS_ALLOW_ALL
+#undef QS_ALLOW_R
 #undef QS_ALLOW
     return e;
 }
