@@ -466,8 +466,13 @@ def bench_surrogate(args):
     def log(msg):
         print("[surrogate] %s" % msg, file=sys.stderr, flush=True)
 
-    cfg = {"epochs": args.epochs} if args.epochs else None
-    fig, sur = surrogate_vs_solver(100000, cfg, log)
+    if args.surrogate_file:
+        # a trained network from a file: the inference alone (no training, no solver runs)
+        from paper_2607_24234_amd import surrogate as S
+        fig, sur = None, S.load(args.surrogate_file)
+    else:
+        cfg = {"epochs": args.epochs} if args.epochs else None
+        fig, sur = surrogate_vs_solver(100000, cfg, log)
     n_q = int(1e8)
     chunk = int(1e7)
     q = torch.as_tensor(inputs.growth_queries(chunk, 3), device="cuda")
@@ -511,7 +516,7 @@ def bench_surrogate(args):
                                       "3 bf16 512x512 layers on the matrix cores, fp32 first/last "
                                       "layers), 1.58 MFLOP per query"},
           cpu, surrogate=fig, network_s_per_query=sur_s / n_q,
-          network_speedup_vs_solver=(fig["solver_s"] / fig["queries"]) / (sur_s / n_q))
+          network_speedup_vs_solver=None if fig is None else (fig["solver_s"] / fig["queries"]) / (sur_s / n_q))
 
 
 def main():
@@ -535,6 +540,9 @@ def main():
                          "3D snapshot")
     ap.add_argument("--epochs", type=int, default=0,
                     help="surrogate training epochs (0: the library's default)")
+    ap.add_argument("--surrogate-file", default=None, metavar="PATH",
+                    help="surrogate workload: load this trained surrogate (qs_surrogate_train's file) and "
+                         "time its inference only, with no training and no solver comparison")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="leave the surrogate-against-solver figures out of the default line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",

@@ -91,6 +91,18 @@ qs_status qs_mlp_train_step(qs_mlp *net, const float *x, const float *t, int32_t
 /* Release the network and its buffers.  NULL is ignored. */
 void qs_mlp_free(qs_mlp *net);
 
+/*
+ * Test hook, host only (no device call): build the arguments of every matrix-core GEMM of one
+ * training step on `batch` rows of a network created with `max_batch`, at the buffer offsets
+ * a real network uses, and check them against what the GEMM kernel assumes (whole 128 x 128
+ * output tiles and 64-long reduction chunks, 16-byte aligned rows long enough for every
+ * split, a grid inside the device limits, every epilogue output present); qs_mlp_grads makes
+ * the same check before each launch.  Returns 0 when all hold, 1 otherwise, -1 for batch
+ * sizes the network would refuse; msg (host, msg_len bytes, may be NULL) gets the split count
+ * or what failed.
+ */
+int32_t qs_debug_mlp_gemm_check(int32_t max_batch, int32_t batch, char *msg, int32_t msg_len);
+
 #ifdef __cplusplus
 }
 #endif

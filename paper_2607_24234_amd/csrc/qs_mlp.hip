@@ -826,34 +826,124 @@ size_t mlp_bytes(int64_t B, std::vector<size_t> *offs) {
     return o;
 }
 
-void gemm_launch(int epi, const GemmArgs &a, int splits, hipStream_t s) {
+// The kernel argument is passed by value: a plain 8-byte-aligned record of pointers and
+// extents, far below the kernel-argument limit.
+static_assert(sizeof(GemmArgs) == 144 && alignof(GemmArgs) == 8, "GemmArgs layout");
+static_assert(std::is_trivially_copyable<GemmArgs>::value, "GemmArgs is copied as bytes");
+// static LDS of gemm_nt: two double-buffered 128-row chunks of A and of B
+static_assert(2 * 2 * 128 * SLD * sizeof(bf16_t) <= 160 * 1024, "gemm_nt LDS fits a compute unit");
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// What gemm_nt assumes of its launch: whole 128 x 128 output tiles, whole 64-long reduction
+// chunks, 16-byte aligned rows of A and B (each thread moves 16 bytes) that hold every split's
+// reduction range, a grid inside the device limits, and the outputs its epilogue writes.
+// Returns "" when they hold, else what does not.
+std::string gemm_check(int epi, const GemmArgs &a, int splits) {
+    if (a.M <= 0 || a.N <= 0 || a.M % 128 || a.N % 128) return "output extent not whole 128 x 128 tiles";
+    if (a.M / 128 > 65535 || a.N / 128 > 2147483647LL) return "grid beyond the device limits";
+    if (splits < 1 || splits > 1024) return "split count out of range";
+    if (a.k_len <= 0 || a.k_len % KC) return "reduction length not whole 64-long chunks";
+    if (!a.A || !a.B || !aligned16(a.A) || !aligned16(a.B)) return "A or B missing or not 16-byte aligned";
+    if (a.lda % 8 || a.ldb % 8) return "row pitch of A or B not a multiple of 16 bytes";
+    if (a.lda < a.k_len * splits || a.ldb < a.k_len * splits) return "rows of A or B shorter than the reduction";
+    if (epi == EPI_FWD && (!a.bias || !a.h || (a.hT && a.ldT < a.M))) return "forward epilogue outputs";
+    if (epi == EPI_BWD && (!a.zprev || (!a.dzf && !a.dzb) || (a.dzT && a.ldT < a.M)))
+        return "backward epilogue inputs or outputs";
+    if (epi == EPI_PART && !a.part) return "partial-sum output";
+    return "";
+}
+
+// the network's buffers inside its one allocation at `b`, at the offsets of mlp_bytes
+void assign_buffers(qs_mlp *c, char *b, const std::vector<size_t> &o) {
+    int k = 0;
+    c->P = (float *)(b + o[k++]); c->G = (float *)(b + o[k++]); c->Mo = (float *)(b + o[k++]); c->Vo = (float *)(b + o[k++]);
+    c->Wb = (bf16_t *)(b + o[k++]); c->WTb = (bf16_t *)(b + o[k++]);
+    c->Wp = (bf16_t *)(b + o[k++]); c->phi = (float *)(b + o[k++]);
+    for (int i = 0; i < 4; ++i) c->z[i] = (float *)(b + o[k++]);
+    for (int i = 0; i < 4; ++i) c->h[i] = (bf16_t *)(b + o[k++]);
+    for (int i = 0; i < 3; ++i) c->hT[i] = (bf16_t *)(b + o[k++]);
+    c->dzb[0] = (bf16_t *)(b + o[k++]); c->dzb[1] = (bf16_t *)(b + o[k++]);
+    c->dzT[0] = (bf16_t *)(b + o[k++]); c->dzT[1] = (bf16_t *)(b + o[k++]);
+    c->dz1 = (float *)(b + o[k++]); c->y = (float *)(b + o[k++]); c->dy = (float *)(b + o[k++]);
+    c->part = (float *)(b + o[k++]); c->colpart = (float *)(b + o[k++]); c->w5part = (float *)(b + o[k++]);
+    c->l1part = (float *)(b + o[k++]); c->lossp = (float *)(b + o[k++]); c->loss = (float *)(b + o[k++]);
+}
+
+// The GEMMs of a training step on B rows: the forward product of hidden layer l (0..2), and
+// for the backward pass of layer l the weight gradient (split over row ranges) and the input
+// gradient, reading and writing the ping-pong buffers `cur` / `cur ^ 1`.
+GemmArgs fwd_args(const qs_mlp *c, int l, int64_t rows) {
+    GemmArgs a{};
+    a.A = c->h[l]; a.lda = D;
+    a.B = c->Wb + (int64_t)l * D * D; a.ldb = D;
+    a.k_len = D; a.M = rows; a.N = D;
+    a.bias = c->P + off_b(l);
+    a.z = c->z[l + 1];
+    a.h = c->h[l + 1];
+    a.hT = l < 2 ? c->hT[l + 1] : nullptr;
+    a.ldT = c->max_batch;
+    return a;
+}
+// row splits of the weight gradients: at most 16, >= 512 rows each, dividing B/64 (each
+// split's rows are whole reduction chunks)
+int wgrad_splits(int64_t B) {
+    int splits = (int)std::max<int64_t>(1, std::min<int64_t>(16, B / 512));
+    while ((B / 64) % splits != 0) --splits;
+    return splits;
+}
+GemmArgs wgrad_args(const qs_mlp *c, int l, int cur, int64_t B, int splits) {
+    GemmArgs w{};
+    w.A = c->dzT[cur]; w.lda = c->max_batch;
+    w.B = c->hT[l]; w.ldb = c->max_batch;
+    w.k_len = B / splits; w.M = D; w.N = D;
+    w.part = c->part;
+    return w;
+}
+GemmArgs dgrad_args(const qs_mlp *c, int l, int cur, int64_t B) {
+    GemmArgs d{};
+    d.A = c->dzb[cur]; d.lda = D;
+    d.B = c->WTb + (int64_t)l * D * D; d.ldb = D;
+    d.k_len = D; d.M = B; d.N = D;
+    d.zprev = c->z[l];
+    d.ldT = c->max_batch;
+    if (l > 0) {
+        d.dzb = c->dzb[cur ^ 1];
+        d.dzT = c->dzT[cur ^ 1];
+        d.colpart = c->colpart;
+    } else {
+        d.dzf = c->dz1;
+    }
+    return d;
+}
+
+hipError_t gemm_launch(int epi, const GemmArgs &a, int splits, hipStream_t s) {
+    const std::string why = gemm_check(epi, a, splits);
+    if (!why.empty()) {
+        qs::set_last_error("gemm_nt launch: " + why);
+        return hipErrorInvalidValue;
+    }
     dim3 grid((unsigned)(a.N / 128), (unsigned)(a.M / 128), (unsigned)splits), block(512);
     if (epi == EPI_FWD) hipLaunchKernelGGL(gemm_nt<EPI_FWD>, grid, block, 0, s, a);
     else if (epi == EPI_BWD) hipLaunchKernelGGL(gemm_nt<EPI_BWD>, grid, block, 0, s, a);
     else hipLaunchKernelGGL(gemm_nt<EPI_PART>, grid, block, 0, s, a);
+    return hipGetLastError();
 }
 
 // training forward pass over a batch of `rows` (multiple of 128) rows: stores z, h and the
 // transposes h^T for the weight gradients, the outputs y, dy and the loss partials
-void forward_train(qs_mlp *c, const float *x, int64_t rows, const float *t, float inv_batch2) {
+hipError_t forward_train(qs_mlp *c, const float *x, int64_t rows, const float *t, float inv_batch2) {
     hipStream_t s = c->stream;
     const int64_t ldT = c->max_batch;
     hipLaunchKernelGGL(l1_fwd, dim3(D / 64, (unsigned)(rows / 64)), dim3(256), 0, s, x, rows, c->P, c->z[0], c->h[0],
                        c->hT[0], ldT);
     for (int l = 0; l < 3; ++l) {
-        GemmArgs a{};
-        a.A = c->h[l]; a.lda = D;
-        a.B = c->Wb + (int64_t)l * D * D; a.ldb = D;
-        a.k_len = D; a.M = rows; a.N = D;
-        a.bias = c->P + off_b(l);
-        a.z = c->z[l + 1];
-        a.h = c->h[l + 1];
-        a.hT = l < 2 ? c->hT[l + 1] : nullptr;
-        a.ldT = ldT;
-        gemm_launch(EPI_FWD, a, 1, s);
+        const hipError_t e = gemm_launch(EPI_FWD, fwd_args(c, l, rows), 1, s);
+        if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(l5_fwd, dim3((unsigned)(rows / 4)), dim3(256), 0, s, c->h[3], c->P, rows, c->y, t, inv_batch2,
                        c->dy, c->lossp);
+    return hipGetLastError();
 }
 
 // bfloat16 copies of W2..W4 for training (row-major and transposed); the packed inference
@@ -908,19 +998,7 @@ qs_status qs_mlp_create(int32_t max_batch, void *hip_stream, qs_mlp **out) {
     std::vector<size_t> o;
     const size_t bytes = mlp_bytes(max_batch, &o);
     if (hipMalloc(&c->mem, bytes) != hipSuccess) { delete c; return mfail(QS_ERR_ALLOC, "hipMalloc of the network buffers failed"); }
-    char *b = static_cast<char *>(c->mem);
-    int k = 0;
-    c->P = (float *)(b + o[k++]); c->G = (float *)(b + o[k++]); c->Mo = (float *)(b + o[k++]); c->Vo = (float *)(b + o[k++]);
-    c->Wb = (bf16_t *)(b + o[k++]); c->WTb = (bf16_t *)(b + o[k++]);
-    c->Wp = (bf16_t *)(b + o[k++]); c->phi = (float *)(b + o[k++]);
-    for (int i = 0; i < 4; ++i) c->z[i] = (float *)(b + o[k++]);
-    for (int i = 0; i < 4; ++i) c->h[i] = (bf16_t *)(b + o[k++]);
-    for (int i = 0; i < 3; ++i) c->hT[i] = (bf16_t *)(b + o[k++]);
-    c->dzb[0] = (bf16_t *)(b + o[k++]); c->dzb[1] = (bf16_t *)(b + o[k++]);
-    c->dzT[0] = (bf16_t *)(b + o[k++]); c->dzT[1] = (bf16_t *)(b + o[k++]);
-    c->dz1 = (float *)(b + o[k++]); c->y = (float *)(b + o[k++]); c->dy = (float *)(b + o[k++]);
-    c->part = (float *)(b + o[k++]); c->colpart = (float *)(b + o[k++]); c->w5part = (float *)(b + o[k++]);
-    c->l1part = (float *)(b + o[k++]); c->lossp = (float *)(b + o[k++]); c->loss = (float *)(b + o[k++]);
+    assign_buffers(c, static_cast<char *>(c->mem), o);
     hipError_t e = hipMemsetAsync(c->mem, 0, bytes, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) {
@@ -1000,7 +1078,7 @@ qs_status qs_mlp_grads(qs_mlp *c, const float *x, const float *t, int32_t batch,
     MLP_HIP(hipSetDevice(c->device), "hipSetDevice");
     hipStream_t s = c->stream;
     const int64_t B = batch, ldT = c->max_batch, tiles = B / 64;
-    forward_train(c, x, B, t, 2.0f / (float)B);
+    MLP_HIP(forward_train(c, x, B, t, 2.0f / (float)B), "forward kernels");
     // last layer
     hipLaunchKernelGGL(l5_bwd, dim3(D / 64, (unsigned)tiles), dim3(256), 0, s, c->dy, c->P, c->z[3], c->h[3],
                        c->dzb[0], c->dzT[0], ldT, c->colpart, c->w5part);
@@ -1010,34 +1088,13 @@ qs_status qs_mlp_grads(qs_mlp *c, const float *x, const float *t, int32_t batch,
                        (int64_t)1, c->G + OFF_W5);
     hipLaunchKernelGGL(reduce_db5, dim3(1), dim3(256), 0, s, c->lossp, (int)(B / 4), c->G, c->loss);
     // layers 4, 3, 2: weight gradient (split over rows), then the input gradient
-    // row splits of the weight gradients: at most 16, >= 512 rows each, dividing B/64 (each
-    // split's rows are whole reduction chunks)
-    int splits = (int)std::max<int64_t>(1, std::min<int64_t>(16, B / 512));
-    while ((B / 64) % splits != 0) --splits;
+    const int splits = wgrad_splits(B);
     int cur = 0;
     for (int l = 2; l >= 0; --l) {
-        GemmArgs w{};
-        w.A = c->dzT[cur]; w.lda = ldT;
-        w.B = c->hT[l]; w.ldb = ldT;
-        w.k_len = B / splits; w.M = D; w.N = D;
-        w.part = c->part;
-        gemm_launch(EPI_PART, w, splits, s);
+        MLP_HIP(gemm_launch(EPI_PART, wgrad_args(c, l, cur, B, splits), splits, s), "weight-gradient GEMM");
         hipLaunchKernelGGL(reduce_parts, dim3(D * D / 256), dim3(256), 0, s, c->part, splits, (int64_t)D * D,
                            (int64_t)D * D, (int64_t)1, c->G + off_w(l));
-        GemmArgs d{};
-        d.A = c->dzb[cur]; d.lda = D;
-        d.B = c->WTb + (int64_t)l * D * D; d.ldb = D;
-        d.k_len = D; d.M = B; d.N = D;
-        d.zprev = c->z[l];
-        d.ldT = ldT;
-        if (l > 0) {
-            d.dzb = c->dzb[cur ^ 1];
-            d.dzT = c->dzT[cur ^ 1];
-            d.colpart = c->colpart;
-        } else {
-            d.dzf = c->dz1;
-        }
-        gemm_launch(EPI_BWD, d, 1, s);
+        MLP_HIP(gemm_launch(EPI_BWD, dgrad_args(c, l, cur, B), 1, s), "input-gradient GEMM");
         if (l > 0)
             hipLaunchKernelGGL(reduce_parts_wide, dim3(D / 4), dim3(256), 0, s, c->colpart, (int)tiles, (int64_t)D,
                                (int64_t)D, (int64_t)1, c->G + off_b(l - 1));
@@ -1082,6 +1139,43 @@ void qs_mlp_free(qs_mlp *c) {
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->mem);
     delete c;
+}
+
+int32_t qs_debug_mlp_gemm_check(int32_t max_batch, int32_t batch, char *msg, int32_t msg_len) {
+    auto say = [&](const std::string &m) {
+        if (msg && msg_len > 0) {
+            std::strncpy(msg, m.c_str(), (size_t)msg_len - 1);
+            msg[msg_len - 1] = '\0';
+        }
+    };
+    if (max_batch < 128 || max_batch % 128 != 0 || max_batch > (1 << 20) || batch < 128 || batch % 128 != 0 ||
+        batch > max_batch) {
+        say("batch sizes outside what qs_mlp_create and qs_mlp_grads accept");
+        return -1;
+    }
+    // the buffers at the offsets of a real network, from a base aligned as hipMalloc aligns
+    qs_mlp c;
+    c.max_batch = max_batch;
+    std::vector<size_t> o;
+    (void)mlp_bytes(max_batch, &o);
+    assign_buffers(&c, reinterpret_cast<char *>((uintptr_t)1 << 40), o);
+    const int64_t B = batch;
+    std::string why;
+    for (int l = 0; l < 3 && why.empty(); ++l) {
+        why = gemm_check(EPI_FWD, fwd_args(&c, l, B), 1);
+        if (!why.empty()) why = "forward layer " + std::to_string(l) + ": " + why;
+    }
+    const int splits = wgrad_splits(B);
+    int cur = 0;
+    for (int l = 2; l >= 0 && why.empty(); --l) {
+        why = gemm_check(EPI_PART, wgrad_args(&c, l, cur, B, splits), splits);
+        if (!why.empty()) { why = "weight gradient " + std::to_string(l) + ": " + why; break; }
+        why = gemm_check(EPI_BWD, dgrad_args(&c, l, cur, B), 1);
+        if (!why.empty()) why = "input gradient " + std::to_string(l) + ": " + why;
+        cur ^= 1;
+    }
+    say(why.empty() ? "ok, " + std::to_string(splits) + " row splits" : why);
+    return why.empty() ? 0 : 1;
 }
 
 }  // extern "C"

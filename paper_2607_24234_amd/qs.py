@@ -91,7 +91,7 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_mlp_train_step", "qs_mlp_free", "qs_growth_targets", "qs_growth_sample",
            "qs_growth_features", "qs_growth_calibrate", "qs_growth_map", "qs_growth_map_noalloc",
            "qs_sync_check", "qs_set_rollback", "qs_debug_set_wait_budget", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
-           "qs_debug_splitmix64", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
+           "qs_debug_splitmix64", "qs_debug_mlp_gemm_check", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
            "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope",
            "qs_regime_map", "qs_surrogate_train", "qs_surrogate_load", "qs_surrogate_net", "qs_surrogate_table",
            "qs_surrogate_free"]
@@ -171,6 +171,8 @@ def lib():
     L.qs_set_rollback.argtypes = [vp, ctypes.c_int32]
     L.qs_debug_set_wait_budget.restype = ctypes.c_int
     L.qs_debug_set_wait_budget.argtypes = [vp, ctypes.c_double]
+    L.qs_debug_mlp_gemm_check.restype = ctypes.c_int32
+    L.qs_debug_mlp_gemm_check.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32]
     L.qs_steps_done.restype = ctypes.c_int64
     L.qs_steps_done.argtypes = [vp]
     L.qs_get_state.restype = ctypes.c_int

@@ -168,3 +168,23 @@ def test_failure_handling_entry_points_reject_null_context():
     assert L.qs_set_rollback(None, 1) == qs.QS_ERR_ARG
     assert L.qs_debug_set_wait_budget(None, 0.0) == qs.QS_ERR_ARG
     assert L.qs_sync_check(None) == qs.QS_ERR_ARG
+
+
+def test_training_gemm_configurations_hold_the_kernel_invariants():
+    """Host only: the arguments of every matrix-core GEMM of a training step, at the buffer
+    offsets of a real network, against what the GEMM kernel assumes (the same check runs
+    before each launch), over the batch sizes qs_mlp_grads accepts, including the 8192 rows
+    the surrogate trains with and batches whose row count divides into few splits."""
+    import ctypes
+    from paper_2607_24234_amd import qs
+    L = qs.lib()
+    buf = ctypes.create_string_buffer(256)
+    for max_batch in (128, 8192, 65536):
+        for batch in sorted({128, 384, 640, 1152, 4096, 8192, 8320, 65536}):
+            if batch > max_batch:
+                continue
+            rc = L.qs_debug_mlp_gemm_check(max_batch, batch, buf, 256)
+            assert rc == 0, (max_batch, batch, buf.value)
+    assert L.qs_debug_mlp_gemm_check(8192, 8192, buf, 256) == 0 and b"16 row splits" in buf.value
+    assert L.qs_debug_mlp_gemm_check(8192, 100, buf, 256) == -1
+    assert L.qs_debug_mlp_gemm_check(1024, 2048, buf, 256) == -1
