@@ -24,6 +24,7 @@ _LIB = os.path.join(HERE, "liborc.so")
 DROP_LONGITUDINAL = 1
 NO_RESTORING = 2
 STEADY_INFLOW = 4
+STATIONARY_FRONT = 16
 
 SEED_NOISE = 0
 SEED_UNIFORM = 1
@@ -102,10 +103,10 @@ def _declare(L):
     L.orc_run_modes.restype = ctypes.c_int
     L.orc_run_modes.argtypes = [B, ctypes.c_int, D, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_int, D, D, D, D, ctypes.c_int, D, D, D,
-                                ctypes.c_int]
+                                ctypes.c_int, D]
     L.orc_mode_fields.restype = ctypes.c_int
     L.orc_mode_fields.argtypes = [B, ctypes.c_double, D, D, D, ctypes.c_double,
-                                  D, D, D, D, D]
+                                  D, D, D, D, D, D]
     L.orc_march_io.restype = ctypes.c_int
     L.orc_march_io.argtypes = [B, D, D, D, D]
     L.orc_collapse.restype = ctypes.c_int
@@ -192,16 +193,28 @@ def seed(beam, k, kind, amp, rng_seed=0, instance=0, n_modes_total=None, mode_of
     return st
 
 
+def _front(beam, front, nm):
+    if not beam.flags & STATIONARY_FRONT:
+        return None
+    if front is None:
+        raise ValueError("the stationary-front option needs the modes' front values")
+    f = np.ascontiguousarray(np.broadcast_to(np.asarray(front, np.complex128), (nm,)))
+    return f
+
+
 def run(beam, k, dtau, n_steps, state, out_every=1, renorm=False, want_fields=True,
-        want_max=True, n_threads=0):
+        want_max=True, n_threads=0, front=None):
     """Advance `state` in place by n_steps RK4 steps; returns (ln_e, ln_b, max_ln_a).
 
     ln_e/ln_b: [n_snap, n_xi, n_modes], max_ln_a: [n_steps, n_modes] (None if not wanted).
+    front: per mode the value n_p holds ahead of the beam (complex, unscaled), required with
+    the STATIONARY_FRONT flag and ignored otherwise.
     """
     k = np.ascontiguousarray(k, dtype=np.float64).ravel()
     nm = len(k)
     if state.n.shape != (nm, beam.n_species, beam.n_xi):
         raise ValueError("state shape mismatch")
+    fr = _front(beam, front, nm)
     out_every = max(1, int(out_every))
     n_snap = 1 if n_steps == 0 else -(-n_steps // out_every)
     ln_e = np.empty((n_snap, beam.n_xi, nm)) if want_fields else None
@@ -210,14 +223,21 @@ def run(beam, k, dtau, n_steps, state, out_every=1, renorm=False, want_fields=Tr
     rc = lib().orc_run_modes(beam.ptr(), nm, _dp(k), float(dtau), int(n_steps), out_every,
                              _dp(state.n.view(np.float64)), _dp(state.pz.view(np.float64)),
                              _dp(state.pt.view(np.float64)), _dp(state.log2_scale),
-                             1 if renorm else 0, _dp(ln_e), _dp(ln_b), _dp(mx), int(n_threads))
+                             1 if renorm else 0, _dp(ln_e), _dp(ln_b), _dp(mx), int(n_threads),
+                             None if fr is None else _dp(fr.view(np.float64)))
     if rc != 0:
         raise RuntimeError("orc_run_modes failed")
     return ln_e, ln_b, mx
 
 
-def mode_fields(beam, k, state, m=0):
-    """Diagnostics of mode m: dict with np (n_p at centres), e_par, ln_e, ln_b, ln_a."""
+def mode_fields(beam, k, state, m=0, front=None):
+    """Diagnostics of mode m: dict with np (n_p at centres), e_par, ln_e, ln_b, ln_a.
+    front: mode m's front value with the STATIONARY_FRONT flag."""
+    fr = None
+    if beam.flags & STATIONARY_FRONT:
+        if front is None:
+            raise ValueError("the stationary-front option needs the mode's front value")
+        fr = np.array([complex(front).real, complex(front).imag])
     N = beam.n_xi
     npc = np.empty(N, np.complex128)
     epar = np.empty(N, np.complex128)
@@ -228,7 +248,7 @@ def mode_fields(beam, k, state, m=0):
     rc = lib().orc_mode_fields(beam.ptr(), float(k), _dp(n.view(np.float64)),
                                _dp(pz.view(np.float64)), _dp(pt.view(np.float64)),
                                float(state.log2_scale[m]), _dp(npc.view(np.float64)),
-                               _dp(epar.view(np.float64)), _dp(ln_e), _dp(ln_b), _dp(ln_a))
+                               _dp(epar.view(np.float64)), _dp(ln_e), _dp(ln_b), _dp(ln_a), _dp(fr))
     if rc != 0:
         raise RuntimeError("orc_mode_fields failed")
     return {"np": npc, "e_par": epar, "ln_e": ln_e, "ln_b": ln_b, "ln_a": ln_a}

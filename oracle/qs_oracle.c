@@ -27,7 +27,9 @@
  *   - pz_s lives on the interior faces (j+1)h, j = 0..N-2; the two outer faces carry no
  *     flux (n0 = 0 outside the beam);  n0 on a face is the mean of the two centres;
  *   - the plasma oscillator is advanced through each cell with its exact solution for a
- *     cell-constant source, starting from n_p = d_xi n_p = 0 ahead of the front;
+ *     cell-constant source, starting from n_p = d_xi n_p = 0 ahead of the front (with the
+ *     stationary-front option, from n_p = F, d_xi n_p = 0, F the mode's front value held for
+ *     every tau: the boundary value of Sec. III.D and Appendix C);
  *   - classic fourth-order Runge-Kutta in tau, each stage one full march over the beam.
  *
  * Fields (derived from Maxwell's equations under the same quasistatic ordering, neglecting
@@ -53,6 +55,7 @@
 #define ORC_DROP_LONGITUDINAL 1 /* drop the gamma^-2 longitudinal term (Eq. CFI_st_master) */
 #define ORC_NO_RESTORING 2      /* replace (d_xi^2 + 1) by d_xi^2 (Eq. CFI_st_master_front) */
 #define ORC_STEADY_INFLOW 4     /* plasma ahead of the front in equilibrium with cell 0 */
+#define ORC_STATIONARY_FRONT 16 /* plasma ahead of the front held at a given n_p, d_xi n_p = 0 */
 
 typedef struct {
     int n_species;
@@ -97,13 +100,14 @@ static double n0_face(const orc_beam *b, int s, int j)
 /* One causal march of Eq. plasma_oscillations_QSA through the beam for the cell-constant
  * charge density rho[j].  Returns n_p and d_xi n_p at the cell centres and d_xi n_p at the
  * rear face of every cell. */
-void orc_march(const orc_beam *b, const double complex *rho, double complex *np_c,
-               double complex *dnp_c, double complex *dnp_f)
+static void march_from(const orc_beam *b, const double complex *rho, double complex front,
+                       double complex *np_c, double complex *dnp_c, double complex *dnp_f)
 {
     const int N = b->n_xi;
     const double h = b->h;
     double complex n = 0.0, dn = 0.0; /* unperturbed plasma ahead of the front */
     if (b->flags & ORC_STEADY_INFLOW) n = rho[0];
+    if (b->flags & ORC_STATIONARY_FRONT) n = front;
     for (int j = 0; j < N; ++j) {
         const double complex r = rho[j];
         if (b->flags & ORC_NO_RESTORING) {
@@ -131,6 +135,12 @@ void orc_march(const orc_beam *b, const double complex *rho, double complex *np_
     }
 }
 
+void orc_march(const orc_beam *b, const double complex *rho, double complex *np_c,
+               double complex *dnp_c, double complex *dnp_f)
+{
+    march_from(b, rho, 0.0, np_c, dnp_c, dnp_f);
+}
+
 /* ------------------------------------------------------------------ per-species state */
 
 /* state of one mode: for species s, arrays of n_xi complex values each
@@ -143,6 +153,7 @@ typedef struct {
 
 typedef struct {
     double complex *rho, *np_c, *dnp_c, *dnp_f;
+    double complex front; /* the mode's front value in the stored state's units */
 } orc_work;
 
 static void charge_density(const orc_beam *b, const orc_state *x, double complex *rho)
@@ -164,7 +175,7 @@ static void rates(const orc_beam *b, double k, const orc_state *x, orc_state *dx
     const double kap = 1.0 / (1.0 + k * k);
 
     charge_density(b, x, w->rho);
-    orc_march(b, w->rho, w->np_c, w->dnp_c, w->dnp_f);
+    march_from(b, w->rho, w->front, w->np_c, w->dnp_c, w->dnp_f);
 
     for (int s = 0; s < b->n_species; ++s) {
         const double qm = b->q[s] / b->m[s];
@@ -238,7 +249,7 @@ static void fields(const orc_beam *b, double k, const orc_state *x, orc_work *w,
     const int N = b->n_xi;
     const double kap = 1.0 / (1.0 + k * k);
     charge_density(b, x, w->rho);
-    orc_march(b, w->rho, w->np_c, w->dnp_c, w->dnp_f);
+    march_from(b, w->rho, w->front, w->np_c, w->dnp_c, w->dnp_f);
     const double shift = log2_scale * log(2.0);
     for (int j = 0; j < N; ++j) {
         double complex epar = -kap * w->dnp_c[j];
@@ -294,6 +305,8 @@ static double complex *zalloc(size_t n) { return (double complex *)calloc(n ? n 
  *   n [((m*S + s)*N + j)*2 + {0,1}],  same for pz and pt.
  * log2_scale[m]: power of two already divided out of mode m (in/out).
  * renorm: if nonzero, renormalize each mode after every step (exact powers of two).
+ * front: with ORC_STATIONARY_FRONT, per mode the complex value F (interleaved re/im, in
+ *   unscaled units) that n_p takes ahead of the front at every tau; else ignored (NULL).
  * Outputs, any may be NULL:
  *   ln_e, ln_b  [n_snap][N][n_modes]   fields of the state at the start of each step s
  *               with s % out_every == 0 (n_snap = ceil(n_steps/out_every)); when
@@ -303,9 +316,11 @@ static double complex *zalloc(size_t n) { return (double complex *)calloc(n ? n 
  */
 int orc_run_modes(const orc_beam *b, int n_modes, const double *k, double dtau, int n_steps,
                   int out_every, double *n_io, double *pz_io, double *pt_io, double *log2_scale,
-                  int renorm, double *ln_e, double *ln_b, double *max_ln_a, int n_threads)
+                  int renorm, double *ln_e, double *ln_b, double *max_ln_a, int n_threads,
+                  const double *front)
 {
     if (!b || b->n_xi < 1 || b->n_species < 1 || n_modes < 0 || n_steps < 0 || !k) return -1;
+    if ((b->flags & ORC_STATIONARY_FRONT) && !front) return -1;
     if (out_every < 1) out_every = 1;
     const int N = b->n_xi, S = b->n_species, len = S * N;
     int status = 0;
@@ -325,7 +340,7 @@ int orc_run_modes(const orc_beam *b, int n_modes, const double *k, double dtau, 
             all[i]->pt = zalloc(len);
             ok = ok && all[i]->n && all[i]->pz && all[i]->pt;
         }
-        orc_work w = {zalloc(N), zalloc(N), zalloc(N), zalloc(N)};
+        orc_work w = {zalloc(N), zalloc(N), zalloc(N), zalloc(N), 0.0};
         double *ln_a = (double *)calloc(N, sizeof(double));
         double *tmp_e = (double *)calloc(N, sizeof(double));
         double *tmp_b = (double *)calloc(N, sizeof(double));
@@ -344,8 +359,11 @@ int orc_run_modes(const orc_beam *b, int n_modes, const double *k, double dtau, 
                 x.pt[i] = pt_io[o] + I * pt_io[o + 1];
             }
             double l2 = log2_scale ? log2_scale[m] : 0.0;
+            const double complex f0 =
+                (b->flags & ORC_STATIONARY_FRONT) ? front[2 * m] + I * front[2 * m + 1] : 0.0;
             int n_snap_steps = n_steps == 0 ? 1 : n_steps;
             for (int st = 0; st < n_snap_steps; ++st) {
+                w.front = f0 * ldexp(1.0, -(int)l2); /* the stored state's units */
                 int snap = (st % out_every == 0);
                 if ((snap && (ln_e || ln_b)) || (max_ln_a && n_steps > 0)) {
                     fields(b, k[m], &x, &w, l2, tmp_e, tmp_b, ln_a, NULL, NULL);
@@ -394,14 +412,17 @@ int orc_run_modes(const orc_beam *b, int n_modes, const double *k, double dtau, 
 }
 
 /* Diagnostics of one mode's state (same layout as one mode of orc_run_modes):
- * np_c, e_par: complex interleaved [N]; ln_e, ln_b, ln_a: [N].  Any may be NULL. */
+ * np_c, e_par: complex interleaved [N]; ln_e, ln_b, ln_a: [N].  Any may be NULL.
+ * front: the mode's front value (re, im; unscaled) with ORC_STATIONARY_FRONT, else NULL. */
 int orc_mode_fields(const orc_beam *b, double k, const double *n_in, const double *pz_in,
                     const double *pt_in, double log2_scale, double *np_c, double *e_par,
-                    double *ln_e, double *ln_b, double *ln_a)
+                    double *ln_e, double *ln_b, double *ln_a, const double *front)
 {
     const int N = b->n_xi, len = b->n_species * N;
+    if ((b->flags & ORC_STATIONARY_FRONT) && !front) return -1;
     orc_state x = {zalloc(len), zalloc(len), zalloc(len)};
-    orc_work w = {zalloc(N), zalloc(N), zalloc(N), zalloc(N)};
+    orc_work w = {zalloc(N), zalloc(N), zalloc(N), zalloc(N), 0.0};
+    if (b->flags & ORC_STATIONARY_FRONT) w.front = (front[0] + I * front[1]) * ldexp(1.0, -(int)log2_scale);
     double *te = (double *)calloc(N, sizeof(double)), *tb = (double *)calloc(N, sizeof(double));
     double *ta = (double *)calloc(N, sizeof(double));
     if (!x.n || !x.pz || !x.pt || !w.rho || !w.np_c || !w.dnp_c || !w.dnp_f || !te || !tb || !ta)
