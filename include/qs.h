@@ -81,7 +81,8 @@ enum {
     QS_FLAG_DROP_LONGITUDINAL = 1, /* drop the gamma^-2 d_xi^2 term: Eq. CFI_st_master */
     QS_FLAG_NO_RESTORING = 2,      /* plasma operator d_xi^2 only: Eq. CFI_st_master_front */
     QS_FLAG_STEADY_INFLOW = 4,     /* plasma ahead of the front equals cell 0 (uniform test) */
-    QS_FLAG_FPERP_SNAPSHOTS = 8    /* output option: snapshots' ln_e holds ln|F_perp| (below) */
+    QS_FLAG_FPERP_SNAPSHOTS = 8,   /* output option: snapshots' ln_e holds ln|F_perp| (below) */
+    QS_FLAG_STATIONARY_FRONT = 16  /* plasma ahead of the front held at its tau = 0 value (below) */
 };
 
 /*
@@ -126,6 +127,17 @@ enum {
  *                                 transverse force E_perp - B_perp = i k Psi on a beam particle
  *                                 (Sec. III.D, the quantity of Figs. 3 and 4); ln_b and the
  *                                 per-step max ln A are unchanged.
+ *                                 QS_FLAG_STATIONARY_FRONT (spectral geometry only; not with
+ *                                 QS_FLAG_STEADY_INFLOW): the plasma ahead of the beam is held
+ *                                 at its tau = 0 state for every step, the boundary value that
+ *                                 Sec. III.D's numerical solution keeps (F_perp(xi = 0, tau) =
+ *                                 F_perp(xi = 0, 0)) and that Appendix C's extended
+ *                                 disturbance has (Eq. extended_BC): per mode n_p = F and
+ *                                 d_xi n_p = 0 at the front, F the charge density of cell 0 in
+ *                                 the state qs_init seeds (the plasma in equilibrium with the
+ *                                 beam's first cell at tau = 0).  F belongs to the context, not
+ *                                 to the state: qs_set_state and checkpoints leave it as
+ *                                 seeded (0 for QS_SEED_NONE and the front impulse).
  */
 typedef struct qs_params {
     int32_t n_species;

@@ -71,7 +71,8 @@ struct Plan {
     std::vector<int2> wave_table;  // [n_wg][wg_waves]: (global block, segment) or (-1, -1)
     // workspace offsets (bytes)
     size_t off_state, off_omega, off_shape, off_k, off_log2s, off_epend, off_inst, off_blk,
-        off_iidx, off_err, off_wtab, total;
+        off_iidx, off_err, off_wtab, off_front, total;
+    int64_t n_blocks = 0;
 };
 
 // 32-bit words of the error region: see StepArgs::err
@@ -181,6 +182,7 @@ qs_status validate_one(const qs_params &p, int i) {
         if (p.precision != QS_FP32) return fail(QS_ERR_UNSUPPORTED, at + "the transverse grid runs in FP32 only");
         if (p.flags & QS_FLAG_STEADY_INFLOW) return fail(QS_ERR_UNSUPPORTED, at + "STEADY_INFLOW is spectral only");
         if (p.flags & QS_FLAG_FPERP_SNAPSHOTS) return fail(QS_ERR_UNSUPPORTED, at + "FPERP_SNAPSHOTS is spectral only");
+        if (p.flags & QS_FLAG_STATIONARY_FRONT) return fail(QS_ERR_UNSUPPORTED, at + "STATIONARY_FRONT is spectral only");
     } else {
         if (p.n_modes < 1 || p.n_modes > (int64_t(1) << 26)) return fail(QS_ERR_ARG, at + "n_modes must be in [1, 2^26]");
         if (!p.kx) return fail(QS_ERR_ARG, at + "kx is required");
@@ -217,8 +219,11 @@ qs_status validate_one(const qs_params &p, int i) {
             if (k2 == 0.0) return fail(QS_ERR_ARG, at + "FRONT_IMPULSE seed needs k != 0 for every mode");
         }
     }
-    if (p.flags & ~(QS_FLAG_DROP_LONGITUDINAL | QS_FLAG_NO_RESTORING | QS_FLAG_STEADY_INFLOW | QS_FLAG_FPERP_SNAPSHOTS))
+    if (p.flags & ~(QS_FLAG_DROP_LONGITUDINAL | QS_FLAG_NO_RESTORING | QS_FLAG_STEADY_INFLOW | QS_FLAG_FPERP_SNAPSHOTS |
+                    QS_FLAG_STATIONARY_FRONT))
         return fail(QS_ERR_ARG, at + "unknown flag bits");
+    if ((p.flags & QS_FLAG_STEADY_INFLOW) && (p.flags & QS_FLAG_STATIONARY_FRONT))
+        return fail(QS_ERR_ARG, at + "STEADY_INFLOW and STATIONARY_FRONT are exclusive");
     return QS_OK;
 }
 
@@ -379,6 +384,8 @@ qs_status make_plan(const qs_params *params, int32_t n, const qs_plan *plan, Pla
     pl.off_iidx = o; o = align_up(o + (size_t)n * sizeof(int32_t));
     pl.off_err = o; o = align_up(o + sizeof(uint32_t) * kErrWords);
     pl.off_wtab = o; o = align_up(o + pl.wave_table.size() * sizeof(int2));
+    pl.off_front = o; o = align_up(o + (size_t)blocks * pl.nc * kWave * sizeof(double));
+    pl.n_blocks = blocks;
     pl.total = o;
     return QS_OK;
 }
@@ -523,6 +530,12 @@ qs_status seed_state(qs_ctx *c, const qs_params *params) {
         }
         i0 = i1;
     }
+    // the stationary front's values: cell 0's charge density of the seeded (tau = 0) state
+    QS_HIP(launch_front_capture(pl.precision, pl.nc, c->at(pl.off_state),
+                                reinterpret_cast<const int32_t *>(c->at(pl.off_blk)),
+                                reinterpret_cast<const InstDev *>(c->at(pl.off_inst)), (int)pl.n_blocks,
+                                reinterpret_cast<double *>(c->at(pl.off_front)), c->stream),
+           "front capture");
     return QS_OK;
 }
 
@@ -660,6 +673,7 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     a.total_modes = (int32_t)pl.total_modes;
     a.err = reinterpret_cast<uint32_t *>(c->at(pl.off_err));
     a.wave_table = reinterpret_cast<const int2 *>(c->at(pl.off_wtab));
+    a.front0 = reinterpret_cast<const double *>(c->at(pl.off_front));
     // a segment waits for its predecessor to finish one step of its own cells: allow 2 s
     // plus 20 us per cell before the wait reports a stall
     a.wait_ticks = (uint64_t)(c->wall_clock_hz * (c->wait_seconds >= 0.0 ? c->wait_seconds

@@ -60,6 +60,8 @@ struct StepArgs {
     int32_t keyed;            // 1: max_ln_a holds order-preserving keys (combined by atomic max)
     uint64_t wait_ticks;      // wall-clock ticks a segment hand-off wait allows before giving up
     const int2 *wave_table;   // per (workgroup, wave slot): (global block, segment) or (-1, -1)
+    const double *front0;     // [global block][column][lane]: rho of cell 0 at tau = 0 (the
+                              // stationary front's n_p, unscaled)
     uint32_t *err;            // [0]: 1 + padded mode after a non-finite renormalization;
                               // [1]: 1 if a segment hand-off wait gave up;
                               // [2..3]: uint64 ~(step << 32 | padded mode) of the first
@@ -92,6 +94,10 @@ struct SeedArgs {
 };
 
 // launchers (qs_spectral.hip)
+// front0[(gb * nc + c) * 64 + lane] = rho of cell 0 of that column of the stored state (the
+// state at tau = 0 when called after seeding)
+hipError_t launch_front_capture(int precision, int nc, const void *state, const int32_t *blk_inst,
+                                const InstDev *inst, int n_blocks, double *front0, hipStream_t s);
 constexpr int kMaxSegments = 16;  // most waves per workgroup of the march kernel
 // Tau-steps the one-column stepping kernels advance per sweep over the state (1 or 2).
 // With 2 the second step follows the first through every cell: its stage inputs at cell j

@@ -275,6 +275,7 @@ march_kernel(StepArgs a) {
     const int c1 = min(N, c0 + I.seg_len);
     const bool has_next = wave + 1 < I.n_seg;
     const bool steady = (I.flags & QS_FLAG_STEADY_INFLOW) != 0;
+    const bool stationary = (I.flags & QS_FLAG_STATIONARY_FRONT) != 0;
     const bool writer = NC >= 2 || (lane & 1) == 0;   // lane that writes per-mode results
 
     TC cT[MPL], cP[MPL], kap2[MPL], k2kap2[MPL];
@@ -332,9 +333,11 @@ march_kernel(StepArgs a) {
 
     // One segment pass of a sweep of K tau-steps: per cell, all four stages of each step, the
     // fields of the state at the step's start (stage-1 values) and the update.
-    auto pass = [&](const bool init_steady, auto steps, auto scaled) __attribute__((always_inline)) {
+    // init_front: the pass starts at the beam front with a steady or stationary front
+    // condition: n_p ahead of the beam is cell 0's current stage value (steady) or held at
+    // cell 0's charge density at tau = 0, in this sweep's units (stationary); d_xi n_p = 0
+    auto pass = [&](const bool init_front, auto steps) __attribute__((always_inline)) {
         constexpr int K = decltype(steps)::value;
-        constexpr bool SCALED = decltype(scaled)::value;  // a pending power of two in the wave
         // step `slot` of the sweep at cell j from its stage-1 values u (TC, pending power of
         // two applied) and Omega at the centre and the rear face: fields, and the updated
         // values un rounded to the storage type
@@ -364,7 +367,11 @@ march_kernel(StepArgs a) {
                     const TC Tm = (m == 0) ? T0[c] : T0[c] + cm * dT[c];
                     const double rd = (double)rm;
                     double &ym = y[sl][m][c], &vm = v[sl][m][c];
-                    if (FIRST && init_steady) { ym = rd; vm = 0.0; }
+                    if (FIRST && init_front) {
+                        ym = steady ? rd
+                                    : a.front0[((int64_t)gb * NC + c) * kWave + lane] * ldexp(1.0, -L[NC >= 2 ? c / 2 : 0]);
+                        vm = 0.0;
+                    }
                     double nc, yn, vn, vc;
                     if (RESTORING) {
                         const double uu = ym - rd;
@@ -446,7 +453,7 @@ march_kernel(StepArgs a) {
                 const int t = NC >= 2 ? c / 2 : 0;
                 // stored values times the pending exact power of two (1 when none)
 #pragma unroll
-                for (int r = 0; r < 3; ++r) u[r][c] = SCALED ? (TC)x[r * NC + c] * scale[t] : (TC)x[r * NC + c];
+                for (int r = 0; r < 3; ++r) u[r][c] = (TC)x[r * NC + c] * scale[t];
             }
             TS un[3][NC];
             step_cell(j, u, Oc, Of, un, first, I0{});
@@ -520,7 +527,8 @@ march_kernel(StepArgs a) {
 #pragma unroll
             for (int sl = 0; sl < NS; ++sl) a2max[sl][t] = (TC)0;
         }
-        // carries at the segment's front face: zero at the beam front, else from wave-1
+        // carries at the segment's front face: zero at the beam front (unperturbed plasma; the
+        // steady and stationary front conditions set n_p at the first cell), else from wave-1
         if (wave == 0) {
 #pragma unroll
             for (int sl = 0; sl < NS; ++sl)
@@ -552,24 +560,11 @@ march_kernel(StepArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             if (lane == 0) __hip_atomic_store(&taken[slot - 1], sweeps + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        // the loads are multiplied by the pending power of two only in the (rare) sweeps
-        // where a lane of the wave has one
-        bool pend = false;
-#pragma unroll
-        for (int t = 0; t < MPL; ++t) pend = pend || scale[t] != (TC)1;
-        const bool scaled = __any(pend ? 1 : 0) != 0;
-        using S1 = std::true_type;
-        using S0 = std::false_type;
         if constexpr (NS == 2) {
-            if (k == 2) {
-                if (scaled) pass(wave == 0 && steady, std::integral_constant<int, 2>{}, S1{});
-                else pass(wave == 0 && steady, std::integral_constant<int, 2>{}, S0{});
-            } else {
-                pass(wave == 0 && steady, std::integral_constant<int, 1>{}, S1{});
-            }
+            if (k == 2) pass(wave == 0 && (steady || stationary), std::integral_constant<int, 2>{});
+            else pass(wave == 0 && (steady || stationary), std::integral_constant<int, 1>{});
         } else {
-            if (scaled) pass(wave == 0 && steady, std::integral_constant<int, 1>{}, S1{});
-            else pass(wave == 0 && steady, std::integral_constant<int, 1>{}, S0{});
+            pass(wave == 0 && (steady || stationary), std::integral_constant<int, 1>{});
         }
 
         // hand the carries at this segment's rear face to the next segment
@@ -686,6 +681,20 @@ hipError_t launch_march_t(bool restoring, bool fields, int snap, bool flat, int 
     return launch_march_r<TS, TC, NC, false>(fields, snap, flat, n_wg, wg_waves, segmented, a, s);
 }
 
+// rho of cell 0 of every column: the front value of the stationary front condition
+template <typename TS, int NC>
+__global__ void __launch_bounds__(256) front_capture(const TS *__restrict__ state, const int32_t *__restrict__ blk_inst,
+                                                     const InstDev *__restrict__ inst, int n_blocks,
+                                                     double *__restrict__ front0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_blocks * NC * kWave) return;
+    const int gb = (int)(i / (NC * kWave));
+    const int c = (int)(i / kWave) % NC, lane = (int)(i % kWave);
+    const InstDev I = inst[blk_inst[gb]];
+    const int b = gb - I.block0;
+    front0[i] = (double)state[I.state_off + (int64_t)b * I.n_xi * 3 * NC * kWave + (int64_t)c * kWave + lane];
+}
+
 template <typename TS, int NC>
 hipError_t launch_seed_t(int n_blocks, int max_n_xi, const SeedArgs &a, hipStream_t s) {
     constexpr int kCellsPerWg = 4;
@@ -695,6 +704,20 @@ hipError_t launch_seed_t(int n_blocks, int max_n_xi, const SeedArgs &a, hipStrea
 }
 
 }  // namespace
+
+hipError_t launch_front_capture(int precision, int nc, const void *state, const int32_t *blk_inst,
+                                const InstDev *inst, int n_blocks, double *front0, hipStream_t s) {
+    const int64_t n = (int64_t)n_blocks * nc * kWave;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (precision == QS_FP64) {
+        if (nc == 1) hipLaunchKernelGGL((front_capture<double, 1>), grid, block, 0, s, static_cast<const double *>(state), blk_inst, inst, n_blocks, front0);
+        else hipLaunchKernelGGL((front_capture<double, 2>), grid, block, 0, s, static_cast<const double *>(state), blk_inst, inst, n_blocks, front0);
+    } else {
+        if (nc == 1) hipLaunchKernelGGL((front_capture<float, 1>), grid, block, 0, s, static_cast<const float *>(state), blk_inst, inst, n_blocks, front0);
+        else hipLaunchKernelGGL((front_capture<float, 2>), grid, block, 0, s, static_cast<const float *>(state), blk_inst, inst, n_blocks, front0);
+    }
+    return hipGetLastError();
+}
 
 size_t march_lds_bytes(int precision, int nc, int wg_waves, bool segmented) {
     if (!segmented) return kFlagInts * sizeof(int);  // no hand-offs: the flags only

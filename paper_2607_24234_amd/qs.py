@@ -29,6 +29,7 @@ PROFILE_FLATTOP, PROFILE_GAUSSIAN, PROFILE_TABLE = 0, 1, 2
 GEOM_SPECTRAL, GEOM_TRANSVERSE_GRID = 0, 1
 SEED_NOISE, SEED_UNIFORM, SEED_FRONT_IMPULSE, SEED_CENTROID, SEED_NONE = 0, 1, 2, 3, 4
 FLAG_DROP_LONGITUDINAL, FLAG_NO_RESTORING, FLAG_STEADY_INFLOW, FLAG_FPERP_SNAPSHOTS = 1, 2, 4, 8
+FLAG_STATIONARY_FRONT = 16
 
 _D = ctypes.POINTER(ctypes.c_double)
 

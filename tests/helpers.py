@@ -35,8 +35,16 @@ def oracle_run(inst, n_steps, out_every=1, modes=None, instance=0, n_threads=0, 
                     n_modes_total=len(k_all), mode_offset=int(m))
         st.n[i], st.pz[i], st.pt[i] = s1.n[0], s1.pz[0], s1.pt[0]
     ln_e, ln_b, mx = O.run(beam, k_all[modes], inst["d_tau"], n_steps, st, out_every=out_every,
-                           renorm=renorm, n_threads=n_threads)
+                           renorm=renorm, n_threads=n_threads, front=front_values(beam, st))
     return ln_e, ln_b, mx, st
+
+
+def front_values(beam, state):
+    """The stationary front's n_p per mode: cell 0's charge density sum_s q_s n_s of `state`
+    (the seeded state at tau = 0); None unless the beam has the STATIONARY_FRONT flag."""
+    if not beam.flags & O.STATIONARY_FRONT:
+        return None
+    return np.einsum("s,ms->m", beam.q, state.n[:, :, 0])
 
 
 def ln_compare(gpu, ref, tol, rel_floor=1e-6, what=""):
