@@ -73,6 +73,18 @@ def build_variant(plant: str, outdir: str | None = None) -> str:
     return out
 
 
+def build_sanitized(outdir: str | None = None) -> str:
+    """Compile a copy of the oracle with AddressSanitizer and UndefinedBehaviorSanitizer (gcc;
+    undefined behaviour aborts) for running the CPU tests under them; returns its path.  The
+    process that loads it needs gcc's libasan first (LD_PRELOAD)."""
+    outdir = outdir or tempfile.mkdtemp(prefix="orc_san_")
+    out = os.path.join(outdir, "liborc_san.so")
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+                           "-o", out, _SRC, _SRC_GRID, "-lm"])
+    return out
+
+
 @contextlib.contextmanager
 def use_library(path: str):
     """Run the oracle's functions on another build of it (e.g. build_variant) inside the block."""
@@ -86,9 +98,11 @@ def use_library(path: str):
 
 
 def lib():
+    """The oracle library: liborc.so (built when stale), or the build named by the
+    ORC_LIBRARY environment variable (e.g. build_sanitized's)."""
     global _lib
     if _lib is None:
-        _lib = _declare(ctypes.CDLL(build()))
+        _lib = _declare(ctypes.CDLL(os.environ.get("ORC_LIBRARY") or build()))
     return _lib
 
 

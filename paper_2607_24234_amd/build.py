@@ -22,15 +22,25 @@ def sources():
     return sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False, out: str = LIB, defines=(), objdir=None) -> str:
-    """Compile every HIP source into libqs.so (always rebuilds)."""
-    objdir = objdir or os.path.join(PKG, "_build")
+# Host-side sanitizers for a CPU-only test build (the device code is compiled as usual): each
+# -fsanitize applies to the host compilation only.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+                 "-Xarch_host", "-g"]
+
+
+def build(verbose: bool = False, out: str = LIB, defines=(), objdir=None, sanitize: bool = False) -> str:
+    """Compile every HIP source into libqs.so (always rebuilds).  sanitize: instrument the
+    host code with AddressSanitizer and UndefinedBehaviorSanitizer (a CPU test build: the
+    process that loads it needs clang's ASan runtime first, LD_PRELOAD)."""
+    objdir = objdir or os.path.join(PKG, "_build" if not sanitize else "_build_san")
     os.makedirs(objdir, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    extra = HOST_SANITIZE if sanitize else []
     cmds, objs = [], []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmds.append([hipcc, *HIP_FLAGS, *["-D" + d for d in defines], "-c", src, "-o", obj])
+        cmds.append([hipcc, *HIP_FLAGS, *extra, *["-D" + d for d in defines], "-c", src, "-o", obj])
         objs.append(obj)
     if verbose:
         for cmd in cmds:
@@ -41,7 +51,7 @@ def build(verbose: bool = False, out: str = LIB, defines=(), objdir=None) -> str
         for f in [pool.submit(subprocess.check_call, cmd) for cmd in cmds]:
             f.result()
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *extra, "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
