@@ -301,31 +301,32 @@ __global__ void __launch_bounds__(256) regime_tile(const T *__restrict__ ln_e, c
 // holds the raw ln values of both fields over the current chunk's span, row i = cell
 // o0 - w + i (o0 the chunk's first output), so every access is a fixed offset from the
 // wave's first row.  Per chunk: each mode's largest value of each field over the span
-// (from the values the threads staged, exchanged through LDS), the terms of each 8-row
-// block summed once, then each wave's windows (head and tail term by term, the middle from
-// block sums).  Meanwhile the rows of the next chunk are in flight into registers; once the
-// chunk is done the last 2w rows move to the front and the new rows follow them.  Every
-// cell is read from memory once (plus a 2w halo where a mode block's outputs are split
-// between workgroups).
+// (from the values the threads staged, exchanged through LDS); the raw halo rows the next
+// chunk keeps into registers; every staged value turned into its term in place, once, with
+// the 8-row block sums; then each wave's windows from the terms (head and tail term by term,
+// the middle from block sums).  Meanwhile the rows of the next chunk are in flight into
+// registers; once the chunk is done the halo rows go to the front and the new rows follow
+// them.  Every cell is read from memory once (plus a 2w halo where a mode block's outputs
+// are split between workgroups) and exponentiated (kChunk + 2w) / kChunk times.
 constexpr int kChunk = 128;
 constexpr int kSpan = 256;
 constexpr int kWaves = 16;               // waves per streaming workgroup
 constexpr int kSub = kChunk / kWaves;    // outputs (and block rows) per wave and chunk
 
 // Outputs ja .. ja+c-1 (c <= TS) of one wave against the chunk's references mE, mB.  E, B
-// point at the wave's first span row (s[0] = cell ja - w), rows 64 apart; bE, bB at the
-// block sums of that row's block (block TS rows, 64 apart), so the middle s[TS .. 2w] is
-// q = (2w + 1 - TS) / TS whole blocks plus a remainder; head and tail terms one by one.
+// point at the wave's first span row (s[0] = cell ja - w), rows 64 apart, holding the terms
+// exp(2 (ln - ref(m))) of the span; bE, bB at the block sums of that row's block (block TS
+// rows, 64 apart), so the middle s[TS .. 2w] is q = (2w + 1 - TS) / TS whole blocks plus a
+// remainder; head and tail terms one by one.
 template <int TS, typename T>
 __device__ __forceinline__ void span_outputs(const T *E, const T *B, const T *bE, const T *bB, int ja, int c, int w,
                                              T mE, T mB, const T *GE, const T *GB, int64_t gst, T *__restrict__ R,
                                              int &first) {
-    const T rE = ref(mE), rB = ref(mB);
     T hE[TS], hB[TS];
 #pragma unroll
     for (int r = 0; r < TS; ++r) {
-        hE[r] = ex(T(2) * (E[r * 64] - rE));
-        hB[r] = ex(T(2) * (B[r * 64] - rB));
+        hE[r] = E[r * 64];
+        hB[r] = B[r * 64];
     }
 #pragma unroll
     for (int r = TS - 2; r >= 0; --r) {
@@ -339,8 +340,8 @@ __device__ __forceinline__ void span_outputs(const T *E, const T *B, const T *bE
         sB += bB[b * 64];
     }
     for (int i = TS * (q + 1); i <= 2 * w; ++i) {
-        sE += ex(T(2) * (E[i * 64] - rE));
-        sB += ex(T(2) * (B[i * 64] - rB));
+        sE += E[i * 64];
+        sB += B[i * 64];
     }
     const T *Et = E + (2 * w + 1) * 64, *Bt = B + (2 * w + 1) * 64;   // the tail
     // the quick form of window_L; outputs that need their own window's sum are marked and
@@ -365,8 +366,8 @@ __device__ __forceinline__ void span_outputs(const T *E, const T *B, const T *bE
                 again |= 1u << r;
             }
             if (r + 1 < c) {
-                pE += ex(T(2) * (Et[r * 64] - rE));
-                pB += ex(T(2) * (Bt[r * 64] - rB));
+                pE += Et[r * 64];
+                pB += Bt[r * 64];
             }
         }
     }
@@ -479,34 +480,8 @@ __global__ void __launch_bounds__(64 * kWaves) regime_stream(const T *__restrict
                 mE = fmax(mE, pm[0][v][lane]);
                 mB = fmax(mB, pm[1][v][lane]);
             }
-            // sums of the terms over kSub-row blocks of the span (each term once)
-            {
-                const T rE = ref(mE), rB = ref(mB);
-                const int len = (o1 - o0) + 2 * w, nblk = (len + kSub - 1) / kSub;
-                for (int b = wv; b < nblk; b += kWaves) {
-                    T a = 0, bb = 0;
-#pragma unroll
-                    for (int i = 0; i < kSub; ++i) {
-                        const int rr = b * kSub + i;
-                        if (rr < len) {
-                            a += ex(T(2) * (sE[rr * 64] - rE));
-                            bb += ex(T(2) * (sB[rr * 64] - rB));
-                        }
-                    }
-                    bsum[0][b][lane] = a;
-                    bsum[1][b][lane] = bb;
-                }
-            }
-            __syncthreads();
-            const int ja = o0 + kSub * wv, c = min(kSub, o1 - ja);
-            if (live && c > 0) {
-                int f = -1;
-                span_outputs<kSub>(sE + kSub * wv * 64, sB + kSub * wv * 64, &bsum[0][wv][lane], &bsum[1][wv][lane], ja,
-                                   c, w, mE, mB, GE, GB, n_modes, R, f);
-                if (first < 0) first = f;
-            }
-            // the last 2w rows move to the front and the new rows follow: this thread's halo
-            // rows into registers now (nothing writes the span before the barrier below)
+            // the last 2w rows move to the front of the next chunk's span as raw values: this
+            // thread's halo rows into registers before the span turns into terms
             constexpr int H = kChunk / kWaves;   // 2w <= kChunk rows of halo
             T he[H], hb[H];
             T a = -INFINITY, bb = -INFINITY;
@@ -522,7 +497,38 @@ __global__ void __launch_bounds__(64 * kWaves) regime_stream(const T *__restrict
                     }
                 }
             }
-            __syncthreads();   // the chunk's windows are summed and every halo row is read
+            __syncthreads();   // every halo row is read
+            // every span value into its term exp(2 (ln - ref(m))) in place (each value
+            // exponentiated once per chunk), with the sums over kSub-row blocks
+            {
+                const T rE = ref(mE), rB = ref(mB);
+                const int len = (o1 - o0) + 2 * w, nblk = (len + kSub - 1) / kSub;
+                for (int b = wv; b < nblk; b += kWaves) {
+                    T sa = 0, sb = 0;
+#pragma unroll
+                    for (int i = 0; i < kSub; ++i) {
+                        const int rr = b * kSub + i;
+                        if (rr < len) {
+                            const T te = ex(T(2) * (sE[rr * 64] - rE)), tb = ex(T(2) * (sB[rr * 64] - rB));
+                            sE[rr * 64] = te;
+                            sB[rr * 64] = tb;
+                            sa += te;
+                            sb += tb;
+                        }
+                    }
+                    bsum[0][b][lane] = sa;
+                    bsum[1][b][lane] = sb;
+                }
+            }
+            __syncthreads();
+            const int ja = o0 + kSub * wv, c = min(kSub, o1 - ja);
+            if (live && c > 0) {
+                int f = -1;
+                span_outputs<kSub>(sE + kSub * wv * 64, sB + kSub * wv * 64, &bsum[0][wv][lane], &bsum[1][wv][lane], ja,
+                                   c, w, mE, mB, GE, GB, n_modes, R, f);
+                if (first < 0) first = f;
+            }
+            __syncthreads();   // the chunk's windows are summed
             if (nn > 0) {      // uniform; then o1 - o0 = kChunk
 #pragma unroll
                 for (int u = 0; u < H; ++u) {
