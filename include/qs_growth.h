@@ -15,11 +15,10 @@
  * at xi_j: the log amplitude smoothed over the two plasma wavelengths behind xi (A itself
  * carries the plasma-period ripple of the response; a one-wavelength box average leaves a
  * ripple wherever the envelope grows across the window, the Hann weights take it to second
- * order).  The solver's answer: per (n_b, gamma) of the queries one beam of cells of width
- * h0 = 200/8192 (the finest of the batched sweep, the same for every answer) reaching two cells
- * beyond the largest xi, d_tau = tau_f/200, FP32 state, the windowed growth of every step's
- * fields, bilinearly interpolated between the two cell centres around xi and the two steps
- * around tau.  A query sent to the solver must have finite values, gamma > 1, k >= 0, xi >= 0
+ * order).  The solver's answer: the query's beam on cells of width h0 = 200/8192 (the finest
+ * of the batched sweep, the same for every answer) reaching at least two cells beyond xi,
+ * d_tau = tau_f/200, FP32 state, the windowed growth of every step's fields, bilinearly
+ * interpolated between the two cell centres around xi and the two steps around tau.  A query sent to the solver must have finite values, gamma > 1, k >= 0, xi >= 0
  * and 0 <= tau <= 1e4 tau_f
  * (QS_ERR_ARG otherwise, naming the query).
  *
@@ -123,9 +122,11 @@ qs_status qs_growth_calibrate(qs_mlp *net, const float *Q, const float *T, int64
  *   QS_GROWTH_AUTO      : the network where the query is inside the box and its bin's
  *                         held-out error is in [0, tol]; the solver elsewhere.
  * used_solver (device [n] bytes, optional): 1 where the solver answered.  The solver path
- * copies the selected queries to the host, groups them by (n_b, gamma), runs batched solver
- * contexts (one instance per group, its distinct k as modes; groups chunked so that one
- * context holds at most 8 GB of state), allocates its buffers, and synchronizes.
+ * copies the selected queries to the host and runs them as the modes of solver contexts of one
+ * instance each, 32 queries of any beams per wavefront: in units of each query's own step the
+ * model is the unit-density beam with the push coefficients scaled by d_tau^2 (the same
+ * discrete solution); queries sorted by the cells they need, chunked so that a context's state
+ * and snapshots stay within 16 GB; it allocates its buffers and synchronizes.
  */
 qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float *q, int64_t n,
                         int32_t mode, float *out, uint8_t *used_solver, void *hip_stream);

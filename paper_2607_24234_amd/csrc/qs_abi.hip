@@ -70,7 +70,7 @@ struct Plan {
     int64_t n_scale = 0;           // entries of the per-(segment, mode) scale arrays
     std::vector<int2> wave_table;  // [n_wg][wg_waves]: (global block, segment) or (-1, -1)
     // workspace offsets (bytes)
-    size_t off_state, off_omega, off_shape, off_k, off_log2s, off_epend, off_inst, off_blk,
+    size_t off_state, off_omega, off_shape, off_k, off_coef, off_log2s, off_epend, off_inst, off_blk,
         off_iidx, off_err, off_wtab, off_front, total;
     int64_t n_blocks = 0;
 };
@@ -377,6 +377,7 @@ qs_status make_plan(const qs_params *params, int32_t n, const qs_plan *plan, Pla
     pl.off_omega = o; o = align_up(o + (size_t)table * pl.ts);
     pl.off_shape = o; o = align_up(o + (size_t)table * sizeof(double));
     pl.off_k = o; o = align_up(o + (size_t)pmodes * sizeof(double));
+    pl.off_coef = o; o = align_up(o + (size_t)pmodes * 2 * sizeof(double));
     pl.off_log2s = o; o = align_up(o + (size_t)nscale * sizeof(int32_t));
     pl.off_epend = o; o = align_up(o + (size_t)nscale * sizeof(int32_t));
     pl.off_inst = o; o = align_up(o + (size_t)n * sizeof(InstDev));
@@ -441,6 +442,7 @@ qs_status upload_tables(qs_ctx *c, const qs_params *params) {
     std::vector<double> shape(pl.table_elems, 0.0);
     std::vector<double> om64(pl.table_elems, 0.0);
     std::vector<double> kmode(pl.total_pmodes, 0.0);
+    std::vector<double> coef(2 * (size_t)pl.total_pmodes, 0.0);
     std::vector<int32_t> iidx(n);
     for (int i = 0; i < n; ++i) {
         const qs_params &p = params[i];
@@ -464,7 +466,12 @@ qs_status upload_tables(qs_ctx *c, const qs_params *params) {
         for (int j = 0; j < N; ++j) of[j] = (j + 1 < N) ? 0.5 * (oc[j] + oc[j + 1]) : 0.0;
         for (int64_t m = 0; m < p.n_modes; ++m) {
             const double kx = p.kx[m], ky = p.ky ? p.ky[m] : 0.0;
-            kmode[d.pmode0 + m] = std::sqrt(kx * kx + ky * ky);
+            const double k = std::sqrt(kx * kx + ky * ky), kp = 1.0 / (1.0 + k * k);
+            kmode[d.pmode0 + m] = k;
+            // push coefficients: d_tau T' = (k^2 kappa/gamma) Omega n_p,
+            // d_tau P' = -(kappa/(gamma^3 h)) Omega d_xi n_p
+            coef[2 * (d.pmode0 + m)] = k * k * kp * d.ginv;
+            coef[2 * (d.pmode0 + m) + 1] = -kp * d.g3inv * d.ih;
         }
         iidx[i] = i;
     }
@@ -481,6 +488,8 @@ qs_status upload_tables(qs_ctx *c, const qs_params *params) {
                           hipMemcpyHostToDevice, c->stream), "copy profile");
     QS_HIP(hipMemcpyAsync(c->at(pl.off_k), kmode.data(), kmode.size() * sizeof(double),
                           hipMemcpyHostToDevice, c->stream), "copy wavenumbers");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_coef), coef.data(), coef.size() * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream), "copy push coefficients");
     QS_HIP(hipMemcpyAsync(c->at(pl.off_inst), pl.inst.data(), pl.inst.size() * sizeof(InstDev),
                           hipMemcpyHostToDevice, c->stream), "copy instance table");
     QS_HIP(hipMemcpyAsync(c->at(pl.off_blk), pl.blk_inst.data(), pl.blk_inst.size() * sizeof(int32_t),
@@ -538,6 +547,28 @@ qs_status seed_state(qs_ctx *c, const qs_params *params) {
            "front capture");
     return QS_OK;
 }
+
+}  // namespace
+
+qs_status qs::set_mode_coefficients(qs_ctx *c, const double *cT, const double *cP) {
+    if (!c || !cT || !cP) return fail(QS_ERR_ARG, "set_mode_coefficients: arguments are required");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "set_mode_coefficients: spectral contexts only");
+    const Plan &pl = c->pl;
+    std::vector<double> coef(2 * (size_t)pl.total_pmodes, 0.0);
+    for (const InstDev &d : pl.inst)
+        for (int m = 0; m < d.n_modes; ++m) {
+            coef[2 * ((size_t)d.pmode0 + m)] = cT[d.mode0 + m];
+            coef[2 * ((size_t)d.pmode0 + m) + 1] = cP[d.mode0 + m];
+        }
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_coef), coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream),
+           "copy push coefficients");
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return QS_OK;
+}
+
+namespace {
 
 bool is_grid(const qs_params *params, int32_t n) {
     return params && n >= 1 && params[0].geometry == QS_GEOM_TRANSVERSE_GRID;
@@ -668,6 +699,7 @@ qs_status qs_step_tau(qs_ctx *c, int32_t n_steps, int32_t out_every, void *out_l
     a.inst = reinterpret_cast<const InstDev *>(c->at(pl.off_inst));
     a.omega = c->at(pl.off_omega);
     a.kmode = reinterpret_cast<const double *>(c->at(pl.off_k));
+    a.coef = reinterpret_cast<const double *>(c->at(pl.off_coef));
     a.log2s = reinterpret_cast<int32_t *>(c->at(pl.off_log2s));
     a.epend = reinterpret_cast<int32_t *>(c->at(pl.off_epend));
     a.total_modes = (int32_t)pl.total_modes;

@@ -391,11 +391,12 @@ constexpr double kCellWidth = 200.0 / 8192.0;
 // cells of width kCellWidth that cover xi in [0, L]
 int cells_for(double L) { return std::max(1, (int)std::ceil(L / kCellWidth - 1e-9)); }
 
-// Solver answers for the queries hq[5 i..] at positions sel; values returned in vals.
-struct Group {
-    double nb, g, L = 0.0, tau_max = 0.0;
-    std::vector<double> ks;
-    std::vector<int64_t> members;  // positions in the selection
+// A query the solver answers: its beam (n_b, gamma), mode k, position, the step d_tau =
+// tau_f/200 of its beam, the cells its answer needs and its fractional step tau/d_tau.
+struct SolverQuery {
+    int64_t pos;        // position in the selection
+    double nb, g, k, xi, d_tau, ts;
+    int cells;
 };
 
 // One solver-answered query: the bilinear interpolation of the discrete windowed growth
@@ -448,80 +449,82 @@ __global__ void __launch_bounds__(256) answer_kernel(const QueryRec *__restrict_
     vals[Q.dst] = (float)acc;
 }
 
-// Solver answers for the selected queries of groups [g0, g1): one batched context, one
-// instance per group, marched in one launch to the last step any query needs with the fields
-// written at every step, then every answer from those snapshots in one kernel.
-qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> &sel,
-                       const std::vector<Group> &groups, size_t g0, size_t g1, hipStream_t s,
+// Solver answers for the queries q[a, b) (sorted by the cells they need), every one a mode
+// of one instance.  The model is linear and tau-invariant, so in units of each query's own
+// step (tau = n d_tau) with T'' = d_tau T' and P'' = d_tau P' the step is 1 and the push
+// coefficients become d_tau^2 cT Omega and d_tau^2 cP Omega: a beam of density n_b and
+// Lorentz factor gamma is the mode with those coefficients in a unit-density instance with
+// unit step (rho, n_p and so the fields are unchanged by the rescaling; the uniform seed
+// has no current).  So 32 queries of any beams fill a wavefront, where one instance per beam
+// would leave one mode per block.  The instance reaches two cells beyond the largest xi of
+// the chunk and is marched to the last step any query needs with the fields written at every
+// step; every answer then comes from those snapshots in one kernel.
+qs_status solve_packed(const std::vector<SolverQuery> &q, size_t a, size_t b, hipStream_t s,
                        std::vector<float> *vals) {
     const double S = 1e-6;
-    const int n_steps_max = 200;  // steps of tau_f
-    const size_t ng = g1 - g0;
-    std::vector<qs_params> params(ng);
-    std::vector<double> qv(1, -1.0), mv(1, 1.0);
-    std::vector<std::vector<double>> nbv(ng);
-    std::vector<int64_t> goff(ng);
-    int64_t snap = 0;
-    for (size_t i = 0; i < ng; ++i) {
-        const Group &G = groups[g0 + i];
-        nbv[i] = {G.nb};
-        qs_params &p = params[i];
-        std::memset(&p, 0, sizeof(p));
-        p.n_species = 1;
-        p.q = qv.data();
-        p.m = mv.data();
-        p.nb_over_np = nbv[i].data();
-        p.gamma_b = G.g;
-        p.length = cells_for(G.L) * kCellWidth;
-        p.profile = QS_PROFILE_FLATTOP;
-        p.geometry = QS_GEOM_SPECTRAL;
-        p.n_modes = (int64_t)G.ks.size();
-        p.kx = const_cast<double *>(G.ks.data());
-        p.n_xi = cells_for(G.L);
-        p.d_tau = tau_final(G.nb, G.g) / n_steps_max;
-        p.precision = QS_FP32;
-        p.seed_kind = QS_SEED_UNIFORM;
-        p.seed_amp = S;
-        goff[i] = snap;
-        snap += (int64_t)p.n_xi * p.n_modes;
+    const int nq = (int)(b - a);
+    int N = 1, last_step = 0;
+    std::vector<double> ks(nq), cT(nq), cP(nq);
+    for (int i = 0; i < nq; ++i) {
+        const SolverQuery &Q = q[a + i];
+        N = std::max(N, Q.cells);
+        const int s0 = (int)std::floor(Q.ts);
+        last_step = std::max(last_step, s0 + (Q.ts > s0 ? 1 : 0));
+        const double k = Q.k, kp = 1.0 / (1.0 + k * k), d2 = Q.d_tau * Q.d_tau;
+        ks[i] = k;
+        cT[i] = d2 * k * k * kp * Q.nb / Q.g;                          // Omega = n_b, gamma^-1
+        cP[i] = -d2 * kp * Q.nb / (Q.g * Q.g * Q.g) / kCellWidth;       // gamma^-3, 1/h
     }
-    std::vector<QueryRec> recs;
-    std::vector<int64_t> slot_pos;  // answer slot -> position in sel
-    int last_step = 0;
-    for (size_t i = 0; i < ng; ++i) {
-        const qs_params &p = params[i];
-        const double h = p.length / p.n_xi;
-        const auto &ks = groups[g0 + i].ks;
-        for (int64_t pos : groups[g0 + i].members) {
-            const float *q = &hq[5 * (size_t)sel[pos]];
-            QueryRec r{};
-            r.base = goff[i] + (int64_t)(std::lower_bound(ks.begin(), ks.end(), (double)q[2]) - ks.begin());
-            r.stride = (int32_t)p.n_modes;
-            r.win = window_cells(h);
-            // cells: centres (j + 1/2) h around xi (clamped to the first and last cell)
-            const double xc = (double)q[3] / h - 0.5;
-            r.j0 = (int)std::floor(xc);
-            r.fx = xc - r.j0;
-            if (r.j0 < 0) { r.j0 = 0; r.fx = 0.0; }
-            if (r.j0 >= p.n_xi - 1) { r.j0 = p.n_xi - 1; r.fx = 0.0; }
-            const double ts = (double)q[4] / p.d_tau;  // tau >= 0 (checked)
-            r.s0 = (int)std::floor(ts);
-            r.ft = ts - r.s0;
-            r.ln_s = std::log(S);
-            r.dst = (int32_t)slot_pos.size();
-            slot_pos.push_back(pos);
-            last_step = std::max(last_step, r.s0 + (r.ft > 0.0 ? 1 : 0));
-            recs.push_back(r);
-        }
+    const double qv[1] = {-1.0}, mv[1] = {1.0}, nbv[1] = {1.0};
+    qs_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.n_species = 1;
+    p.q = qv;
+    p.m = mv;
+    p.nb_over_np = nbv;
+    p.gamma_b = 2.0;   // its push coefficients are replaced below
+    p.length = N * kCellWidth;
+    p.profile = QS_PROFILE_FLATTOP;
+    p.geometry = QS_GEOM_SPECTRAL;
+    p.n_modes = nq;
+    p.kx = ks.data();
+    p.n_xi = N;
+    p.d_tau = 1.0;
+    p.precision = QS_FP32;
+    p.seed_kind = QS_SEED_UNIFORM;
+    p.seed_amp = S;
+    std::vector<QueryRec> recs(nq);
+    for (int i = 0; i < nq; ++i) {
+        const SolverQuery &Q = q[a + i];
+        QueryRec &r = recs[i];
+        r.base = i;
+        r.stride = nq;
+        r.win = window_cells(kCellWidth);
+        // cells: centres (j + 1/2) h around xi (clamped to the first and last cell)
+        const double xc = Q.xi / kCellWidth - 0.5;
+        r.j0 = (int)std::floor(xc);
+        r.fx = xc - r.j0;
+        if (r.j0 < 0) { r.j0 = 0; r.fx = 0.0; }
+        if (r.j0 >= N - 1) { r.j0 = N - 1; r.fx = 0.0; }
+        r.s0 = (int)std::floor(Q.ts);
+        r.ft = Q.ts - r.s0;
+        r.ln_s = std::log(S);
+        r.dst = i;
     }
     const int n_snap = last_step + 1;  // the states at steps 0 .. last_step
+    const int64_t snap = (int64_t)N * nq;
     qs_ctx *ctx = nullptr;
-    qs_status st = qs_init(params.data(), (int32_t)params.size(), s, nullptr, 0, &ctx);
+    qs_status st = qs_init(&p, 1, s, nullptr, 0, &ctx);
     if (st != QS_OK) return st;
+    st = qs::set_mode_coefficients(ctx, cT.data(), cP.data());
+    if (st != QS_OK) {
+        qs_free(ctx);
+        return st;
+    }
     char *buf = nullptr;
     const size_t snap_bytes = (((size_t)snap * n_snap * 2 * sizeof(float) + 255) / 256) * 256;
     const size_t rec_bytes = recs.size() * sizeof(QueryRec);
-    if (hipMalloc(&buf, snap_bytes + rec_bytes + slot_pos.size() * sizeof(float)) != hipSuccess) {
+    if (hipMalloc(&buf, snap_bytes + rec_bytes + (size_t)nq * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         qs_free(ctx);
         return gfail(QS_ERR_ALLOC, "growth map: snapshot buffers");
@@ -533,17 +536,17 @@ qs_status solve_groups(const std::vector<float> &hq, const std::vector<int64_t> 
         st = gfail(QS_ERR_HIP, "growth map: copy query records");
     if (st == QS_OK) st = n_snap > 1 ? qs_step_tau(ctx, n_snap, 1, le, lb, nullptr) : qs_step_tau(ctx, 0, 1, le, lb, nullptr);
     if (st == QS_OK) {
-        hipLaunchKernelGGL(answer_kernel, dim3(blocks_for((int64_t)recs.size())), dim3(256), 0, s, d_recs,
-                           (int)recs.size(), le, lb, snap, d_vals);
+        hipLaunchKernelGGL(answer_kernel, dim3(blocks_for((int64_t)nq)), dim3(256), 0, s, d_recs, nq, le, lb, snap,
+                           d_vals);
         if (hipGetLastError() != hipSuccess) st = gfail(QS_ERR_HIP, "growth map: answer kernel");
     }
-    std::vector<float> hv(slot_pos.size());
+    std::vector<float> hv(nq);
     if (st == QS_OK && (hipMemcpyAsync(hv.data(), d_vals, hv.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
                         hipStreamSynchronize(s) != hipSuccess))
         st = gfail(QS_ERR_HIP, "growth map: copy answers");
     if (st == QS_OK) st = qs_sync_check(ctx);
     if (st == QS_OK)
-        for (size_t slot = 0; slot < hv.size(); ++slot) (*vals)[slot_pos[slot]] = hv[slot];
+        for (int i = 0; i < nq; ++i) (*vals)[q[a + i].pos] = hv[i];
     (void)hipFree(buf);
     qs_free(ctx);
     return st;
@@ -565,60 +568,44 @@ qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t>
                                          " cannot go to the solver: it needs finite values, gamma > 1, k >= 0, "
                                          "xi >= 0 and 0 <= tau <= 1e4 tau_f");
     }
-    std::map<std::pair<uint32_t, uint32_t>, int> gid;
-    std::vector<Group> groups;
-    for (size_t p = 0; p < sel.size(); ++p) {
-        const float *q = &hq[5 * (size_t)sel[p]];
-        const auto key = std::make_pair(__builtin_bit_cast(uint32_t, q[0]), __builtin_bit_cast(uint32_t, q[1]));
-        auto it = gid.find(key);
-        int id;
-        if (it == gid.end()) {
-            id = (int)groups.size();
-            gid[key] = id;
-            groups.emplace_back();
-            groups.back().nb = std::exp((double)q[0]);
-            groups.back().g = std::exp((double)q[1]);
-        } else {
-            id = it->second;
-        }
-        Group &G = groups[id];
-        G.L = std::max(G.L, (double)q[3]);
-        G.tau_max = std::max(G.tau_max, (double)q[4]);
-        G.ks.push_back((double)q[2]);
-        G.members.push_back((int64_t)p);
+    std::vector<SolverQuery> q(sel.size());
+    for (size_t i = 0; i < sel.size(); ++i) {
+        const float *x = &hq[5 * (size_t)sel[i]];
+        SolverQuery &Q = q[i];
+        Q.pos = (int64_t)i;
+        Q.nb = std::exp((double)x[0]);
+        Q.g = std::exp((double)x[1]);
+        Q.k = (double)x[2];
+        Q.xi = (double)x[3];
+        Q.d_tau = tau_final(Q.nb, Q.g) / 200.0;
+        Q.ts = (double)x[4] / Q.d_tau;
+        // two cells beyond xi: the cell centre behind the query is in the beam and is not the
+        // last cell (the beam's rear face carries no current, which changes the last cell's
+        // charge -- and only that cell's, the march being causal)
+        Q.cells = cells_for(Q.xi + 2.0 * kCellWidth);
     }
+    std::sort(q.begin(), q.end(), [](const SolverQuery &x, const SolverQuery &y) {
+        return x.cells != y.cells ? x.cells < y.cells : x.pos < y.pos;
+    });
     vals->assign(sel.size(), 0.f);
-    for (Group &G : groups) {
-        std::sort(G.ks.begin(), G.ks.end());
-        G.ks.erase(std::unique(G.ks.begin(), G.ks.end()), G.ks.end());
-        // two cells beyond the largest xi: the cell centre behind each query is in the beam and
-        // is not the last cell (the beam's rear face carries no current, which changes the last
-        // cell's charge -- and only that cell's, the march being causal)
-        G.L = G.L + 2.0 * kCellWidth;
-    }
-    // run the groups in chunks whose solver state and snapshots (every step up to the last one
-    // any of the chunk's queries needs) stay within a fixed budget
-    const size_t kBudget = size_t(8) << 30;
-    size_t g0 = 0;
-    while (g0 < groups.size()) {
-        size_t g1 = g0, state = 0, cells = 0;
+    // chunks of consecutive queries (sorted by the cells they need) whose solver state and
+    // snapshots (every step up to the last one any of them needs) stay within a fixed budget
+    const size_t kBudget = size_t(16) << 30;
+    size_t a = 0;
+    while (a < q.size()) {
+        size_t b = a;
         int steps = 1;
-        while (g1 < groups.size()) {
-            const Group &G = groups[g1];
-            const size_t c = (size_t)cells_for(G.L);
-            const size_t blocks = (G.ks.size() + 31) / 32;
-            const int st_g = (int)std::ceil(G.tau_max / (tau_final(G.nb, G.g) / 200.0)) + 2;
-            const size_t bytes = (state + blocks * c * 3 * 64 * 4) +
-                                 (cells + c * G.ks.size()) * 8 * (size_t)std::max(steps, st_g);
-            if (g1 > g0 && (bytes > kBudget || g1 - g0 >= 65536)) break;
-            state += blocks * c * 3 * 64 * 4;
-            cells += c * G.ks.size();
-            steps = std::max(steps, st_g);
-            ++g1;
+        while (b < q.size()) {
+            const size_t n = b + 1 - a, cells = (size_t)q[b].cells;   // the largest so far
+            const int st_q = (int)std::ceil(q[b].ts) + 2;
+            const size_t bytes = (n + 31) / 32 * cells * 3 * 64 * 4 + cells * n * 8 * (size_t)std::max(steps, st_q);
+            if (b > a && (bytes > kBudget || n > 65536)) break;
+            steps = std::max(steps, st_q);
+            ++b;
         }
-        qs_status st = solve_groups(hq, sel, groups, g0, g1, s, vals);
+        qs_status st = solve_packed(q, a, b, s, vals);
         if (st != QS_OK) return st;
-        g0 = g1;
+        a = b;
     }
     return QS_OK;
 }

@@ -46,6 +46,8 @@ struct StepArgs {
     const InstDev *inst;
     const void *omega;        // TC elements: per instance [n_xi] centres then [n_xi] faces
     const double *kmode;      // |k| per padded mode
+    const double *coef;       // per padded mode (cT, cP): d_tau T' = cT Omega n_p and
+                              // d_tau P' = cP Omega d_xi n_p (k^2 kappa/gamma, -kappa/(gamma^3 h))
     int32_t *log2s;           // per (segment, padded mode): applied power of two (L)
     int32_t *epend;           // per (segment, padded mode): pending exponent (next step)
     void *ln_e, *ln_b;        // snapshot outputs (TS) or null
@@ -92,6 +94,11 @@ struct SeedArgs {
     const int32_t *inst_index; // instance index per instance (for the RNG counter)
     int32_t block_base;        // global block index of blockIdx.x == 0
 };
+
+// Replace the per-mode push coefficients (cT, cP above; host arrays of the context's modes in
+// qs_params order) of a spectral context: lets modes of one instance stand for beams of other
+// densities, Lorentz factors and steps (qs_growth.hip).  Synchronous.
+qs_status set_mode_coefficients(qs_ctx *c, const double *cT, const double *cP);
 
 // launchers (qs_spectral.hip)
 // front0[(gb * nc + c) * 64 + lane] = rho of cell 0 of that column of the stored state (the

@@ -289,8 +289,8 @@ march_kernel(StepArgs a) {
         const double kp = 1.0 / (1.0 + k * k);
         kap2[t] = (TC)(kp * kp);
         k2kap2[t] = (TC)(k * k * kp * kp);
-        cT[t] = (TC)(k * k * kp * I.ginv);
-        cP[t] = (TC)(-kp * I.g3inv * I.ih);
+        cT[t] = (TC)a.coef[2 * (I.pmode0 + mloc[t])];
+        cP[t] = (TC)a.coef[2 * (I.pmode0 + mloc[t]) + 1];
         sidx[t] = I.scale_off + (int64_t)wave * I.n_blocks * CL::MODES_PER_BLOCK + mloc[t];
         L[t] = a.log2s[sidx[t]];
         ep[t] = a.epend[sidx[t]];
