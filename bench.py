@@ -401,12 +401,16 @@ def bench_regime(args):
            "algorithmic_bytes_per_launch": 12.0 * cells, "avg_launch_ms": launch * 1e3}, cpu)
 
 
-def surrogate_vs_solver(n_cmp, cfg=None, log=None):
+def surrogate_vs_solver(n_cmp, cfg=None, log=None, n_stream=10_000_000):
     """The growth-map surrogate end to end: trained by the library (qs_surrogate_train, its
     default configuration unless `cfg`), then n_cmp scattered box queries answered by the
     solver alone and by AUTO at tolerance 1e-2 (network where the held-out error table
     trusts it, solver elsewhere), each timed with its own fallback and device
     synchronization; the errors are AUTO's and the network's against the solver's answers.
+    The per-query comparison: the solver's time per query on that batch (its batched
+    throughput) against AUTO's per query on a stream of n_stream scattered queries, error
+    estimation and fallback included (on n_cmp alone AUTO's time is mostly the latency of its
+    one fallback run, which does not shrink with the number of queries it answers).
     Returns (the figures, the loaded surrogate)."""
     import tempfile
     import numpy as np
@@ -442,9 +446,27 @@ def surrogate_vs_solver(n_cmp, cfg=None, log=None):
     da = (auto - sol).abs().cpu().numpy().astype(np.float64)
     dn = (net - sol).abs().cpu().numpy().astype(np.float64)
     n_sol = int(used.sum().item())
-    log("AUTO %.4f s (%d to the solver), SOLVER %.3f s: %.1fx" % (auto_s, n_sol, sol_s, sol_s / auto_s))
+    log("AUTO %.4f s (%d to the solver), SOLVER %.3f s on the same %d: %.1fx" % (auto_s, n_sol, sol_s, n_cmp,
+                                                                               sol_s / auto_s))
+    del q, auto, used
+    qb = torch.as_tensor(inputs.growth_queries(n_stream, 4 + n_stream), device="cuda")
+    ob = torch.empty(n_stream, device="cuda")
+    ub = torch.zeros(n_stream, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    qs.growth_map(sur.net, sur.table, 1e-2, qb, qs.GROWTH_AUTO, ob, ub)
+    torch.cuda.synchronize()
+    stream_s = time.perf_counter() - t
+    n_fb = int(ub.sum().item())
+    del qb, ob, ub
+    per_sol, per_auto = sol_s / n_cmp, stream_s / n_stream
+    log("AUTO on a stream of %d: %.4f s (%d to the solver), %.2f ns per query against the solver's %.2f us: %.0fx"
+        % (n_stream, stream_s, n_fb, per_auto * 1e9, per_sol * 1e6, per_sol / per_auto))
     fig = {"queries": n_cmp, "tol": 1e-2,
-           "auto_s": auto_s, "solver_s": sol_s, "auto_speedup_vs_solver": sol_s / auto_s,
+           "solver_s": sol_s, "solver_s_per_query": per_sol,
+           "auto_s": auto_s, "auto_speedup_same_batch": sol_s / auto_s,
+           "auto_stream": {"queries": n_stream, "s": stream_s, "to_solver": n_fb, "s_per_query": per_auto},
+           "auto_speedup_per_query": per_sol / per_auto,
            "auto_fraction_to_solver": n_sol / n_cmp,
            "auto_err_vs_solver": {"rms": float(np.sqrt(np.mean(da * da))), "p99": float(np.percentile(da, 99)),
                                   "max": float(da.max()), "within_tol": float(np.mean(da <= 1e-2))},

@@ -238,7 +238,8 @@ qs_status qs_get_plan(const qs_ctx *ctx, qs_plan *plan, int32_t *n_workgroups,
  * Advance every instance by n_steps >= 0 tau-steps of its own d_tau (the hot path: one
  * fused causal march over xi per step carrying all four Runge-Kutta stages; each snapshot
  * interval runs as one persistent launch, which writes the interval's snapshot during its
- * first sweep when the plan has one column per lane).
+ * first sweep when the plan has one column per lane; snapshots at every step run as one
+ * launch whose sweeps, with one column per lane, still take two steps and write both).
  * Outputs (device pointers, each may be NULL; element type double for QS_FP64, float for
  * QS_FP32), for the modes of all instances concatenated in instance order (mode index
  * M = sum of n_modes of the earlier instances + m):

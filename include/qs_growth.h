@@ -121,12 +121,17 @@ qs_status qs_growth_calibrate(qs_mlp *net, const float *Q, const float *T, int64
  *   QS_GROWTH_SOLVER    : the solver for every query (net and table ignored; may be NULL).
  *   QS_GROWTH_AUTO      : the network where the query is inside the box and its bin's
  *                         held-out error is in [0, tol]; the solver elsewhere.
- * used_solver (device [n] bytes, optional): 1 where the solver answered.  The solver path
- * copies the selected queries to the host and runs them as the modes of solver contexts of one
- * instance each, 32 queries of any beams per wavefront: in units of each query's own step the
- * model is the unit-density beam with the push coefficients scaled by d_tau^2 (the same
- * discrete solution); queries sorted by the cells they need, chunked so that a context's state
- * and snapshots stay within 16 GB; it allocates its buffers and synchronizes.
+ * used_solver (device [n] bytes, optional): 1 where the solver answered.  AUTO picks out the
+ * queries for the solver on the device and copies only those to the host.  The solver path
+ * runs its queries as the modes of solver contexts, 32 queries of any beams per wavefront: in
+ * units of each query's own step the model is the unit-density beam with the push
+ * coefficients scaled by d_tau^2 (the same discrete solution).  Queries are sorted by the last
+ * step they read and cut into chunks of at most 32768; a chunk's queries, sorted by the cells
+ * they need, form instances of 32 that each reach two cells beyond their largest xi.  The
+ * context marches without fields to the chunk's first step read, then writes the fields of
+ * every later step, kept only for each instance's rear cells that the windows read, and the
+ * answers are summed from those snapshots.  It allocates its buffers (within 16 GB per chunk)
+ * and synchronizes.
  */
 qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float *q, int64_t n,
                         int32_t mode, float *out, uint8_t *used_solver, void *hip_stream);

@@ -568,6 +568,30 @@ qs_status qs::set_mode_coefficients(qs_ctx *c, const double *cT, const double *c
     return QS_OK;
 }
 
+qs_status qs::set_snapshot_cells(qs_ctx *c, const int32_t *first, int64_t *snap_elems) {
+    if (!c || !first || !snap_elems) return fail(QS_ERR_ARG, "set_snapshot_cells: arguments are required");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "set_snapshot_cells: spectral contexts only");
+    Plan &pl = c->pl;
+    for (size_t i = 0; i < pl.inst.size(); ++i)
+        if (first[i] < 0 || first[i] >= pl.inst[i].n_xi)
+            return fail(QS_ERR_ARG, "set_snapshot_cells: first cell of instance " + std::to_string(i) + " out of range");
+    int64_t snap = 0;
+    for (size_t i = 0; i < pl.inst.size(); ++i) {
+        InstDev &d = pl.inst[i];
+        d.snap_first = first[i];
+        d.snap_off = snap;
+        snap += (int64_t)(d.n_xi - d.snap_first) * d.n_modes;
+    }
+    pl.snap_elems = snap;
+    *snap_elems = snap;
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_inst), pl.inst.data(), pl.inst.size() * sizeof(InstDev), hipMemcpyHostToDevice,
+                          c->stream),
+           "copy instance table");
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return QS_OK;
+}
+
 namespace {
 
 bool is_grid(const qs_params *params, int32_t n) {

@@ -315,6 +315,19 @@ __global__ void __launch_bounds__(256) scatter_kernel(const int64_t *__restrict_
     if (used) used[idx[i]] = 1;
 }
 
+// The queries flagged for the solver, appended in any order (slots from a counter) with their
+// positions: at most cap of them are written, the counter ends at their number.
+__global__ void __launch_bounds__(256) select_kernel(const float *__restrict__ q, const uint8_t *__restrict__ flag,
+                                                     int64_t n, unsigned long long *__restrict__ count,
+                                                     int64_t *__restrict__ idx, float *__restrict__ rows, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const int64_t slot = (int64_t)atomicAdd(count, 1ull);
+    if (slot >= cap) return;
+    idx[slot] = i;
+    for (int d = 0; d < 5; ++d) rows[5 * slot + d] = q[5 * i + d];
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 constexpr int kMaxDevices = 64;
@@ -392,173 +405,238 @@ constexpr double kCellWidth = 200.0 / 8192.0;
 int cells_for(double L) { return std::max(1, (int)std::ceil(L / kCellWidth - 1e-9)); }
 
 // A query the solver answers: its beam (n_b, gamma), mode k, position, the step d_tau =
-// tau_f/200 of its beam, the cells its answer needs and its fractional step tau/d_tau.
+// tau_f/200 of its beam, the cells its answer needs, its fractional step tau/d_tau and the
+// last step whose fields it reads.
 struct SolverQuery {
     int64_t pos;        // position in the selection
     double nb, g, k, xi, d_tau, ts;
-    int cells;
+    int cells, last;
 };
 
 // One solver-answered query: the bilinear interpolation of the discrete windowed growth
 // between the two cell centres around its xi and the two steps around its tau.
 struct QueryRec {
-    int64_t base;     // snapshot element of (instance, mode) at cell 0 of step 0
+    int64_t base;     // snapshot element of (instance, mode) at the instance's first stored cell
     int32_t stride;   // the instance's mode count (elements between cells)
     int32_t win;      // window cells
     int32_t j0, s0;   // first cell and first step
     int32_t dst;      // answer slot
-    int32_t pad;
+    int32_t first;    // the instance's first stored cell
     double fx, ft;    // interpolation weights of cell j0 + 1 and step s0 + 1
     double ln_s;
 };
 
-// The windowed growth at one cell of one snapshot column by the direct Hann-weighted sum over
-// its window (the definition, in FP64; the full target pass over every cell is not needed
-// for a few queries).
-__device__ inline double growth_at(const float *__restrict__ le, const float *__restrict__ lb, int64_t base,
-                                   int32_t stride, int j, int win, double ln_s) {
+// The windowed growth at cell j of one snapshot column by the direct Hann-weighted sum over
+// its window (the definition, in FP64), the window's cells spread over the wavefront's lanes;
+// every lane returns the result.
+__device__ inline double growth_wave(const float *__restrict__ le, const float *__restrict__ lb, int64_t base,
+                                     int32_t stride, int j, int first, int win, double ln_s, int lane) {
     const int cnt = min(j + 1, win);
     double num = 0.0, den = 0.0;
-    for (int i = 0; i < cnt; ++i) {
+    for (int i = lane; i < cnt; i += qs::kWave) {
         const double s = sin(kPi * (i + 0.5) / win);
         const double w = s * s;
-        const int64_t e = base + (int64_t)(j - i) * stride;
+        const int64_t e = base + (int64_t)(j - i - first) * stride;
         num += w * a2_rel(le[e], lb[e], ln_s);
         den += w;
+    }
+    for (int o = qs::kWave / 2; o > 0; o >>= 1) {
+        num += __shfl_xor(num, o);
+        den += __shfl_xor(den, o);
     }
     return 0.5 * log(num / den);
 }
 
+// One wavefront per record of recs[0, n): the terms of its answer whose step lies in the
+// window of snapshots [step_lo, step_lo + n_win) are added to acc[dst] in the order
+// (step s0, cell j0), (s0, j0 + 1), (s0 + 1, j0), (s0 + 1, j0 + 1); windows pass in step order,
+// so every answer is summed in that order whichever windows hold its two steps.
 __global__ void __launch_bounds__(256) answer_kernel(const QueryRec *__restrict__ recs, int n,
                                                      const float *__restrict__ le, const float *__restrict__ lb,
-                                                     int64_t snap_elems, float *__restrict__ vals) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+                                                     int64_t snap_elems, int step_lo, int n_win,
+                                                     double *__restrict__ acc) {
+    const int r = (int)((blockIdx.x * blockDim.x + threadIdx.x) / qs::kWave);
+    const int lane = (int)threadIdx.x % qs::kWave;
     if (r >= n) return;
     const QueryRec Q = recs[r];
-    double acc = 0.0;
+    double sum = acc[Q.dst];
     for (int c = 0; c < 2; ++c) {
         const double wt = c == 0 ? 1.0 - Q.ft : Q.ft;
-        if (wt == 0.0) continue;
-        const int64_t row = Q.base + (int64_t)(Q.s0 + c) * snap_elems;
+        const int t = Q.s0 + c - step_lo;
+        if (wt == 0.0 || t < 0 || t >= n_win) continue;
+        const int64_t row = Q.base + (int64_t)t * snap_elems;
         for (int d = 0; d < 2; ++d) {
             const double w = wt * (d == 0 ? 1.0 - Q.fx : Q.fx);
             if (w == 0.0) continue;
-            acc += w * growth_at(le, lb, row, Q.stride, Q.j0 + d, Q.win, Q.ln_s);
+            sum += w * growth_wave(le, lb, row, Q.stride, Q.j0 + d, Q.first, Q.win, Q.ln_s, lane);
         }
     }
-    vals[Q.dst] = (float)acc;
+    if (lane == 0) acc[Q.dst] = sum;
 }
 
-// Solver answers for the queries q[a, b) (sorted by the cells they need), every one a mode
-// of one instance.  The model is linear and tau-invariant, so in units of each query's own
-// step (tau = n d_tau) with T'' = d_tau T' and P'' = d_tau P' the step is 1 and the push
-// coefficients become d_tau^2 cT Omega and d_tau^2 cP Omega: a beam of density n_b and
-// Lorentz factor gamma is the mode with those coefficients in a unit-density instance with
-// unit step (rho, n_p and so the fields are unchanged by the rescaling; the uniform seed
-// has no current).  So 32 queries of any beams fill a wavefront, where one instance per beam
-// would leave one mode per block.  The instance reaches two cells beyond the largest xi of
-// the chunk and is marched to the last step any query needs with the fields written at every
-// step; every answer then comes from those snapshots in one kernel.
-qs_status solve_packed(const std::vector<SolverQuery> &q, size_t a, size_t b, hipStream_t s,
-                       std::vector<float> *vals) {
+// Budgets of one solver context: queries, and bytes of state plus snapshots.
+constexpr int kChunkQueries = 32768;
+constexpr size_t kChunkBytes = size_t(16) << 30;
+constexpr int kGroup = 32;   // queries per instance: the modes of one 64-lane column block
+
+// Solver answers for the queries q[a, b), every one a mode of a unit-density instance.  The
+// model is linear and tau-invariant, so in units of each query's own step (tau = n d_tau)
+// with T'' = d_tau T' and P'' = d_tau P' the step is 1 and the push coefficients become
+// d_tau^2 cT Omega and d_tau^2 cP Omega: a beam of density n_b and Lorentz factor gamma is the
+// mode with those coefficients in a unit-density instance with unit step (rho, n_p and so
+// the fields are unchanged by the rescaling; the uniform seed has no current).  So 32
+// queries of any beams fill a wavefront.  The chunk's queries, sorted by the cells they
+// need, form instances of 32, each reaching two cells beyond its largest xi; the context
+// marches without fields to the first step any query reads, then writes the fields of every
+// step up to the last one read into a rolling window of snapshots, and each window's
+// answers are accumulated before the next overwrites it.
+qs_status solve_chunk(const std::vector<SolverQuery> &all, size_t a, size_t b, hipStream_t s,
+                      std::vector<float> *vals) {
     const double S = 1e-6;
     const int nq = (int)(b - a);
-    int N = 1, last_step = 0;
+    std::vector<SolverQuery> q(all.begin() + a, all.begin() + b);
+    std::stable_sort(q.begin(), q.end(), [](const SolverQuery &x, const SolverQuery &y) { return x.cells < y.cells; });
+    const int n_inst = (nq + kGroup - 1) / kGroup;
     std::vector<double> ks(nq), cT(nq), cP(nq);
     for (int i = 0; i < nq; ++i) {
-        const SolverQuery &Q = q[a + i];
-        N = std::max(N, Q.cells);
-        const int s0 = (int)std::floor(Q.ts);
-        last_step = std::max(last_step, s0 + (Q.ts > s0 ? 1 : 0));
+        const SolverQuery &Q = q[i];
         const double k = Q.k, kp = 1.0 / (1.0 + k * k), d2 = Q.d_tau * Q.d_tau;
         ks[i] = k;
         cT[i] = d2 * k * k * kp * Q.nb / Q.g;                          // Omega = n_b, gamma^-1
         cP[i] = -d2 * kp * Q.nb / (Q.g * Q.g * Q.g) / kCellWidth;       // gamma^-3, 1/h
     }
-    const double qv[1] = {-1.0}, mv[1] = {1.0}, nbv[1] = {1.0};
-    qs_params p;
-    std::memset(&p, 0, sizeof(p));
-    p.n_species = 1;
-    p.q = qv;
-    p.m = mv;
-    p.nb_over_np = nbv;
-    p.gamma_b = 2.0;   // its push coefficients are replaced below
-    p.length = N * kCellWidth;
-    p.profile = QS_PROFILE_FLATTOP;
-    p.geometry = QS_GEOM_SPECTRAL;
-    p.n_modes = nq;
-    p.kx = ks.data();
-    p.n_xi = N;
-    p.d_tau = 1.0;
-    p.precision = QS_FP32;
-    p.seed_kind = QS_SEED_UNIFORM;
-    p.seed_amp = S;
+    static const double qv[1] = {-1.0}, mv[1] = {1.0}, nbv[1] = {1.0};
+    const int win = window_cells(kCellWidth);
+    std::vector<qs_params> ps(n_inst);
+    std::vector<int32_t> first(n_inst);
     std::vector<QueryRec> recs(nq);
-    for (int i = 0; i < nq; ++i) {
-        const SolverQuery &Q = q[a + i];
-        QueryRec &r = recs[i];
-        r.base = i;
-        r.stride = nq;
-        r.win = window_cells(kCellWidth);
-        // cells: centres (j + 1/2) h around xi (clamped to the first and last cell)
-        const double xc = Q.xi / kCellWidth - 0.5;
-        r.j0 = (int)std::floor(xc);
-        r.fx = xc - r.j0;
-        if (r.j0 < 0) { r.j0 = 0; r.fx = 0.0; }
-        if (r.j0 >= N - 1) { r.j0 = N - 1; r.fx = 0.0; }
-        r.s0 = (int)std::floor(Q.ts);
-        r.ft = Q.ts - r.s0;
-        r.ln_s = std::log(S);
-        r.dst = i;
+    int64_t snap = 0;
+    int s_min = 1 << 30, s_max = 0;
+    for (int g = 0; g < n_inst; ++g) {
+        const int i0 = g * kGroup, i1 = std::min(nq, i0 + kGroup);
+        const int N = q[i1 - 1].cells;   // the group's largest
+        qs_params &p = ps[g];
+        std::memset(&p, 0, sizeof(p));
+        p.n_species = 1;
+        p.q = qv;
+        p.m = mv;
+        p.nb_over_np = nbv;
+        p.gamma_b = 2.0;   // its push coefficients are replaced below
+        p.length = N * kCellWidth;
+        p.profile = QS_PROFILE_FLATTOP;
+        p.geometry = QS_GEOM_SPECTRAL;
+        p.n_modes = i1 - i0;
+        p.kx = ks.data() + i0;
+        p.n_xi = N;
+        p.d_tau = 1.0;
+        p.precision = QS_FP32;
+        p.seed_kind = QS_SEED_UNIFORM;
+        p.seed_amp = S;
+        int jmin = N;
+        for (int i = i0; i < i1; ++i) {
+            const SolverQuery &Q = q[i];
+            QueryRec &r = recs[i];
+            r.stride = i1 - i0;
+            r.win = win;
+            // cells: centres (j + 1/2) h around xi (clamped to the first and last cell)
+            const double xc = Q.xi / kCellWidth - 0.5;
+            r.j0 = (int)std::floor(xc);
+            r.fx = xc - r.j0;
+            if (r.j0 < 0) { r.j0 = 0; r.fx = 0.0; }
+            if (r.j0 >= N - 1) { r.j0 = N - 1; r.fx = 0.0; }
+            r.s0 = (int)std::floor(Q.ts);
+            r.ft = Q.ts - r.s0;
+            r.ln_s = std::log(S);
+            r.dst = i;
+            jmin = std::min(jmin, r.j0);
+            s_min = std::min(s_min, r.s0);
+            s_max = std::max(s_max, Q.last);
+        }
+        // the snapshots keep the cells any window of the group reads: from its lowest cell on
+        // (the group's queries lie within a few cells of each other, near its rear)
+        first[g] = std::max(0, jmin - win + 1);
+        for (int i = i0; i < i1; ++i) {
+            recs[i].base = snap + (i - i0);
+            recs[i].first = first[g];
+        }
+        snap += (int64_t)(N - first[g]) * (i1 - i0);
     }
-    const int n_snap = last_step + 1;  // the states at steps 0 .. last_step
-    const int64_t snap = (int64_t)N * nq;
+    // records in step order: a window of steps [lo, hi) serves those with lo - 1 <= s0 < hi
+    std::stable_sort(recs.begin(), recs.end(), [](const QueryRec &x, const QueryRec &y) { return x.s0 < y.s0; });
+    std::vector<int> rs0(nq);
+    for (int i = 0; i < nq; ++i) rs0[i] = recs[i].s0;
+
     qs_ctx *ctx = nullptr;
-    qs_status st = qs_init(&p, 1, s, nullptr, 0, &ctx);
+    qs_status st = qs_init(ps.data(), n_inst, s, nullptr, 0, &ctx);
     if (st != QS_OK) return st;
     st = qs::set_mode_coefficients(ctx, cT.data(), cP.data());
+    int64_t snap_ctx = 0;
+    if (st == QS_OK) st = qs::set_snapshot_cells(ctx, first.data(), &snap_ctx);
+    if (st == QS_OK && snap_ctx != snap) st = gfail(QS_ERR_HIP, "growth map: snapshot layout mismatch");
     if (st != QS_OK) {
         qs_free(ctx);
         return st;
     }
+    const size_t state_bytes = qs_workspace_size_ex(ps.data(), n_inst, nullptr);
+    const size_t per_snap = (size_t)snap * 2 * sizeof(float);
+    const size_t room = kChunkBytes > state_bytes ? kChunkBytes - state_bytes : 0;
+    const int n_win = (int)std::max<size_t>(1, std::min<size_t>((size_t)(s_max - s_min + 1), room / per_snap));
     char *buf = nullptr;
-    const size_t snap_bytes = (((size_t)snap * n_snap * 2 * sizeof(float) + 255) / 256) * 256;
-    const size_t rec_bytes = recs.size() * sizeof(QueryRec);
-    if (hipMalloc(&buf, snap_bytes + rec_bytes + (size_t)nq * sizeof(float)) != hipSuccess) {
+    const size_t snap_bytes = ((per_snap * n_win + 255) / 256) * 256;
+    const size_t rec_bytes = ((recs.size() * sizeof(QueryRec) + 255) / 256) * 256;
+    if (hipMalloc(&buf, snap_bytes + rec_bytes + (size_t)nq * sizeof(double)) != hipSuccess) {
         (void)hipGetLastError();
         qs_free(ctx);
         return gfail(QS_ERR_ALLOC, "growth map: snapshot buffers");
     }
-    float *le = reinterpret_cast<float *>(buf), *lb = le + (size_t)snap * n_snap;
+    float *le = reinterpret_cast<float *>(buf), *lb = le + (size_t)snap * n_win;
     QueryRec *d_recs = reinterpret_cast<QueryRec *>(buf + snap_bytes);
-    float *d_vals = reinterpret_cast<float *>(buf + snap_bytes + rec_bytes);
-    if (hipMemcpyAsync(d_recs, recs.data(), rec_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    double *d_acc = reinterpret_cast<double *>(buf + snap_bytes + rec_bytes);
+    if (hipMemcpyAsync(d_recs, recs.data(), recs.size() * sizeof(QueryRec), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(d_acc, 0, (size_t)nq * sizeof(double), s) != hipSuccess)
         st = gfail(QS_ERR_HIP, "growth map: copy query records");
-    if (st == QS_OK) st = n_snap > 1 ? qs_step_tau(ctx, n_snap, 1, le, lb, nullptr) : qs_step_tau(ctx, 0, 1, le, lb, nullptr);
-    if (st == QS_OK) {
-        hipLaunchKernelGGL(answer_kernel, dim3(blocks_for((int64_t)nq)), dim3(256), 0, s, d_recs, nq, le, lb, snap,
-                           d_vals);
-        if (hipGetLastError() != hipSuccess) st = gfail(QS_ERR_HIP, "growth map: answer kernel");
+    if (st == QS_OK && s_min > 0) st = qs_step_tau(ctx, s_min, 1, nullptr, nullptr, nullptr);
+    for (int lo = s_min; st == QS_OK && lo <= s_max;) {
+        const int cnt = std::min(n_win, s_max + 1 - lo);   // snapshots of steps lo .. lo + cnt - 1
+        // the state at the start of step lo + cnt - 1 is the last one written: a stepping call
+        // writes the state before each of its steps, so the last snapshot of the run, at
+        // s_max, comes from a call that only writes the current state
+        const bool last = lo + cnt - 1 == s_max;
+        const int n_steps = last ? cnt - 1 : cnt;
+        if (n_steps > 0) st = qs_step_tau(ctx, n_steps, 1, le, lb, nullptr);
+        if (st == QS_OK && last)
+            st = qs_step_tau(ctx, 0, 1, le + (size_t)snap * n_steps, lb + (size_t)snap * n_steps, nullptr);
+        const int ra = (int)(std::lower_bound(rs0.begin(), rs0.end(), lo - 1) - rs0.begin());
+        const int rb = (int)(std::lower_bound(rs0.begin(), rs0.end(), lo + cnt) - rs0.begin());
+        if (st == QS_OK && rb > ra) {
+            const int64_t threads = (int64_t)(rb - ra) * qs::kWave;
+            hipLaunchKernelGGL(answer_kernel, dim3(blocks_for(threads)), dim3(256), 0, s, d_recs + ra, rb - ra, le, lb,
+                               snap, lo, cnt, d_acc);
+            if (hipGetLastError() != hipSuccess) st = gfail(QS_ERR_HIP, "growth map: answer kernel");
+        }
+        lo += cnt;
     }
-    std::vector<float> hv(nq);
-    if (st == QS_OK && (hipMemcpyAsync(hv.data(), d_vals, hv.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    std::vector<double> hv(nq);
+    if (st == QS_OK && (hipMemcpyAsync(hv.data(), d_acc, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
                         hipStreamSynchronize(s) != hipSuccess))
         st = gfail(QS_ERR_HIP, "growth map: copy answers");
     if (st == QS_OK) st = qs_sync_check(ctx);
     if (st == QS_OK)
-        for (int i = 0; i < nq; ++i) (*vals)[q[a + i].pos] = hv[i];
+        for (int i = 0; i < nq; ++i) (*vals)[q[i].pos] = (float)hv[i];
     (void)hipFree(buf);
     qs_free(ctx);
     return st;
 }
 
 
-qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t> &sel, hipStream_t s,
-                        std::vector<float> *vals) {
+// Solver answers vals[i] for the queries rows[5 i .. 5 i + 4] (host), i < sel.size(); sel[i] is
+// the query's position in the caller's array (named in errors).
+qs_status solve_queries(const float *rows, const std::vector<int64_t> &sel, hipStream_t s, std::vector<float> *vals) {
     // the solver needs a physical beam and a point on or behind its front at tau >= 0; the
     // step count follows tau (tau_f/200 per step), so tau beyond tau_f marches further
-    for (int64_t p : sel) {
-        const float *q = &hq[5 * (size_t)p];
+    for (size_t i = 0; i < sel.size(); ++i) {
+        const int64_t p = sel[i];
+        const float *q = rows + 5 * i;
         bool ok = true;
         for (int d = 0; d < 5; ++d) ok = ok && std::isfinite(q[d]);
         ok = ok && q[1] > 0.0f && q[2] >= 0.0f && q[3] >= 0.0f && q[4] >= 0.0f;
@@ -570,7 +648,7 @@ qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t>
     }
     std::vector<SolverQuery> q(sel.size());
     for (size_t i = 0; i < sel.size(); ++i) {
-        const float *x = &hq[5 * (size_t)sel[i]];
+        const float *x = rows + 5 * i;
         SolverQuery &Q = q[i];
         Q.pos = (int64_t)i;
         Q.nb = std::exp((double)x[0]);
@@ -579,31 +657,32 @@ qs_status solve_queries(const std::vector<float> &hq, const std::vector<int64_t>
         Q.xi = (double)x[3];
         Q.d_tau = tau_final(Q.nb, Q.g) / 200.0;
         Q.ts = (double)x[4] / Q.d_tau;
+        const int s0 = (int)std::floor(Q.ts);
+        Q.last = s0 + (Q.ts > s0 ? 1 : 0);
         // two cells beyond xi: the cell centre behind the query is in the beam and is not the
         // last cell (the beam's rear face carries no current, which changes the last cell's
         // charge -- and only that cell's, the march being causal)
         Q.cells = cells_for(Q.xi + 2.0 * kCellWidth);
     }
+    // chunks of consecutive queries in the order of the last step they read: a chunk
+    // marches to its largest, so queries of similar steps share one; within the budgets of
+    // queries and of state plus one snapshot per chunk
     std::sort(q.begin(), q.end(), [](const SolverQuery &x, const SolverQuery &y) {
-        return x.cells != y.cells ? x.cells < y.cells : x.pos < y.pos;
+        return x.last != y.last ? x.last < y.last : (x.cells != y.cells ? x.cells < y.cells : x.pos < y.pos);
     });
     vals->assign(sel.size(), 0.f);
-    // chunks of consecutive queries (sorted by the cells they need) whose solver state and
-    // snapshots (every step up to the last one any of them needs) stay within a fixed budget
-    const size_t kBudget = size_t(16) << 30;
     size_t a = 0;
     while (a < q.size()) {
-        size_t b = a;
-        int steps = 1;
-        while (b < q.size()) {
-            const size_t n = b + 1 - a, cells = (size_t)q[b].cells;   // the largest so far
-            const int st_q = (int)std::ceil(q[b].ts) + 2;
-            const size_t bytes = (n + 31) / 32 * cells * 3 * 64 * 4 + cells * n * 8 * (size_t)std::max(steps, st_q);
-            if (b > a && (bytes > kBudget || n > 65536)) break;
-            steps = std::max(steps, st_q);
+        size_t b = a, cells = 0;
+        while (b < q.size() && b - a < (size_t)kChunkQueries) {
+            // state (3 rows of 64 lanes per 32 queries) and one snapshot, from the query's own
+            // cells (every instance reaches its largest: bounded by the next query's cells)
+            const size_t c = (size_t)q[b].cells;
+            if (b > a && (cells + c) * (24 + 8) * 2 > kChunkBytes) break;
+            cells += c;
             ++b;
         }
-        qs_status st = solve_packed(q, a, b, s, vals);
+        qs_status st = solve_chunk(q, a, b, s, vals);
         if (st != QS_OK) return st;
         a = b;
     }
@@ -756,26 +835,65 @@ qs_status qs_growth_map(qs_mlp *net, const float *table, float tol, const float 
         G_HIP(hipStreamSynchronize(s), "synchronize");
         return QS_OK;
     }
-    // which queries go to the solver
-    std::vector<float> hq((size_t)n * 5);
-    G_HIP(hipMemcpyAsync(hq.data(), q, hq.size() * sizeof(float), hipMemcpyDeviceToHost, s), "copy queries");
+    // which queries go to the solver, with their rows, in the order of their positions
     std::vector<int64_t> sel;
+    std::vector<float> rows;
     if (mode == QS_GROWTH_AUTO) {
         flag = used_solver;
         if (!flag && hipMalloc(&flag, (size_t)n) != hipSuccess) { cleanup(); return gfail(QS_ERR_ALLOC, "allocate flags"); }
         hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, n, base, out, table, tol, flag);
-        std::vector<uint8_t> hf((size_t)n);
-        if (hipMemcpyAsync(hf.data(), flag, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) { cleanup(); return gfail(QS_ERR_HIP, "copy flags"); }
-        for (int64_t i = 0; i < n; ++i) if (hf[i]) sel.push_back(i);
+        // the flagged queries are compacted on the device: a first pass counts them into a
+        // buffer for up to 65536, a second pass fills one of the counted size if they are more
+        int64_t cap = std::min<int64_t>(n, 65536), cnt = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            char *sb = nullptr;
+            const size_t bytes = 256 + (size_t)cap * (sizeof(int64_t) + 5 * sizeof(float));
+            if (hipMalloc(&sb, bytes) != hipSuccess) { (void)hipGetLastError(); cleanup(); return gfail(QS_ERR_ALLOC, "allocate selection"); }
+            auto *d_cnt = reinterpret_cast<unsigned long long *>(sb);
+            auto *d_idx = reinterpret_cast<int64_t *>(sb + 256);
+            auto *d_rows = reinterpret_cast<float *>(sb + 256 + (size_t)cap * sizeof(int64_t));
+            unsigned long long hc = 0;
+            hipError_t e = hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long), s);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(select_kernel, dim3(blocks_for(n)), dim3(256), 0, s, q, flag, n, d_cnt, d_idx, d_rows, cap);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(&hc, d_cnt, sizeof(hc), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            cnt = (int64_t)hc;
+            std::vector<int64_t> hi;
+            std::vector<float> hr;
+            if (e == hipSuccess && cnt <= cap) {
+                hi.resize((size_t)cnt);
+                hr.resize((size_t)cnt * 5);
+                if (cnt > 0) e = hipMemcpyAsync(hi.data(), d_idx, hi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess && cnt > 0) e = hipMemcpyAsync(hr.data(), d_rows, hr.size() * sizeof(float), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+            }
+            (void)hipFree(sb);
+            if (e != hipSuccess) { cleanup(); return gfail(QS_ERR_HIP, std::string("select solver queries: ") + hipGetErrorString(e)); }
+            if (cnt > cap) { cap = cnt; continue; }
+            std::vector<int64_t> order((size_t)cnt);
+            for (int64_t i = 0; i < cnt; ++i) order[i] = i;
+            std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return hi[x] < hi[y]; });
+            sel.resize((size_t)cnt);
+            rows.resize((size_t)cnt * 5);
+            for (int64_t i = 0; i < cnt; ++i) {
+                sel[i] = hi[order[i]];
+                for (int d = 0; d < 5; ++d) rows[5 * i + d] = hr[5 * order[i] + d];
+            }
+            break;
+        }
     } else {
+        rows.resize((size_t)n * 5);
+        G_HIP(hipMemcpyAsync(rows.data(), q, rows.size() * sizeof(float), hipMemcpyDeviceToHost, s), "copy queries");
         G_HIP(hipStreamSynchronize(s), "synchronize");
         sel.resize((size_t)n);
         for (int64_t i = 0; i < n; ++i) sel[i] = i;
     }
     if (!sel.empty()) {
         std::vector<float> vals;
-        st = solve_queries(hq, sel, s, &vals);
+        st = solve_queries(rows.data(), sel, s, &vals);
         if (st == QS_OK) {
             int64_t *d_idx = nullptr;
             float *d_val = nullptr;

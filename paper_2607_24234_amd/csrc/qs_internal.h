@@ -25,7 +25,7 @@ struct InstDev {
     int32_t pmode0;      // first padded global mode index
     int32_t mode0;       // first global (unpadded) mode index
     int32_t flags;       // QS_FLAG_*
-    int32_t pad_;
+    int32_t snap_first;  // first cell written to snapshots (rows j - snap_first); 0 unless narrowed
     int64_t state_off;   // element offset of block 0 in the state array
     int64_t omega_off;   // element offset of this instance's Omega tables (centres, then faces)
     int64_t snap_off;    // element offset of this instance inside one snapshot
@@ -99,6 +99,13 @@ struct SeedArgs {
 // qs_params order) of a spectral context: lets modes of one instance stand for beams of other
 // densities, Lorentz factors and steps (qs_growth.hip).  Synchronous.
 qs_status set_mode_coefficients(qs_ctx *c, const double *cT, const double *cP);
+
+// Narrow the snapshots of a spectral context to the cells j >= first[i] of each instance i
+// (host array of n_instances, 0 <= first[i] < n_xi): instance i then holds
+// [n_xi - first[i]][n_modes] elements of each snapshot, row j - first[i] for cell j, at the
+// running offset over the instances (qs_growth.hip reads only the rear cells).  *snap_elems
+// receives the elements of one snapshot.  Synchronous; QS_ERR_ARG for an invalid cell.
+qs_status set_snapshot_cells(qs_ctx *c, const int32_t *first, int64_t *snap_elems);
 
 // launchers (qs_spectral.hip)
 // front0[(gb * nc + c) * 64 + lane] = rho of cell 0 of that column of the stored state (the

@@ -239,13 +239,14 @@ __device__ __forceinline__ bool wait_flag(int *flag, int target, int *abort, uin
     return true;
 }
 
-// Snapshot forms of the march: none; every step of the launch (one step per sweep); the
+// Snapshot forms of the march: none; every step of the launch (with one column per lane the
+// sweeps keep two steps and write the fields of both; one step per sweep otherwise); the
 // launch's first step only, inside the stepping kernel (its sweeps keep their step count).
 constexpr int kSnapNone = 0, kSnapEvery = 1, kSnapFirst = 2;
 
 template <typename TS, typename TC, int NC, bool RESTORING, bool FIELDS, int SNAP, bool FLAT>
 __global__ void __launch_bounds__(sizeof(TS) == 4 && NC == 1 ? (kSweepSlots == 2 ? 768 : 1024) : 512)
-__attribute__((amdgpu_waves_per_eu(NC == 1 && SNAP != kSnapEvery ? (sizeof(TS) == 8 ? (kSweepSlots == 2 ? 2 : 4) : (kSweepSlots == 2 ? 3 : 5)) : 1)))
+__attribute__((amdgpu_waves_per_eu(NC == 1 ? (sizeof(TS) == 8 ? (kSweepSlots == 2 ? 2 : 4) : (kSweepSlots == 2 ? 3 : 5)) : 1)))
 march_kernel(StepArgs a) {
     using CL = Cols<NC>;
     using PL = Payload<TC, NC>;
@@ -321,14 +322,14 @@ march_kernel(StepArgs a) {
 
     // steps one sweep can take: two for the stepping kernels with one column per lane, where
     // the second step's carries still fit the register budget; one otherwise
-    constexpr int NS = (SNAP != kSnapEvery && NC == 1) ? kSweepSlots : 1;
+    constexpr int NS = NC == 1 ? kSweepSlots : 1;
     double y[NS][4][NC], v[NS][4][NC];  // per step of the sweep and stage: n_p and d_xi n_p at the front face
     TC pp[NS][4][NC];                   // stage inputs of P' at the front face of the current cell
     TC scale[MPL], rmax[MPL], a2max[NS][MPL];
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
 
-    int64_t snap_row = a.snap_base;  // snapshot of the current step (kSnapEvery: one step per sweep)
+    int64_t snap_row = a.snap_base;  // snapshot of the sweep's first step (kSnapEvery: the next at + snap_stride)
     bool snap_now = SNAP == kSnapEvery;  // kSnapFirst: the first sweep's first step
 
     // One segment pass of a sweep of K tau-steps: per cell, all four stages of each step, the
@@ -427,9 +428,10 @@ march_kernel(StepArgs a) {
                             if (NC >= 2) s2 = k2kap2[t] * (ncf0[2 * t] * ncf0[2 * t] + ncf0[2 * t + 1] * ncf0[2 * t + 1]);
                             else s2 = pair_sum(k2kap2[0] * ncf0[0] * ncf0[0]);
                         }
-                        if (writer && mloc[t] < I.n_modes) {
+                        if (writer && mloc[t] < I.n_modes && j >= I.snap_first) {
                             const double sh = (double)L[t] * 0.69314718055994530942;
-                            const int64_t o = snap_row + I.snap_off + (int64_t)j * I.n_modes + mloc[t];
+                            const int64_t o = snap_row + (SNAP == kSnapEvery ? sl * a.snap_stride : 0) + I.snap_off +
+                                              (int64_t)(j - I.snap_first) * I.n_modes + mloc[t];
                             static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(s2) + sh);
                             static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
                         }
