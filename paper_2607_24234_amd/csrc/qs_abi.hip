@@ -439,11 +439,14 @@ GuardArgs guard_args(qs_ctx *c) {
 qs_status upload_tables(qs_ctx *c, const qs_params *params) {
     const Plan &pl = c->pl;
     const int n = (int)pl.inst.size();
-    std::vector<double> shape(pl.table_elems, 0.0);
-    std::vector<double> om64(pl.table_elems, 0.0);
     std::vector<double> kmode(pl.total_pmodes, 0.0);
     std::vector<double> coef(2 * (size_t)pl.total_pmodes, 0.0);
     std::vector<int32_t> iidx(n);
+    // tables: a flat-top instance's are constants, filled on the device; the others are built
+    // here and copied per instance
+    std::vector<FlatTable> flat;
+    std::vector<std::vector<double>> shapes, oms;
+    std::vector<std::vector<float>> om32s;
     for (int i = 0; i < n; ++i) {
         const qs_params &p = params[i];
         const InstDev &d = pl.inst[i];
@@ -451,19 +454,41 @@ qs_status upload_tables(qs_ctx *c, const qs_params *params) {
         const double h = p.length / N;
         double q2nm = 0.0;  // sum_s q_s^2 nb_s / m_s
         for (int s = 0; s < p.n_species; ++s) q2nm += p.q[s] * p.q[s] * p.nb_over_np[s] / p.m[s];
-        double *f = shape.data() + d.omega_off;
-        double *oc = om64.data() + d.omega_off;
-        double *of = oc + N;
-        for (int j = 0; j < N; ++j) {
-            const double xi = (j + 0.5) * h;
-            if (p.profile == QS_PROFILE_FLATTOP) f[j] = 1.0;
-            else if (p.profile == QS_PROFILE_GAUSSIAN) {
-                const double z = (xi - p.xi_center) / p.sigma_xi;
-                f[j] = std::exp(-0.5 * z * z);
-            } else f[j] = p.profile_table[j];
-            oc[j] = q2nm * f[j];
+        if (p.profile == QS_PROFILE_FLATTOP) {
+            FlatTable ft;
+            ft.off = d.omega_off;
+            ft.n = N;
+            ft.pad = 0;
+            ft.q2nm = q2nm;
+            flat.push_back(ft);
+        } else {
+            shapes.emplace_back(2 * (size_t)N, 0.0);
+            oms.emplace_back(2 * (size_t)N, 0.0);
+            double *f = shapes.back().data();
+            double *oc = oms.back().data();
+            double *of = oc + N;
+            for (int j = 0; j < N; ++j) {
+                const double xi = (j + 0.5) * h;
+                if (p.profile == QS_PROFILE_GAUSSIAN) {
+                    const double z = (xi - p.xi_center) / p.sigma_xi;
+                    f[j] = std::exp(-0.5 * z * z);
+                } else f[j] = p.profile_table[j];
+                oc[j] = q2nm * f[j];
+            }
+            for (int j = 0; j < N; ++j) of[j] = (j + 1 < N) ? 0.5 * (oc[j] + oc[j + 1]) : 0.0;
+            QS_HIP(hipMemcpyAsync(reinterpret_cast<double *>(c->at(pl.off_shape)) + d.omega_off, f,
+                                  2 * (size_t)N * sizeof(double), hipMemcpyHostToDevice, c->stream), "copy profile");
+            if (pl.precision == QS_FP64) {
+                QS_HIP(hipMemcpyAsync(reinterpret_cast<double *>(c->at(pl.off_omega)) + d.omega_off, oc,
+                                      2 * (size_t)N * sizeof(double), hipMemcpyHostToDevice, c->stream),
+                       "copy Omega tables");
+            } else {
+                om32s.emplace_back(oms.back().begin(), oms.back().end());
+                QS_HIP(hipMemcpyAsync(reinterpret_cast<float *>(c->at(pl.off_omega)) + d.omega_off, om32s.back().data(),
+                                      2 * (size_t)N * sizeof(float), hipMemcpyHostToDevice, c->stream),
+                       "copy Omega tables");
+            }
         }
-        for (int j = 0; j < N; ++j) of[j] = (j + 1 < N) ? 0.5 * (oc[j] + oc[j + 1]) : 0.0;
         for (int64_t m = 0; m < p.n_modes; ++m) {
             const double kx = p.kx[m], ky = p.ky ? p.ky[m] : 0.0;
             const double k = std::sqrt(kx * kx + ky * ky), kp = 1.0 / (1.0 + k * k);
@@ -475,17 +500,18 @@ qs_status upload_tables(qs_ctx *c, const qs_params *params) {
         }
         iidx[i] = i;
     }
-    if (pl.precision == QS_FP64) {
-        QS_HIP(hipMemcpyAsync(c->at(pl.off_omega), om64.data(), om64.size() * sizeof(double),
-                              hipMemcpyHostToDevice, c->stream), "copy Omega tables");
-    } else {
-        std::vector<float> om32(om64.begin(), om64.end());
-        QS_HIP(hipMemcpyAsync(c->at(pl.off_omega), om32.data(), om32.size() * sizeof(float),
-                              hipMemcpyHostToDevice, c->stream), "copy Omega tables");
-        QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    if (!flat.empty()) {
+        // the descriptions are staged in the state array, which seeding clears next (it holds
+        // at least 3 x 64 elements per cell of every instance, far more than one description)
+        if (flat.size() * sizeof(FlatTable) > (size_t)pl.state_elems * pl.ts)
+            return fail(QS_ERR_HIP, "flat tables: staging does not fit");
+        auto *d_flat = reinterpret_cast<FlatTable *>(c->at(pl.off_state));
+        QS_HIP(hipMemcpyAsync(d_flat, flat.data(), flat.size() * sizeof(FlatTable), hipMemcpyHostToDevice, c->stream),
+               "copy flat tables");
+        QS_HIP(launch_flat_tables(pl.precision, d_flat, (int)flat.size(), reinterpret_cast<double *>(c->at(pl.off_shape)),
+                                  c->at(pl.off_omega), c->stream),
+               "flat tables");
     }
-    QS_HIP(hipMemcpyAsync(c->at(pl.off_shape), shape.data(), shape.size() * sizeof(double),
-                          hipMemcpyHostToDevice, c->stream), "copy profile");
     QS_HIP(hipMemcpyAsync(c->at(pl.off_k), kmode.data(), kmode.size() * sizeof(double),
                           hipMemcpyHostToDevice, c->stream), "copy wavenumbers");
     QS_HIP(hipMemcpyAsync(c->at(pl.off_coef), coef.data(), coef.size() * sizeof(double),

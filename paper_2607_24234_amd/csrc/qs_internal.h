@@ -107,7 +107,18 @@ qs_status set_mode_coefficients(qs_ctx *c, const double *cT, const double *cP);
 // receives the elements of one snapshot.  Synchronous; QS_ERR_ARG for an invalid cell.
 qs_status set_snapshot_cells(qs_ctx *c, const int32_t *first, int64_t *snap_elems);
 
+// The tables of a flat-top instance: Omega = q2nm at every centre and at every inner face (the
+// outer face 0), profile 1, at element offset `off` of the tables ([n] centres, [n] faces).
+struct FlatTable {
+    int64_t off;
+    int32_t n;
+    int32_t pad;
+    double q2nm;   // sum over species of q^2 n_b / m
+};
+
 // launchers (qs_spectral.hip)
+// flat-top instances' tables: shape (double) and omega (TC of the precision), one block each
+hipError_t launch_flat_tables(int precision, const FlatTable *ft, int n, double *shape, void *omega, hipStream_t s);
 // front0[(gb * nc + c) * 64 + lane] = rho of cell 0 of that column of the stored state (the
 // state at tau = 0 when called after seeding)
 hipError_t launch_front_capture(int precision, int nc, const void *state, const int32_t *blk_inst,

@@ -697,6 +697,17 @@ __global__ void __launch_bounds__(256) front_capture(const TS *__restrict__ stat
     front0[i] = (double)state[I.state_off + (int64_t)b * I.n_xi * 3 * NC * kWave + (int64_t)c * kWave + lane];
 }
 
+template <typename TC>
+__global__ void __launch_bounds__(256) flat_tables(const FlatTable *__restrict__ ft, double *__restrict__ shape,
+                                                   TC *__restrict__ omega) {
+    const FlatTable F = ft[blockIdx.x];
+    const int64_t n2 = 2 * (int64_t)F.n;
+    for (int64_t j = threadIdx.x; j < n2; j += blockDim.x) {
+        shape[F.off + j] = j < F.n ? 1.0 : 0.0;
+        omega[F.off + j] = (TC)(j + 1 < n2 ? F.q2nm : 0.0);   // the last face is the outer one
+    }
+}
+
 template <typename TS, int NC>
 hipError_t launch_seed_t(int n_blocks, int max_n_xi, const SeedArgs &a, hipStream_t s) {
     constexpr int kCellsPerWg = 4;
@@ -706,6 +717,15 @@ hipError_t launch_seed_t(int n_blocks, int max_n_xi, const SeedArgs &a, hipStrea
 }
 
 }  // namespace
+
+hipError_t launch_flat_tables(int precision, const FlatTable *ft, int n, double *shape, void *omega, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (precision == QS_FP64)
+        hipLaunchKernelGGL(flat_tables<double>, dim3(n), dim3(256), 0, s, ft, shape, static_cast<double *>(omega));
+    else
+        hipLaunchKernelGGL(flat_tables<float>, dim3(n), dim3(256), 0, s, ft, shape, static_cast<float *>(omega));
+    return hipGetLastError();
+}
 
 hipError_t launch_front_capture(int precision, int nc, const void *state, const int32_t *blk_inst,
                                 const InstDev *inst, int n_blocks, double *front0, hipStream_t s) {
