@@ -541,6 +541,29 @@ def bench_surrogate(args):
           network_speedup_vs_solver=None if fig is None else (fig["solver_s"] / fig["queries"]) / (sur_s / n_q))
 
 
+def bench_growth_solver(args):
+    """The growth map's solver alone on args.queries scattered box queries (the method without
+    the surrogate): every query marched to its own xi and tau, 32 of any beams per wavefront,
+    timed around one qs_growth_map call with its host preparation and synchronization."""
+    import torch
+    from paper_2607_24234_amd import inputs, qs
+
+    n = args.queries
+    q = torch.as_tensor(inputs.growth_queries(n, 3 + n), device="cuda")
+    out = torch.empty(n, device="cuda")
+    qs.growth_map(None, None, 0.0, q[:8], qs.GROWTH_SOLVER, out[:8])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    qs.growth_map(None, None, 0.0, q, qs.GROWTH_SOLVER, out)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    assert bool(torch.isfinite(out).all())
+    _line("growth-map queries answered by the solver", n / sec, "queries/s", 1, 1, sec * 1e3, "f32",
+          {"workload": "growth-map queries uniform over log n_b in [-3, -1], log gamma in [1, 4], k in "
+                       "[0.05, 4], xi in [0, 200], tau in [0, tau_f]; the solver alone", "queries": n},
+          None, None, s_per_query=sec / n)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,13 +576,17 @@ def main():
                     help="march launch plan of the spectral and batched workloads: the autotuner's "
                          "(timed candidates, a few seconds) or the built-in heuristic")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate", "svea", "regime"],
+    ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate", "svea", "regime",
+                                           "growth_solver"],
                     default="spectral3d",
                     help="spectral3d (default, the headline line); batched: 256-instance sweep in "
                          "one persistent launch; finite_width: 256^2 transverse grid x 8192 cells; "
                          "surrogate: growth-map queries, network against solver; svea: the envelope-"
                          "approximation variant on the 3D mode set; regime: the E/B regime map of a "
-                         "3D snapshot")
+                         "3D snapshot; growth_solver: the growth map's solver alone on --queries "
+                         "scattered queries")
+    ap.add_argument("--queries", type=int, default=1_000_000,
+                    help="growth_solver workload: number of scattered queries")
     ap.add_argument("--epochs", type=int, default=0,
                     help="surrogate training epochs (0: the library's default)")
     ap.add_argument("--surrogate-file", default=None, metavar="PATH",
@@ -595,7 +622,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "spectral3d":
         {"batched": bench_batched, "finite_width": bench_finite_width,
-         "surrogate": bench_surrogate, "svea": bench_svea, "regime": bench_regime}[args.workload](args)
+         "surrogate": bench_surrogate, "svea": bench_svea, "regime": bench_regime,
+         "growth_solver": bench_growth_solver}[args.workload](args)
         return
     inst = inputs.spectral3d()
     prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64
