@@ -227,6 +227,28 @@ def test_growth_map_solver_matches_oracle(qs):
     assert np.max(np.abs(got - ref)) <= 1e-4, np.abs(got - ref)
 
 
+def test_growth_map_solver_large_batch_sampled(qs):
+    """40,000 scattered box queries in one call (more than one chunk of 32,768, several
+    snapshot windows, instances of 32 queries sized to their own cells, snapshots of their rear
+    cells only): 64 sampled answers against the oracle's definition, each query its own beam,
+    to the FP32 bar of ln A; the same 64 answered alone agree with the batch's to FP32 rounding
+    of a different plan."""
+    import torch
+    from paper_2607_24234_amd import inputs
+    n = 40000
+    q = inputs.growth_queries(n, 2024)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    qs.growth_map(None, None, 0.0, torch.as_tensor(q, device="cuda"), qs.GROWTH_SOLVER, out)
+    got = out.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    pick = np.random.default_rng(7).choice(n, 64, replace=False)
+    ref = _oracle_solver_answers(q[pick])
+    assert np.max(np.abs(got[pick] - ref)) <= 1e-4, np.abs(got[pick] - ref)
+    alone = torch.empty(len(pick), dtype=torch.float32, device="cuda")
+    qs.growth_map(None, None, 0.0, torch.as_tensor(q[pick], device="cuda"), qs.GROWTH_SOLVER, alone)
+    assert np.max(np.abs(alone.cpu().numpy() - got[pick])) <= 2e-5
+
+
 def test_growth_map_surrogate_and_auto(qs):
     import torch
     net, P = _net(qs, 6)
