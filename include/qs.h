@@ -246,7 +246,8 @@ qs_status qs_get_plan(const qs_ctx *ctx, qs_plan *plan, int32_t *n_workgroups,
  *   out_ln_e, out_ln_b : field snapshots of the state at the start of every step s of this
  *                        call with s % out_every == 0; snapshot t of instance i starts at
  *                        element t * S + off_i with S = sum_i n_xi_i * n_modes_i and
- *                        off_i = sum_{i'<i} n_xi_i' * n_modes_i', then [n_xi_i][n_modes_i].
+ *                        off_i = sum_{i'<i} n_xi_i' * n_modes_i', then [n_xi_i][n_modes_i]
+ *                        (rows padded instead after qs_set_snapshot_align).
  *                        With n_steps == 0 one snapshot of the current state is written and
  *                        the state does not change.
  *   out_max_ln_a       : [n_steps][total modes] max over xi of ln A at the start of each step.
@@ -284,6 +285,24 @@ qs_status qs_sync_check(qs_ctx *ctx);
  * Errors: QS_ERR_ARG, QS_ERR_UNSUPPORTED (transverse-grid context), QS_ERR_ALLOC.
  */
 qs_status qs_set_rollback(qs_ctx *ctx, int32_t enable);
+
+/*
+ * Snapshot row alignment (spectral contexts; library design choice, not physics).  With
+ * align > 1 the snapshots that later qs_step_tau and qs_graph_create calls write pad each
+ * instance's rows to a multiple of `align` modes: instance i holds [n_xi_i][ld_i] elements of
+ * each snapshot, ld_i = n_modes_i rounded up to a multiple of align, the row of cell j holding
+ * mode m at j * ld_i + m, from off_i = sum_{i'<i} n_xi_i' ld_i'; a snapshot holds
+ * S = sum_i n_xi_i ld_i elements (*snapshot_elems, may be NULL) and the padding is not
+ * written.  The march writes the modes of one wavefront (32 with one column per lane) as one
+ * piece of each row, so with rows aligned to that piece (align 32, and a buffer aligned to
+ * 128 bytes) each piece fills whole cache lines: partly written lines otherwise cost the
+ * memory a read before the write.  align = 1 restores the dense layout (the default).  The
+ * state, checkpoints and every other output are unaffected.  Synchronous.
+ * Errors: QS_ERR_ARG (align not a power of two in [1, 1024]), QS_ERR_UNSUPPORTED
+ * (transverse-grid context), QS_ERR_STATE (the context has graphs: free them first, they
+ * keep the layout they were made with), QS_ERR_HIP.
+ */
+qs_status qs_set_snapshot_align(qs_ctx *ctx, int32_t align, int64_t *snapshot_elems);
 
 /*
  * Number of tau-steps taken since qs_init (host).  Returns -1 for a NULL context.

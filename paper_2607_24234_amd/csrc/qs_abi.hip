@@ -266,6 +266,7 @@ qs_status make_plan(const qs_params *params, int32_t n, const qs_plan *plan, Pla
         d.state_off = state;
         d.omega_off = table;
         d.snap_off = snap;
+        d.snap_ld = (int32_t)p.n_modes;
         const double h = p.length / p.n_xi;
         const bool drop = (p.flags & QS_FLAG_DROP_LONGITUDINAL) != 0;
         d.h = h;
@@ -406,6 +407,7 @@ struct qs_ctx {
     char *ws = nullptr;
     bool owns_ws = false;
     int64_t steps_done = 0;
+    int32_t graphs = 0;   // live graphs (they read the instance table, snapshot layout included)
     // the state holds invalid results (a reported failure with no rollback copy); stepping is
     // refused until qs_set_state or qs_load_checkpoint replaces it
     bool poisoned = false;
@@ -606,7 +608,7 @@ qs_status qs::set_snapshot_cells(qs_ctx *c, const int32_t *first, int64_t *snap_
         InstDev &d = pl.inst[i];
         d.snap_first = first[i];
         d.snap_off = snap;
-        snap += (int64_t)(d.n_xi - d.snap_first) * d.n_modes;
+        snap += (int64_t)(d.n_xi - d.snap_first) * d.snap_ld;
     }
     pl.snap_elems = snap;
     *snap_elems = snap;
@@ -875,6 +877,30 @@ qs_status qs_sync_check(qs_ctx *c) {
     return fail(st, msg + "; the state is invalid until replaced (qs_set_state or qs_load_checkpoint)");
 }
 
+qs_status qs_set_snapshot_align(qs_ctx *c, int32_t align, int64_t *snapshot_elems) {
+    if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
+    if (c->grid) return fail(QS_ERR_UNSUPPORTED, "transverse-grid contexts have their own snapshot layout");
+    if (align < 1 || align > 1024 || (align & (align - 1)) != 0)
+        return fail(QS_ERR_ARG, "align must be a power of two in [1, 1024]");
+    if (c->graphs > 0) return fail(QS_ERR_STATE, "the context has live graphs, which keep its snapshot layout");
+    Plan &pl = c->pl;
+    int64_t snap = 0;
+    for (InstDev &d : pl.inst) {
+        d.snap_first = 0;
+        d.snap_ld = (int32_t)(((int64_t)d.n_modes + align - 1) / align * align);
+        d.snap_off = snap;
+        snap += (int64_t)d.n_xi * d.snap_ld;
+    }
+    pl.snap_elems = snap;
+    if (snapshot_elems) *snapshot_elems = snap;
+    QS_HIP(hipSetDevice(c->device), "hipSetDevice");
+    QS_HIP(hipMemcpyAsync(c->at(pl.off_inst), pl.inst.data(), pl.inst.size() * sizeof(InstDev), hipMemcpyHostToDevice,
+                          c->stream),
+           "copy instance table");
+    QS_HIP(hipStreamSynchronize(c->stream), "synchronize");
+    return QS_OK;
+}
+
 qs_status qs_set_rollback(qs_ctx *c, int32_t enable) {
     if (!c) return fail(QS_ERR_ARG, "ctx is NULL");
     if (c->grid) return fail(QS_ERR_UNSUPPORTED, "transverse-grid contexts have no rollback copy");
@@ -1029,13 +1055,19 @@ struct CkptHeader {
 constexpr uint64_t kCkptMagic = 0x3130544B50435351ull;
 
 uint64_t shape_hash(const Plan &pl) {
-    // FNV-1a over the instance table (sizes, offsets and step constants)
+    // FNV-1a over the instance table (sizes, offsets and step constants; the snapshot layout
+    // is no part of the state)
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](const void *p, size_t n) {
         const unsigned char *b = static_cast<const unsigned char *>(p);
         for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
     };
-    for (const InstDev &d : pl.inst) mix(&d, sizeof(d));
+    for (InstDev d : pl.inst) {
+        d.snap_off = 0;
+        d.snap_first = 0;
+        d.snap_ld = 0;
+        mix(&d, sizeof(d));
+    }
     mix(&pl.precision, sizeof(pl.precision));
     mix(&pl.nc, sizeof(pl.nc));
     mix(pl.wave_table.data(), pl.wave_table.size() * sizeof(int2));
@@ -1338,6 +1370,7 @@ qs_status qs_graph_create(qs_ctx *c, int32_t n_steps, int32_t out_every, void *o
     q->ctx = c;
     q->exec = exec;
     q->n_steps = n_steps;
+    ++c->graphs;
     *out = q;
     return QS_OK;
 }
@@ -1358,6 +1391,7 @@ void qs_graph_free(qs_graph *g) {
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
     (void)hipGraphExecDestroy(g->exec);
+    --g->ctx->graphs;
     delete g;
 }
 

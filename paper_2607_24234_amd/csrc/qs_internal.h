@@ -32,6 +32,8 @@ struct InstDev {
     int64_t scale_off;   // offset of (segment 0, mode 0) in the per-(mode, segment) scale arrays
     int32_t n_seg;       // xi-segments (waves per block) of this instance
     int32_t seg_len;     // cells per segment (the last one may be shorter)
+    int32_t snap_ld;     // elements between the snapshot rows of consecutive cells (>= n_modes)
+    int32_t pad_;
     double h, ih;        // cell width, 1/h (0 when the longitudinal term is dropped)
     double dtau;
     double ginv, g3inv;  // gamma^-1, gamma^-3 (g3inv is 0 when the longitudinal term is dropped)
@@ -102,7 +104,7 @@ qs_status set_mode_coefficients(qs_ctx *c, const double *cT, const double *cP);
 
 // Narrow the snapshots of a spectral context to the cells j >= first[i] of each instance i
 // (host array of n_instances, 0 <= first[i] < n_xi): instance i then holds
-// [n_xi - first[i]][n_modes] elements of each snapshot, row j - first[i] for cell j, at the
+// [n_xi - first[i]][snap_ld] elements of each snapshot, row j - first[i] for cell j, at the
 // running offset over the instances (qs_growth.hip reads only the rear cells).  *snap_elems
 // receives the elements of one snapshot.  Synchronous; QS_ERR_ARG for an invalid cell.
 qs_status set_snapshot_cells(qs_ctx *c, const int32_t *first, int64_t *snap_elems);

@@ -431,7 +431,7 @@ march_kernel(StepArgs a) {
                         if (writer && mloc[t] < I.n_modes && j >= I.snap_first) {
                             const double sh = (double)L[t] * 0.69314718055994530942;
                             const int64_t o = snap_row + (SNAP == kSnapEvery ? sl * a.snap_stride : 0) + I.snap_off +
-                                              (int64_t)(j - I.snap_first) * I.n_modes + mloc[t];
+                                              (int64_t)(j - I.snap_first) * I.snap_ld + mloc[t];
                             static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(s2) + sh);
                             static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
                         }

@@ -91,7 +91,7 @@ EXPORTS = ["qs_abi_version", "qs_last_error", "qs_workspace_size", "qs_workspace
            "qs_mlp_forward", "qs_mlp_grads", "qs_mlp_get_grads", "qs_mlp_set_grads", "qs_mlp_adamw",
            "qs_mlp_train_step", "qs_mlp_free", "qs_growth_targets", "qs_growth_sample",
            "qs_growth_features", "qs_growth_calibrate", "qs_growth_map", "qs_growth_map_noalloc",
-           "qs_sync_check", "qs_set_rollback", "qs_debug_set_wait_budget", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
+           "qs_sync_check", "qs_set_rollback", "qs_set_snapshot_align", "qs_debug_set_wait_budget", "qs_steps_done", "qs_get_state", "qs_set_state", "qs_free",
            "qs_debug_splitmix64", "qs_debug_mlp_gemm_check", "qs_checkpoint_size", "qs_save_checkpoint", "qs_load_checkpoint",
            "qs_svea_coefficients", "qs_svea_seed_impulse", "qs_svea_step", "qs_svea_ln_envelope",
            "qs_regime_map", "qs_surrogate_train", "qs_surrogate_load", "qs_surrogate_net", "qs_surrogate_table",
@@ -170,6 +170,8 @@ def lib():
     L.qs_sync_check.argtypes = [vp]
     L.qs_set_rollback.restype = ctypes.c_int
     L.qs_set_rollback.argtypes = [vp, ctypes.c_int32]
+    L.qs_set_snapshot_align.restype = ctypes.c_int
+    L.qs_set_snapshot_align.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
     L.qs_debug_set_wait_budget.restype = ctypes.c_int
     L.qs_debug_set_wait_budget.argtypes = [vp, ctypes.c_double]
     L.qs_debug_mlp_gemm_check.restype = ctypes.c_int32
@@ -635,7 +637,9 @@ class Solver:
         self.n_modes = [x.n_modes for x in self._insts]
         self.n_xi = [x.n_xi for x in self._insts]
         self.total_modes = sum(self.n_modes)
-        self.snap_elems = sum(m * n for m, n in zip(self.n_modes, self.n_xi))
+        self.state_elems = sum(m * n for m, n in zip(self.n_modes, self.n_xi))
+        self.snap_ld = list(self.n_modes)   # snapshot row length per instance (qs_set_snapshot_align)
+        self.snap_elems = self.state_elems
         self.dtype = torch.float64 if precision == QS_FP64 else torch.float32
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream() if stream is None else stream
@@ -676,10 +680,20 @@ class Solver:
         return res
 
     def snapshot_view(self, flat, instance=0):
-        """View of one instance's block of a snapshot row as [n_xi, n_modes]."""
-        off = sum(m * n for m, n in zip(self.n_modes[:instance], self.n_xi[:instance]))
-        n, m = self.n_xi[instance], self.n_modes[instance]
-        return flat[..., off:off + n * m].reshape(*flat.shape[:-1], n, m)
+        """View of one instance's block of a snapshot row as [n_xi, n_modes] (the padding of
+        aligned rows left out)."""
+        off = sum(ld * n for ld, n in zip(self.snap_ld[:instance], self.n_xi[:instance]))
+        n, m, ld = self.n_xi[instance], self.n_modes[instance], self.snap_ld[instance]
+        return flat[..., off:off + n * ld].reshape(*flat.shape[:-1], n, ld)[..., :m]
+
+    def set_snapshot_align(self, align):
+        """Pad each instance's snapshot rows to a multiple of `align` modes
+        (qs_set_snapshot_align; 1 = dense)."""
+        elems = ctypes.c_int64()
+        _check(lib().qs_set_snapshot_align(self.ctx, int(align), ctypes.byref(elems)))
+        self.snap_ld = [-(-m // align) * align for m in self.n_modes]
+        self.snap_elems = int(elems.value)
+        assert self.snap_elems == sum(ld * n for ld, n in zip(self.snap_ld, self.n_xi))
 
     def sync_check(self):
         _check(lib().qs_sync_check(self.ctx))
@@ -700,7 +714,7 @@ class Solver:
     def get_state(self):
         """Canonical state: list (per instance) of dicts rho, j_par, j_perp [n_modes, n_xi]
         complex128 and log2_scale [n_modes]."""
-        tot = self.snap_elems
+        tot = self.state_elems
         rho = np.empty(2 * tot)
         jpa = np.empty(2 * tot)
         jpe = np.empty(2 * tot)

@@ -188,3 +188,38 @@ def test_tuner_and_cache(qs, tmp_path, monkeypatch):
     for i in (0, 7):
         _, _, mx, _ = oracle_run(insts[i], 20, instance=i)
         ln_compare(mx_all[:, 70 * i:70 * (i + 1)], mx, FP32_TOL, what="tuned %d" % i)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_aligned_snapshot_rows_equal_dense(qs, precision):
+    """qs_set_snapshot_align: two instances with odd mode counts, their snapshot rows padded to
+    32 modes, give bitwise the dense layout's values at every snapshot (only the addresses
+    change), leave the padding unwritten and the per-step maxima unchanged; the call is
+    refused while a graph of the context exists."""
+    import torch
+    insts = [_slab(n_xi=150, length=20.0, kx=np.linspace(0.1, 3.0, 45), d_tau=30.0),
+             _slab(n_xi=97, length=12.0, kx=np.linspace(0.2, 2.5, 70), d_tau=25.0)]
+    a = qs.Solver(insts, precision=precision, segment_cells=40)
+    b = qs.Solver(insts, precision=precision, segment_cells=40)
+    b.set_snapshot_align(32)
+    assert b.snap_ld == [64, 96] and b.snap_elems == 150 * 64 + 97 * 96
+    n, every = 12, 4
+    ra = a.step(n, out_every=every, snapshots=True, max_ln_a=True)
+    out = {k: torch.full((n // every, b.snap_elems), float("nan"), dtype=b.dtype, device="cuda")
+           for k in ("ln_e", "ln_b")}
+    rb = b.step(n, out_every=every, snapshots=True, max_ln_a=True, out=out)
+    assert torch.equal(ra["max_ln_a"], rb["max_ln_a"])
+    for key in ("ln_e", "ln_b"):
+        for i in range(2):
+            x, y = a.snapshot_view(ra[key], i), b.snapshot_view(rb[key], i)
+            assert x.shape == y.shape and torch.equal(x, y)
+            off = sum(ld * m for ld, m in zip(b.snap_ld[:i], b.n_xi[:i]))
+            rows = rb[key][:, off:off + b.n_xi[i] * b.snap_ld[i]].reshape(n // every, b.n_xi[i], b.snap_ld[i])
+            assert bool(torch.isnan(rows[..., b.n_modes[i]:]).all())
+    g = qs.Graph(b, 4, out_every=4, snapshots=True)
+    with pytest.raises(qs.QSError) as e:
+        b.set_snapshot_align(1)
+    assert e.value.status == qs.QS_ERR_STATE
+    g.close()
+    b.set_snapshot_align(1)
+    assert b.snap_elems == a.snap_elems
