@@ -26,6 +26,12 @@
  * Fields at cell centres: E_par = -H[d_xi n_p], E_perp = -grad H[rho - n_p],
  * |B_perp| = |grad H[rho]|, H = (1 - Lap_perp)^-1 (the transverse form of the spectral
  * oracle's fields).
+ *
+ * Pinned (tests/test_oracle_grid.py): the FFT against a library transform; one transverse
+ * Fourier mode in a uniform beam against the spectral oracle; zero density; linearity; the
+ * mirror symmetries of the seeds; x <-> y transposition and whole-cell translation of a
+ * random problem.  Parity unpinned: the growth of narrow beams beyond these reductions (the
+ * paper leaves the geometric factor of the finite-width growth open, Sec. IV.B).
  */
 #include <complex.h>
 #include <math.h>

@@ -105,3 +105,55 @@ def test_mirror_symmetries():
     assert np.max(np.abs(od.rho + od.rho[:, :, mirror])) <= 1e-12 * s
     # the hosing seed grows: the run is not trivial
     assert s > 1.02 * s0
+
+
+def _random_problem(n=16, n_xi=16, seed=5):
+    """A square periodic grid with a random, nowhere-symmetric positive Omega(xi, y, x) and a
+    random state."""
+    rng = np.random.default_rng(seed)
+    omega = 0.02 * (0.5 + rng.random((n_xi, n, n)))
+    G = O.Grid(n, n, n_xi, 7.0, 7.0, 0.25, 40.0, omega)
+    st = O.GridState(G)
+    for v in st.arrays():
+        v[...] = 1e-3 * rng.standard_normal(v.shape)
+    st.jpar[-1] = 0.0   # the rear face carries no current
+    return omega, G, st
+
+
+def test_transpose_symmetry():
+    """x <-> y on a square grid: the problem with Omega and the state transposed (and j_x, j_y
+    exchanged) evolves into the transposed solution.  An x/y mix-up anywhere in the transverse
+    solve (a k_x where k_y belongs, a wrong stride of the column transform) breaks it."""
+    omega, G, a = _random_problem()
+    Gt = O.Grid(G.nx, G.ny, G.n_xi, G.lx, G.ly, G.h, G.gamma, omega.transpose(0, 2, 1).copy())
+    b = O.GridState(Gt)
+    b.rho[...] = a.rho.transpose(0, 2, 1)
+    b.jpar[...] = a.jpar.transpose(0, 2, 1)
+    b.jx[...] = a.jy.transpose(0, 2, 1)
+    b.jy[...] = a.jx.transpose(0, 2, 1)
+    ea, ba, ma = O.grid_run(G, 3.0, 4, a)
+    eb, bb, mb = O.grid_run(Gt, 3.0, 4, b)
+    for x, y in ((a.rho, b.rho), (a.jpar, b.jpar), (a.jx, b.jy), (a.jy, b.jx)):
+        assert np.max(np.abs(x.transpose(0, 2, 1) - y)) <= 1e-12 * np.max(np.abs(x))
+    assert np.max(np.abs(ea.transpose(0, 1, 3, 2) - eb)) <= 1e-10
+    assert np.max(np.abs(ba.transpose(0, 1, 3, 2) - bb)) <= 1e-10
+    assert np.max(np.abs(ma - mb)) <= 1e-10
+    # the run is not trivial: the state changed
+    _, _, c = _random_problem()
+    assert np.max(np.abs(a.rho - c.rho)) > 1e-3 * np.max(np.abs(c.rho))
+
+
+def test_translation_equivariance():
+    """Periodic grid: the problem rolled by whole cells in x and y (Omega and the state)
+    evolves into the rolled solution."""
+    omega, G, a = _random_problem(seed=9)
+    sx, sy = 5, 3
+    roll = lambda v: np.roll(v, (sy, sx), axis=(-2, -1))
+    Gr = O.Grid(G.nx, G.ny, G.n_xi, G.lx, G.ly, G.h, G.gamma, roll(omega).copy())
+    b = O.GridState(Gr)
+    for vb, va in zip(b.arrays(), a.arrays()):
+        vb[...] = roll(va)
+    O.grid_run(G, 3.0, 4, a, want_fields=False, want_max=False)
+    O.grid_run(Gr, 3.0, 4, b, want_fields=False, want_max=False)
+    for va, vb in zip(a.arrays(), b.arrays()):
+        assert np.max(np.abs(roll(va) - vb)) <= 1e-12 * np.max(np.abs(va))
