@@ -428,12 +428,20 @@ march_kernel(StepArgs a) {
                             if (NC >= 2) s2 = k2kap2[t] * (ncf0[2 * t] * ncf0[2 * t] + ncf0[2 * t + 1] * ncf0[2 * t + 1]);
                             else s2 = pair_sum(k2kap2[0] * ncf0[0] * ncf0[0]);
                         }
-                        if (writer && mloc[t] < I.n_modes && j >= I.snap_first) {
+                        if (mloc[t] < I.n_modes && j >= I.snap_first) {
                             const double sh = (double)L[t] * 0.69314718055994530942;
                             const int64_t o = snap_row + (SNAP == kSnapEvery ? sl * a.snap_stride : 0) + I.snap_off +
                                               (int64_t)(j - I.snap_first) * I.snap_ld + mloc[t];
-                            static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(s2) + sh);
-                            static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
+                            if (NC >= 2) {
+                                static_cast<TS *>(a.ln_e)[o] = (TS)(0.5 * (double)log(s2) + sh);
+                                static_cast<TS *>(a.ln_b)[o] = (TS)(0.5 * (double)log(b2) + sh);
+                            } else {
+                                // the mode's two lanes hold the same sums: the even lane writes
+                                // ln|E|, the odd one ln|B|, in one store
+                                const bool odd = (lane & 1) != 0;
+                                TS *dst = static_cast<TS *>(odd ? a.ln_b : a.ln_e);
+                                dst[o] = (TS)(0.5 * (double)log(odd ? b2 : s2) + sh);
+                            }
                         }
                     }
                 }
