@@ -138,6 +138,33 @@ def test_spectral3d_headline_fp32_all_steps(qs):
     s.close()
 
 
+def test_spectral3d_twenty_step_call_aligned(qs):
+    """The benchmark's short form: 5 steps, then one call of 20 steps whose first step writes
+    the snapshot into rows aligned to 32 modes, with the autotuner's plan for 20-step calls (2
+    segments of 2048 cells); 16 sampled modes of the per-step maxima and of the snapshot (the
+    state after 5 steps) against the FP64 oracle."""
+    import torch
+    from paper_2607_24234_amd import inputs
+    inst = inputs.spectral3d()
+    sample = _sample_3d(inst["kx"], inst["ky"])
+    s = qs.Solver([inst], precision=qs.QS_FP32, columns_per_lane=1, segment_cells=2048)
+    s.set_snapshot_align(32)
+    assert s.plan()["max_segments"] == 2 and s.snap_elems == inst["n_xi"] * 205888
+    idx = torch.as_tensor(sample, device="cuda")
+    warm = s.step(5, max_ln_a=True)
+    out = s.step(20, out_every=20, snapshots=True, max_ln_a=True)
+    gm = torch.cat([warm["max_ln_a"], out["max_ln_a"]])[:, idx].cpu().numpy()
+    ge = s.snapshot_view(out["ln_e"])[:, :, idx].cpu().numpy()
+    gb = s.snapshot_view(out["ln_b"])[:, :, idx].cpu().numpy()
+    del out, warm
+    torch.cuda.synchronize()
+    s.sync_check()
+    ln_e, ln_b, mx, _ = oracle_run(inst, 25, out_every=5, modes=sample, renorm=True)
+    ln_compare(gm, mx, FP32_TOL, what="3d 20-step call max ln A")
+    fields_compare(ge, gb, ln_e[1:2], ln_b[1:2], FP32_TOL, what="3d 20-step call snapshot")
+    s.close()
+
+
 def test_spectral3d_fp64_200_steps(qs):
     """The same workload in FP64 for 200 steps (three 1366-cell segments), snapshots every
     100 steps: 16 sampled modes to 1e-9."""
