@@ -43,33 +43,41 @@ def kernel_source_hash():
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(precision_name, steps_per_launch):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy) from
-    the rocprofv3 counter summary, per tau-step, times the steps of one launch -- only if the
-    counters were taken on the current kernel source (else None)."""
-    p = os.path.join(ROOT, "profiles", "march_spectral3d_traffic.json")
-    if not os.path.exists(p):
-        return None
+def _counter_entry(path, precision_name, steps_per_launch):
+    """The counter summary entry for this precision taken on launches of this many steps, if
+    it was taken on the current kernel source (else None)."""
     try:
-        d = json.load(open(p))
-        e = d.get(precision_name)
-        if not e or e.get("kernel_sha256_16") != kernel_source_hash():
-            return None
-        return float(e["bytes_per_step"]) * steps_per_launch
+        d = json.load(open(path))
+    except Exception:
+        return None
+    for key, e in d.items():
+        if key.split("_")[0] != precision_name or not isinstance(e, dict):
+            continue
+        if e.get("kernel_sha256_16") == kernel_source_hash() and int(e.get("steps_per_dispatch", 0)) == int(steps_per_launch):
+            return e
+    return None
+
+
+def read_traffic(precision_name, steps_per_launch):
+    """HBM bytes of one launch (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy) from
+    the rocprofv3 counter summary taken on launches of the same length and the current kernel
+    source (else None)."""
+    e = _counter_entry(os.path.join(ROOT, "profiles", "march_spectral3d_traffic.json"), precision_name,
+                       steps_per_launch)
+    try:
+        return None if e is None else float(e["bytes_per_step"]) * steps_per_launch
     except Exception:
         return None
 
 
-def read_valu(precision_name):
+def read_valu(precision_name, steps_per_launch):
     """Wave64 VALU instructions per cell-update of the stepping launch (SQ_INSTS_VALU over
-    the launch's cell-updates) from the rocprofv3 counter summary -- only if the counters
-    were taken on the current kernel source (else None)."""
-    p = os.path.join(ROOT, "profiles", "march_spectral3d_valu.json")
+    the launch's cell-updates) from the rocprofv3 counter summary taken on launches of the
+    same length and the current kernel source (else None)."""
+    e = _counter_entry(os.path.join(ROOT, "profiles", "march_spectral3d_valu.json"), precision_name,
+                       steps_per_launch)
     try:
-        e = json.load(open(p))[precision_name]
-        if e.get("kernel_sha256_16") != kernel_source_hash():
-            return None
-        return float(e["wave_instructions_per_cell_update"])
+        return None if e is None else float(e["wave_instructions_per_cell_update"])
     except Exception:
         return None
 
@@ -691,7 +699,7 @@ def main():
     flops = FLOP_PER_CELL_UPDATE * rate / 1e12   # TFLOP/s of the method's arithmetic
     bpc = 24 if prec == qs.QS_FP32 else 48       # state bytes per cell-update, two steps per sweep
     traffic = read_traffic(args.precision, steps_per_launch)
-    valu = read_valu(args.precision)
+    valu = read_valu(args.precision, steps_per_launch)
     growth = float((max_buf[K - 1].max() - max_buf[0].max()).item()) if K > 1 else 0.0
     plan = solver.plan()
 
