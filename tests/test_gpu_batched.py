@@ -216,10 +216,22 @@ def test_aligned_snapshot_rows_equal_dense(qs, precision):
             off = sum(ld * m for ld, m in zip(b.snap_ld[:i], b.n_xi[:i]))
             rows = rb[key][:, off:off + b.n_xi[i] * b.snap_ld[i]].reshape(n // every, b.n_xi[i], b.snap_ld[i])
             assert bool(torch.isnan(rows[..., b.n_modes[i]:]).all())
-    g = qs.Graph(b, 4, out_every=4, snapshots=True)
+    # a graph made on the aligned context writes the aligned layout on every replay: the same
+    # values as eager aligned steps from the same state; the layout cannot change under it
+    c = qs.Solver(insts, precision=precision, segment_cells=40)
+    c.set_snapshot_align(32)
+    c.step(n)
+    g = qs.Graph(b, 4, out_every=2, snapshots=True, max_ln_a=True)
     with pytest.raises(qs.QSError) as e:
         b.set_snapshot_align(1)
     assert e.value.status == qs.QS_ERR_STATE
+    for _ in range(2):
+        rg = g.replay()
+        torch.cuda.synchronize()
+        rc = c.step(4, out_every=2, snapshots=True, max_ln_a=True)
+        for key in ("ln_e", "ln_b", "max_ln_a"):
+            assert torch.equal(rg[key], rc[key]) if key == "max_ln_a" else all(
+                torch.equal(b.snapshot_view(rg[key], i), c.snapshot_view(rc[key], i)) for i in range(2))
     g.close()
     b.set_snapshot_align(1)
     assert b.snap_elems == a.snap_elems
