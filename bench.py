@@ -467,6 +467,7 @@ def surrogate_vs_solver(n_cmp, cfg=None, log=None, n_stream=10_000_000):
     stream_s = time.perf_counter() - t
     n_fb = int(ub.sum().item())
     del qb, ob, ub
+    dense = dense_map_vs_surrogate(sur, log)
     per_sol, per_auto = sol_s / n_cmp, stream_s / n_stream
     log("AUTO on a stream of %d: %.4f s (%d to the solver), %.2f ns per query against the solver's %.2f us: %.0fx"
         % (n_stream, stream_s, n_fb, per_auto * 1e9, per_sol * 1e6, per_sol / per_auto))
@@ -475,6 +476,7 @@ def surrogate_vs_solver(n_cmp, cfg=None, log=None, n_stream=10_000_000):
            "auto_s": auto_s, "auto_speedup_same_batch": sol_s / auto_s,
            "auto_stream": {"queries": n_stream, "s": stream_s, "to_solver": n_fb, "s_per_query": per_auto},
            "auto_speedup_per_query": per_sol / per_auto,
+           "dense_map": dense,
            "auto_fraction_to_solver": n_sol / n_cmp,
            "auto_err_vs_solver": {"rms": float(np.sqrt(np.mean(da * da))), "p99": float(np.percentile(da, 99)),
                                   "max": float(da.max()), "within_tol": float(np.mean(da <= 1e-2))},
@@ -484,6 +486,83 @@ def surrogate_vs_solver(n_cmp, cfg=None, log=None, n_stream=10_000_000):
            "queries_recipe": "uniform over log10 n_b in [-3, -1], log10 gamma in [1, 4], k in [0.05, 4], "
                              "xi in [0, 200], tau in [0, tau_f]"}
     return fig, sur
+
+
+def dense_map_vs_surrogate(sur, log):
+    """Dense growth maps of 8 beams (n_b in {0.003, 0.03} x gamma in {20, 100, 500, 2500}, the
+    uniform seed S = 1e-6), each 128 modes k in [0.05, 4] x 8192 cells of width h0 = 200/8192 x
+    the 201 steps 0..200 of its tau_f/200: 1.7e9 outputs.  The solver marches the 8 beams in one
+    context, writing the fields of every step, and takes the windowed growth of every output
+    (qs_growth_targets): about one cell-update per output.  The network (surrogate mode, no
+    fallback) answers the same points as queries at the cell centres and steps, beam by beam
+    (the queries of a beam are made before its timed calls).  Both timed on the device with
+    their buffers allocated before."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import inputs, qs
+
+    n_k, n_xi, n_steps = 128, 8192, 200
+    ks = np.linspace(0.05, 4.0, n_k)
+    beams = [(nb, g) for nb in (0.003, 0.03) for g in (20.0, 100.0, 500.0, 2500.0)]
+    insts = [dict(species=[inputs.ELECTRON + (nb,)], gamma=g, length=200.0, n_xi=n_xi, kx=ks, ky=None,
+                  d_tau=10.0 * math.sqrt(g / nb) / n_steps, seed_kind=inputs.SEED_UNIFORM, seed_amp=1e-6, rng_seed=0)
+             for nb, g in beams]
+    s = qs.Solver(insts, precision=qs.QS_FP32)
+    n_snap = n_steps + 1
+    le = torch.empty((n_snap, s.snap_elems), dtype=torch.float32, device="cuda")
+    lb = torch.empty_like(le)
+    G = torch.empty_like(le)
+    gi = qs.GrowthInstances(insts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.step(n_steps, out_every=1, snapshots=True, out={"ln_e": le[:n_steps], "ln_b": lb[:n_steps]})
+    s.step(0, snapshots=True, out={"ln_e": le[n_steps:], "ln_b": lb[n_steps:]})
+    qs.growth_targets(gi, le, lb, G, stream=s.stream)
+    torch.cuda.synchronize()
+    solver_s = time.perf_counter() - t
+    s.sync_check()
+    del le, lb
+    # beam b's block of a snapshot row: [cell][mode] at offset b * n_xi * n_k
+    per = n_snap * n_xi * n_k
+    h0 = 200.0 / n_xi
+    kt = torch.as_tensor(ks, device="cuda")
+    chunk = 10_000_000
+    net_s, sq, mx, within, p99s = 0.0, 0.0, 0.0, 0.0, []
+    y = torch.empty(per, dtype=torch.float32, device="cuda")
+    for b, (nb, g) in enumerate(beams):
+        dt = insts[b]["d_tau"]
+        idx = torch.arange(per, device="cuda", dtype=torch.int64)
+        m, j, st = idx % n_k, (idx // n_k) % n_xi, idx // (n_k * n_xi)
+        q = torch.stack([torch.full((per,), math.log(nb), device="cuda", dtype=torch.float64),
+                         torch.full((per,), math.log(g), device="cuda", dtype=torch.float64),
+                         kt[m], (j.double() + 0.5) * h0, st.double() * dt], 1).float()
+        del idx, m, j, st
+        if b == 0:
+            qs.growth_map(sur.net, None, 0.0, q[:1024], qs.GROWTH_SURROGATE, y[:1024], stream=sur.net.stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a in range(0, per, chunk):
+            qs.growth_map(sur.net, None, 0.0, q[a:a + chunk], qs.GROWTH_SURROGATE, y[a:a + chunk],
+                          stream=sur.net.stream)
+        torch.cuda.synchronize()
+        net_s += time.perf_counter() - t
+        del q
+        ref = G.view(n_snap, len(beams), n_xi * n_k)[:, b].reshape(-1)
+        fin = torch.isfinite(ref)
+        d = (y - ref)[fin].double().abs()
+        sq += float(d.pow(2).sum())
+        mx = max(mx, float(d.max()))
+        within += float((d <= 1e-2).double().sum())
+        p99s.append(float(torch.quantile(d[::97].float(), 0.99)))
+    n = per * len(beams)
+    err = {"rms": math.sqrt(sq / n), "p99_worst_beam": max(p99s), "max": mx, "within_1e-2": within / n}
+    log("dense maps (%d beams x %d modes x %d cells x %d steps = %.2e outputs): solver %.4f s, network %.3f s "
+        "(solver %.0fx faster); network against the solver's maps: %s" % (len(beams), n_k, n_xi, n_snap, n, solver_s,
+                                                                         net_s, net_s / solver_s, err))
+    s.close()
+    return {"outputs": n, "beams": [{"nb_over_np": nb, "gamma_b": g} for nb, g in beams], "modes": n_k,
+            "cells": n_xi, "steps": n_snap, "solver_s": solver_s, "network_s": net_s,
+            "solver_speedup": net_s / solver_s, "network_err_vs_solver": err}
 
 
 def bench_surrogate(args):
