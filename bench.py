@@ -651,6 +651,42 @@ def bench_growth_solver(args):
           None, None, s_per_query=sec / n)
 
 
+def bench_mlp_train(args):
+    """The surrogate network's training step alone (forward, backward and AdamW on random data,
+    no surrogate build) at batches of 8192, 32,768 and 65,536 examples; the line reports the
+    largest."""
+    import numpy as np
+    import torch
+    from paper_2607_24234_amd import qs
+
+    net = qs.MLP(max_batch=65536)
+    rng = np.random.default_rng(0)
+    net.set_params((0.02 * rng.standard_normal(net.n_params)).astype(np.float32))
+    x = torch.rand((65536 * 8, 5), device="cuda") * 2 - 1
+    t = torch.randn(65536 * 8, device="cuda")
+    res = {}
+    for B, n in ((8192, 400), (32768, 100), (65536, 50)):
+        for _ in range(5):
+            net.train_step(x[:B], t[:B], 1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            o = (i * B) % (65536 * 8 - B)
+            net.train_step(x[o:o + B], t[o:o + B], 1e-4)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / n
+        res[B] = per
+        print("[mlp_train] batch %d: %.1f us per step, %.1f TFLOP/s" % (B, per * 1e6, 4.7e6 * B / per / 1e12),
+              file=sys.stderr, flush=True)
+    B = 65536
+    tf = 4.7e6 * B / res[B] / 1e12
+    _line("surrogate training examples/s", B / res[B], "examples/s", 50, 5, res[B] * 1e3, "bf16",
+          {"workload": "network 5-512x4-1 AdamW steps on random data", "batch": B},
+          {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": tf / 2500.0, "traffic": None,
+           "kernel": "one training step (forward, backward, AdamW: ~25 kernels), 4.7 MFLOP per example"},
+          None, us_per_step={str(k): v * 1e6 for k, v in res.items()})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -664,14 +700,14 @@ def main():
                          "(timed candidates, a few seconds) or the built-in heuristic")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", choices=["spectral3d", "batched", "finite_width", "surrogate", "svea", "regime",
-                                           "growth_solver"],
+                                           "growth_solver", "mlp_train"],
                     default="spectral3d",
                     help="spectral3d (default, the headline line); batched: 256-instance sweep in "
                          "one persistent launch; finite_width: 256^2 transverse grid x 8192 cells; "
                          "surrogate: growth-map queries, network against solver; svea: the envelope-"
                          "approximation variant on the 3D mode set; regime: the E/B regime map of a "
                          "3D snapshot; growth_solver: the growth map's solver alone on --queries "
-                         "scattered queries")
+                         "scattered queries; mlp_train: the network's training step alone")
     ap.add_argument("--queries", type=int, default=1_000_000,
                     help="growth_solver workload: number of scattered queries")
     ap.add_argument("--epochs", type=int, default=0,
@@ -710,7 +746,7 @@ def main():
     if args.workload != "spectral3d":
         {"batched": bench_batched, "finite_width": bench_finite_width,
          "surrogate": bench_surrogate, "svea": bench_svea, "regime": bench_regime,
-         "growth_solver": bench_growth_solver}[args.workload](args)
+         "growth_solver": bench_growth_solver, "mlp_train": bench_mlp_train}[args.workload](args)
         return
     inst = inputs.spectral3d()
     prec = qs.QS_FP32 if args.precision == "fp32" else qs.QS_FP64
